@@ -1,0 +1,61 @@
+"""Dense FFT Fresnel propagation (Sec. 6.1).
+
+The paraxial transfer function is separable: T(f_x, f_y) = e^(ikz) T(f_x) T(f_y)
+with T(f) = exp(-i pi lambda z f^2).  The constant phase e^(ikz) is dropped
+(reading), the grid is periodic with no zero padding (the FFT and the lattice
+models of Sec. 6.2 are both periodic), and f runs over numpy's ``fftfreq``
+ordering, i.e. bin N/2 is the negative Nyquist frequency.
+
+E_z = IFFT2( FFT2(E_0) * T ) is the plain definition of what the MPO path
+computes: in the lossless regime the MPS/MPO result equals it exactly (Sec. 5,
+image formation is "exactly equivalent" to the grid FFT computation).
+"""
+import numpy as np
+
+
+def transfer_1d(n_side, lam, dx, z):
+    """T(f) = exp(-i pi lam z f^2) on the FFT frequency grid (Sec. 6.1)."""
+    f = np.fft.fftfreq(n_side, d=dx)
+    return np.exp(-1j * np.pi * lam * z * f * f)
+
+
+def fresnel_dense(e0, lam, dx, z):
+    """Propagate an N x N field by distance z (complex128)."""
+    e0 = np.asarray(e0, dtype=np.complex128)
+    n_side = e0.shape[0]
+    t = transfer_1d(n_side, lam, dx, z)
+    h = t[:, None] * t[None, :]
+    return np.fft.ifft2(np.fft.fft2(e0) * h)
+
+
+def fresnel_1d(u, lam, dx, z):
+    """1-D propagation of a length-N vector (periodic)."""
+    u = np.asarray(u, dtype=np.complex128)
+    t = transfer_1d(u.shape[0], lam, dx, z)
+    return np.fft.ifft(np.fft.fft(u) * t)
+
+
+def fresnel_matrix_1d(n_side, lam, dx, z):
+    """Dense N x N real-space propagator F^-1 diag(T) F (Sec. 6.1, Fig. MPO of
+    the optical propagation): column j is the propagated unit vector e_j."""
+    eye = np.eye(n_side, dtype=np.complex128)
+    t = transfer_1d(n_side, lam, dx, z)
+    return np.fft.ifft(np.fft.fft(eye, axis=0) * t[:, None], axis=0)
+
+
+def gaussian_beam_exact(n_side, w0, lam, dx, z, ca, cb):
+    """Closed-form paraxial propagation of exp(-r^2/w0^2) (r in pixels).
+
+    Derived from the transfer function of Sec. 6.1: the Fourier transform of a
+    Gaussian is Gaussian, the quadratic phase adds to its exponent, giving
+    E_z = q^-1 exp(-r^2 / (w0^2 q)),  q = 1 + i z / z_R,  z_R = pi w0^2 / lam,
+    with w0 and r converted to metres by dx.  Valid on the periodic grid while
+    the beam tails stay negligible at the grid edge.
+    """
+    w = w0 * dx
+    zr = np.pi * w * w / lam
+    q = 1.0 + 1j * z / zr
+    a = (np.arange(n_side)[:, None] - ca) * dx
+    b = (np.arange(n_side)[None, :] - cb) * dx
+    r2 = a * a + b * b
+    return np.exp(-r2 / (w * w * q)) / q

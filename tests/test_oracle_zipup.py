@@ -1,0 +1,139 @@
+"""Pins for the oracle's zip-up / sweep / rounding / decompression.
+
+References independent of the zip-up code: the dense FFT propagation (lossless
+regime is exact), a fast Walsh-Hadamard transform written here, the identity
+operator, and the textbook fact that TT-rounding of an exact TT equals the
+TT-SVD of its dense vector.
+"""
+import numpy as np
+import pytest
+
+from oracle import fresnel as F
+from oracle import mpo as M
+from oracle import quantics as Q
+from oracle import ttsvd as T
+from oracle import zipup as Z
+import synth
+
+LAM, DX = 500e-9, 1e-6
+BIG = 1 << 20
+
+
+def _axis_mpos(n, z):
+    c = M.mpo_from_matrix(F.fresnel_matrix_1d(1 << n, LAM, DX, z), n)
+    return M.embed_axis(c, "x"), M.embed_axis(c, "y")
+
+
+def _propagate(cores, wx, wy, chi, chi_zip=None):
+    c1, _ = Z.mpo_apply(cores, wx, chi, chi_zip)
+    return Z.mpo_apply(c1, wy, chi, chi_zip)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_lossless_equals_fft_random_8x8(seed):
+    n = 3
+    e0 = synth.random_field(seed, 8)
+    cores = T.tt_svd(Q.to_quantics(e0), 2 * n, chi=BIG)
+    wx, wy = _axis_mpos(n, 3e-6)
+    out, nrm = _propagate(cores, wx, wy, BIG)
+    ref = F.fresnel_dense(e0, LAM, DX, 3e-6)
+    assert _rel(Z.to_dense(out, n), ref) < 1e-12
+    assert abs(nrm - np.linalg.norm(ref)) < 1e-12 * np.linalg.norm(ref)
+
+
+def test_lossless_equals_fft_blob_64():
+    n = 6
+    img = synth.blob_image(0)
+    cores = T.tt_svd(Q.to_quantics(img), 2 * n, chi=64)
+    wx, wy = _axis_mpos(n, 1e-3)
+    out, _ = _propagate(cores, wx, wy, BIG)
+    ref = F.fresnel_dense(img, LAM, DX, 1e-3)
+    assert _rel(Z.to_dense(out, n), ref) < 1e-11
+    # output left-canonical
+    for c in out[:-1]:
+        mat = c.reshape(-1, c.shape[2])
+        assert np.allclose(mat.conj().T @ mat, np.eye(c.shape[2]), atol=1e-10)
+
+
+def test_identity_mpo_is_noop():
+    n = 5
+    e0 = synth.aperture_field(3, n=32)
+    cores = T.tt_svd(Q.to_quantics(e0), 2 * n, chi=BIG)
+    ident = [M.identity_core(1) for _ in range(2 * n)]
+    out, _ = Z.mpo_apply(cores, ident, BIG)
+    assert _rel(Z.to_dense(out, n), e0) < 1e-13
+
+
+def _fwht(v):
+    v = v.copy()
+    h = 1
+    while h < v.size:
+        for i in range(0, v.size, 2 * h):
+            a = v[i:i + h].copy()
+            b = v[i + h:i + 2 * h].copy()
+            v[i:i + h] = a + b
+            v[i + h:i + 2 * h] = a - b
+        h *= 2
+    return v / np.sqrt(v.size)
+
+
+def test_hadamard_mpo_equals_fast_wht():
+    n = 4
+    e0 = synth.random_field(8, 16)
+    v = Q.to_quantics(e0)
+    cores = T.tt_svd(v, 2 * n, chi=BIG)
+    out, _ = Z.mpo_apply(cores, M.hadamard_mpo(2 * n), BIG)
+    assert np.allclose(T.tt_dense(out), _fwht(v), atol=1e-12)
+
+
+@pytest.mark.parametrize("chi", [4, 8, 16])
+def test_lossless_zip_then_sweep_equals_ttsvd(chi):
+    n = 5
+    e0 = synth.aperture_field(4, n=32)
+    cores = T.tt_svd(Q.to_quantics(e0), 2 * n, chi=BIG)
+    wx, _ = _axis_mpos(n, 1e-3)
+    exact = Z.to_dense(Z.mpo_apply(cores, wx, BIG)[0], n)
+    got, _ = Z.mpo_apply(cores, wx, chi, chi_zip=BIG)
+    opt = T.tt_svd(Q.to_quantics(exact), 2 * n, chi)
+    assert _rel(T.tt_dense(got), T.tt_dense(opt)) < 1e-10
+    assert Z.bonds(got) == T.bonds(opt)
+
+
+@pytest.mark.parametrize("chi", [4, 8])
+def test_tt_truncate_equals_ttsvd(chi):
+    n = 5
+    e0 = synth.aperture_field(6, n=32)
+    exact = T.tt_svd(Q.to_quantics(e0), 2 * n, chi=BIG)
+    # scramble the gauge: multiply a random invertible matrix into each bond
+    rng = np.random.default_rng(0)
+    cores = [c.copy() for c in exact]
+    for k in range(len(cores) - 1):
+        r = cores[k].shape[2]
+        g = rng.standard_normal((r, r)) + np.eye(r) * 3
+        cores[k] = np.tensordot(cores[k], g, axes=(2, 0))
+        cores[k + 1] = np.tensordot(np.linalg.inv(g), cores[k + 1], axes=(1, 0))
+    got, nrm = Z.tt_truncate(cores, chi)
+    opt = T.tt_svd(Q.to_quantics(e0), 2 * n, chi)
+    assert _rel(T.tt_dense(got), T.tt_dense(opt)) < 1e-9
+    assert abs(nrm - np.linalg.norm(T.tt_dense(opt))) < 1e-9 * nrm
+
+
+def test_truncated_zipup_bounded_by_opt():
+    """chi_zip = chi (classic zip-up): error at least the optimal one and
+    within a small factor of it (the zip-up is the identical algorithm on
+    both sides of the GPU parity test; this bound is the only pin)."""
+    n = 6
+    img = synth.blob_image(2)
+    cores = T.tt_svd(Q.to_quantics(img), 2 * n, chi=32)
+    wx, wy = _axis_mpos(n, 1e-3)
+    ref = F.fresnel_dense(Z.to_dense(cores, n), LAM, DX, 1e-3)
+    got, _ = _propagate(cores, wx, wy, 16)
+    opt = T.tt_svd(Q.to_quantics(ref), 2 * n, 16)
+    e_got = _rel(Z.to_dense(got, n), ref)
+    e_opt = _rel(Z.to_dense(opt, n), ref)
+    assert e_got >= e_opt * (1 - 1e-9)
+    assert e_got < 5.0 * e_opt          # two sequential capped applications
