@@ -1,0 +1,199 @@
+/*
+ * qtt.h -- C ABI of libqtt, the MI355X (gfx950) quantics-MPS Fresnel path.
+ *
+ * What the library computes (paper: "Tensor network methods for
+ * quantum-inspired image processing and classical optics"):
+ *   - tt_encode:    a 2^n x 2^n image/field -> quantics MPS (bit-interleaved
+ *                   coordinates, Sec. 3) by sequential SVD (Sec. 4, App. A);
+ *   - mpo_apply:    MPO x MPS (Sec. 5; the Fresnel propagator of Sec. 6.1 is
+ *                   one MPO per axis) by zip-up, then an SVD truncation sweep;
+ *   - tt_truncate:  recompression of an MPS (QR sweep + SVD sweep);
+ *   - tt_to_dense:  decompression back to the N x N grid (Sec. 3, Fig. 6);
+ *   - mpo_apply_backward: adjoint of mpo_apply for gradient-based inverse
+ *                   problems (phase retrieval, listed as future work in Sec. 7).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Sites.  An N x N grid, N = 2^n, has m = 2n sites of dimension 2.  Site
+ *   2p-1 (1-based) is bit p of the row index a, site 2p bit p of the column
+ *   index b, most significant bit first (reading of Sec. 3).
+ * MPS storage (qtt_mps).  Device memory, caller-owned.  Core k (0-based) sits
+ *   at element offset k * chi_cap * 2 * chi_cap and is laid out
+ *   [r_k][s][r_(k+1)] row-major with row stride 2*chi_cap and physical stride
+ *   chi_cap (capacity layout: entries outside the actual bonds are ignored
+ *   and may hold anything).  The actual bond dimensions live on the DEVICE in
+ *   bonds[0..m] (bonds[0] = bonds[m] = 1) and are written by the library, so
+ *   no call ever synchronises with the host.  Element type is complex64
+ *   (QTT_C64, interleaved re/im floats) or complex128 (QTT_C128).
+ * MPO storage (qtt_mpo).  Device cores [D_k][t][s][D_(k+1)] row-major with
+ *   actual bonds (host array d_bonds[0..m]) -- operator bonds are static --
+ *   core k at element offset k * d_cap * 4 * d_cap; t is the output bit and s
+ *   the input bit.  site_kind[k] = 1 marks an identity site whose bond is
+ *   passed through (D_k == D_(k+1), core not read); NULL means all general.
+ * Truncation (qtt_opts).  At every bond, with lam_i the squared singular
+ *   values in descending order, keep
+ *       k = min(cap, k_eps, #{lam_i > tau * lam_1}), at least 1,
+ *   k_eps = smallest k with sum_{i>k} lam_i <= cutoff * sum_i lam_i
+ *   (cutoff = 0 disables it).  The zip-up uses cap = chi_zip (0 -> chi_max),
+ *   the sweep cap = chi_max.  tau <= 0 selects the default 1e-13.
+ * Precision.  QTT_PREC_FP32: complex64 operands, FP32 MFMA contractions;
+ *   Gram matrices accumulated and eigen-decomposed in FP64.  QTT_PREC_FP64:
+ *   complex128 throughout.  QTT_PREC_BF16: contraction operands rounded to
+ *   bfloat16, FP32 accumulation, FP64 Gram/eigen.
+ * Ownership.  The library never allocates device memory.  Every call takes a
+ *   caller-owned device workspace `ws` of at least tt_workspace_size(...)
+ *   bytes; its first 256 bytes hold the device status word.
+ * Streams.  Every call is enqueued on `stream` (a hipStream_t; NULL = the
+ *   default stream) and returns without synchronising.
+ * Errors.  Argument errors are detected on the host before anything is
+ *   enqueued and returned as negative codes.  Numerical failures (non-finite
+ *   values reaching an eigensolver) are recorded in the device status word
+ *   and reported by tt_check_status after it synchronises the stream.  No
+ *   call aborts the process and no C++ exception crosses this boundary.
+ *   tt_last_error() returns a message for the last failing call on the
+ *   calling thread.
+ */
+#ifndef QTT_H
+#define QTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum qtt_status {
+  QTT_OK = 0,
+  QTT_ERR_ARG = -1,        /* NULL pointer or invalid parameter              */
+  QTT_ERR_SHAPE = -2,      /* side not a power of two, m mismatch, n < 1     */
+  QTT_ERR_DTYPE = -3,      /* unsupported or mismatched element type         */
+  QTT_ERR_WORKSPACE = -4,  /* workspace (or saved buffer) too small          */
+  QTT_ERR_CAPACITY = -5,   /* chi_max > chi_cap, or bonds exceed capacity    */
+  QTT_ERR_HIP = -6,        /* a HIP runtime call failed                      */
+  QTT_ERR_NONFINITE = -7,  /* device: NaN/Inf reached a Gram/eigensolver     */
+  QTT_ERR_NOCONVERGE = -8  /* device: eigenvalue iteration cap reached       */
+};
+
+enum qtt_dtype { QTT_C64 = 1, QTT_C128 = 2, QTT_F32 = 3, QTT_F64 = 4 };
+enum qtt_prec { QTT_PREC_FP32 = 0, QTT_PREC_BF16 = 1, QTT_PREC_FP64 = 2 };
+enum qtt_op {
+  QTT_OP_ENCODE = 1, QTT_OP_APPLY = 2, QTT_OP_TRUNCATE = 3,
+  QTT_OP_TO_DENSE = 4, QTT_OP_APPLY_BACKWARD = 5
+};
+
+typedef struct {
+  int32_t n_sites;   /* m = 2n                                             */
+  int32_t chi_cap;   /* capacity bond dimension of the storage             */
+  int32_t dtype;     /* QTT_C64 or QTT_C128                                */
+  void* cores;       /* device, n_sites * chi_cap * 2 * chi_cap elements   */
+  int32_t* bonds;    /* device, n_sites + 1 ints                           */
+  double* norm;      /* device FP64 scalar ||psi||_2 written by the library, or NULL */
+} qtt_mps;
+
+typedef struct {
+  int32_t n_sites;
+  int32_t d_cap;
+  int32_t dtype;              /* QTT_C64 or QTT_C128 (matching the MPS)    */
+  const void* cores;          /* device, n_sites * d_cap * 4 * d_cap       */
+  const int32_t* d_bonds;     /* HOST, n_sites + 1 ints, d_bonds[0] = d_bonds[m] = 1 */
+  const int32_t* site_kind;   /* HOST, n_sites ints or NULL (0 general, 1 identity) */
+} qtt_mpo;
+
+typedef struct {
+  int32_t chi_max;   /* final bond cap                                     */
+  int32_t chi_zip;   /* zip-up bond cap, 0 -> chi_max                      */
+  double cutoff;     /* relative discarded-weight target (0 = off)         */
+  double tau;        /* numerical-zero threshold on lam_i / lam_1 (<=0: 1e-13) */
+  int32_t prec;      /* qtt_prec                                           */
+} qtt_opts;
+
+/* Bytes of device workspace needed by an operation on MPS of n_sites sites
+ * stored at capacity chi_cap, with MPO capacity d_cap (ignored by ops that
+ * take no MPO).  Returns 0 on invalid arguments. */
+size_t tt_workspace_size(int op, int n_sites, int chi_cap, int d_cap, int prec);
+
+/* Encode an N x N image into a quantics MPS by sequential SVD (Sec. 3, Sec. 4,
+ * App. A).  img: device, row-major N x N of img_dtype (F32/F64 real or
+ * C64/C128 complex); N = 2^log2_side, log2_side >= 1; out->n_sites must be
+ * 2*log2_side; opts->chi_max <= out->chi_cap.  The output is left-canonical
+ * with the norm in the last core; *out->norm receives ||img||_2 of the kept
+ * approximation.  opts->prec selects FP32 (out C64) or FP64 (out C128). */
+int tt_encode(const void* img, int img_dtype, int log2_side, const qtt_opts* opts,
+              qtt_mps* out, void* ws, size_t ws_bytes, void* stream);
+
+/* out = W . in by zip-up (right to left, cap chi_zip) followed by an SVD
+ * truncation sweep (left to right, cap chi_max): the MPO x MPS product of
+ * Sec. 5 with truncation.  `in` should be left-canonical (as produced by
+ * tt_encode, tt_truncate and mpo_apply).  out is left-canonical, *out->norm =
+ * ||out||.  in and out must not alias.  saved: if non-NULL, a device buffer of
+ * at least tt_saved_size(...) bytes that receives what mpo_apply_backward needs
+ * (the per-site zip-up carries); NULL skips it. */
+int mpo_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts,
+              qtt_mps* out, void* saved, size_t saved_bytes,
+              void* ws, size_t ws_bytes, void* stream);
+
+/* Recompress an MPS in place: QR sweep right to left, then SVD sweep left to
+ * right with cap opts->chi_max (TT-rounding).  Output left-canonical. */
+int tt_truncate(qtt_mps* inout, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream);
+
+/* Decompress: out[a][b] (row-major N x N, out_dtype C64 or C128) = the field
+ * the MPS represents (Sec. 3, decompression in Fig. 6). */
+int tt_to_dense(const qtt_mps* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of the `saved` buffer mpo_apply needs for a later backward call. */
+size_t tt_saved_size(int n_sites, int chi_cap, int d_cap, int prec);
+
+/* Adjoint of mpo_apply.  Given the forward input `in`, the operator W, the
+ * options used forward, the `saved` buffer filled by the forward call, the
+ * forward output `out` (its cores and bonds) and grad_out (same layout and
+ * bonds as out; PyTorch convention for a real loss L: dL/dRe + i dL/dIm),
+ * writes grad_in (same layout and bonds as in).  The truncated eigen/SVD
+ * steps are differentiated at fixed kept ranks; each site's forward
+ * intermediates are recomputed from the saved carries. */
+int mpo_apply_backward(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts,
+                       const void* saved, size_t saved_bytes,
+                       const qtt_mps* out, const qtt_mps* grad_out, qtt_mps* grad_in,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of tt_to_dense: grad_dense (device row-major N x N complex, same
+ * dtype as the MPS) -> grad (same layout and bonds as in). */
+int tt_to_dense_backward(const qtt_mps* in, const void* grad_dense, qtt_mps* grad,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* ---- auxiliary entry points (the building blocks of the calls above) ---- */
+
+/* C = op(A) . op(B) for dense row-major complex matrices through the MFMA
+ * contraction kernel used by every step above.  A is M x K (lda), B is K x N
+ * (ldb), C is M x N (ldc), all device pointers; conj_a / conj_b conjugate the
+ * operand elements.  prec QTT_PREC_FP32 (complex64) or QTT_PREC_FP64
+ * (complex128).  Asynchronous on `stream`. */
+int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void* B, int ldb, int conj_b,
+             void* C, int ldc, int prec, void* stream);
+
+/* Batched Hermitian eigen-decomposition with the keep rule of the truncation
+ * steps (Sec. 4: squared singular values of a bond cut are the eigenvalues of
+ * its Gram matrix).  G: device, batch x n x n complex128 row-major Hermitian
+ * (overwritten).  Writes, per matrix b: kept[b] (device int) from the keep
+ * rule with cap kcap / cutoff / tau, evals[b*kcap + i] (device double, the
+ * kept eigenvalues in descending order, zero beyond kept[b]) and
+ * evecs[b*n*kcap + p*kcap + i] (device complex128, eigenvector i).  n <= 512.
+ * ws: tt_heev_workspace_size(n, kcap, batch) bytes. */
+size_t tt_heev_workspace_size(int n, int kcap, int batch);
+int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int* kept, double* evals,
+            void* evecs, void* ws, size_t ws_bytes, void* stream);
+
+/* Synchronise `stream`, read the device status word in ws, reset it to 0 and
+ * return it (QTT_OK or a negative qtt_status). */
+int tt_check_status(void* ws, void* stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* tt_last_error(void);
+
+/* Library version string. */
+const char* tt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QTT_H */

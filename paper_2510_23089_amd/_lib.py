@@ -1,0 +1,105 @@
+"""ctypes view of libqtt's C ABI (include/qtt.h).  Argument marshalling only.
+
+The shared library is built in-tree (``python -m paper_2510_23089_amd.build``);
+loading fails loudly if it is missing -- there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqtt.so")
+
+QTT_C64, QTT_C128, QTT_F32, QTT_F64 = 1, 2, 3, 4
+PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
+OP_ENCODE, OP_APPLY, OP_TRUNCATE, OP_TO_DENSE, OP_APPLY_BACKWARD = 1, 2, 3, 4, 5
+
+STATUS = {
+    0: "QTT_OK", -1: "QTT_ERR_ARG", -2: "QTT_ERR_SHAPE", -3: "QTT_ERR_DTYPE",
+    -4: "QTT_ERR_WORKSPACE", -5: "QTT_ERR_CAPACITY", -6: "QTT_ERR_HIP",
+    -7: "QTT_ERR_NONFINITE", -8: "QTT_ERR_NOCONVERGE",
+}
+
+# every symbol include/qtt.h declares
+EXPORTS = [
+    "tt_workspace_size", "tt_encode", "mpo_apply", "tt_truncate", "tt_to_dense",
+    "tt_saved_size", "mpo_apply_backward", "tt_to_dense_backward",
+    "tt_check_status", "tt_last_error", "tt_version",
+    "tt_cgemm", "tt_heev_workspace_size", "tt_heev",
+]
+
+
+class QttMps(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("chi_cap", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("cores", ctypes.c_void_p), ("bonds", ctypes.c_void_p), ("norm", ctypes.c_void_p)]
+
+
+class QttMpo(ctypes.Structure):
+    _fields_ = [("n_sites", ctypes.c_int32), ("d_cap", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("cores", ctypes.c_void_p), ("d_bonds", ctypes.c_void_p), ("site_kind", ctypes.c_void_p)]
+
+
+class QttOpts(ctypes.Structure):
+    _fields_ = [("chi_max", ctypes.c_int32), ("chi_zip", ctypes.c_int32), ("cutoff", ctypes.c_double),
+                ("tau", ctypes.c_double), ("prec", ctypes.c_int32)]
+
+
+class QttError(RuntimeError):
+    def __init__(self, code, where, msg):
+        super().__init__("%s failed with %s (%d): %s" % (where, STATUS.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libqtt.so and declare the signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libqtt.so not built at %s; run `python -m paper_2510_23089_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp, sz, i32, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_double
+    lib.tt_workspace_size.argtypes = [i32, i32, i32, i32, i32]
+    lib.tt_workspace_size.restype = sz
+    lib.tt_saved_size.argtypes = [i32, i32, i32, i32]
+    lib.tt_saved_size.restype = sz
+    lib.tt_encode.argtypes = [vp, i32, i32, P(QttOpts), P(QttMps), vp, sz, vp]
+    lib.tt_encode.restype = i32
+    lib.mpo_apply.argtypes = [P(QttMps), P(QttMpo), P(QttOpts), P(QttMps), vp, sz, vp, sz, vp]
+    lib.mpo_apply.restype = i32
+    lib.tt_truncate.argtypes = [P(QttMps), P(QttOpts), vp, sz, vp]
+    lib.tt_truncate.restype = i32
+    lib.tt_to_dense.argtypes = [P(QttMps), vp, i32, vp, sz, vp]
+    lib.tt_to_dense.restype = i32
+    lib.mpo_apply_backward.argtypes = [P(QttMps), P(QttMpo), P(QttOpts), vp, sz, P(QttMps), P(QttMps),
+                                       P(QttMps), vp, sz, vp]
+    lib.mpo_apply_backward.restype = i32
+    lib.tt_to_dense_backward.argtypes = [P(QttMps), vp, P(QttMps), vp, sz, vp]
+    lib.tt_to_dense_backward.restype = i32
+    lib.tt_cgemm.argtypes = [i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, i32, vp]
+    lib.tt_cgemm.restype = i32
+    lib.tt_heev_workspace_size.argtypes = [i32, i32, i32]
+    lib.tt_heev_workspace_size.restype = sz
+    lib.tt_heev.argtypes = [vp, i32, i32, i32, dbl, dbl, vp, vp, vp, vp, sz, vp]
+    lib.tt_heev.restype = i32
+    lib.tt_check_status.argtypes = [vp, vp]
+    lib.tt_check_status.restype = i32
+    lib.tt_last_error.argtypes = []
+    lib.tt_last_error.restype = ctypes.c_char_p
+    lib.tt_version.argtypes = []
+    lib.tt_version.restype = ctypes.c_char_p
+    for name in ("tt_apply_workspace_size", "tt_batch_workspace_size", "tt_propagate_batched",
+                 "tt_apply_backward_workspace_size", "tt_refine_workspace_size", "tt_refine"):
+        if hasattr(lib, name):
+            getattr(lib, name).restype = sz if name.endswith("size") else i32
+    _lib = lib
+    return lib
+
+
+def check(code, where):
+    if code != 0:
+        msg = _lib.tt_last_error().decode() if _lib is not None else ""
+        raise QttError(code, where, msg)

@@ -1,0 +1,219 @@
+"""Python binding of libqtt: device tensors from PyTorch, compute in HIP.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+path runs in libqtt's kernels through the C ABI (see include/qtt.h).  Nothing
+here computes on the host except argument marshalling and bookkeeping.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_WS_CACHE = {}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def workspace(nbytes, device=None, key="default"):
+    """Cached device workspace (zero-initialised on first use: the status word
+    must start at 0)."""
+    device = device or torch.device("cuda")
+    k = (key, str(device))
+    buf = _WS_CACHE.get(k)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.zeros(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _WS_CACHE[k] = buf
+    return buf
+
+
+def _prec_code(prec):
+    return {"fp32": L.PREC_FP32, "bf16": L.PREC_BF16, "fp64": L.PREC_FP64}[prec]
+
+
+def _ctype(prec):
+    return torch.complex128 if prec == "fp64" else torch.complex64
+
+
+class MPS:
+    """Device MPS in capacity layout: cores (m, chi_cap, 2, chi_cap), bonds (m+1) int32."""
+
+    def __init__(self, n_sites, chi_cap, dtype=torch.complex64, device="cuda"):
+        self.n_sites = int(n_sites)
+        self.chi_cap = int(chi_cap)
+        self.cores = torch.zeros((n_sites, chi_cap, 2, chi_cap), dtype=dtype, device=device)
+        self.bonds = torch.ones(n_sites + 1, dtype=torch.int32, device=device)
+        self.norm = torch.zeros(1, dtype=torch.float64, device=device)
+
+    @property
+    def dtype(self):
+        return self.cores.dtype
+
+    @property
+    def prec(self):
+        return "fp64" if self.cores.dtype == torch.complex128 else "fp32"
+
+    def cstruct(self):
+        s = L.QttMps()
+        s.n_sites = self.n_sites
+        s.chi_cap = self.chi_cap
+        s.dtype = L.QTT_C128 if self.cores.dtype == torch.complex128 else L.QTT_C64
+        s.cores = self.cores.data_ptr()
+        s.bonds = self.bonds.data_ptr()
+        s.norm = self.norm.data_ptr()
+        return s
+
+    def host_cores(self):
+        """List of numpy cores [r_k, 2, r_(k+1)] (synchronises)."""
+        b = self.bonds.cpu().numpy()
+        c = self.cores.cpu().numpy()
+        return [c[k, :b[k], :, :b[k + 1]].copy() for k in range(self.n_sites)]
+
+    def host_bonds(self):
+        return [int(x) for x in self.bonds.cpu().numpy()]
+
+    @classmethod
+    def from_host(cls, cores, chi_cap=None, dtype=torch.complex64, device="cuda"):
+        m = len(cores)
+        cap = chi_cap or max(max(c.shape[0], c.shape[2]) for c in cores)
+        out = cls(m, cap, dtype=dtype, device=device)
+        host = np.zeros((m, cap, 2, cap), dtype=np.complex128)
+        bonds = [1]
+        for k, c in enumerate(cores):
+            host[k, :c.shape[0], :, :c.shape[2]] = c
+            bonds.append(c.shape[2])
+        out.cores.copy_(torch.from_numpy(host).to(dtype))
+        out.bonds.copy_(torch.tensor(bonds, dtype=torch.int32))
+        return out
+
+
+class MPO:
+    """Device MPO: flat cores, core k at offset k*d_cap*4*d_cap, dense
+    [D_k][t][s][D_(k+1)] with actual bonds; bonds and site kinds on the host."""
+
+    def __init__(self, cores, site_kind=None, dtype=torch.complex64, device="cuda", d_cap=None):
+        m = len(cores)
+        self.n_sites = m
+        self.d_bonds = np.array([1] + [int(c.shape[3]) for c in cores], dtype=np.int32)
+        assert int(cores[0].shape[0]) == 1 and self.d_bonds[-1] == 1
+        self.d_cap = int(d_cap or max(self.d_bonds.max(), max(int(c.shape[0]) for c in cores)))
+        stride = self.d_cap * 4 * self.d_cap
+        flat = np.zeros(m * stride, dtype=np.complex128)
+        for k, c in enumerate(cores):
+            v = np.asarray(c, dtype=np.complex128).reshape(-1)
+            flat[k * stride:k * stride + v.size] = v
+        self.flat = torch.from_numpy(flat).to(dtype).to(device)
+        self.site_kind = None if site_kind is None else np.array(site_kind, dtype=np.int32)
+        self.host = [np.asarray(c) for c in cores]
+
+    def cstruct(self):
+        s = L.QttMpo()
+        s.n_sites = self.n_sites
+        s.d_cap = self.d_cap
+        s.dtype = L.QTT_C128 if self.flat.dtype == torch.complex128 else L.QTT_C64
+        s.cores = self.flat.data_ptr()
+        s.d_bonds = self.d_bonds.ctypes.data
+        s.site_kind = self.site_kind.ctypes.data if self.site_kind is not None else None
+        return s
+
+
+def _opts(chi_max, chi_zip=0, cutoff=0.0, tau=0.0, prec="fp32"):
+    o = L.QttOpts()
+    o.chi_max = int(chi_max)
+    o.chi_zip = int(chi_zip or 0)
+    o.cutoff = float(cutoff)
+    o.tau = float(tau)
+    o.prec = _prec_code(prec)
+    return o
+
+
+def check_status(key="default"):
+    lib = L.load()
+    ws = workspace(256, key=key)
+    L.check(lib.tt_check_status(_ptr(ws), _stream()), "tt_check_status")
+
+
+# ------------------------------------------------------------------ entry points
+def tt_encode(img, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None):
+    """Encode a square 2^n x 2^n device tensor (float32/64, complex64/128)."""
+    lib = L.load()
+    assert img.is_cuda and img.dim() == 2 and img.shape[0] == img.shape[1]
+    n = int(img.shape[0]).bit_length() - 1
+    if (1 << n) != img.shape[0]:
+        raise ValueError("side must be a power of two")
+    img = img.contiguous()
+    dt = {torch.float32: L.QTT_F32, torch.float64: L.QTT_F64,
+          torch.complex64: L.QTT_C64, torch.complex128: L.QTT_C128}[img.dtype]
+    m = 2 * n
+    if out is None:
+        out = MPS(m, chi_cap or chi, dtype=_ctype(prec), device=img.device)
+    o = _opts(chi, 0, cutoff, tau, prec)
+    nb = lib.tt_workspace_size(L.OP_ENCODE, m, int(chi), 1, o.prec)
+    ws = workspace(nb, img.device)
+    s = out.cstruct()
+    L.check(lib.tt_encode(_ptr(img), dt, n, ctypes.byref(o), ctypes.byref(s), _ptr(ws), nb, _stream()), "tt_encode")
+    return out
+
+
+def mpo_apply(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_cap=None):
+    lib = L.load()
+    prec = psi.prec
+    if out is None:
+        out = MPS(psi.n_sites, chi_cap or chi, dtype=psi.dtype, device=psi.cores.device)
+    o = _opts(chi, chi_zip, cutoff, tau, prec)
+    cap = max(psi.chi_cap, out.chi_cap, int(chi_zip or 0), int(chi))
+    nb = lib.tt_workspace_size(L.OP_APPLY, psi.n_sites, cap, mpo.d_cap, o.prec)
+    ws = workspace(nb, psi.cores.device)
+    si, so, w = psi.cstruct(), out.cstruct(), mpo.cstruct()
+    L.check(lib.mpo_apply(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), ctypes.byref(so), None, 0,
+                          _ptr(ws), nb, _stream()), "mpo_apply")
+    return out
+
+
+def tt_truncate(psi, chi, cutoff=0.0, tau=0.0):
+    lib = L.load()
+    o = _opts(chi, 0, cutoff, tau, psi.prec)
+    nb = lib.tt_workspace_size(L.OP_TRUNCATE, psi.n_sites, psi.chi_cap, 1, o.prec)
+    ws = workspace(nb, psi.cores.device)
+    s = psi.cstruct()
+    L.check(lib.tt_truncate(ctypes.byref(s), ctypes.byref(o), _ptr(ws), nb, _stream()), "tt_truncate")
+    return psi
+
+
+def tt_to_dense(psi, out=None):
+    lib = L.load()
+    n = psi.n_sites // 2
+    if out is None:
+        out = torch.empty((1 << n, 1 << n), dtype=psi.dtype, device=psi.cores.device)
+    dt = L.QTT_C128 if out.dtype == torch.complex128 else L.QTT_C64
+    nb = lib.tt_workspace_size(L.OP_TO_DENSE, psi.n_sites, psi.chi_cap, 1,
+                               L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32)
+    ws = workspace(nb, psi.cores.device, key="dense")
+    s = psi.cstruct()
+    L.check(lib.tt_to_dense(ctypes.byref(s), _ptr(out), dt, _ptr(ws), nb, _stream()), "tt_to_dense")
+    return out
+
+
+class FresnelPropagator:
+    """Both axis MPOs of the Fresnel propagator for an N x N grid (Sec. 6.1)."""
+
+    def __init__(self, n, lam, dx, z, dtype=torch.complex64, device="cuda", rel=1e-12):
+        from . import mpo_build as B
+        w1 = B.fresnel_axis(n, lam, dx, z, rel)
+        cx, kx = B.embed(w1, "x")
+        cy, ky = B.embed(w1, "y")
+        dcap = max(B.bonds(w1))
+        self.wx = MPO(cx, kx, dtype=dtype, device=device, d_cap=dcap)
+        self.wy = MPO(cy, ky, dtype=dtype, device=device, d_cap=dcap)
+        self.axis_cores = w1
+
+    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None):
+        mid = mpo_apply(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp)
+        return mpo_apply(mid, self.wy, chi, chi_zip, cutoff, tau, out=out)

@@ -1,0 +1,62 @@
+// Shared device-side helpers of libqtt (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// A problem dimension known only on the device: value = c * (*p0) * (*p1),
+// a NULL pointer contributing 1.  Bond dimensions chosen by the eigensolver
+// are written to device memory and read back through these by later kernels
+// in the same stream, so the host never waits for them.
+struct DimExpr {
+  int c;
+  const int* p0;
+  const int* p1;
+};
+
+__device__ __forceinline__ int dim_eval(const DimExpr& d) {
+  int v = d.c;
+  if (d.p0) v *= *d.p0;
+  if (d.p1) v *= *d.p1;
+  return v;
+}
+
+// Division by a run-time constant d >= 1 for n < 2^31 (Granlund-Montgomery
+// round-up method): q = (umulhi(n, mul) + n) >> shift.
+struct FastDiv {
+  uint32_t d, mul, shift;
+};
+
+__device__ __forceinline__ uint32_t fdiv(const FastDiv& f, uint32_t n) {
+  uint64_t t = (uint64_t)__umulhi(n, f.mul) + n;
+  return (uint32_t)(t >> f.shift);
+}
+
+// One operand (or the result) of a batched complex contraction.  A logical
+// matrix index pair (x, y) is split as x = xh * Lx + xl, y = yh * Ly + yl
+// (Lx, Ly given by FastDiv of the owning dimension) and addressed at
+//   ptr + batch * sb + xh * sxh + xl * sxl + yh * syh + yl * syl
+// in complex elements.  This expresses every reshape/permutation the zip-up,
+// sweep, encode and decompression steps need without copies.
+struct Operand {
+  void* ptr;
+  long long sxh, sxl, syh, syl, sb;
+  int conj;
+};
+
+struct GemmArgs {
+  DimExpr M, N, K, batch;
+  FastDiv fm, fn, fk;     // low extents of the split M, N, K indices
+  Operand A, B, C;        // A: (M, K); B: (K, N); C: (M, N)
+  int accumulate;         // C += A.B instead of C = A.B
+  int ksplit;             // >1: blockIdx.y selects a K chunk; C gets batch stride csplit
+  long long csplit;       // complex-element stride between K-chunk partial results
+  int tiles_n;            // tile-grid width used to decode blockIdx.x
+  int Mmax, Nmax, Kmax, Bmax;   // host bounds: device sizes are clamped to these
+};
+
+// Device status word (first 4 bytes of every workspace).
+enum { ST_OK = 0, ST_NONFINITE = -7, ST_NOCONVERGE = -8 };
+
+__device__ __forceinline__ void set_status(int* st, int code) {
+  if (st) atomicCAS(st, 0, code);
+}

@@ -1,0 +1,301 @@
+// Batched complex contraction on CDNA4 matrix cores.
+//
+// Every tensor contraction of the zip-up, the truncation sweep, the encode
+// projections and the decompression is a batched complex matrix product
+// C = op(A) . op(B) over reshaped/permuted views of the cores (Operand
+// strides).  A complex product is run as ONE real product on the embedding
+//   [Re C | Im C] = [Re A | Im A] . [[Re B, Im B], [-Im B, Re B]],
+// i.e. the interleaved complex rows of A are already the real operand and the
+// 2x2 real block of each B element is generated while reading B's LDS tile.
+// This keeps complex64/complex128 interleaved in HBM and in the output with no
+// separate real/imaginary planes and no extra passes.
+//
+// Tiles: 64x64 complex outputs per 256-thread workgroup, 16 complex of depth
+// per LDS stage, 4 waves in a 2x2 arrangement, each wave a 32x64 real block
+// made of 16x16 MFMA tiles (v_mfma_f32_16x16x4f32 for FP32,
+// v_mfma_f64_16x16x4f64 for FP64 Gram matrices and the FP64 path).  Global
+// loads of the next stage are issued into registers before the MFMAs of the
+// current stage (software pipelining).  Dimensions are read from the device
+// (DimExpr), so tiles beyond the actual bond dimensions exit at once.
+#include "common.h"
+#include "kernels.h"
+
+namespace qtt {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename TC> struct Mfma;
+template <> struct Mfma<float> {
+  typedef floatx4 acc_t;
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  typedef doublex4 acc_t;
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { typedef float2 t; };
+template <> struct Vec2<double> { typedef double2 t; };
+
+constexpr int BM = 64, BN = 64, BKC = 16;   // complex tile sizes
+constexpr int PADA = 4, PADB = 4;
+constexpr int NT = 256;
+constexpr int A_PER_T = BM * BKC / NT;      // complex elements of A per thread per stage
+constexpr int B_PER_T = BKC * BN / NT;
+
+__device__ __forceinline__ long long split_off(const FastDiv& f, uint32_t x, long long sh, long long sl) {
+  uint32_t h = fdiv(f, x);
+  uint32_t l = x - h * f.d;
+  return (long long)h * sh + (long long)l * sl;
+}
+
+template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM>
+__global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
+  typedef typename Vec2<TIn>::t in2;
+  typedef typename Mfma<TC>::acc_t acc_t;
+  const int bz = blockIdx.z;
+  if (bz >= min(dim_eval(g.batch), g.Bmax)) return;
+  const int M = min(dim_eval(g.M), g.Mmax), N = min(dim_eval(g.N), g.Nmax), K = min(dim_eval(g.K), g.Kmax);
+  const int tm = blockIdx.x / g.tiles_n, tn = blockIdx.x % g.tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M || n0 >= N) return;
+  int kbeg = 0, kend = K;
+  if (g.ksplit > 1) {
+    int chunk = (K + g.ksplit - 1) / g.ksplit;
+    chunk = (chunk + BKC - 1) / BKC * BKC;
+    kbeg = blockIdx.y * chunk;
+    kend = min(K, kbeg + chunk);
+  }
+
+  __shared__ TC As[2 * BKC][BM + PADA];
+  __shared__ TC Bs[BKC][2 * BN + PADB];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const TIn* Ap = (const TIn*)g.A.ptr + 2 * (long long)bz * g.A.sb;
+  const TIn* Bp = (const TIn*)g.B.ptr + 2 * (long long)bz * g.B.sb;
+
+  // ---- per-thread fixed parts of the load addresses
+  int a_i[A_PER_T], a_k[A_PER_T];
+  long long a_rowoff[A_PER_T];
+  int b_k[B_PER_T], b_j[B_PER_T];
+  long long b_coloff[B_PER_T];
+#pragma unroll
+  for (int r = 0; r < A_PER_T; ++r) {
+    int e = t + r * NT;
+    if (AKM) { a_k[r] = e % BKC; a_i[r] = e / BKC; }
+    else     { a_i[r] = e % BM;  a_k[r] = e / BM; }
+    int gi = m0 + a_i[r];
+    a_rowoff[r] = gi < M ? split_off(g.fm, gi, g.A.sxh, g.A.sxl) : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < B_PER_T; ++r) {
+    int e = t + r * NT;
+    if (BKM) { b_k[r] = e % BKC; b_j[r] = e / BKC; }
+    else     { b_j[r] = e % BN;  b_k[r] = e / BN; }
+    int gj = n0 + b_j[r];
+    b_coloff[r] = gj < N ? split_off(g.fn, gj, g.B.syh, g.B.syl) : -1;
+  }
+
+  in2 ra[A_PER_T], rb[B_PER_T];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < A_PER_T; ++r) {
+      int gk = k0 + a_k[r];
+      in2 v; v.x = 0; v.y = 0;
+      if (a_rowoff[r] >= 0 && gk < kend) {
+        long long o = a_rowoff[r] + split_off(g.fk, gk, g.A.syh, g.A.syl);
+        v = *(const in2*)(Ap + 2 * o);
+      }
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < B_PER_T; ++r) {
+      int gk = k0 + b_k[r];
+      in2 v; v.x = 0; v.y = 0;
+      if (b_coloff[r] >= 0 && gk < kend) {
+        long long o = b_coloff[r] + split_off(g.fk, gk, g.B.sxh, g.B.sxl);
+        v = *(const in2*)(Bp + 2 * o);
+      }
+      rb[r] = v;
+    }
+  };
+  auto store_stage = [&]() {
+#pragma unroll
+    for (int r = 0; r < A_PER_T; ++r) {
+      TC re = (TC)ra[r].x, im = (TC)ra[r].y;
+      As[2 * a_k[r]][a_i[r]] = re;
+      As[2 * a_k[r] + 1][a_i[r]] = g.A.conj ? -im : im;
+    }
+#pragma unroll
+    for (int r = 0; r < B_PER_T; ++r) {
+      TC re = (TC)rb[r].x, im = (TC)rb[r].y;
+      Bs[b_k[r]][2 * b_j[r]] = re;
+      Bs[b_k[r]][2 * b_j[r] + 1] = g.B.conj ? -im : im;
+    }
+  };
+
+  constexpr int MI = BM / 32;   // 16-row MFMA blocks per wave
+  constexpr int NJ = BN / 16;   // 16-real-column MFMA blocks per wave (BN real cols)
+  acc_t acc[MI][NJ];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int cpart = lq & 1;
+  const TC bsign = cpart ? (TC)-1 : (TC)1;
+
+  if (kbeg < kend) {
+    load_stage(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += BKC) {
+      __syncthreads();
+      store_stage();
+      __syncthreads();
+      if (k0 + BKC < kend) load_stage(k0 + BKC);
+#pragma unroll
+      for (int ks = 0; ks < BKC / 2; ++ks) {
+        TC af[MI], bf[NJ];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) af[i] = As[ks * 4 + lq][wm * (BM / 2) + i * 16 + l16];
+        const int kc = ks * 2 + (lane >> 5);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          int jr = wn * BN + j * 16 + l16;
+          TC v = Bs[kc][jr ^ cpart];
+          bf[j] = (jr & 1) ? v : v * bsign;
+        }
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<TC>::op(af[i], bf[j], acc[i][j]);
+      }
+    }
+  }
+
+  // ---- epilogue: lanes (l, l^1) hold (re, im) of one complex output
+  TOut* Cp = (TOut*)g.C.ptr + 2 * ((long long)bz * g.C.sb + (long long)blockIdx.y * g.csplit);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    int jr = wn * BN + j * 16 + l16;
+    int gj = n0 + (jr >> 1);
+    long long coff = gj < N ? split_off(g.fn, gj, g.C.syh, g.C.syl) : -1;
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        TC v = acc[i][j][r];
+        TC pv = __shfl_xor(v, 1);
+        // output row of accumulator element r: the f32 16x16x4 MFMA gives lane
+        // group lq rows 4*lq + r, the f64 one rows 4*r + lq
+        const int row = sizeof(TC) == 8 ? (4 * r + lq) : (lq * 4 + r);
+        int gi = m0 + wm * (BM / 2) + i * 16 + row;
+        if (!(lane & 1) && coff >= 0 && gi < M) {
+          long long o = split_off(g.fm, gi, g.C.sxh, g.C.sxl) + coff;
+          typename Vec2<TOut>::t* dst = (typename Vec2<TOut>::t*)(Cp + 2 * o);
+          typename Vec2<TOut>::t w;
+          w.x = (TOut)v;
+          w.y = (TOut)pv;
+          if (g.accumulate) {
+            typename Vec2<TOut>::t old = *dst;
+            w.x += old.x;
+            w.y += old.y;
+          }
+          *dst = w;
+        }
+      }
+    }
+  }
+}
+
+// Sum of K-chunk partial results: out[i][j] = sum_c part[c][i][j], i, j < n.
+__global__ void ksplit_reduce_kernel(const double2* __restrict__ part, long long cstride, int nsplit,
+                                     double2* __restrict__ out, int ld, DimExpr nrows, DimExpr ncols,
+                                     long long bstride_part, long long bstride_out, DimExpr batch) {
+  const int b = blockIdx.z;
+  if (b >= dim_eval(batch)) return;
+  const int nr = min(dim_eval(nrows), (int)gridDim.y), nc = min(dim_eval(ncols), ld);
+  const int i = blockIdx.y;
+  if (i >= nr) return;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nc; j += gridDim.x * blockDim.x) {
+    double2 s = make_double2(0.0, 0.0);
+    const double2* p = part + b * bstride_part + (long long)i * ld + j;
+    for (int c = 0; c < nsplit; ++c) {
+      double2 v = p[c * cstride];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    out[b * bstride_out + (long long)i * ld + j] = s;
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d < 1 ? 1 : d;
+  uint32_t l = 0;
+  while ((1ull << l) < f.d) ++l;
+  f.shift = l;
+  f.mul = (uint32_t)(((1ull << 32) * ((1ull << l) - f.d)) / f.d + 1);
+  return f;
+}
+
+template <typename TIn, typename TC, typename TOut>
+static hipError_t launch_typed(const GemmArgs& g, dim3 grid, bool akm, bool bkm, hipStream_t s) {
+  if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true>), grid, dim3(NT), 0, s, g);
+  else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false>), grid, dim3(NT), 0, s, g);
+  else if (bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, true>), grid, dim3(NT), 0, s, g);
+  else hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, false>), grid, dim3(NT), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
+  GemmArgs g;
+  g.M = sp.M; g.N = sp.N; g.K = sp.K; g.batch = sp.batch;
+  g.fm = make_fastdiv(sp.mlo); g.fn = make_fastdiv(sp.nlo); g.fk = make_fastdiv(sp.klo);
+  g.A = sp.A; g.B = sp.B; g.C = sp.C;
+  g.accumulate = sp.accumulate;
+  g.ksplit = sp.ksplit < 1 ? 1 : sp.ksplit;
+  g.csplit = sp.csplit;
+  int tiles_m = (sp.m_bound + BM - 1) / BM;
+  int tiles_n = (sp.n_bound + BN - 1) / BN;
+  if (tiles_m < 1 || tiles_n < 1 || sp.batch_bound < 1) return hipSuccess;
+  g.tiles_n = tiles_n;
+  g.Mmax = sp.m_bound; g.Nmax = sp.n_bound; g.Kmax = sp.k_bound; g.Bmax = sp.batch_bound;
+  dim3 grid(tiles_m * tiles_n, g.ksplit, sp.batch_bound);
+  // coalescing pattern: which index is unit-stride in memory
+  bool akm = (sp.A.syl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.A.syh == 1);
+  bool bkm = (sp.B.sxl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.B.sxh == 1);
+  switch (sp.types) {
+    case GEMM_F32: return launch_typed<float, float, float>(g, grid, akm, bkm, s);
+    case GEMM_F32_GRAM64: return launch_typed<float, double, double>(g, grid, akm, bkm, s);
+    case GEMM_F64: return launch_typed<double, double, double>(g, grid, akm, bkm, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,
+                         DimExpr nrows, DimExpr ncols, int rows_bound, int cols_bound,
+                         long long bstride_part, long long bstride_out, DimExpr batch, int batch_bound,
+                         hipStream_t s) {
+  int bx = (cols_bound + 255) / 256;
+  if (bx < 1 || rows_bound < 1 || batch_bound < 1) return hipSuccess;
+  hipLaunchKernelGGL(ksplit_reduce_kernel, dim3(bx, rows_bound, batch_bound), dim3(256), 0, s,
+                     (const double2*)part, cstride, nsplit, (double2*)out, ld, nrows, ncols,
+                     bstride_part, bstride_out, batch);
+  return hipGetLastError();
+}
+
+}  // namespace qtt

@@ -1,0 +1,95 @@
+// Host-side launch interface of the libqtt kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "common.h"
+
+namespace qtt {
+
+enum GemmTypes { GEMM_F32 = 0, GEMM_F32_GRAM64 = 1, GEMM_F64 = 2 };
+
+// C(M,N) = op(A)(M,K) . op(B)(K,N), batched.  Sizes are device expressions;
+// *_bound are host upper bounds used only to size the launch grid.
+struct GemmSpec {
+  DimExpr M, N, K, batch;
+  int mlo, nlo, klo;            // low extents of the split indices (1 = unsplit)
+  int m_bound, n_bound, batch_bound;
+  int k_bound = 1 << 30;
+  Operand A, B, C;
+  int accumulate = 0;
+  int ksplit = 1;
+  long long csplit = 0;
+  int types = GEMM_F32;
+};
+
+FastDiv make_fastdiv(uint32_t d);
+hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s);
+hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,
+                         DimExpr nrows, DimExpr ncols, int rows_bound, int cols_bound,
+                         long long bstride_part, long long bstride_out, DimExpr batch, int batch_bound,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------- eigensolver
+// Batched Hermitian eigen-decomposition of FP64 Gram matrices followed by the
+// keep rule, for the truncation of one bond.  Matrices are n x n (n a device
+// value), stored full with leading dimension ld, batch stride gstride.
+// Up to kcap eigenpairs (descending) are computed; the kept count k is
+// written to *kout (device int, one per batch entry, stride kstride).
+struct EigEmit {
+  // Writes out[(p / lo) * s_hi + (p % lo) * s_lo + i * s_col] = f(V[p][i])
+  // for p < n, i < k, where f applies conj (if conj) and multiplies by
+  // sigma_i^pow (pow in {-1, 0, 1}).  dtype: 0 = complex float, 1 = complex double.
+  void* ptr = nullptr;
+  long long s_hi = 0, s_lo = 0, s_col = 0, s_batch = 0;
+  int lo = 1;
+  int conj = 0;
+  int pow = 0;
+  int dtype = 0;
+};
+
+struct EigSpec {
+  double* G;                  // n x n Hermitian (destroyed)
+  int ld;
+  long long gstride;
+  DimExpr n;
+  int n_bound;
+  int kcap;                   // bond cap
+  double cutoff, tau;
+  int* kout;                  // device, kept counts
+  long long kstride;
+  int batch;                  // number of matrices (host-known)
+  // workspace pointers (carved by the caller; sizes from eig_ws_bytes)
+  void* ws;
+  int* status;
+  EigEmit emit[3];
+  int nemit;
+  double* sigma_out;          // optional: device FP64 singular values [batch][kcap]
+};
+
+size_t eig_ws_bytes(int n_bound, int kcap, int batch);
+hipError_t eig_launch(const EigSpec& sp, hipStream_t s);
+hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s);
+
+// ---------------------------------------------------------------- misc
+// Quantics permutation of a row-major N x N image into the flat quantics
+// vector (dir = 0) or back (dir = 1).  src/dst element types given by the
+// qtt_dtype codes; the quantics side is always complex (float or double).
+hipError_t quantics_permute(const void* src, int src_dtype, void* dst, int dst_dtype, int log2_side,
+                            int dir, hipStream_t s);
+// Frobenius norm of a (rows x cols) complex block (strides ld_r, ld_c), FP64 result.
+hipError_t block_norm(const void* p, int dtype, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
+                      long long ld_r, long long ld_c, double* out, hipStream_t s);
+// Store complex 1 at p[0] (dtype 0 float, 1 double).
+hipError_t set_one(void* p, int dtype, hipStream_t s);
+// Copy a (rows x cols) complex block with arbitrary strides (dtype 0 float, 1 double).
+hipError_t block_copy(const void* src, long long s_rs, long long s_cs, void* dst, long long d_rs,
+                      long long d_cs, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound, int dtype,
+                      hipStream_t s);
+// Set dev[i] = val for the given list (used for boundary bonds).
+hipError_t set_ints(int* dev, int count, int val, hipStream_t s);
+hipError_t copy_ints(const int* src, int* dst, int count, hipStream_t s);
+// Clamped copy of caller bonds (see misc.hip).
+hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, hipStream_t s);
+// Scan a complex buffer for non-finite values and flag the status word.
+hipError_t check_finite(const void* p, int dtype, long long count, int* status, hipStream_t s);
+
+}  // namespace qtt

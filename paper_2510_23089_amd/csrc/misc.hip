@@ -1,0 +1,193 @@
+// Element-wise and reduction kernels of libqtt: the quantics index map of
+// Sec. 3 (row-major image <-> bit-interleaved vector), block copies, FP64
+// Frobenius norms and the non-finite scan.
+#include "common.h"
+#include "kernels.h"
+
+namespace qtt {
+
+// Compact the bits at even positions of x (bit 2q -> bit q).
+__device__ __forceinline__ uint32_t compact_even(uint32_t x) {
+  x &= 0x55555555u;
+  x = (x | (x >> 1)) & 0x33333333u;
+  x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+  x = (x | (x >> 4)) & 0x00FF00FFu;
+  x = (x | (x >> 8)) & 0x0000FFFFu;
+  return x;
+}
+// Spread the bits of x (bit q -> bit 2q).
+__device__ __forceinline__ uint32_t spread_even(uint32_t x) {
+  x &= 0x0000FFFFu;
+  x = (x | (x << 8)) & 0x00FF00FFu;
+  x = (x | (x << 4)) & 0x0F0F0F0Fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+__device__ __forceinline__ void load_elem(const void* p, int dtype, long long i, double& re, double& im) {
+  switch (dtype) {
+    case 1: { float2 v = ((const float2*)p)[i]; re = v.x; im = v.y; break; }      // C64
+    case 2: { double2 v = ((const double2*)p)[i]; re = v.x; im = v.y; break; }    // C128
+    case 3: { re = ((const float*)p)[i]; im = 0.0; break; }                       // F32
+    default: { re = ((const double*)p)[i]; im = 0.0; break; }                     // F64
+  }
+}
+__device__ __forceinline__ void store_elem(void* p, int dtype, long long i, double re, double im) {
+  if (dtype == 1) ((float2*)p)[i] = make_float2((float)re, (float)im);
+  else ((double2*)p)[i] = make_double2(re, im);
+}
+
+// dir 0: dst[q] = src[a*N + b]  (q = quantics index of pixel (a, b))
+// dir 1: dst[a*N + b] = src[q]
+// The quantics index interleaves a_1 b_1 a_2 b_2 ... (a bits at odd positions
+// counted from the least significant bit, b bits at even positions).
+__global__ void quantics_kernel(const void* src, int sdt, void* dst, int ddt, int n, long long total, int dir) {
+  for (long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x; o < total;
+       o += (long long)gridDim.x * blockDim.x) {
+    long long in;
+    if (dir == 0) {
+      uint32_t q = (uint32_t)o;
+      uint32_t a = compact_even(q >> 1), b = compact_even(q);
+      in = ((long long)a << n) | b;
+    } else {
+      uint32_t a = (uint32_t)(o >> n), b = (uint32_t)(o & ((1ll << n) - 1));
+      in = (long long)((spread_even(a) << 1) | spread_even(b));
+    }
+    double re, im;
+    load_elem(src, sdt, in, re, im);
+    store_elem(dst, ddt, o, re, im);
+  }
+}
+
+hipError_t quantics_permute(const void* src, int src_dtype, void* dst, int dst_dtype, int log2_side, int dir,
+                            hipStream_t s) {
+  long long total = 1ll << (2 * log2_side);
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(quantics_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, src_dtype, dst, dst_dtype,
+                     log2_side, total, dir);
+  return hipGetLastError();
+}
+
+// Sum of |x|^2 over a rows x cols block (strides ld_r, ld_c), one workgroup,
+// fixed reduction order (deterministic).
+__global__ __launch_bounds__(1024) void block_norm_kernel(const void* p, int dtype, DimExpr rows, DimExpr cols,
+                                                          int rmax, int cmax, long long ld_r, long long ld_c,
+                                                          double* out) {
+  const int nr = min(dim_eval(rows), rmax), nc = min(dim_eval(cols), cmax);
+  const long long tot = (long long)nr * nc;
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    long long r = e / nc, c = e - r * nc;
+    long long off = r * ld_r + c * ld_c;
+    double re, im;
+    if (dtype == 0) { float2 v = ((const float2*)p)[off]; re = v.x; im = v.y; }
+    else { double2 v = ((const double2*)p)[off]; re = v.x; im = v.y; }
+    acc += re * re + im * im;
+  }
+  __shared__ double red[16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    *out = sqrt(s);
+  }
+}
+
+hipError_t block_norm(const void* p, int dtype, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
+                      long long ld_r, long long ld_c, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(block_norm_kernel, dim3(1), dim3(1024), 0, s, p, dtype, rows, cols, rows_bound, cols_bound,
+                     ld_r, ld_c, out);
+  return hipGetLastError();
+}
+
+__global__ void block_copy_kernel(const void* src, long long s_rs, long long s_cs, void* dst, long long d_rs,
+                                  long long d_cs, DimExpr rows, DimExpr cols, int cmax, int dtype) {
+  const int nr = min(dim_eval(rows), (int)gridDim.y), nc = min(dim_eval(cols), cmax);
+  const int r = blockIdx.y;
+  if (r >= nr) return;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    if (dtype == 0) ((float2*)dst)[r * d_rs + c * d_cs] = ((const float2*)src)[r * s_rs + c * s_cs];
+    else ((double2*)dst)[r * d_rs + c * d_cs] = ((const double2*)src)[r * s_rs + c * s_cs];
+  }
+}
+
+hipError_t block_copy(const void* src, long long s_rs, long long s_cs, void* dst, long long d_rs, long long d_cs,
+                      DimExpr rows, DimExpr cols, int rows_bound, int cols_bound, int dtype, hipStream_t s) {
+  if (rows_bound < 1 || cols_bound < 1) return hipSuccess;
+  int bx = (cols_bound + 255) / 256;
+  hipLaunchKernelGGL(block_copy_kernel, dim3(bx, rows_bound), dim3(256), 0, s, src, s_rs, s_cs, dst, d_rs, d_cs,
+                     rows, cols, cols_bound, dtype);
+  return hipGetLastError();
+}
+
+__global__ void set_ints_kernel(int* p, int count, int val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = val;
+}
+hipError_t set_ints(int* dev, int count, int val, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(set_ints_kernel, dim3((count + 255) / 256), dim3(256), 0, s, dev, count, val);
+  return hipGetLastError();
+}
+__global__ void copy_ints_kernel(const int* a, int* b, int count) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) b[i] = a[i];
+}
+hipError_t copy_ints(const int* src, int* dst, int count, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(copy_ints_kernel, dim3((count + 255) / 256), dim3(256), 0, s, src, dst, count);
+  return hipGetLastError();
+}
+
+__global__ void check_finite_kernel(const void* p, int dtype, long long count, int* status) {
+  bool bad = false;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x) {
+    double v = dtype == 0 ? (double)((const float*)p)[i] : ((const double*)p)[i];
+    if (!isfinite(v)) bad = true;
+  }
+  if (bad) set_status(status, ST_NONFINITE);
+}
+hipError_t check_finite(const void* p, int dtype, long long count, int* status, hipStream_t s) {
+  long long blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, dtype, count, status);
+  return hipGetLastError();
+}
+
+// Copy caller-provided bond dimensions into the workspace, clamped to
+// [1, min(cap, 2^k, 2^(m-k))]; out-of-range input flags the status word.  All
+// kernels read the clamped copy, so no device-side size can exceed the
+// storage the host sized its buffers and launch grids for.
+__global__ void sanitize_bonds_kernel(const int* src, int* dst, int m, int cap, int* status) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > m) return;
+  int e = min(k, m - k);
+  int bound = e >= 30 ? cap : min(cap, 1 << e);
+  int v = src[k];
+  int c = min(max(v, 1), bound);
+  if (c != v) set_status(status, -5);
+  dst[k] = c;
+}
+hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(sanitize_bonds_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, s, src, dst, m, cap, status);
+  return hipGetLastError();
+}
+
+// Write one complex element (used to seed the zip-up carry with 1).
+__global__ void set_one_kernel(void* p, int dtype) {
+  if (dtype == 0) ((float2*)p)[0] = make_float2(1.f, 0.f);
+  else ((double2*)p)[0] = make_double2(1.0, 0.0);
+}
+hipError_t set_one(void* p, int dtype, hipStream_t s) {
+  hipLaunchKernelGGL(set_one_kernel, dim3(1), dim3(1), 0, s, p, dtype);
+  return hipGetLastError();
+}
+
+}  // namespace qtt

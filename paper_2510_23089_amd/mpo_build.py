@@ -1,0 +1,191 @@
+"""Host (float64) construction of the Fresnel propagator as matrix product operators.
+
+Route of Sec. 6.1 (figure of the MPO product): the real-space propagator of one
+axis is U = QFT_br^H . diag_br(T) . QFT_br, where
+  * QFT_br is the unitary DFT with bit-reversed output, finite-rank as an MPO
+    (Sec. 5).  It is built here from its circuit: for each qubit, a Hadamard
+    followed by controlled phases with every later qubit; each such layer is
+    a bond-2 MPO (the control bit rides along the bond) and the layers are
+    multiplied in and recompressed one at a time;
+  * diag_br(T) is diagonal in the bit-reversed frequency register, with
+    T(f) = exp(-i pi lambda z f^2) (paraxial transfer function, Sec. 6.1) on
+    the FFT frequency grid; its MPO is the sequential-SVD tensor train of the
+    length-N diagonal (each core delta_{ts} V[a, t, b]);
+  * the two products are formed pairwise with SVD recompression.
+The 2-D operator is U^(x) (x) U^(y) (Sec. 6.1, separability): each axis MPO is
+embedded in the 2n-site quantics chain with identity sites on the other axis.
+
+Core convention: W[D_l, t, s, D_r], t = output bit, s = input bit, MSB first.
+This module is host setup (not timed); it shares no code with the test oracle.
+"""
+import numpy as np
+
+H1 = np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0)
+
+
+# ------------------------------------------------------------------ helpers
+def _keep(s, rel):
+    """Smallest rank whose discarded squared weight is <= rel^2 of the total."""
+    w = s * s
+    tot = w.sum()
+    if tot <= 0.0:
+        return 1
+    tail = np.append(np.cumsum(w[::-1])[::-1][1:], 0.0)
+    return max(1, int(np.argmax(tail <= rel * rel * tot)) + 1)
+
+
+def compress(cores, rel=1e-13):
+    """Recompress an MPO: QR sweep left to right, then SVD sweep right to left
+    keeping per bond a relative discarded weight <= rel^2 / (n-1)."""
+    c = [np.asarray(x, dtype=np.complex128) for x in cores]
+    n = len(c)
+    if n == 1:
+        return c
+    for k in range(n - 1):
+        dl, _, _, dr = c[k].shape
+        q, r = np.linalg.qr(c[k].reshape(dl * 4, dr))
+        c[k] = q.reshape(dl, 2, 2, -1)
+        c[k + 1] = np.tensordot(r, c[k + 1], axes=(1, 0))
+    per = rel / np.sqrt(n - 1)
+    for k in range(n - 1, 0, -1):
+        dl, _, _, dr = c[k].shape
+        u, s, vh = np.linalg.svd(c[k].reshape(dl, 4 * dr), full_matrices=False)
+        r = _keep(s, per)
+        c[k] = vh[:r].reshape(r, 2, 2, dr)
+        c[k - 1] = np.tensordot(c[k - 1], u[:, :r] * s[:r], axes=(3, 0))
+    return c
+
+
+def mul(a, b):
+    """Operator product A . B of two MPOs (bond dimensions multiply)."""
+    out = []
+    for wa, wb in zip(a, b):
+        t = np.einsum("atub,cusd->actsbd", wa, wb)
+        al, cl, _, _, ar, cr = t.shape
+        out.append(t.reshape(al * cl, 2, 2, ar * cr))
+    return out
+
+
+def dagger(a):
+    return [np.conj(w.transpose(0, 2, 1, 3)) for w in a]
+
+
+def dense(cores):
+    """Densify (small n only; used by tests and checks)."""
+    n = len(cores)
+    acc = np.ones((1, 1), dtype=np.complex128)
+    for c in cores:
+        acc = np.tensordot(acc, c, axes=(acc.ndim - 1, 0))
+    acc = acc.reshape((2,) * (2 * n))
+    order = [2 * p for p in range(n)] + [2 * p + 1 for p in range(n)]
+    return acc.transpose(order).reshape(1 << n, 1 << n)
+
+
+# ------------------------------------------------------------------ QFT
+def _layer(n, q):
+    """Hadamard on qubit q then controlled phases exp(-2 pi i c x / 2^(d+1))
+    between its output bit c and the (untransformed) input bit x of qubit q+d."""
+    cores = []
+    for p in range(n):
+        if p < q:
+            w = np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1)
+        elif p == q:
+            if q == n - 1:
+                w = H1.astype(np.complex128).reshape(1, 2, 2, 1)
+            else:
+                w = np.zeros((1, 2, 2, 2), dtype=np.complex128)
+                for t in range(2):
+                    w[0, t, :, t] = H1[t, :]
+        else:
+            d = p - q
+            last = p == n - 1
+            w = np.zeros((2, 2, 2, 1 if last else 2), dtype=np.complex128)
+            for c in range(2):
+                for x in range(2):
+                    w[c, x, x, 0 if last else c] = np.exp(-2j * np.pi * c * x / 2.0 ** (d + 1))
+        cores.append(w)
+    return cores
+
+
+def qft_br(n, rel=1e-14):
+    """P_rev F as an MPO: F[k, j] = exp(-2 pi i j k / N)/sqrt(N) with the
+    output register in bit-reversed order."""
+    acc = _layer(n, 0)
+    for q in range(1, n):
+        acc = compress(mul(_layer(n, q), acc), rel)
+    return acc
+
+
+# ------------------------------------------------------------------ diagonal
+def _vec_tt(v, rel):
+    """Sequential-SVD tensor train of a length-2^n vector (MSB first)."""
+    n = int(round(np.log2(v.size)))
+    rem = v.reshape(1, -1).astype(np.complex128)
+    cores = []
+    r = 1
+    per = rel / np.sqrt(max(n - 1, 1))
+    for _ in range(n - 1):
+        u, s, vh = np.linalg.svd(rem.reshape(2 * r, -1), full_matrices=False)
+        k = _keep(s, per)
+        cores.append(u[:, :k].reshape(r, 2, k))
+        rem = s[:k, None] * vh[:k]
+        r = k
+    cores.append(rem.reshape(r, 2, 1))
+    return cores
+
+
+def bit_reverse(n):
+    idx = np.arange(1 << n)
+    rev = np.zeros_like(idx)
+    for p in range(n):
+        rev |= ((idx >> p) & 1) << (n - 1 - p)
+    return rev
+
+
+def transfer(n, lam, dx, z):
+    """T(f) = exp(-i pi lambda z f^2) on numpy's FFT frequency grid."""
+    f = np.fft.fftfreq(1 << n, d=dx)
+    return np.exp(-1j * np.pi * lam * z * f * f)
+
+
+def diag_br(n, lam, dx, z, rel=1e-14):
+    v = transfer(n, lam, dx, z)[bit_reverse(n)]
+    out = []
+    for c in _vec_tt(v, rel):
+        r0, _, r1 = c.shape
+        w = np.zeros((r0, 2, 2, r1), dtype=np.complex128)
+        w[:, 0, 0, :] = c[:, 0, :]
+        w[:, 1, 1, :] = c[:, 1, :]
+        out.append(w)
+    return out
+
+
+# ------------------------------------------------------------------ propagator
+def fresnel_axis(n, lam, dx, z, rel=1e-12):
+    """Per-axis real-space Fresnel propagator QFT_br^H diag_br(T) QFT_br."""
+    q = qft_br(n)
+    d = diag_br(n, lam, dx, z)
+    dq = compress(mul(d, q), rel * 1e-2)
+    return compress(mul(dagger(q), dq), rel)
+
+
+def identity_core(d):
+    return np.einsum("ab,ts->atsb", np.eye(d), np.eye(2)).astype(np.complex128)
+
+
+def embed(cores_1d, axis):
+    """2n-site quantics MPO for one axis; returns (cores, site_kind) with
+    site_kind 1 on the identity (pass-through) sites."""
+    cores, kind = [], []
+    for c in cores_1d:
+        if axis == "x":
+            cores += [c, identity_core(c.shape[3])]
+            kind += [0, 1]
+        else:
+            cores += [identity_core(c.shape[0]), c]
+            kind += [1, 0]
+    return cores, kind
+
+
+def bonds(cores):
+    return [1] + [int(c.shape[3]) for c in cores]

@@ -16,3 +16,12 @@ def pytest_configure(config):
 def rng():
     import numpy as np
     return np.random.default_rng(1234)
+
+
+def pytest_collection_modifyitems(config, items):
+    # import torch once at collection so the first GPU test does not pay for it
+    if any(item.get_closest_marker("gpu") for item in items):
+        try:
+            import torch  # noqa: F401
+        except Exception:
+            pass

@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI library: it loads, exports every symbol the
+public header declares, and rejects bad arguments before touching the GPU
+(no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2510_23089_amd", "libqtt.so")
+HDR = os.path.join(ROOT, "include", "qtt.h")
+
+
+def _declared():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.skip("libqtt.so not built (run __graft_entry__.build())")
+    from paper_2510_23089_amd import _lib
+    return _lib.load(LIB)
+
+
+def test_header_declares_the_core_calls():
+    names = _declared()
+    for n in ("tt_encode", "mpo_apply", "tt_truncate", "tt_to_dense", "mpo_apply_backward"):
+        assert n in names
+
+
+def test_every_declared_symbol_exported(lib):
+    from paper_2510_23089_amd import _lib
+    for n in _declared():
+        assert hasattr(lib, n), "missing export %s" % n
+    assert sorted(_lib.EXPORTS) == sorted(_declared())
+
+
+def test_version_and_sizes(lib):
+    from paper_2510_23089_amd import _lib as L
+    assert b"gfx950" in lib.tt_version()
+    assert lib.tt_workspace_size(L.OP_APPLY, 20, 128, 32, L.PREC_FP32) > 0
+    assert lib.tt_workspace_size(L.OP_ENCODE, 20, 128, 1, L.PREC_FP32) > 0
+    assert lib.tt_workspace_size(L.OP_TO_DENSE, 20, 128, 1, L.PREC_FP32) > 0
+    assert lib.tt_workspace_size(L.OP_APPLY, 3, 128, 32, L.PREC_FP32) == 0        # odd site count
+    assert lib.tt_workspace_size(L.OP_APPLY, 20, 1000, 32, L.PREC_FP32) == 0      # capacity too large
+    # FP64 needs more than FP32
+    assert lib.tt_workspace_size(L.OP_APPLY, 12, 32, 8, L.PREC_FP64) > lib.tt_workspace_size(L.OP_APPLY, 12, 32, 8, L.PREC_FP32)
+
+
+def test_argument_errors_before_enqueue(lib):
+    """Invalid arguments are rejected on the host with negative codes; the
+    pointers here are never dereferenced on a device."""
+    from paper_2510_23089_amd import _lib as L
+    fake = ctypes.c_void_p(0x1000)
+    s = L.QttMps(12, 32, L.QTT_C64, 0x1000, 0x2000, 0)
+    o = L.QttOpts(64, 0, 0.0, 0.0, L.PREC_FP32)           # chi_max > chi_cap
+    rc = lib.tt_encode(fake, L.QTT_F32, 6, ctypes.byref(o), ctypes.byref(s), fake, 1 << 30, None)
+    assert rc == -5 and b"chi_max" in lib.tt_last_error()
+    o = L.QttOpts(16, 0, 0.0, 0.0, L.PREC_FP32)
+    rc = lib.tt_encode(fake, L.QTT_F32, 5, ctypes.byref(o), ctypes.byref(s), fake, 1 << 30, None)
+    assert rc == -2                                         # 12 sites vs log2_side 5
+    rc = lib.tt_encode(fake, L.QTT_F32, 6, ctypes.byref(o), ctypes.byref(s), fake, 16, None)
+    assert rc == -4                                         # workspace too small
+    rc = lib.tt_encode(None, L.QTT_F32, 6, ctypes.byref(o), ctypes.byref(s), fake, 1 << 30, None)
+    assert rc == -1
+    rc = lib.tt_encode(fake, 99, 6, ctypes.byref(o), ctypes.byref(s), fake, 1 << 30, None)
+    assert rc == -3
+    s64 = L.QttMps(12, 32, L.QTT_C64, 0x1000, 0x2000, 0)
+    o64 = L.QttOpts(16, 0, 0.0, 0.0, L.PREC_FP64)          # precision/dtype mismatch
+    rc = lib.tt_encode(fake, L.QTT_F32, 6, ctypes.byref(o64), ctypes.byref(s64), fake, 1 << 30, None)
+    assert rc == -3
+    # mpo_apply: MPO site count mismatch, aliasing, MPO boundary bonds
+    bonds = (ctypes.c_int32 * 13)(*([1] + [2] * 11 + [1]))
+    w = L.QttMpo(10, 2, L.QTT_C64, 0x3000, ctypes.cast(bonds, ctypes.c_void_p), None)
+    out = L.QttMps(12, 32, L.QTT_C64, 0x5000, 0x6000, 0)
+    rc = lib.mpo_apply(ctypes.byref(s), ctypes.byref(w), ctypes.byref(o), ctypes.byref(out), None, 0, fake, 1 << 30, None)
+    assert rc == -2
+    rc = lib.mpo_apply(ctypes.byref(s), ctypes.byref(w), ctypes.byref(o), ctypes.byref(s), None, 0, fake, 1 << 30, None)
+    assert rc == -1
+    bad = (ctypes.c_int32 * 13)(*([2] + [2] * 11 + [1]))
+    w = L.QttMpo(12, 2, L.QTT_C64, 0x3000, ctypes.cast(bad, ctypes.c_void_p), None)
+    rc = lib.mpo_apply(ctypes.byref(s), ctypes.byref(w), ctypes.byref(o), ctypes.byref(out), None, 0, fake, 1 << 30, None)
+    assert rc == -2
+    # tt_heev / tt_cgemm shape checks
+    assert lib.tt_heev(fake, 1000, 1, 4, 0.0, 0.0, fake, fake, fake, fake, 1 << 30, None) == -2
+    assert lib.tt_cgemm(0, 4, 4, fake, 4, 0, fake, 4, 0, fake, 4, L.PREC_FP32, None) == -2

@@ -1,0 +1,142 @@
+"""GPU unit tests of the two building blocks behind every step of the path:
+the MFMA complex contraction (tt_cgemm) and the FP64 Hermitian eigensolver
+with the keep rule (tt_heev).  References: numpy matmul / eigh in float64."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2510_23089_amd import _lib as L
+    return L, L.load()
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (64, 64, 16), (100, 37, 53), (130, 200, 70), (17, 300, 129)])
+@pytest.mark.parametrize("conj", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_cgemm(prec, shape, conj):
+    torch = need_gpu()
+    L, lib = _lib()
+    M, N, K = shape
+    say("cgemm", prec, shape, conj)
+    rng = np.random.default_rng(M * 1000 + N + K)
+    a = rng.standard_normal((M, K + 3)) + 1j * rng.standard_normal((M, K + 3))
+    b = rng.standard_normal((K, N + 2)) + 1j * rng.standard_normal((K, N + 2))
+    dt = torch.complex64 if prec == "fp32" else torch.complex128
+    da = torch.from_numpy(a).to(dt).cuda()
+    db = torch.from_numpy(b).to(dt).cuda()
+    dc = torch.zeros((M, N + 1), dtype=dt, device="cuda")
+    code = L.PREC_FP32 if prec == "fp32" else L.PREC_FP64
+    rc = lib.tt_cgemm(M, N, K, da.data_ptr(), K + 3, conj[0], db.data_ptr(), N + 2, conj[1], dc.data_ptr(), N + 1,
+                      code, _stream(torch))
+    L.check(rc, "tt_cgemm")
+    torch.cuda.synchronize()
+    aa = a[:, :K].conj() if conj[0] else a[:, :K]
+    bb = b[:, :N].conj() if conj[1] else b[:, :N]
+    if prec == "fp32":
+        aa = aa.astype(np.complex64).astype(np.complex128)
+        bb = bb.astype(np.complex64).astype(np.complex128)
+    ref = aa @ bb
+    got = dc.cpu().numpy()[:, :N]
+    tol = 2e-6 if prec == "fp32" else 1e-13
+    assert rel(got, ref) < tol
+
+
+def _heev(torch, L, lib, mats, kcap, cutoff=0.0, tau=0.0):
+    batch, n, _ = mats.shape
+    g = torch.from_numpy(np.ascontiguousarray(mats)).to(torch.complex128).cuda()
+    kept = torch.zeros(batch, dtype=torch.int32, device="cuda")
+    ev = torch.zeros((batch, kcap), dtype=torch.float64, device="cuda")
+    vec = torch.zeros((batch, n, kcap), dtype=torch.complex128, device="cuda")
+    nb = lib.tt_heev_workspace_size(n, kcap, batch)
+    ws = torch.zeros(nb, dtype=torch.uint8, device="cuda")
+    rc = lib.tt_heev(g.data_ptr(), n, batch, kcap, cutoff, tau, kept.data_ptr(), ev.data_ptr(), vec.data_ptr(),
+                     ws.data_ptr(), nb, _stream(torch))
+    L.check(rc, "tt_heev")
+    torch.cuda.synchronize()
+    st = int(ws[:4].view(torch.int32).cpu()[0])
+    return kept.cpu().numpy(), ev.cpu().numpy(), vec.cpu().numpy(), st
+
+
+def _rand_herm(rng, n, spectrum=None):
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    q, _ = np.linalg.qr(x)
+    if spectrum is None:
+        spectrum = np.sort(rng.uniform(0.0, 1.0, n))[::-1]
+    return (q * spectrum) @ q.conj().T
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 33, 64, 100, 128, 200, 256])
+def test_heev_random(n):
+    torch = need_gpu()
+    L, lib = _lib()
+    say("heev", n)
+    rng = np.random.default_rng(n)
+    # a Gram-like spectrum decaying over many decades, and a flat one
+    specs = [np.sort(10.0 ** rng.uniform(-9, 2, n))[::-1], np.sort(rng.uniform(0.1, 1.0, n))[::-1]]
+    mats = np.stack([_rand_herm(rng, n, s) for s in specs])
+    kcap = max(1, min(n, 96))
+    kept, ev, vec, st = _heev(torch, L, lib, mats, kcap)
+    assert st == 0
+    for b in range(2):
+        w, v = np.linalg.eigh(mats[b])
+        w = w[::-1]
+        v = v[:, ::-1]
+        k = int(kept[b])
+        assert k == min(n, kcap)
+        assert np.max(np.abs(ev[b, :k] - w[:k])) < 1e-12 * abs(w[0])
+        u = vec[b, :, :k]
+        # orthogonality, weighted by the singular values the vectors carry in a
+        # truncation (sqrt of the eigenvalues), and unweighted at a looser bar
+        e = np.abs(u.conj().T @ u - np.eye(k))
+        wgt = np.sqrt(np.outer(ev[b, :k], ev[b, :k])) / abs(w[0])
+        assert np.max(e * wgt) < 1e-12
+        assert np.max(e) < 1e-6
+        # eigen-equation residual
+        res = mats[b] @ u - u * ev[b, :k]
+        assert np.max(np.abs(res)) < 1e-10 * abs(w[0])
+
+
+def test_heev_keep_rule_and_degenerate():
+    torch = need_gpu()
+    L, lib = _lib()
+    rng = np.random.default_rng(7)
+    n = 40
+    spec = np.concatenate([[5.0, 3.0, 3.0, 3.0, 1.0], 1e-16 * np.ones(n - 5)])
+    spec2 = np.concatenate([[8.0, 4.0, 2.0, 1.0], np.zeros(n - 4)])
+    mats = np.stack([_rand_herm(rng, n, spec), _rand_herm(rng, n, spec2), np.zeros((n, n)), np.eye(n)])
+    kept, ev, vec, st = _heev(torch, L, lib, mats, 10)
+    assert st == 0
+    assert kept[0] == 5                 # tau drops the 1e-16 tail
+    assert kept[1] == 4
+    assert kept[2] == 1                 # zero matrix keeps one
+    assert kept[3] == 10                # identity: capped, degenerate cluster
+    u = vec[0, :, :5]
+    assert np.max(np.abs(u.conj().T @ u - np.eye(5))) < 1e-9
+    assert np.max(np.abs(mats[0] @ u - u * ev[0, :5])) < 1e-10
+    u = vec[3, :, :10]
+    assert np.max(np.abs(u.conj().T @ u - np.eye(10))) < 1e-9
+    # relative discarded-weight rule: total 15, tails 7, 3, 1, 0 (cutoffs kept
+    # off the exact boundaries, which rounding of the trace decides)
+    kept, ev, vec, st = _heev(torch, L, lib, mats[1:2].copy(), 10, cutoff=3.05 / 15.0)
+    assert kept[0] == 2
+    kept, ev, vec, st = _heev(torch, L, lib, mats[1:2].copy(), 10, cutoff=2.95 / 15.0)
+    assert kept[0] == 3
+
+
+def test_heev_nonfinite_flags_status():
+    torch = need_gpu()
+    L, lib = _lib()
+    m = np.eye(8, dtype=np.complex128)
+    m[3, 3] = np.nan
+    kept, ev, vec, st = _heev(torch, L, lib, m[None], 4)
+    assert st == -7

@@ -1,0 +1,176 @@
+"""GPU parity of the hot path against the CPU float64 oracle.
+
+Bars: FP32 path at untruncated bond dimension <= 1e-5 relative L2 against the
+exact (dense FFT) result; against the oracle's identically truncated result
+<= 1e-4; FP64 path <= 1e-10.  Inputs are seeded synthetic fields; every
+oracle input (cores, MPOs) is computed by the oracle itself and uploaded.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import need_gpu, say, rel
+from oracle import fresnel as F
+from oracle import mpo as OM
+from oracle import quantics as Q
+from oracle import ttsvd as T
+from oracle import zipup as Z
+import synth
+
+pytestmark = pytest.mark.gpu
+LAM, DX = 500e-9, 1e-6
+BIG = 1 << 20
+
+
+def _api():
+    from paper_2510_23089_amd import api
+    return api
+
+
+def _oracle_mpos(n, z):
+    c = OM.mpo_from_matrix(F.fresnel_matrix_1d(1 << n, LAM, DX, z), n)
+    return OM.embed_axis(c, "x"), OM.embed_axis(c, "y"), c
+
+
+def _dev_mpo(api, torch, cores, dtype):
+    return api.MPO(cores, None, dtype=dtype)
+
+
+def _dense(api, psi):
+    return api.tt_to_dense(psi).cpu().numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_encode_blob_vs_oracle(prec):
+    torch = need_gpu()
+    api = _api()
+    img = synth.blob_image(0)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    d_img = torch.from_numpy(img).to(dt).cuda()
+    for chi, tol in ((64, 1e-5), (32, 1e-4), (8, 1e-4)):
+        say("encode", prec, chi)
+        psi = api.tt_encode(d_img, chi, prec=prec)
+        api.check_status()
+        got = _dense(api, psi)
+        ref_cores = T.tt_svd(Q.to_quantics(img), 12, chi, tau=1e-13)
+        ref = Z.to_dense(ref_cores, 6)
+        if prec == "fp64":
+            tol = 1e-10
+        assert rel(got, ref) < tol, (chi, rel(got, ref))
+        if chi < 64:
+            assert psi.host_bonds() == T.bonds(ref_cores)
+        assert abs(float(psi.norm.cpu()[0]) - np.linalg.norm(ref)) < 1e-5 * np.linalg.norm(ref)
+
+
+def test_to_dense_roundtrip_random():
+    torch = need_gpu()
+    api = _api()
+    for n in (1, 2, 3, 5):
+        say("to_dense", n)
+        e0 = synth.random_field(n, 1 << n)
+        cores = T.tt_svd(Q.to_quantics(e0), 2 * n, BIG)
+        psi = api.MPS.from_host(cores, chi_cap=max(2, 1 << n))
+        got = _dense(api, psi)
+        assert rel(got, e0) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_apply_lossless_random_8x8(prec):
+    torch = need_gpu()
+    api = _api()
+    dt = torch.complex64 if prec == "fp32" else torch.complex128
+    n = 3
+    z = 3e-6
+    wx, wy, _ = _oracle_mpos(n, z)
+    for seed in (0, 1):
+        say("lossless 8x8", prec, seed)
+        e0 = synth.random_field(seed, 8)
+        cores = T.tt_svd(Q.to_quantics(e0), 2 * n, BIG)
+        psi = api.MPS.from_host(cores, chi_cap=8, dtype=dt)
+        mx = _dev_mpo(api, torch, wx, dt)
+        my = _dev_mpo(api, torch, wy, dt)
+        mid = api.mpo_apply(psi, mx, 64, chi_cap=64)
+        out = api.mpo_apply(mid, my, 64, chi_cap=64)
+        api.check_status()
+        ref = F.fresnel_dense(e0, LAM, DX, z)
+        tol = 1e-5 if prec == "fp32" else 1e-11
+        assert rel(_dense(api, out), ref) < tol
+        assert abs(float(out.norm.cpu()[0]) - np.linalg.norm(ref)) < tol * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_apply_lossless_blob_64(prec):
+    """Untruncated bond dimension (chi = 64 = exact max rank of a 64x64 grid)."""
+    torch = need_gpu()
+    api = _api()
+    dt = torch.complex64 if prec == "fp32" else torch.complex128
+    n = 6
+    z = 1e-3
+    img = synth.blob_image(0)
+    cores = T.tt_svd(Q.to_quantics(img), 12, 64)
+    wx, wy, _ = _oracle_mpos(n, z)
+    psi = api.MPS.from_host(cores, chi_cap=64, dtype=dt)
+    say("lossless blob", prec)
+    mid = api.mpo_apply(psi, _dev_mpo(api, torch, wx, dt), 64, chi_zip=128, chi_cap=64)
+    out = api.mpo_apply(mid, _dev_mpo(api, torch, wy, dt), 64, chi_zip=128, chi_cap=64)
+    api.check_status()
+    ref = F.fresnel_dense(img, LAM, DX, z)
+    tol = 1e-5 if prec == "fp32" else 1e-10
+    assert rel(_dense(api, out), ref) < tol
+
+
+@pytest.mark.parametrize("chi", [8, 16, 32])
+def test_apply_truncated_blob_vs_oracle(chi):
+    """Identically truncated: GPU zip-up + sweep vs the oracle's, same input
+    cores and MPO (both from the oracle)."""
+    torch = need_gpu()
+    api = _api()
+    n = 6
+    z = 1e-3
+    img = synth.blob_image(3)
+    cores = T.tt_svd(Q.to_quantics(img), 12, 32)
+    wx, wy, _ = _oracle_mpos(n, z)
+    c1, _ = Z.mpo_apply(cores, wx, chi, tau=1e-13)
+    ref_cores, ref_norm = Z.mpo_apply(c1, wy, chi, tau=1e-13)
+    ref = Z.to_dense(ref_cores, n)
+    for prec, tol in (("fp32", 1e-4), ("fp64", 1e-10)):
+        say("truncated blob", chi, prec)
+        dt = torch.complex64 if prec == "fp32" else torch.complex128
+        psi = api.MPS.from_host(cores, chi_cap=32, dtype=dt)
+        mid = api.mpo_apply(psi, _dev_mpo(api, torch, wx, dt), chi)
+        out = api.mpo_apply(mid, _dev_mpo(api, torch, wy, dt), chi)
+        api.check_status()
+        assert rel(_dense(api, out), ref) < tol, (prec, rel(_dense(api, out), ref))
+        assert out.host_bonds() == Z.bonds(ref_cores)
+
+
+def test_truncate_vs_oracle():
+    torch = need_gpu()
+    api = _api()
+    n = 5
+    e0 = synth.aperture_field(6, n=32)
+    exact = T.tt_svd(Q.to_quantics(e0), 2 * n, BIG)
+    for chi in (4, 8, 32):
+        say("truncate", chi)
+        ref_cores, _ = Z.tt_truncate(exact, chi, tau=1e-13)
+        psi = api.MPS.from_host(exact, chi_cap=32)
+        api.tt_truncate(psi, chi)
+        api.check_status()
+        assert rel(_dense(api, psi), Z.to_dense(ref_cores, n)) < (1e-4 if chi < 32 else 1e-5)
+        if chi < 32:
+            assert psi.host_bonds() == Z.bonds(ref_cores)
+
+
+def test_product_mpo_end_to_end_blob():
+    """The library's own host-built Fresnel MPO (QFT^H diag QFT route) with
+    GPU encode and propagation, untruncated, vs the dense FFT oracle."""
+    torch = need_gpu()
+    api = _api()
+    img = synth.blob_image(1)
+    say("product end-to-end")
+    d_img = torch.from_numpy(img).to(torch.float32).cuda()
+    psi = api.tt_encode(d_img, 64)
+    prop = api.FresnelPropagator(6, LAM, DX, 1e-3)
+    out = prop(psi, 64, chi_zip=128)
+    api.check_status()
+    ref = F.fresnel_dense(img, LAM, DX, 1e-3)
+    assert rel(_dense(api, out), ref) < 1e-5
