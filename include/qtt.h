@@ -100,6 +100,32 @@ typedef struct {
   const int32_t* site_kind;   /* HOST, n_sites ints or NULL (0 general, 1 identity) */
 } qtt_mpo;
 
+/* A batch of `count` MPS of identical shape in one allocation: field f's
+ * core k at element offset (f * n_sites + k) * chi_cap * 2 * chi_cap, its
+ * bonds at bonds[f * (n_sites + 1) + k], its norm at norms[f]. */
+typedef struct {
+  int32_t count;
+  int32_t n_sites;
+  int32_t chi_cap;
+  int32_t dtype;
+  void* cores;
+  int32_t* bonds;    /* device, count * (n_sites + 1) */
+  double* norms;     /* device, count, or NULL */
+} qtt_mps_batch;
+
+/* A batch of `count` MPOs sharing one bond profile (pad cores with zeros to
+ * make profiles equal): field f's core k at element offset
+ * (f * n_sites + k) * d_cap * 4 * d_cap, dense [D_k][t][s][D_(k+1)]. */
+typedef struct {
+  int32_t count;
+  int32_t n_sites;
+  int32_t d_cap;
+  int32_t dtype;
+  const void* cores;
+  const int32_t* d_bonds;     /* HOST, n_sites + 1 ints shared by the batch */
+  const int32_t* site_kind;   /* HOST, n_sites ints or NULL */
+} qtt_mpo_batch;
+
 typedef struct {
   int32_t chi_max;   /* final bond cap                                     */
   int32_t chi_zip;   /* zip-up bond cap, 0 -> chi_max                      */
@@ -112,6 +138,10 @@ typedef struct {
  * stored at capacity chi_cap, with MPO capacity d_cap (ignored by ops that
  * take no MPO).  Returns 0 on invalid arguments. */
 size_t tt_workspace_size(int op, int n_sites, int chi_cap, int d_cap, int prec);
+
+/* Workspace of the batched calls below for `count` fields (capacity sizes
+ * as for tt_workspace_size). */
+size_t tt_workspace_size_batched(int op, int count, int n_sites, int chi_cap, int d_cap, int prec);
 
 /* Encode an N x N image into a quantics MPS by sequential SVD (Sec. 3, Sec. 4,
  * App. A).  img: device, row-major N x N of img_dtype (F32/F64 real or
@@ -132,6 +162,19 @@ int tt_encode(const void* img, int img_dtype, int log2_side, const qtt_opts* opt
 int mpo_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts,
               qtt_mps* out, void* saved, size_t saved_bytes,
               void* ws, size_t ws_bytes, void* stream);
+
+/* Batched forms: every field advances site by site in lockstep, one launch
+ * per kernel covering the whole batch, so the per-bond eigen-decompositions
+ * of different fields run concurrently.  img: count row-major N x N images
+ * back to back; chi_dev: NULL or device ints (one per field) that lower the
+ * bond cap of individual fields below opts->chi_max (uneven chi in one
+ * batch).  Fields of different side length are batched by zero-padding them
+ * to a common side with identity MPO sites on the padded bits. */
+int tt_encode_batched(const void* img, int img_dtype, int log2_side, const qtt_opts* opts, const int32_t* chi_dev,
+                      qtt_mps_batch* out, void* ws, size_t ws_bytes, void* stream);
+int mpo_apply_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt_opts* opts, const int32_t* chi_dev,
+                      qtt_mps_batch* out, void* ws, size_t ws_bytes, void* stream);
+int tt_to_dense_batched(const qtt_mps_batch* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream);
 
 /* Recompress an MPS in place: QR sweep right to left, then SVD sweep left to
  * right with cap opts->chi_max (TT-rounding).  Output left-canonical. */
@@ -182,6 +225,18 @@ int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void
 size_t tt_heev_workspace_size(int n, int kcap, int batch);
 int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int* kept, double* evals,
             void* evecs, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- diagnostics: per-launch timing of one kernel class ----
+ * tt_prof_begin(what, nlog, max_entries, max_launches): from now on, every
+ * launch of kernel class `what` (1 = the streaming Householder
+ * tridiagonalisation used for Gram matrices larger than 128, 2 = the
+ * LDS-resident one used up to 128) is bracketed by HIP events on its stream and writes its
+ * actual matrix size n to the device int array nlog (one entry per matrix).
+ * tt_prof_end(launches, entries, total_ms): synchronise, return the number of
+ * launches, of nlog entries written, and the summed event time in ms; stops
+ * recording.  Not thread-safe; intended for benchmarks. */
+int tt_prof_begin(int what, int* nlog, int max_entries, int max_launches);
+int tt_prof_end(int* launches, int* entries, double* total_ms);
 
 /* Synchronise `stream`, read the device status word in ws, reset it to 0 and
  * return it (QTT_OK or a negative qtt_status). */

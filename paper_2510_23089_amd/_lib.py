@@ -24,7 +24,8 @@ EXPORTS = [
     "tt_workspace_size", "tt_encode", "mpo_apply", "tt_truncate", "tt_to_dense",
     "tt_saved_size", "mpo_apply_backward", "tt_to_dense_backward",
     "tt_check_status", "tt_last_error", "tt_version",
-    "tt_cgemm", "tt_heev_workspace_size", "tt_heev",
+    "tt_cgemm", "tt_heev_workspace_size", "tt_heev", "tt_prof_begin", "tt_prof_end",
+    "tt_workspace_size_batched", "tt_encode_batched", "mpo_apply_batched", "tt_to_dense_batched",
 ]
 
 
@@ -36,6 +37,18 @@ class QttMps(ctypes.Structure):
 class QttMpo(ctypes.Structure):
     _fields_ = [("n_sites", ctypes.c_int32), ("d_cap", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("cores", ctypes.c_void_p), ("d_bonds", ctypes.c_void_p), ("site_kind", ctypes.c_void_p)]
+
+
+class QttMpsBatch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n_sites", ctypes.c_int32), ("chi_cap", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("cores", ctypes.c_void_p), ("bonds", ctypes.c_void_p),
+                ("norms", ctypes.c_void_p)]
+
+
+class QttMpoBatch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n_sites", ctypes.c_int32), ("d_cap", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("cores", ctypes.c_void_p), ("d_bonds", ctypes.c_void_p),
+                ("site_kind", ctypes.c_void_p)]
 
 
 class QttOpts(ctypes.Structure):
@@ -85,6 +98,18 @@ def load(path=LIB_PATH):
     lib.tt_heev_workspace_size.restype = sz
     lib.tt_heev.argtypes = [vp, i32, i32, i32, dbl, dbl, vp, vp, vp, vp, sz, vp]
     lib.tt_heev.restype = i32
+    lib.tt_prof_begin.argtypes = [i32, vp, i32, i32]
+    lib.tt_prof_begin.restype = i32
+    lib.tt_prof_end.argtypes = [P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double)]
+    lib.tt_prof_end.restype = i32
+    lib.tt_workspace_size_batched.argtypes = [i32, i32, i32, i32, i32, i32]
+    lib.tt_workspace_size_batched.restype = sz
+    lib.tt_encode_batched.argtypes = [vp, i32, i32, P(QttOpts), vp, P(QttMpsBatch), vp, sz, vp]
+    lib.tt_encode_batched.restype = i32
+    lib.mpo_apply_batched.argtypes = [P(QttMpsBatch), P(QttMpoBatch), P(QttOpts), vp, P(QttMpsBatch), vp, sz, vp]
+    lib.mpo_apply_batched.restype = i32
+    lib.tt_to_dense_batched.argtypes = [P(QttMpsBatch), vp, i32, vp, sz, vp]
+    lib.tt_to_dense_batched.restype = i32
     lib.tt_check_status.argtypes = [vp, vp]
     lib.tt_check_status.restype = i32
     lib.tt_last_error.argtypes = []

@@ -201,6 +201,154 @@ def tt_to_dense(psi, out=None):
     return out
 
 
+class MPSBatch:
+    """count MPS of one shape in one allocation: cores (count, m, chi_cap, 2, chi_cap)."""
+
+    def __init__(self, count, n_sites, chi_cap, dtype=torch.complex64, device="cuda"):
+        self.count = int(count)
+        self.n_sites = int(n_sites)
+        self.chi_cap = int(chi_cap)
+        self.cores = torch.zeros((count, n_sites, chi_cap, 2, chi_cap), dtype=dtype, device=device)
+        self.bonds = torch.ones((count, n_sites + 1), dtype=torch.int32, device=device)
+        self.norms = torch.zeros(count, dtype=torch.float64, device=device)
+
+    @property
+    def dtype(self):
+        return self.cores.dtype
+
+    @property
+    def prec(self):
+        return "fp64" if self.cores.dtype == torch.complex128 else "fp32"
+
+    def cstruct(self):
+        s = L.QttMpsBatch()
+        s.count = self.count
+        s.n_sites = self.n_sites
+        s.chi_cap = self.chi_cap
+        s.dtype = L.QTT_C128 if self.cores.dtype == torch.complex128 else L.QTT_C64
+        s.cores = self.cores.data_ptr()
+        s.bonds = self.bonds.data_ptr()
+        s.norms = self.norms.data_ptr()
+        return s
+
+    def fill_from(self, psi, index=None):
+        """Copy a single MPS (same n_sites, chi_cap <= ours) into one or all fields (device copy)."""
+        idx = range(self.count) if index is None else [index]
+        c = psi.chi_cap
+        for f in idx:
+            self.cores[f, :, :c, :, :c].copy_(psi.cores)
+            self.bonds[f].copy_(psi.bonds)
+        return self
+
+    def field(self, f):
+        """Host cores of field f (synchronises)."""
+        b = self.bonds[f].cpu().numpy()
+        c = self.cores[f].cpu().numpy()
+        return [c[k, :b[k], :, :b[k + 1]].copy() for k in range(self.n_sites)]
+
+
+class MPOBatch:
+    """count MPOs padded to one bond profile (zero padding leaves each operator unchanged)."""
+
+    def __init__(self, mpos, dtype=torch.complex64, device="cuda"):
+        m = mpos[0].n_sites if isinstance(mpos[0], MPO) else len(mpos[0])
+        hosts = [x.host if isinstance(x, MPO) else x for x in mpos]
+        kinds = [x.site_kind if isinstance(x, MPO) else None for x in mpos]
+        self.count = len(hosts)
+        self.n_sites = m
+        prof = np.ones(m + 1, dtype=np.int32)
+        for h in hosts:
+            prof = np.maximum(prof, [1] + [int(c.shape[3]) for c in h])
+        self.d_bonds = prof.astype(np.int32)
+        self.d_cap = int(prof.max())
+        kind = kinds[0]
+        if kind is not None and all(k is not None and np.array_equal(k, kind) for k in kinds):
+            ok = all(prof[k] == prof[k + 1] for k in range(m) if kind[k] == 1)
+            self.site_kind = np.array(kind, dtype=np.int32) if ok else None
+        else:
+            self.site_kind = None
+        stride = self.d_cap * 4 * self.d_cap
+        flat = np.zeros((self.count, m * stride), dtype=np.complex128)
+        for f, h in enumerate(hosts):
+            for k, c in enumerate(h):
+                w = np.zeros((prof[k], 2, 2, prof[k + 1]), dtype=np.complex128)
+                w[:c.shape[0], :, :, :c.shape[3]] = c
+                flat[f, k * stride:k * stride + w.size] = w.reshape(-1)
+        self.flat = torch.from_numpy(flat).to(dtype).to(device)
+
+    def cstruct(self):
+        s = L.QttMpoBatch()
+        s.count = self.count
+        s.n_sites = self.n_sites
+        s.d_cap = self.d_cap
+        s.dtype = L.QTT_C128 if self.flat.dtype == torch.complex128 else L.QTT_C64
+        s.cores = self.flat.data_ptr()
+        s.d_bonds = self.d_bonds.ctypes.data
+        s.site_kind = self.site_kind.ctypes.data if self.site_kind is not None else None
+        return s
+
+
+def mpo_apply_batched(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_dev=None, chi_cap=None):
+    lib = L.load()
+    if out is None:
+        out = MPSBatch(psi.count, psi.n_sites, chi_cap or chi, dtype=psi.dtype, device=psi.cores.device)
+    o = _opts(chi, chi_zip, cutoff, tau, psi.prec)
+    cap = max(psi.chi_cap, out.chi_cap, int(chi_zip or 0), int(chi))
+    nb = lib.tt_workspace_size_batched(L.OP_APPLY, psi.count, psi.n_sites, cap, mpo.d_cap, o.prec)
+    ws = workspace(nb, psi.cores.device)
+    si, so, w = psi.cstruct(), out.cstruct(), mpo.cstruct()
+    L.check(lib.mpo_apply_batched(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), _ptr(chi_dev),
+                                  ctypes.byref(so), _ptr(ws), nb, _stream()), "mpo_apply_batched")
+    return out
+
+
+def tt_encode_batched(imgs, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None, chi_dev=None):
+    """imgs: device tensor (count, N, N)."""
+    lib = L.load()
+    count = int(imgs.shape[0])
+    n = int(imgs.shape[1]).bit_length() - 1
+    imgs = imgs.contiguous()
+    dt = {torch.float32: L.QTT_F32, torch.float64: L.QTT_F64,
+          torch.complex64: L.QTT_C64, torch.complex128: L.QTT_C128}[imgs.dtype]
+    if out is None:
+        out = MPSBatch(count, 2 * n, chi_cap or chi, dtype=_ctype(prec), device=imgs.device)
+    o = _opts(chi, 0, cutoff, tau, prec)
+    nb = lib.tt_workspace_size_batched(L.OP_ENCODE, count, 2 * n, int(chi), 1, o.prec)
+    ws = workspace(nb, imgs.device, key="encode")
+    s = out.cstruct()
+    L.check(lib.tt_encode_batched(_ptr(imgs), dt, n, ctypes.byref(o), _ptr(chi_dev), ctypes.byref(s), _ptr(ws), nb,
+                                  _stream()), "tt_encode_batched")
+    return out
+
+
+def tt_to_dense_batched(psi, out=None):
+    lib = L.load()
+    n = psi.n_sites // 2
+    if out is None:
+        out = torch.empty((psi.count, 1 << n, 1 << n), dtype=psi.dtype, device=psi.cores.device)
+    dt = L.QTT_C128 if out.dtype == torch.complex128 else L.QTT_C64
+    nb = lib.tt_workspace_size_batched(L.OP_TO_DENSE, psi.count, psi.n_sites, psi.chi_cap, 1,
+                                       L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32)
+    ws = workspace(nb, psi.cores.device, key="dense")
+    s = psi.cstruct()
+    L.check(lib.tt_to_dense_batched(ctypes.byref(s), _ptr(out), dt, _ptr(ws), nb, _stream()), "tt_to_dense_batched")
+    return out
+
+
+class FresnelBatch:
+    """x- and y-axis Fresnel MPOs for several distances z, batched (one field per z)."""
+
+    def __init__(self, n, lam, dx, zs, dtype=torch.complex64, device="cuda", rel=1e-12):
+        props = [FresnelPropagator(n, lam, dx, z, dtype=dtype, device=device, rel=rel) for z in zs]
+        self.wx = MPOBatch([p.wx for p in props], dtype=dtype, device=device)
+        self.wy = MPOBatch([p.wy for p in props], dtype=dtype, device=device)
+        self.count = len(zs)
+
+    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None, chi_dev=None):
+        mid = mpo_apply_batched(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp, chi_dev=chi_dev)
+        return mpo_apply_batched(mid, self.wy, chi, chi_zip, cutoff, tau, out=out, chi_dev=chi_dev)
+
+
 class FresnelPropagator:
     """Both axis MPOs of the Fresnel propagator for an N x N grid (Sec. 6.1)."""
 

@@ -34,27 +34,30 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(QTT_ERR_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
   } while (0)
 
-DimExpr dx(int c, const int* p0 = nullptr, const int* p1 = nullptr) {
+DimExpr dx(int c, const int* p0 = nullptr, const int* p1 = nullptr, int bs = 0) {
   DimExpr d;
   d.c = c;
   d.p0 = p0;
   d.p1 = p1;
+  d.bs = bs;
   return d;
 }
 
-Operand opd(const void* p, ll sxh, ll sxl, ll syh, ll syl, int conj = 0, ll sb = 0) {
+// Operand view; sb = stride between fields.
+Operand opd(const void* p, ll sxh, ll sxl, ll syh, ll syl, int conj = 0, ll sb = 0, ll sb2 = 0) {
   Operand o;
   o.ptr = const_cast<void*>(p);
   o.sxh = sxh; o.sxl = sxl; o.syh = syh; o.syl = syl;
   o.conj = conj;
   o.sb = sb;
+  o.sb2 = sb2;
   return o;
 }
 
 ll pow2_cap(int e, ll cap) { return e >= 40 ? cap : std::min<ll>(cap, 1ll << e); }
 
 // Workspace carving: the same code computes sizes (base == nullptr) and
-// pointers, so tt_workspace_size and the entry points always agree.
+// pointers, so the size queries and the entry points always agree.
 struct Carver {
   char* base;
   size_t off = 0;
@@ -67,13 +70,13 @@ struct Carver {
   }
 };
 
-constexpr size_t PART_BYTES = 32ull << 20;   // Gram K-split partials
+constexpr size_t PART_BYTES = 32ull << 20;   // Gram K-split partials (all fields)
 
-int ksplit_for(int nb, ll kb) {
-  int tiles = ((nb + 63) / 64) * ((nb + 63) / 64);
+int ksplit_for(int nb, ll kb, int nf) {
+  int tiles = ((nb + 63) / 64) * ((nb + 63) / 64) * std::max(nf, 1);
   ll want = std::max<ll>(1, 256 / std::max(tiles, 1));
   ll bykb = std::max<ll>(1, kb / 256);
-  ll bymem = std::max<ll>(1, (ll)(PART_BYTES / (16ull * (size_t)nb * nb)));
+  ll bymem = std::max<ll>(1, (ll)(PART_BYTES / (16ull * (size_t)nb * nb * std::max(nf, 1))));
   return (int)std::min<ll>({want, bykb, bymem, 256});
 }
 
@@ -83,35 +86,39 @@ struct Ctx {
   int gemm_t;          // GEMM_F32 / GEMM_F64
   int gram_t;          // GEMM_F32_GRAM64 / GEMM_F64
   size_t csz;          // bytes per complex element
+  int nf = 1;          // fields in the batch
+  int bs = 0;          // per-field stride of bond arrays (ints)
   int* status;
-  // Gram / eig scratch
-  double* G;
+  double* G;           // nf Gram matrices, ld gld, stride gld^2
   int gld;
   double* part;
   void* eigws;
   int eig_nb, eig_kc;
+  const int* kcap_dev = nullptr;   // optional per-field bond cap
 };
 
-// Hermitian Gram matrix into ctx.G (ld gld): G = op(A) . op(B), sizes n x n.
+DimExpr dv(const Ctx& c, int k, const int* p0 = nullptr, const int* p1 = nullptr) { return dx(k, p0, p1, c.bs); }
+
+// Hermitian Gram matrices (one per field) into ctx.G: G = op(A) . op(B).
 int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb, DimExpr K, int klo, ll kb) {
-  int ks = ksplit_for(c.gld, kb);
+  int ks = ksplit_for(c.gld, kb, c.nf);
   GemmSpec g;
   g.M = n; g.N = n; g.K = K; g.batch = dx(1);
   g.mlo = nlo; g.nlo = nlo; g.klo = klo;
-  g.m_bound = nb; g.n_bound = nb; g.batch_bound = 1;
+  g.m_bound = nb; g.n_bound = nb; g.batch_bound = 1; g.nfield = c.nf;
   g.A = A; g.B = B;
   g.types = c.gram_t;
   // the result is a plain n x n matrix: address it through the same (hi, lo)
   // split as the M and N indices
-  const ll ld = c.gld;
+  const ll ld = c.gld, gs = ld * ld;
   if (ks > 1) {
-    g.C = opd(c.part, nlo * ld, ld, nlo, 1);
+    g.C = opd(c.part, nlo * ld, ld, nlo, 1, 0, (ll)ks * gs);
     g.ksplit = ks;
-    g.csplit = (ll)c.gld * c.gld;
+    g.csplit = gs;
     HIPCHK(gemm_launch(g, c.s));
-    HIPCHK(ksplit_reduce(c.part, (ll)c.gld * c.gld, ks, c.G, c.gld, n, n, nb, nb, 0, 0, dx(1), 1, c.s));
+    HIPCHK(ksplit_reduce(c.part, gs, ks, c.G, c.gld, n, n, nb, nb, (ll)ks * gs, gs, dx(1), c.nf, c.s));
   } else {
-    g.C = opd(c.G, nlo * ld, ld, nlo, 1);
+    g.C = opd(c.G, nlo * ld, ld, nlo, 1, 0, gs);
     HIPCHK(gemm_launch(g, c.s));
   }
   return QTT_OK;
@@ -122,28 +129,29 @@ int gemm(Ctx& c, DimExpr M, int mlo, int mb, DimExpr N, int nlo, int nb, DimExpr
   GemmSpec g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.mlo = mlo; g.nlo = nlo; g.klo = klo;
-  g.m_bound = mb; g.n_bound = nb; g.batch_bound = batch_bound;
+  g.m_bound = mb; g.n_bound = nb; g.batch_bound = batch_bound; g.nfield = c.nf;
   g.A = A; g.B = B; g.C = C;
   g.types = c.gemm_t;
   HIPCHK(gemm_launch(g, c.s));
   return QTT_OK;
 }
 
-EigEmit emit(void* p, int lo, ll s_hi, ll s_lo, ll s_col, int conj, int pow, int dtype) {
+EigEmit emit(void* p, int lo, ll s_hi, ll s_lo, ll s_col, int conj, int pow, int dtype, ll s_batch = 0) {
   EigEmit e;
   e.ptr = p; e.lo = lo; e.s_hi = s_hi; e.s_lo = s_lo; e.s_col = s_col;
-  e.conj = conj; e.pow = pow; e.dtype = dtype;
+  e.conj = conj; e.pow = pow; e.dtype = dtype; e.s_batch = s_batch;
   return e;
 }
 
 int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kout, std::initializer_list<EigEmit> em) {
   EigSpec e;
-  e.G = c.G; e.ld = c.gld; e.gstride = 0;
+  e.G = c.G; e.ld = c.gld; e.gstride = (ll)c.gld * c.gld;
   e.n = n; e.n_bound = nb;
   e.kcap = std::min(kcap, c.eig_kc);
   e.cutoff = cutoff; e.tau = tau;
-  e.kout = kout; e.kstride = 0;
-  e.batch = 1;
+  e.kout = kout; e.kstride = c.bs;
+  e.kcap_dev = c.kcap_dev;
+  e.batch = c.nf;
   e.ws = c.eigws;
   e.status = c.status;
   e.nemit = 0;
@@ -167,6 +175,7 @@ struct ApplyPlan {
   std::vector<int> rin, beta, rout, D;
   std::vector<int> kind;
   int gram_nb;     // largest Gram size
+  int rmax, dmax;
 };
 
 ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_zip, const int* dbonds,
@@ -197,50 +206,74 @@ ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_z
   }
   for (int k = 0; k < m - 1; ++k) g = std::max(g, std::min(2 * p.rout[k], p.beta[k + 1]));
   p.gram_nb = g;
+  p.rmax = *std::max_element(p.rin.begin(), p.rin.end());
+  p.dmax = *std::max_element(p.D.begin(), p.D.end());
   return p;
 }
 
 struct ApplyBufs {
   int* status;
-  int* inb;       // sanitised copy of the input bonds
-  int* zbonds;
-  void* Z;        // zip cores [m][zc][2][zc]
-  void* carry[2]; // [a][b][w]: rin_max x zc x dcap
-  void* X;        // [a][b][s][w]
-  void* Mb;       // [a][w][b][t]
-  void* V1;       // FP32/FP64 eigvector copies [n][zc]
+  int* inb;        // sanitised copy of the input bonds, nf x (m+1)
+  int* zbonds;     // zip bonds, nf x (m+1)
+  void* Z;         // zip cores [m][zc][2][zc] per field
+  void* carry[2];  // [a][b][w]: rmax x zc x dmax per field
+  void* X;         // [a][b][s][w]
+  void* Mb;        // [a][w][b][t]
+  void* V1;        // eigenvector copies [n][zc]
   void* V2;
-  void* center[2];// [r][t][b] with strides (2 zc, zc)
-  void* R;        // [i][b] ld zc
+  void* center[2]; // [r][t][b] with strides (2 zc, zc)
+  void* R;         // [i][b] ld zc
   double* G;
   double* part;
   void* eigws;
+  // per-field strides (complex elements)
+  ll sZ, sC, sX, sV, sCtr, sR;
 };
 
-ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz) {
+ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   ApplyBufs b;
-  int rmax = *std::max_element(p.rin.begin(), p.rin.end());
-  int dmax = *std::max_element(p.D.begin(), p.D.end());
-  size_t zc = p.zc;
-  b.status = (int*)cv.take(256);
-  b.inb = (int*)cv.take((p.m + 1) * sizeof(int));
-  b.zbonds = (int*)cv.take((p.m + 1) * sizeof(int));
-  b.Z = cv.take((size_t)p.m * zc * 2 * zc * csz);
-  b.carry[0] = cv.take((size_t)rmax * zc * dmax * csz);
-  b.carry[1] = cv.take((size_t)rmax * zc * dmax * csz);
-  b.X = cv.take((size_t)rmax * zc * 2 * dmax * csz);
-  b.Mb = cv.take((size_t)rmax * zc * 2 * dmax * csz);
+  const size_t zc = p.zc;
   size_t nmax = std::max<size_t>(p.gram_nb, 1);
-  b.V1 = cv.take(nmax * zc * csz);
-  b.V2 = cv.take(nmax * zc * csz);
-  b.center[0] = cv.take(zc * 2 * zc * csz);
-  b.center[1] = cv.take(zc * 2 * zc * csz);
-  b.R = cv.take(zc * zc * csz);
-  b.G = (double*)cv.take(nmax * nmax * 16);
-  b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256 * nmax * nmax * 16));
-  b.eigws = cv.take(eig_ws_bytes((int)nmax, std::max(p.chi_zip, p.chi_max), 1));
+  b.sZ = (ll)p.m * zc * 2 * zc;
+  b.sC = (ll)p.rmax * zc * p.dmax;
+  b.sX = (ll)p.rmax * zc * 2 * p.dmax;
+  b.sV = (ll)nmax * zc;
+  b.sCtr = (ll)zc * 2 * zc;
+  b.sR = (ll)zc * zc;
+  b.status = (int*)cv.take(256);
+  b.inb = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
+  b.zbonds = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
+  b.Z = cv.take(nf * b.sZ * csz);
+  b.carry[0] = cv.take(nf * b.sC * csz);
+  b.carry[1] = cv.take(nf * b.sC * csz);
+  b.X = cv.take(nf * b.sX * csz);
+  b.Mb = cv.take(nf * b.sX * csz);
+  b.V1 = cv.take(nf * b.sV * csz);
+  b.V2 = cv.take(nf * b.sV * csz);
+  b.center[0] = cv.take(nf * b.sCtr * csz);
+  b.center[1] = cv.take(nf * b.sCtr * csz);
+  b.R = cv.take(nf * b.sR * csz);
+  b.G = (double*)cv.take((size_t)nf * nmax * nmax * 16);
+  b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256 * nmax * nmax * 16 * (size_t)nf));
+  b.eigws = cv.take(eig_ws_bytes((int)nmax, std::max(p.chi_zip, p.chi_max), nf));
   return b;
 }
+
+// Internal batched views (a single MPS is a batch of one).
+struct MpsB {
+  int nf, m, cap, dtype;
+  void* cores;
+  int* bonds;
+  double* norms;
+  ll fstride() const { return (ll)m * cap * 2 * cap; }
+};
+struct MpoB {
+  int nf, m, dcap, dtype;
+  const void* cores;
+  const int* dbonds;
+  const int* kind;
+  ll fstride() const { return (ll)m * dcap * 4 * dcap; }
+};
 
 int check_mps(const qtt_mps* a, const char* name) {
   if (!a) return fail(QTT_ERR_ARG, "%s is NULL", name);
@@ -251,6 +284,28 @@ int check_mps(const qtt_mps* a, const char* name) {
   return QTT_OK;
 }
 
+int check_mpsb(const qtt_mps_batch* a, const char* name) {
+  if (!a) return fail(QTT_ERR_ARG, "%s is NULL", name);
+  if (a->count < 1 || a->count > 4096) return fail(QTT_ERR_ARG, "%s: count %d outside [1, 4096]", name, a->count);
+  qtt_mps one;
+  one.n_sites = a->n_sites; one.chi_cap = a->chi_cap; one.dtype = a->dtype;
+  one.cores = a->cores; one.bonds = a->bonds; one.norm = a->norms;
+  return check_mps(&one, name);
+}
+
+MpsB view(const qtt_mps* a) {
+  MpsB v;
+  v.nf = 1; v.m = a->n_sites; v.cap = a->chi_cap; v.dtype = a->dtype;
+  v.cores = a->cores; v.bonds = a->bonds; v.norms = a->norm;
+  return v;
+}
+MpsB view(const qtt_mps_batch* a) {
+  MpsB v;
+  v.nf = a->count; v.m = a->n_sites; v.cap = a->chi_cap; v.dtype = a->dtype;
+  v.cores = a->cores; v.bonds = a->bonds; v.norms = a->norms;
+  return v;
+}
+
 void opts_defaults(const qtt_opts* o, int cap, qtt_opts& out) {
   if (o) out = *o;
   else { out.chi_max = cap; out.chi_zip = 0; out.cutoff = 0.0; out.tau = 0.0; out.prec = QTT_PREC_FP32; }
@@ -258,33 +313,43 @@ void opts_defaults(const qtt_opts* o, int cap, qtt_opts& out) {
   if (!(out.tau > 0.0)) out.tau = 1e-13;
 }
 
-// ------------------------------------------------------------ zip-up + sweep
-int run_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts& o, qtt_mps* out, const ApplyPlan& p,
-              ApplyBufs& b, hipStream_t s) {
-  const int m = p.m;
-  const int real = in->dtype == QTT_C128 ? 1 : 0;
+Ctx make_ctx(hipStream_t s, int real, int nf, int m, int* status) {
   Ctx c;
   c.s = s; c.real = real;
   c.gemm_t = real ? GEMM_F64 : GEMM_F32;
   c.gram_t = real ? GEMM_F64 : GEMM_F32_GRAM64;
   c.csz = real ? 16 : 8;
-  c.status = b.status;
+  c.nf = nf;
+  c.bs = m + 1;
+  c.status = status;
+  return c;
+}
+
+// ------------------------------------------------------------ zip-up + sweep
+int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out, const ApplyPlan& p, ApplyBufs& b,
+              const int* chi_dev, hipStream_t s) {
+  const int m = p.m, nf = in.nf;
+  const int real = in.dtype == QTT_C128 ? 1 : 0;
+  Ctx c = make_ctx(s, real, nf, m, b.status);
   c.G = b.G; c.gld = std::max(p.gram_nb, 1); c.part = b.part; c.eigws = b.eigws;
   c.eig_nb = c.gld; c.eig_kc = std::max(p.chi_zip, p.chi_max);
-  const ll ci = in->chi_cap, co = out->chi_cap, zc = p.zc;
+  const ll ci = in.cap, co = out.cap, zc = p.zc;
   const size_t csz = c.csz;
-  char* inc = (char*)in->cores;
-  char* outc = (char*)out->cores;
+  const ll sIn = in.fstride(), sOut = out.fstride(), sW = W.fstride();
+  char* inc = (char*)in.cores;
+  char* outc = (char*)out.cores;
   char* Zc = (char*)b.Z;
-  const char* Wc = W ? (const char*)W->cores : nullptr;
+  const char* Wc = (const char*)W.cores;
   auto core_in = [&](int k) { return inc + (size_t)k * ci * 2 * ci * csz; };
   auto core_out = [&](int k) { return outc + (size_t)k * co * 2 * co * csz; };
   auto core_z = [&](int k) { return Zc + (size_t)k * zc * 2 * zc * csz; };
   const ll dcap = p.dcap;
+  const int bs = c.bs;
 
-  HIPCHK(sanitize_bonds(in->bonds, b.inb, m, (int)ci, b.status, s));
-  HIPCHK(set_ints(b.zbonds, m + 1, 1, s));
-  HIPCHK(set_one(b.carry[0], real, s));
+  HIPCHK(sanitize_bonds(in.bonds, b.inb, m, (int)ci, b.status, nf, s));
+  HIPCHK(set_ints(b.zbonds, nf * bs, 1, s));
+  c.kcap_dev = chi_dev;          // per-field caps lower both the zip-up and the sweep caps
+  HIPCHK(set_one_b(b.carry[0], b.sC, real, nf, s));
   int cur = 0;
   // ---- zip-up, right to left
   for (int k = m - 1; k >= 0; --k) {
@@ -297,178 +362,202 @@ int run_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts& o, qtt_mps* o
     void* carry_next = b.carry[cur ^ 1];
     // GEMM1: X[(a,s),(b,w)] = A_k[(a,s), a'] C[a', (b,w)]
     {
-      Operand A = opd(core_in(k), 2 * ci, ci, 1, 0);
-      Operand B = opd(carry, zc * Db, 0, Db, 1);
-      Operand C = ident ? opd(b.Mb, 2 * zc * Db, 1, 2, 2 * zc) : opd(b.X, zc * 2 * Db, Db, 2 * Db, 1);
-      int r = gemm(c, dx(2, ra), 2, 2 * p.rin[k], dx(Db, bet), Db, Db * p.beta[k + 1], dx(1, rb), 1, A, B, C);
+      Operand A = opd(core_in(k), 2 * ci, ci, 1, 0, 0, sIn);
+      Operand B = opd(carry, zc * Db, 0, Db, 1, 0, b.sC);
+      Operand C = ident ? opd(b.Mb, 2 * zc * Db, 1, 2, 2 * zc, 0, b.sX) : opd(b.X, zc * 2 * Db, Db, 2 * Db, 1, 0, b.sX);
+      int r = gemm(c, dv(c, 2, ra), 2, 2 * p.rin[k], dv(c, Db, bet), Db, Db * p.beta[k + 1], dv(c, 1, rb), 1, A, B, C);
       if (r) return r;
     }
     if (!ident) {
-      // GEMM2 (batched over a): M[a][w'][b][t] = sum_{s,w} X[a][b][s][w] W[w'][t][s][w]
-      Operand A = opd(b.X, 2 * Db, 0, 1, 0, 0, zc * 2 * Db);
-      Operand B = opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 1, 0, 4 * Db, 2 * Db);
-      Operand C = opd(b.Mb, 2, 0, 2 * zc, 1, 0, (ll)Da * zc * 2);
-      int r = gemm(c, dx(1, bet), 1, p.beta[k + 1], dx(2 * Da), 2, 2 * Da, dx(2 * Db), 1, A, B, C, dx(1, ra),
+      // GEMM2 (inner batch over a): M[a][w'][b][t] = sum_{s,w} X[a][b][s][w] W[w'][t][s][w]
+      Operand A = opd(b.X, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db);
+      Operand B = opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 1, 0, 4 * Db, 2 * Db, 0, sW);
+      Operand C = opd(b.Mb, 2, 0, 2 * zc, 1, 0, b.sX, (ll)Da * zc * 2);
+      int r = gemm(c, dv(c, 1, bet), 1, p.beta[k + 1], dx(2 * Da), 2, 2 * Da, dx(2 * Db), 1, A, B, C, dv(c, 1, ra),
                    p.rin[k]);
       if (r) return r;
     }
     // M_k = [(a, w'), (b, t)]: rows p = a*Da + w' (strides 2 zc Da, 2 zc), cols q = 2b + t (stride 1)
     if (k == 0) {
       // one row: B_0[0][t][b] = M[0][0][b][t]
-      HIPCHK(block_copy(b.Mb, 2, 1, core_z(0), 1, zc, dx(1, bet), dx(2), p.beta[1], 2, real, s));
+      HIPCHK(block_copy_b(b.Mb, 2, 1, b.sX, core_z(0), 1, zc, b.sZ, dv(c, 1, bet), dx(2), p.beta[1], 2, real, nf, s));
       break;
     }
     const ll pb = (ll)p.rin[k] * Da, qb = 2ll * p.beta[k + 1];
     int* kout = b.zbonds + k;
     if (qb <= pb) {
       // column side: G = M^H M (q x q)
-      Operand A = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1);
-      Operand B = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0);
-      int r = gram(c, A, B, dx(2, bet), 1, (int)qb, dx(Da, ra), Da, pb);
+      Operand A = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
+      Operand B = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
+      int r = gram(c, A, B, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da, pb);
       if (r) return r;
-      r = eig(c, dx(2, bet), (int)qb, p.beta[k], o.cutoff, o.tau, kout,
-              {emit(b.V1, 1, zc, 0, 1, 0, 0, real),                    // V [q][i]
-               emit(core_z(k), 2, 1, zc, 2 * zc, 1, 0, real)});        // B_k[i][t][b] = conj V[(b,t)][i]
+      r = eig(c, dv(c, 2, bet), (int)qb, p.beta[k], o.cutoff, o.tau, kout,
+              {emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV),                      // V [q][i]
+               emit(core_z(k), 2, 1, zc, 2 * zc, 1, 0, real, b.sZ)});          // B_k[i][t][b] = conj V[(b,t)][i]
       if (r) return r;
       // carry_next[a][i][w'] = sum_q M[(a,w')][q] V[q][i]
-      Operand A2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0);
-      Operand B2 = opd(b.V1, zc, 0, 1, 0);
-      Operand C2 = opd(carry_next, zc * Da, 1, Da, 0);
-      r = gemm(c, dx(Da, ra), Da, (int)pb, dx(1, kout), 1, p.beta[k], dx(2, bet), 1, A2, B2, C2);
+      Operand A2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
+      Operand B2 = opd(b.V1, zc, 0, 1, 0, 0, b.sV);
+      Operand C2 = opd(carry_next, zc * Da, 1, Da, 0, 0, b.sC);
+      r = gemm(c, dv(c, Da, ra), Da, (int)pb, dv(c, 1, kout), 1, p.beta[k], dv(c, 2, bet), 1, A2, B2, C2);
       if (r) return r;
     } else {
       // row side: G = M M^H (p x p)
-      Operand A = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0);
-      Operand B = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1);
-      int r = gram(c, A, B, dx(Da, ra), Da, (int)pb, dx(2, bet), 1, qb);
+      Operand A = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
+      Operand B = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
+      int r = gram(c, A, B, dv(c, Da, ra), Da, (int)pb, dv(c, 2, bet), 1, qb);
       if (r) return r;
-      r = eig(c, dx(Da, ra), (int)pb, p.beta[k], o.cutoff, o.tau, kout,
-              {emit(carry_next, Da, zc * Da, 1, Da, 0, 1, real),        // carry = U sigma
-               emit(b.V1, 1, zc, 0, 1, 0, -1, real)});                 // U / sigma [p][i]
+      r = eig(c, dv(c, Da, ra), (int)pb, p.beta[k], o.cutoff, o.tau, kout,
+              {emit(carry_next, Da, zc * Da, 1, Da, 0, 1, real, b.sC),         // carry = U sigma
+               emit(b.V1, 1, zc, 0, 1, 0, -1, real, b.sV)});                   // U / sigma [p][i]
       if (r) return r;
       // B_k[i][t][b] = sum_p conj(U/sigma)[p][i] M[p][(b,t)]
-      Operand A2 = opd(b.V1, 1, 0, (ll)Da * zc, zc, 1);     // K index p = (a, w') of a plain [p][i] matrix
-      Operand B2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 2, 1);
-      Operand C2 = opd(core_z(k), 2 * zc, 0, 1, zc);
-      r = gemm(c, dx(1, kout), 1, p.beta[k], dx(2, bet), 2, (int)qb, dx(Da, ra), Da, A2, B2, C2);
+      Operand A2 = opd(b.V1, 1, 0, (ll)Da * zc, zc, 1, b.sV);     // K index p = (a, w') of a plain [p][i] matrix
+      Operand B2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 2, 1, 0, b.sX);
+      Operand C2 = opd(core_z(k), 2 * zc, 0, 1, zc, 0, b.sZ);
+      r = gemm(c, dv(c, 1, kout), 1, p.beta[k], dv(c, 2, bet), 2, (int)qb, dv(c, Da, ra), Da, A2, B2, C2);
       if (r) return r;
     }
     cur ^= 1;
   }
   // ---- sweep, left to right
-  HIPCHK(set_ints(out->bonds, 1, 1, s));
-  HIPCHK(set_ints(out->bonds + m, 1, 1, s));
+  HIPCHK(set_ints_strided(out.bonds, 1, bs, nf, 1, s));
+  HIPCHK(set_ints_strided(out.bonds + m, 1, bs, nf, 1, s));
   int cc = 0;
   const char* center = core_z(0);
+  ll sCenter = b.sZ;
+  c.kcap_dev = chi_dev;
   for (int k = 0; k < m - 1; ++k) {
-    const int* rk = out->bonds + k;
+    const int* rk = out.bonds + k;
     const int* bk = b.zbonds + k + 1;
     const int* bk2 = b.zbonds + k + 2;
-    int* kout = out->bonds + k + 1;
+    int* kout = out.bonds + k + 1;
     const ll pb = 2ll * p.rout[k], qb = p.beta[k + 1];
     void* next = b.center[cc];
     const char* znext = core_z(k + 1);
     // M = center [(r,t), b]: strides (2 zc, zc) rows, 1 cols
     if (qb < pb) {
-      Operand A = opd(center, 1, 0, 2 * zc, zc, 1);
-      Operand B = opd(center, 2 * zc, zc, 1, 0);
-      int r = gram(c, A, B, dx(1, bk), 1, (int)qb, dx(2, rk), 2, pb);
+      Operand A = opd(center, 1, 0, 2 * zc, zc, 1, sCenter);
+      Operand B = opd(center, 2 * zc, zc, 1, 0, 0, sCenter);
+      int r = gram(c, A, B, dv(c, 1, bk), 1, (int)qb, dv(c, 2, rk), 2, pb);
       if (r) return r;
-      r = eig(c, dx(1, bk), (int)qb, p.rout[k + 1], o.cutoff, o.tau, kout,
-              {emit(b.V1, 1, zc, 0, 1, 0, -1, real),     // V / sigma
-               emit(b.V2, 1, zc, 0, 1, 0, 1, real)});    // V * sigma
+      r = eig(c, dv(c, 1, bk), (int)qb, p.rout[k + 1], o.cutoff, o.tau, kout,
+              {emit(b.V1, 1, zc, 0, 1, 0, -1, real, b.sV),     // V / sigma
+               emit(b.V2, 1, zc, 0, 1, 0, 1, real, b.sV)});    // V * sigma
       if (r) return r;
       // out core k [(r,t)][i] = M V/sigma
-      r = gemm(c, dx(2, rk), 2, (int)pb, dx(1, kout), 1, p.rout[k + 1], dx(1, bk), 1, opd(center, 2 * zc, zc, 1, 0),
-               opd(b.V1, zc, 0, 1, 0), opd(core_out(k), 2 * co, co, 1, 0));
+      r = gemm(c, dv(c, 2, rk), 2, (int)pb, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 1, bk), 1,
+               opd(center, 2 * zc, zc, 1, 0, 0, sCenter), opd(b.V1, zc, 0, 1, 0, 0, b.sV),
+               opd(core_out(k), 2 * co, co, 1, 0, 0, sOut));
       if (r) return r;
       // next [i][t][b''] = sum_b sigma_i conj(V[b][i]) Z_{k+1}[b][t][b'']
-      r = gemm(c, dx(1, kout), 1, p.rout[k + 1], dx(2, bk2), 2, 2 * p.beta[k + 2], dx(1, bk), 1,
-               opd(b.V2, 1, 0, zc, 0, 1), opd(znext, 2 * zc, 0, 1, zc), opd(next, 2 * zc, 0, 1, zc));
+      r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 2, bk2), 2, 2 * p.beta[k + 2], dv(c, 1, bk), 1,
+               opd(b.V2, 1, 0, zc, 0, 1, b.sV), opd(znext, 2 * zc, 0, 1, zc, 0, b.sZ),
+               opd(next, 2 * zc, 0, 1, zc, 0, b.sCtr));
       if (r) return r;
     } else {
-      Operand A = opd(center, 2 * zc, zc, 1, 0);
-      Operand B = opd(center, 1, 0, 2 * zc, zc, 1);
-      int r = gram(c, A, B, dx(2, rk), 2, (int)pb, dx(1, bk), 1, qb);
+      Operand A = opd(center, 2 * zc, zc, 1, 0, 0, sCenter);
+      Operand B = opd(center, 1, 0, 2 * zc, zc, 1, sCenter);
+      int r = gram(c, A, B, dv(c, 2, rk), 2, (int)pb, dv(c, 1, bk), 1, qb);
       if (r) return r;
-      r = eig(c, dx(2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout,
-              {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real),   // out core k = U
-               emit(b.V1, 1, zc, 0, 1, 0, 0, real)});            // U [p][i]
+      r = eig(c, dv(c, 2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout,
+              {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut),   // out core k = U
+               emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV)});            // U [p][i]
       if (r) return r;
       // R[i][b] = sum_p conj(U[p][i]) M[p][b]
-      r = gemm(c, dx(1, kout), 1, p.rout[k + 1], dx(1, bk), 1, (int)qb, dx(2, rk), 2, opd(b.V1, 1, 0, 2 * zc, zc, 1),
-               opd(center, 2 * zc, zc, 1, 0), opd(b.R, zc, 0, 1, 0));
+      r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 1, bk), 1, (int)qb, dv(c, 2, rk), 2,
+               opd(b.V1, 1, 0, 2 * zc, zc, 1, b.sV), opd(center, 2 * zc, zc, 1, 0, 0, sCenter),
+               opd(b.R, zc, 0, 1, 0, 0, b.sR));
       if (r) return r;
-      r = gemm(c, dx(1, kout), 1, p.rout[k + 1], dx(2, bk2), 2, 2 * p.beta[k + 2], dx(1, bk), 1,
-               opd(b.R, zc, 0, 1, 0), opd(znext, 2 * zc, 0, 1, zc), opd(next, 2 * zc, 0, 1, zc));
+      r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 2, bk2), 2, 2 * p.beta[k + 2], dv(c, 1, bk), 1,
+               opd(b.R, zc, 0, 1, 0, 0, b.sR), opd(znext, 2 * zc, 0, 1, zc, 0, b.sZ),
+               opd(next, 2 * zc, 0, 1, zc, 0, b.sCtr));
       if (r) return r;
     }
     center = (const char*)next;
+    sCenter = b.sCtr;
     cc ^= 1;
   }
   // last core: out[m-1][r][t][0] = center[r][t][0]
-  const int* rl = out->bonds + m - 1;
-  HIPCHK(block_copy(center, 2 * zc, zc, core_out(m - 1), 2 * co, co, dx(1, rl), dx(2), p.rout[m - 1], 2, real, s));
-  if (out->norm)
-    HIPCHK(block_norm(core_out(m - 1), real, dx(1, rl), dx(2), p.rout[m - 1], 2, 2 * co, co, out->norm, s));
+  const int* rl = out.bonds + m - 1;
+  HIPCHK(block_copy_b(center, 2 * zc, zc, sCenter, core_out(m - 1), 2 * co, co, sOut, dv(c, 1, rl), dx(2),
+                      p.rout[m - 1], 2, real, nf, s));
+  if (out.norms)
+    HIPCHK(block_norm_b(core_out(m - 1), real, dv(c, 1, rl), dx(2), p.rout[m - 1], 2, 2 * co, co, sOut, out.norms,
+                        nf, s));
   return QTT_OK;
 }
 
-int apply_common(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts, qtt_mps* out, void* ws,
-                 size_t ws_bytes, void* stream, bool identity) {
-  int r;
-  if ((r = check_mps(in, "in"))) return r;
-  if ((r = check_mps(out, "out"))) return r;
-  if (in->n_sites != out->n_sites) return fail(QTT_ERR_SHAPE, "in/out n_sites differ");
-  if (in->dtype != out->dtype) return fail(QTT_ERR_DTYPE, "in/out dtypes differ");
-  if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
-  const int m = in->n_sites;
-  qtt_opts o;
-  opts_defaults(opts, out->chi_cap, o);
-  if (o.chi_max < 1 || o.chi_max > out->chi_cap) return fail(QTT_ERR_CAPACITY, "chi_max %d outside [1, %d]", o.chi_max, out->chi_cap);
-  if (o.chi_zip < 1 || o.chi_zip > 256) return fail(QTT_ERR_CAPACITY, "chi_zip %d outside [1, 256]", o.chi_zip);
-  if (o.prec != QTT_PREC_FP32 && o.prec != QTT_PREC_FP64) return fail(QTT_ERR_ARG, "precision %d not supported here", o.prec);
-  if ((o.prec == QTT_PREC_FP64) != (in->dtype == QTT_C128)) return fail(QTT_ERR_DTYPE, "precision and dtype disagree");
-  std::vector<int> dbonds(m + 1, 1), kind(m, 1);
-  int dcap = 1;
-  if (!identity) {
-    if (!W || !W->cores || !W->d_bonds) return fail(QTT_ERR_ARG, "MPO is NULL or incomplete");
-    if (W->n_sites != m) return fail(QTT_ERR_SHAPE, "MPO has %d sites, MPS %d", W->n_sites, m);
-    if (W->dtype != in->dtype) return fail(QTT_ERR_DTYPE, "MPO dtype differs from MPS dtype");
-    if (W->d_bonds[0] != 1 || W->d_bonds[m] != 1) return fail(QTT_ERR_SHAPE, "MPO boundary bonds must be 1");
-    for (int k = 0; k <= m; ++k) {
-      if (W->d_bonds[k] < 1 || W->d_bonds[k] > W->d_cap) return fail(QTT_ERR_CAPACITY, "MPO bond %d = %d outside [1, d_cap]", k, W->d_bonds[k]);
-      dbonds[k] = W->d_bonds[k];
-    }
-    for (int k = 0; k < m; ++k) {
-      kind[k] = W->site_kind ? W->site_kind[k] : 0;
-      if (kind[k] == 1 && dbonds[k] != dbonds[k + 1]) return fail(QTT_ERR_SHAPE, "identity site %d changes the bond", k);
-    }
-    dcap = W->d_cap;
-  }
-  ApplyPlan p = make_apply_plan(m, in->chi_cap, out->chi_cap, o.chi_max, o.chi_zip, dbonds.data(), kind.data(), dcap);
-  size_t csz = in->dtype == QTT_C128 ? 16 : 8;
+size_t apply_bytes(const ApplyPlan& p, size_t csz, int nf) {
   Carver cv(nullptr);
-  carve_apply(cv, p, csz);
-  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
-  Carver cw(ws);
-  ApplyBufs b = carve_apply(cw, p, csz);
-  qtt_mpo Wl;
-  if (identity) {
-    Wl.n_sites = m; Wl.d_cap = 1; Wl.dtype = in->dtype; Wl.cores = nullptr; Wl.d_bonds = dbonds.data(); Wl.site_kind = kind.data();
-    W = &Wl;
-  }
-  return run_apply(in, W, o, out, p, b, (hipStream_t)stream);
+  carve_apply(cv, p, csz, nf);
+  return cv.off;
 }
 
-size_t apply_ws(int m, int chi_cap, int d_cap, int prec, bool identity) {
+// Validate and run one (batched) application.  identity: W ignored, every
+// site an identity pass-through of bond 1 (used by tt_truncate).
+int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opts* opts, const MpsB& out,
+                 const int* chi_dev, void* ws, size_t ws_bytes, void* stream, bool identity) {
+  if (in.m != out.m) return fail(QTT_ERR_SHAPE, "in/out n_sites differ");
+  if (in.nf != out.nf) return fail(QTT_ERR_SHAPE, "in/out batch counts differ");
+  if (in.dtype != out.dtype) return fail(QTT_ERR_DTYPE, "in/out dtypes differ");
+  if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
+  const int m = in.m;
+  qtt_opts o;
+  opts_defaults(opts, out.cap, o);
+  if (o.chi_max < 1 || o.chi_max > out.cap) return fail(QTT_ERR_CAPACITY, "chi_max %d outside [1, %d]", o.chi_max, out.cap);
+  if (o.chi_zip < 1 || o.chi_zip > 256) return fail(QTT_ERR_CAPACITY, "chi_zip %d outside [1, 256]", o.chi_zip);
+  if (o.prec != QTT_PREC_FP32 && o.prec != QTT_PREC_FP64) return fail(QTT_ERR_ARG, "precision %d not supported here", o.prec);
+  if ((o.prec == QTT_PREC_FP64) != (in.dtype == QTT_C128)) return fail(QTT_ERR_DTYPE, "precision and dtype disagree");
+  std::vector<int> dbonds(m + 1, 1), kind(m, 1);
+  MpoB W;
+  W.nf = in.nf; W.m = m; W.dcap = 1; W.dtype = in.dtype; W.cores = nullptr;
+  if (!identity) {
+    const int* db;
+    const int* kd;
+    int n_sites, dcap, dtype;
+    if (W1) {
+      if (!W1->cores || !W1->d_bonds) return fail(QTT_ERR_ARG, "MPO is NULL or incomplete");
+      n_sites = W1->n_sites; dcap = W1->d_cap; dtype = W1->dtype; db = W1->d_bonds; kd = W1->site_kind;
+      W.cores = W1->cores;
+      if (in.nf != 1) return fail(QTT_ERR_ARG, "single MPO with a batch");
+    } else {
+      if (!Wb || !Wb->cores || !Wb->dbonds) return fail(QTT_ERR_ARG, "MPO batch is NULL or incomplete");
+      if (Wb->nf != in.nf) return fail(QTT_ERR_SHAPE, "MPO batch count differs from MPS batch count");
+      n_sites = Wb->m; dcap = Wb->dcap; dtype = Wb->dtype; db = Wb->dbonds; kd = Wb->kind;
+      W.cores = Wb->cores;
+    }
+    if (n_sites != m) return fail(QTT_ERR_SHAPE, "MPO has %d sites, MPS %d", n_sites, m);
+    if (dtype != in.dtype) return fail(QTT_ERR_DTYPE, "MPO dtype differs from MPS dtype");
+    if (db[0] != 1 || db[m] != 1) return fail(QTT_ERR_SHAPE, "MPO boundary bonds must be 1");
+    if (dcap < 1 || dcap > 512) return fail(QTT_ERR_CAPACITY, "MPO d_cap %d outside [1, 512]", dcap);
+    for (int k = 0; k <= m; ++k) {
+      if (db[k] < 1 || db[k] > dcap) return fail(QTT_ERR_CAPACITY, "MPO bond %d = %d outside [1, d_cap]", k, db[k]);
+      dbonds[k] = db[k];
+    }
+    for (int k = 0; k < m; ++k) {
+      kind[k] = kd ? kd[k] : 0;
+      if (kind[k] == 1 && dbonds[k] != dbonds[k + 1]) return fail(QTT_ERR_SHAPE, "identity site %d changes the bond", k);
+    }
+    W.dcap = dcap;
+  }
+  W.dbonds = dbonds.data();
+  W.kind = kind.data();
+  ApplyPlan p = make_apply_plan(m, in.cap, out.cap, o.chi_max, o.chi_zip, dbonds.data(), kind.data(), W.dcap);
+  size_t csz = in.dtype == QTT_C128 ? 16 : 8;
+  size_t need = apply_bytes(p, csz, in.nf);
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  Carver cw(ws);
+  ApplyBufs b = carve_apply(cw, p, csz, in.nf);
+  return run_apply(in, W, o, out, p, b, chi_dev, (hipStream_t)stream);
+}
+
+size_t apply_ws(int m, int chi_cap, int d_cap, int prec, bool identity, int nf) {
   std::vector<int> db(m + 1, identity ? 1 : d_cap);
   db[0] = db[m] = 1;
   std::vector<int> kind(m, identity ? 1 : 0);
   ApplyPlan p = make_apply_plan(m, chi_cap, chi_cap, chi_cap, chi_cap, db.data(), kind.data(), identity ? 1 : d_cap);
-  Carver cv(nullptr);
-  carve_apply(cv, p, prec == QTT_PREC_FP64 ? 16 : 8);
-  return cv.off;
+  return apply_bytes(p, prec == QTT_PREC_FP64 ? 16 : 8, nf);
 }
 
 // ------------------------------------------------------------ encode
@@ -480,81 +569,90 @@ struct EncBufs {
   double* G;
   double* part;
   void* eigws;
+  ll sq;      // per-field stride of the 2^m vectors
+  ll sV;
+  int nmax;
 };
 
-EncBufs carve_encode(Carver& cv, int m, int chi, size_t csz) {
+EncBufs carve_encode(Carver& cv, int m, int chi, size_t csz, int nf) {
   EncBufs b;
-  size_t nq = 1ull << m;
-  int nmax = std::min(2 * chi, 1 << (m / 2 + 1));
-  nmax = std::max(nmax, 2);
+  b.sq = 1ll << m;
+  b.nmax = std::max(2, std::min(2 * chi, 1 << (m / 2 + 1)));
+  b.sV = (ll)b.nmax * chi;
   b.status = (int*)cv.take(256);
-  b.v = cv.take(nq * csz);
-  b.Rb[0] = cv.take(nq * csz);
-  b.Rb[1] = cv.take(nq * csz);
-  b.V1 = cv.take((size_t)nmax * chi * csz);
-  b.G = (double*)cv.take((size_t)nmax * nmax * 16);
-  b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256ull * nmax * nmax * 16));
-  b.eigws = cv.take(eig_ws_bytes(nmax, chi, 1));
+  b.v = cv.take(nf * b.sq * csz);
+  b.Rb[0] = cv.take(nf * b.sq * csz);
+  b.Rb[1] = cv.take(nf * b.sq * csz);
+  b.V1 = cv.take(nf * b.sV * csz);
+  b.G = (double*)cv.take((size_t)nf * b.nmax * b.nmax * 16);
+  b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256ull * b.nmax * b.nmax * 16 * nf));
+  b.eigws = cv.take(eig_ws_bytes(b.nmax, chi, nf));
   return b;
 }
 
-int encode_impl(const void* img, int img_dtype, int n, const qtt_opts& o, qtt_mps* out, EncBufs& b, hipStream_t s) {
-  const int m = 2 * n;
-  const int real = out->dtype == QTT_C128 ? 1 : 0;
+// img: nf images of N x N (field stride N^2 elements of img_dtype)
+int encode_impl(const void* img, int img_dtype, int n, const qtt_opts& o, const MpsB& out, EncBufs& b,
+                const int* chi_dev, hipStream_t s) {
+  const int m = 2 * n, nf = out.nf;
+  const int real = out.dtype == QTT_C128 ? 1 : 0;
   const int chi = o.chi_max;
-  Ctx c;
-  c.s = s; c.real = real;
-  c.gemm_t = real ? GEMM_F64 : GEMM_F32;
-  c.gram_t = real ? GEMM_F64 : GEMM_F32_GRAM64;
-  c.csz = real ? 16 : 8;
-  c.status = b.status;
-  int nmax = std::max(2, std::min(2 * chi, 1 << (m / 2 + 1)));
-  c.G = b.G; c.gld = nmax; c.part = b.part; c.eigws = b.eigws; c.eig_nb = nmax; c.eig_kc = chi;
-  const ll co = out->chi_cap;
-  char* outc = (char*)out->cores;
+  Ctx c = make_ctx(s, real, nf, m, b.status);
+  c.G = b.G; c.gld = b.nmax; c.part = b.part; c.eigws = b.eigws; c.eig_nb = b.nmax; c.eig_kc = chi;
+  c.kcap_dev = chi_dev;
+  const ll co = out.cap, sOut = out.fstride();
+  char* outc = (char*)out.cores;
   auto core_out = [&](int k) { return outc + (size_t)k * co * 2 * co * c.csz; };
   std::vector<int> rb = mps_bounds(m, chi);
-  HIPCHK(quantics_permute(img, img_dtype, b.v, real ? QTT_C128 : QTT_C64, n, 0, s));
-  HIPCHK(set_ints(out->bonds, 1, 1, s));
-  HIPCHK(set_ints(out->bonds + m, 1, 1, s));
+  const size_t isz = img_dtype == QTT_C128 ? 16 : (img_dtype == QTT_F32 ? 4 : 8);
+  for (int f = 0; f < nf; ++f)
+    HIPCHK(quantics_permute((const char*)img + (size_t)f * (b.sq * isz), img_dtype,
+                            (char*)b.v + (size_t)f * b.sq * c.csz, real ? QTT_C128 : QTT_C64, n, 0, s));
+  HIPCHK(set_ints_strided(out.bonds, 1, c.bs, nf, 1, s));
+  HIPCHK(set_ints_strided(out.bonds + m, 1, c.bs, nf, 1, s));
   const void* Rcur = b.v;
   int rsel = 0;
   for (int k = 0; k < m - 1; ++k) {
-    const int* rk = out->bonds + k;
-    int* kout = out->bonds + k + 1;
+    const int* rk = out.bonds + k;
+    int* kout = out.bonds + k + 1;
     const ll q = 1ll << (m - k - 1);
     const ll pb = 2ll * rb[k];
     void* Rn = b.Rb[rsel];
     // M[(r,s)][c] = R_k[r][s*q + c]: row strides (2q, q), col stride 1
     if (pb <= q) {
-      int r = gram(c, opd(Rcur, 2 * q, q, 1, 0), opd(Rcur, 1, 0, 2 * q, q, 1), dx(2, rk), 2, (int)pb, dx((int)q), 1, q);
+      int r = gram(c, opd(Rcur, 2 * q, q, 1, 0, 0, b.sq), opd(Rcur, 1, 0, 2 * q, q, 1, b.sq), dv(c, 2, rk), 2,
+                   (int)pb, dx((int)q), 1, q);
       if (r) return r;
-      r = eig(c, dx(2, rk), (int)pb, rb[k + 1], o.cutoff, o.tau, kout,
-              {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real),   // A_k = U
-               emit(b.V1, 1, chi, 0, 1, 0, 0, real)});           // U [p][i]
+      r = eig(c, dv(c, 2, rk), (int)pb, rb[k + 1], o.cutoff, o.tau, kout,
+              {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut),   // A_k = U
+               emit(b.V1, 1, chi, 0, 1, 0, 0, real, b.sV)});           // U [p][i]
       if (r) return r;
       // R_{k+1}[i][c] = sum_p conj(U[p][i]) M[p][c]
-      r = gemm(c, dx(1, kout), 1, rb[k + 1], dx((int)q), 1, (int)q, dx(2, rk), 2, opd(b.V1, 1, 0, 2 * chi, chi, 1),
-               opd(Rcur, 2 * q, q, 1, 0), opd(Rn, q, 0, 1, 0));
+      r = gemm(c, dv(c, 1, kout), 1, rb[k + 1], dx((int)q), 1, (int)q, dv(c, 2, rk), 2,
+               opd(b.V1, 1, 0, 2 * chi, chi, 1, b.sV), opd(Rcur, 2 * q, q, 1, 0, 0, b.sq),
+               opd(Rn, q, 0, 1, 0, 0, b.sq));
       if (r) return r;
     } else {
-      int r = gram(c, opd(Rcur, 1, 0, 2 * q, q, 1), opd(Rcur, 2 * q, q, 1, 0), dx((int)q), 1, (int)q, dx(2, rk), 2, pb);
+      int r = gram(c, opd(Rcur, 1, 0, 2 * q, q, 1, b.sq), opd(Rcur, 2 * q, q, 1, 0, 0, b.sq), dx((int)q), 1, (int)q,
+                   dv(c, 2, rk), 2, pb);
       if (r) return r;
       r = eig(c, dx((int)q), (int)q, rb[k + 1], o.cutoff, o.tau, kout,
-              {emit(b.V1, 1, chi, 0, 1, 0, -1, real),            // V / sigma [c][i]
-               emit(Rn, 1, 1, 0, q, 1, 1, real)});               // R_{k+1}[i][c] = sigma_i conj V[c][i]
+              {emit(b.V1, 1, chi, 0, 1, 0, -1, real, b.sV),            // V / sigma [c][i]
+               emit(Rn, 1, 1, 0, q, 1, 1, real, b.sq)});               // R_{k+1}[i][c] = sigma_i conj V[c][i]
       if (r) return r;
-      r = gemm(c, dx(2, rk), 2, (int)pb, dx(1, kout), 1, rb[k + 1], dx((int)q), 1, opd(Rcur, 2 * q, q, 1, 0),
-               opd(b.V1, chi, 0, 1, 0), opd(core_out(k), 2 * co, co, 1, 0));
+      r = gemm(c, dv(c, 2, rk), 2, (int)pb, dv(c, 1, kout), 1, rb[k + 1], dx((int)q), 1,
+               opd(Rcur, 2 * q, q, 1, 0, 0, b.sq), opd(b.V1, chi, 0, 1, 0, 0, b.sV),
+               opd(core_out(k), 2 * co, co, 1, 0, 0, sOut));
       if (r) return r;
     }
     Rcur = Rn;
     rsel ^= 1;
   }
   // last core: [r][s][0] = R[r][s]
-  const int* rl = out->bonds + m - 1;
-  HIPCHK(block_copy(Rcur, 2, 1, core_out(m - 1), 2 * co, co, dx(1, rl), dx(2), rb[m - 1], 2, real, s));
-  if (out->norm) HIPCHK(block_norm(core_out(m - 1), real, dx(1, rl), dx(2), rb[m - 1], 2, 2 * co, co, out->norm, s));
+  const int* rl = out.bonds + m - 1;
+  HIPCHK(block_copy_b(Rcur, 2, 1, b.sq, core_out(m - 1), 2 * co, co, sOut, dv(c, 1, rl), dx(2), rb[m - 1], 2, real,
+                      nf, s));
+  if (out.norms)
+    HIPCHK(block_norm_b(core_out(m - 1), real, dv(c, 1, rl), dx(2), rb[m - 1], 2, 2 * co, co, sOut, out.norms, nf, s));
   return QTT_OK;
 }
 
@@ -565,69 +663,78 @@ struct DenseBufs {
   void* P[2];
   void* Q[2];
   void* E;
+  ll sP, sQ, sE;
 };
 
-DenseBufs carve_dense(Carver& cv, int m, int chi, size_t csz) {
+DenseBufs carve_dense(Carver& cv, int m, int chi, size_t csz, int nf) {
   DenseBufs b;
   int h = m / 2;
+  b.sP = ((ll)1 << h) * chi;
+  b.sQ = ((ll)1 << (m - h)) * chi;
+  b.sE = (ll)1 << m;
   b.status = (int*)cv.take(256);
-  b.bonds = (int*)cv.take((m + 1) * sizeof(int));
-  b.P[0] = cv.take(((size_t)1 << h) * chi * csz);
-  b.P[1] = cv.take(((size_t)1 << h) * chi * csz);
-  b.Q[0] = cv.take(((size_t)1 << (m - h)) * chi * csz);
-  b.Q[1] = cv.take(((size_t)1 << (m - h)) * chi * csz);
-  b.E = cv.take(((size_t)1 << m) * csz);
+  b.bonds = (int*)cv.take((size_t)nf * (m + 1) * sizeof(int));
+  b.P[0] = cv.take(nf * b.sP * csz);
+  b.P[1] = cv.take(nf * b.sP * csz);
+  b.Q[0] = cv.take(nf * b.sQ * csz);
+  b.Q[1] = cv.take(nf * b.sQ * csz);
+  b.E = cv.take(nf * b.sE * csz);
   return b;
 }
 
-int dense_impl(const qtt_mps* in, void* out, int out_dtype, DenseBufs& b, hipStream_t s) {
-  const int m = in->n_sites, h = m / 2;
-  const int real = in->dtype == QTT_C128 ? 1 : 0;
-  Ctx c;
-  c.s = s; c.real = real;
-  c.gemm_t = real ? GEMM_F64 : GEMM_F32;
-  c.csz = real ? 16 : 8;
-  const ll ch = in->chi_cap;
+// out: nf dense N x N fields (stride N^2 elements of out_dtype)
+int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream_t s) {
+  const int m = in.m, h = m / 2, nf = in.nf;
+  const int real = in.dtype == QTT_C128 ? 1 : 0;
+  Ctx c = make_ctx(s, real, nf, m, b.status);
+  const ll ch = in.cap, sIn = in.fstride();
   std::vector<int> rb = mps_bounds(m, ch);
-  char* inc = (char*)in->cores;
+  char* inc = (char*)in.cores;
   auto core = [&](int k) { return inc + (size_t)k * ch * 2 * ch * c.csz; };
-  HIPCHK(sanitize_bonds(in->bonds, b.bonds, m, (int)ch, b.status, s));
+  HIPCHK(sanitize_bonds(in.bonds, b.bonds, m, (int)ch, b.status, nf, s));
   const int* bonds = b.bonds;
   // left: P_1 = core 0 as [s][b] (row stride ch); P_{k+1}[(l,s)][b] = P_k[l][r] A_k[r][s][b]
   const void* P = core(0);
-  ll pld = ch;
+  ll pld = ch, sP = sIn;
   int psel = 0;
   for (int k = 1; k < h; ++k) {
     const ll rows = 1ll << k;
     void* Pn = b.P[psel];
-    int r = gemm(c, dx((int)rows), 1, (int)rows, dx(2, bonds + k + 1), 2, 2 * rb[k + 1], dx(1, bonds + k), 1,
-                 opd(P, pld, 0, 1, 0), opd(core(k), 2 * ch, 0, 1, ch), opd(Pn, 2 * ch, 0, 1, ch));
+    int r = gemm(c, dx((int)rows), 1, (int)rows, dv(c, 2, bonds + k + 1), 2, 2 * rb[k + 1], dv(c, 1, bonds + k), 1,
+                 opd(P, pld, 0, 1, 0, 0, sP), opd(core(k), 2 * ch, 0, 1, ch, 0, sIn),
+                 opd(Pn, 2 * ch, 0, 1, ch, 0, b.sP));
     if (r) return r;
     P = Pn;
     pld = ch;
+    sP = b.sP;
     psel ^= 1;
   }
   // right: Q_{m-1}[r][s] = core m-1 [r][s][0]; Q_k[(r,s)][c] = A_k[(r,s)][b] Q_{k+1}[b][c]
   const void* Q = core(m - 1);
-  ll qrs = 2 * ch, qcs = ch;   // row / column strides of Q_{k+1}
+  ll qrs = 2 * ch, qcs = ch, sQ = sIn;   // row / column strides of Q_{k+1}
   int qsel = 0;
   for (int k = m - 2; k >= h; --k) {
     const ll cols = 1ll << (m - k - 1);
     void* Qn = b.Q[qsel];
-    int r = gemm(c, dx(2, bonds + k), 2, 2 * rb[k], dx((int)cols), 1, (int)cols, dx(1, bonds + k + 1), 1,
-                 opd(core(k), 2 * ch, ch, 1, 0), opd(Q, qrs, 0, qcs, 0), opd(Qn, 2 * cols, cols, 1, 0));
+    int r = gemm(c, dv(c, 2, bonds + k), 2, 2 * rb[k], dx((int)cols), 1, (int)cols, dv(c, 1, bonds + k + 1), 1,
+                 opd(core(k), 2 * ch, ch, 1, 0, 0, sIn), opd(Q, qrs, 0, qcs, 0, 0, sQ),
+                 opd(Qn, 2 * cols, cols, 1, 0, 0, b.sQ));
     if (r) return r;
     Q = Qn;
     qrs = 2 * cols;
     qcs = 1;
+    sQ = b.sQ;
     qsel ^= 1;
   }
   // E[l][c] = P_h[l][r] Q_h[r][c]
   const ll L = 1ll << h, Rn = 1ll << (m - h);
-  int r = gemm(c, dx((int)L), 1, (int)L, dx((int)Rn), 1, (int)Rn, dx(1, bonds + h), 1, opd(P, pld, 0, 1, 0),
-               opd(Q, qrs, 0, qcs, 0), opd(b.E, Rn, 0, 1, 0));
+  int r = gemm(c, dx((int)L), 1, (int)L, dx((int)Rn), 1, (int)Rn, dv(c, 1, bonds + h), 1,
+               opd(P, pld, 0, 1, 0, 0, sP), opd(Q, qrs, 0, qcs, 0, 0, sQ), opd(b.E, Rn, 0, 1, 0, 0, b.sE));
   if (r) return r;
-  HIPCHK(quantics_permute(b.E, real ? QTT_C128 : QTT_C64, out, out_dtype, m / 2, 1, s));
+  const size_t osz = out_dtype == QTT_C128 ? 16 : 8;
+  for (int f = 0; f < nf; ++f)
+    HIPCHK(quantics_permute((char*)b.E + (size_t)f * b.sE * c.csz, real ? QTT_C128 : QTT_C64,
+                            (char*)out + (size_t)f * b.sE * osz, out_dtype, m / 2, 1, s));
   return QTT_OK;
 }
 
@@ -640,22 +747,26 @@ const char* tt_last_error(void) { return g_err.c_str(); }
 const char* tt_version(void) { return "libqtt 0.1 (gfx950)"; }
 
 size_t tt_workspace_size(int op, int n_sites, int chi_cap, int d_cap, int prec) {
-  if (n_sites < 2 || (n_sites & 1) || chi_cap < 1 || chi_cap > 256) return 0;
+  return tt_workspace_size_batched(op, 1, n_sites, chi_cap, d_cap, prec);
+}
+
+size_t tt_workspace_size_batched(int op, int count, int n_sites, int chi_cap, int d_cap, int prec) {
+  if (n_sites < 2 || (n_sites & 1) || chi_cap < 1 || chi_cap > 256 || count < 1) return 0;
   size_t csz = prec == QTT_PREC_FP64 ? 16 : 8;
   switch (op) {
     case QTT_OP_ENCODE: {
       Carver cv(nullptr);
-      carve_encode(cv, n_sites, chi_cap, csz);
+      carve_encode(cv, n_sites, chi_cap, csz, count);
       return cv.off;
     }
     case QTT_OP_APPLY:
       if (d_cap < 1) return 0;
-      return apply_ws(n_sites, chi_cap, d_cap, prec, false);
+      return apply_ws(n_sites, chi_cap, d_cap, prec, false, count);
     case QTT_OP_TRUNCATE:
-      return apply_ws(n_sites, chi_cap, 1, prec, true);
+      return apply_ws(n_sites, chi_cap, 1, prec, true, count);
     case QTT_OP_TO_DENSE: {
       Carver cv(nullptr);
-      carve_dense(cv, n_sites, chi_cap, csz);
+      carve_dense(cv, n_sites, chi_cap, csz, count);
       return cv.off;
     }
     default:
@@ -668,6 +779,26 @@ size_t tt_saved_size(int n_sites, int chi_cap, int d_cap, int prec) {
   return 0;
 }
 
+static int encode_common(const void* img, int img_dtype, int log2_side, const qtt_opts* opts, const MpsB& out,
+                         const int* chi_dev, void* ws, size_t ws_bytes, void* stream) {
+  if (!img) return fail(QTT_ERR_ARG, "img is NULL");
+  if (log2_side < 1 || log2_side > 15) return fail(QTT_ERR_SHAPE, "log2_side %d outside [1, 15]", log2_side);
+  if (out.m != 2 * log2_side) return fail(QTT_ERR_SHAPE, "out has %d sites, need %d", out.m, 2 * log2_side);
+  if (img_dtype < QTT_C64 || img_dtype > QTT_F64) return fail(QTT_ERR_DTYPE, "bad img dtype %d", img_dtype);
+  if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
+  qtt_opts o;
+  opts_defaults(opts, out.cap, o);
+  if (o.chi_max < 1 || o.chi_max > out.cap) return fail(QTT_ERR_CAPACITY, "chi_max %d outside [1, %d]", o.chi_max, out.cap);
+  if ((o.prec == QTT_PREC_FP64) != (out.dtype == QTT_C128)) return fail(QTT_ERR_DTYPE, "precision and dtype disagree");
+  size_t csz = out.dtype == QTT_C128 ? 16 : 8;
+  Carver cv(nullptr);
+  carve_encode(cv, out.m, o.chi_max, csz, out.nf);
+  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
+  Carver cw(ws);
+  EncBufs b = carve_encode(cw, out.m, o.chi_max, csz, out.nf);
+  return encode_impl(img, img_dtype, log2_side, o, out, b, chi_dev, (hipStream_t)stream);
+}
+
 int tt_encode(const void* img, int img_dtype, int log2_side, const qtt_opts* opts, qtt_mps* out, void* ws,
               size_t ws_bytes, void* stream) {
   g_err.clear();
@@ -675,52 +806,77 @@ int tt_encode(const void* img, int img_dtype, int log2_side, const qtt_opts* opt
   if (!img) return fail(QTT_ERR_ARG, "img is NULL");
   if (log2_side < 1 || log2_side > 15) return fail(QTT_ERR_SHAPE, "log2_side %d outside [1, 15]", log2_side);
   if ((r = check_mps(out, "out"))) return r;
-  if (out->n_sites != 2 * log2_side) return fail(QTT_ERR_SHAPE, "out has %d sites, need %d", out->n_sites, 2 * log2_side);
-  if (img_dtype < QTT_C64 || img_dtype > QTT_F64) return fail(QTT_ERR_DTYPE, "bad img dtype %d", img_dtype);
-  if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
-  qtt_opts o;
-  opts_defaults(opts, out->chi_cap, o);
-  if (o.chi_max < 1 || o.chi_max > out->chi_cap) return fail(QTT_ERR_CAPACITY, "chi_max %d outside [1, %d]", o.chi_max, out->chi_cap);
-  if ((o.prec == QTT_PREC_FP64) != (out->dtype == QTT_C128)) return fail(QTT_ERR_DTYPE, "precision and dtype disagree");
-  size_t csz = out->dtype == QTT_C128 ? 16 : 8;
-  Carver cv(nullptr);
-  carve_encode(cv, out->n_sites, o.chi_max, csz);
-  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
-  Carver cw(ws);
-  EncBufs b = carve_encode(cw, out->n_sites, o.chi_max, csz);
-  return encode_impl(img, img_dtype, log2_side, o, out, b, (hipStream_t)stream);
+  return encode_common(img, img_dtype, log2_side, opts, view(out), nullptr, ws, ws_bytes, stream);
+}
+
+int tt_encode_batched(const void* img, int img_dtype, int log2_side, const qtt_opts* opts, const int32_t* chi_dev,
+                      qtt_mps_batch* out, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mpsb(out, "out"))) return r;
+  return encode_common(img, img_dtype, log2_side, opts, view(out), chi_dev, ws, ws_bytes, stream);
 }
 
 int mpo_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts, qtt_mps* out, void* saved,
               size_t saved_bytes, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   (void)saved; (void)saved_bytes;
-  if (in && out && in->cores == out->cores) return fail(QTT_ERR_ARG, "in and out must not alias");
-  return apply_common(in, W, opts, out, ws, ws_bytes, stream, false);
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if ((r = check_mps(out, "out"))) return r;
+  if (in->cores == out->cores) return fail(QTT_ERR_ARG, "in and out must not alias");
+  if (!W) return fail(QTT_ERR_ARG, "MPO is NULL");
+  return apply_common(view(in), W, nullptr, opts, view(out), nullptr, ws, ws_bytes, stream, false);
+}
+
+int mpo_apply_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt_opts* opts, const int32_t* chi_dev,
+                      qtt_mps_batch* out, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mpsb(in, "in"))) return r;
+  if ((r = check_mpsb(out, "out"))) return r;
+  if (in->cores == out->cores) return fail(QTT_ERR_ARG, "in and out must not alias");
+  if (!W) return fail(QTT_ERR_ARG, "MPO batch is NULL");
+  MpoB wb;
+  wb.nf = W->count; wb.m = W->n_sites; wb.dcap = W->d_cap; wb.dtype = W->dtype;
+  wb.cores = W->cores; wb.dbonds = W->d_bonds; wb.kind = W->site_kind;
+  return apply_common(view(in), nullptr, &wb, opts, view(out), chi_dev, ws, ws_bytes, stream, false);
 }
 
 int tt_truncate(qtt_mps* inout, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
+  int r;
+  if ((r = check_mps(inout, "inout"))) return r;
   qtt_opts o;
-  if (!inout) return fail(QTT_ERR_ARG, "inout is NULL");
   opts_defaults(opts, inout->chi_cap, o);
   o.chi_zip = inout->chi_cap;     // the right-to-left pass only removes numerical zeros
-  return apply_common(inout, nullptr, &o, inout, ws, ws_bytes, stream, true);
+  return apply_common(view(inout), nullptr, nullptr, &o, view(inout), nullptr, ws, ws_bytes, stream, true);
+}
+
+static int dense_common(const MpsB& in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  if (!out || !ws) return fail(QTT_ERR_ARG, "out/workspace is NULL");
+  if (out_dtype != QTT_C64 && out_dtype != QTT_C128) return fail(QTT_ERR_DTYPE, "out dtype must be C64 or C128");
+  size_t csz = in.dtype == QTT_C128 ? 16 : 8;
+  Carver cv(nullptr);
+  carve_dense(cv, in.m, in.cap, csz, in.nf);
+  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
+  Carver cw(ws);
+  DenseBufs b = carve_dense(cw, in.m, in.cap, csz, in.nf);
+  return dense_impl(in, out, out_dtype, b, (hipStream_t)stream);
 }
 
 int tt_to_dense(const qtt_mps* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   int r;
   if ((r = check_mps(in, "in"))) return r;
-  if (!out || !ws) return fail(QTT_ERR_ARG, "out/workspace is NULL");
-  if (out_dtype != QTT_C64 && out_dtype != QTT_C128) return fail(QTT_ERR_DTYPE, "out dtype must be C64 or C128");
-  size_t csz = in->dtype == QTT_C128 ? 16 : 8;
-  Carver cv(nullptr);
-  carve_dense(cv, in->n_sites, in->chi_cap, csz);
-  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
-  Carver cw(ws);
-  DenseBufs b = carve_dense(cw, in->n_sites, in->chi_cap, csz);
-  return dense_impl(in, out, out_dtype, b, (hipStream_t)stream);
+  return dense_common(view(in), out, out_dtype, ws, ws_bytes, stream);
+}
+
+int tt_to_dense_batched(const qtt_mps_batch* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mpsb(in, "in"))) return r;
+  return dense_common(view(in), out, out_dtype, ws, ws_bytes, stream);
 }
 
 int mpo_apply_backward(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts, const void* saved,
@@ -782,6 +938,42 @@ int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int*
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(eig_launch(e, s));
   if (evals) HIPCHK(eig_copy_evals(e, evals, kcap, s));
+  return QTT_OK;
+}
+
+int tt_prof_begin(int what, int* nlog, int max_entries, int max_launches) {
+  g_err.clear();
+  if ((what != PROF_TRIDIAG && what != PROF_TRIDIAG_LDS) || !nlog || max_entries < 1 || max_launches < 1)
+    return fail(QTT_ERR_ARG, "tt_prof_begin: bad arguments");
+  if (g_prof.ev) {
+    for (int i = 0; i < 2 * g_prof.max_launches; ++i) hipEventDestroy(g_prof.ev[i]);
+    delete[] g_prof.ev;
+    g_prof.ev = nullptr;
+  }
+  g_prof.ev = new hipEvent_t[2 * (size_t)max_launches];
+  for (int i = 0; i < 2 * max_launches; ++i) HIPCHK(hipEventCreate(&g_prof.ev[i]));
+  g_prof.what = what;
+  g_prof.nlog = nlog;
+  g_prof.max = max_entries;
+  g_prof.slot = 0;
+  g_prof.launches = 0;
+  g_prof.max_launches = max_launches;
+  return QTT_OK;
+}
+
+int tt_prof_end(int* launches, int* entries, double* total_ms) {
+  g_err.clear();
+  double tot = 0.0;
+  for (int i = 0; i < g_prof.launches; ++i) {
+    HIPCHK(hipEventSynchronize(g_prof.ev[2 * i + 1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
+    tot += ms;
+  }
+  if (launches) *launches = g_prof.launches;
+  if (entries) *entries = g_prof.slot;
+  if (total_ms) *total_ms = tot;
+  g_prof.what = PROF_NONE;
   return QTT_OK;
 }
 

@@ -3,20 +3,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-// A problem dimension known only on the device: value = c * (*p0) * (*p1),
-// a NULL pointer contributing 1.  Bond dimensions chosen by the eigensolver
-// are written to device memory and read back through these by later kernels
-// in the same stream, so the host never waits for them.
+// A problem dimension known only on the device: for batch entry (field) f,
+// value = c * p0[f*bs] * p1[f*bs], a NULL pointer contributing 1.  Bond
+// dimensions chosen by the eigensolver are written to device memory and read
+// back through these by later kernels in the same stream, so the host never
+// waits for them; bs is the per-field stride of the bond arrays.
 struct DimExpr {
   int c;
   const int* p0;
   const int* p1;
+  int bs;
 };
 
-__device__ __forceinline__ int dim_eval(const DimExpr& d) {
+__device__ __forceinline__ int dim_eval(const DimExpr& d, int f = 0) {
   int v = d.c;
-  if (d.p0) v *= *d.p0;
-  if (d.p1) v *= *d.p1;
+  if (d.p0) v *= d.p0[(long long)f * d.bs];
+  if (d.p1) v *= d.p1[(long long)f * d.bs];
   return v;
 }
 
@@ -37,14 +39,18 @@ __device__ __forceinline__ uint32_t fdiv(const FastDiv& f, uint32_t n) {
 //   ptr + batch * sb + xh * sxh + xl * sxl + yh * syh + yl * syl
 // in complex elements.  This expresses every reshape/permutation the zip-up,
 // sweep, encode and decompression steps need without copies.
+// sb: stride between fields (outer batch), sb2: stride of the inner batch index.
 struct Operand {
   void* ptr;
-  long long sxh, sxl, syh, syl, sb;
+  long long sxh, sxl, syh, syl, sb, sb2;
   int conj;
 };
 
+// Two-level batch: blockIdx.z = f * b2cap + a, f the field, a an inner
+// batch index bounded by the device value batch(f).
 struct GemmArgs {
   DimExpr M, N, K, batch;
+  int b2cap;
   FastDiv fm, fn, fk;     // low extents of the split M, N, K indices
   Operand A, B, C;        // A: (M, K); B: (K, N); C: (M, N)
   int accumulate;         // C += A.B instead of C = A.B

@@ -29,7 +29,6 @@
 namespace qtt {
 
 constexpr int EIG_NMAX = 512;       // largest Gram matrix (2 * chi_cap, chi_cap <= 256)
-constexpr int TRI_NT = 256;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -98,108 +97,241 @@ __host__ __device__ inline EigWs eig_ws_carve(void* base, int b, int nb, int kc)
 }
 
 // ------------------------------------------------------------ 1. tridiag
-__global__ __launch_bounds__(TRI_NT) void tridiag_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
-                                                         void* wsbase, int nb, int kc) {
+// (a) n <= 128: the packed lower triangle (n(n+1)/2 complex doubles, <= 132 KB)
+//     lives in LDS for the whole reduction; 1024 threads, 8 per row for the
+//     matrix-vector product and the rank-2 update.
+constexpr int TL_NMAX = 128;
+constexpr int TL_NT = 1024;
+constexpr int TL_TRI = TL_NMAX * (TL_NMAX + 1) / 2;
+
+__device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1) >> 1) + c; }   // r >= c
+
+template <int NT>
+__device__ double2 block_sum2(double2 v, double* red) {
+  double a = wave_sum(v.x), b = wave_sum(v.y);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
+  __syncthreads();
+  double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) { s.x += red[2 * i]; s.y += red[2 * i + 1]; }
+  return s;
+}
+
+__device__ void householder(double2 alpha, double xnorm2, double2& tau, double2& scale, double& beta) {
+  if (xnorm2 == 0.0 && alpha.y == 0.0) {
+    tau = make_double2(0.0, 0.0);
+    beta = alpha.x;
+    scale = make_double2(0.0, 0.0);
+  } else {
+    double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
+    beta = alpha.x >= 0.0 ? -nrm : nrm;
+    tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    double2 den = make_double2(alpha.x - beta, alpha.y);
+    double dd = den.x * den.x + den.y * den.y;
+    scale = make_double2(den.x / dd, -den.y / dd);
+  }
+}
+
+__global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
+                                                            void* wsbase, int nb, int kc, int* nlog) {
   const int b = blockIdx.x;
-  const int n = dim_eval(nexp);
+  const int n = min(dim_eval(nexp, b), min(nb, TL_NMAX));
+  if (nlog && threadIdx.x == 0) nlog[b] = n;
+  double2* A = Gall + (long long)b * gstride;
+  EigWs W = eig_ws_carve(wsbase, b, nb, kc);
+  __shared__ double2 L[TL_TRI];
+  __shared__ double2 V[TL_NMAX], P[TL_NMAX];
+  __shared__ double red[2 * TL_NT / 64];
+  __shared__ double2 s_tau, s_scale;
+  const int tid = threadIdx.x;
+  {
+    // packed lower triangle, all loads independent: element e -> (r, c)
+    const int T = n * (n + 1) / 2;
+    for (int e = tid; e < T; e += TL_NT) {
+      int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+      while (tri(r + 1, 0) <= e) ++r;
+      while (tri(r, 0) > e) --r;
+      L[e] = A[(long long)r * ld + (e - tri(r, 0))];
+    }
+  }
+  __syncthreads();
+  const int rl = tid >> 3, sl = tid & 7;      // row slot and lane within the row's 8 threads
+  for (int j = 0; j < n - 1; ++j) {
+    const int j1 = j + 1;
+    double loc = 0.0;
+    for (int r = j1 + 1 + tid; r < n; r += TL_NT) {
+      double2 x = L[tri(r, j)];
+      loc += x.x * x.x + x.y * x.y;
+    }
+    double xnorm2 = block_sum<TL_NT>(loc, red);
+    if (tid == 0) {
+      double2 tau, scale;
+      double beta;
+      householder(L[tri(j1, j)], xnorm2, tau, scale, beta);
+      W.d[j] = L[tri(j, j)].x;
+      W.e[j] = beta;
+      W.e2[j] = beta * beta;
+      W.tau[j] = tau;
+      s_tau = tau;
+      s_scale = scale;
+    }
+    __syncthreads();
+    const double2 tau = s_tau, scale = s_scale;
+    for (int r = j1 + tid; r < n; r += TL_NT) {
+      double2 v = r == j1 ? make_double2(1.0, 0.0) : cmul(L[tri(r, j)], scale);
+      V[r] = v;
+      if (r > j1) A[(long long)j * ld + r] = v;   // reflector kept for the back-transformation
+    }
+    __syncthreads();
+    if (tau.x == 0.0 && tau.y == 0.0) continue;
+    // p = tau A v over the trailing block (A Hermitian, lower triangle stored)
+    {
+      const int r = j1 + rl;
+      double2 acc = make_double2(0.0, 0.0);
+      if (r < n) {
+        for (int c = j1 + sl; c < n; c += 8) {
+          double2 a = c <= r ? L[tri(r, c)] : make_double2(L[tri(c, r)].x, -L[tri(c, r)].y);
+          acc = cadd(acc, cmul(a, V[c]));
+        }
+      }
+#pragma unroll
+      for (int o = 1; o < 8; o <<= 1) {
+        acc.x += __shfl_xor(acc.x, o);
+        acc.y += __shfl_xor(acc.y, o);
+      }
+      if (r < n && sl == 0) P[r] = cmul(tau, acc);
+    }
+    __syncthreads();
+    // w = p - (tau/2)(p^H v) v, kept in P
+    double2 dl = make_double2(0.0, 0.0);
+    for (int r = j1 + tid; r < n; r += TL_NT) dl = cadd(dl, cmulc(P[r], V[r]));
+    double2 dot = block_sum2<TL_NT>(dl, red);
+    const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
+    for (int r = j1 + tid; r < n; r += TL_NT) P[r] = cadd(P[r], cmul(alpha2, V[r]));
+    __syncthreads();
+    // rank-2 update of the lower trailing triangle: A -= v w^H + w v^H
+    {
+      const int r = j1 + rl;
+      if (r < n) {
+        const double2 vr = V[r], wr = P[r];
+        for (int c = j1 + sl; c <= r; c += 8) {
+          double2 a = L[tri(r, c)];
+          a = csub(a, cmul(vr, make_double2(P[c].x, -P[c].y)));
+          a = csub(a, cmul(wr, make_double2(V[c].x, -V[c].y)));
+          L[tri(r, c)] = a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && n >= 1) W.d[n - 1] = L[tri(n - 1, n - 1)].x;
+}
+
+// (b) 128 < n <= 512: the full matrix is streamed from L2 each step.  The
+//     rank-2 update of step j is fused with the matrix-vector product of step
+//     j+1; 1024 threads, each column split over 4 row quarters so that four
+//     times as many loads are in flight.
+constexpr int TS_NT = 1024;
+constexpr int TS_SPLIT = 4;
+constexpr int TS_COLS = TS_NT / TS_SPLIT;     // 256 columns per pass
+__global__ __launch_bounds__(TS_NT) void tridiag_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
+                                                        void* wsbase, int nb, int kc, int* nlog) {
+  const int b = blockIdx.x;
+  const int n = min(dim_eval(nexp, b), nb);
+  if (nlog && threadIdx.x == 0) nlog[b] = n;
   double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 vp[EIG_NMAX], wp[EIG_NMAX], vn[EIG_NMAX], pn[EIG_NMAX];
-  __shared__ double red[TRI_NT / 64];
+  __shared__ double2 part[TS_SPLIT][TS_COLS];
+  __shared__ double red[2 * TS_NT / 64];
   __shared__ double2 s_tau, s_scale;
-  __shared__ double s_beta;
   const int tid = threadIdx.x;
+  const int cl = tid % TS_COLS, q = tid / TS_COLS;
   bool pending = false;
   for (int j = 0; j < n - 1; ++j) {
     const int j1 = j + 1;
+    const int np = n - j1;
     // (a) finish row j with the pending rank-2 update of step j-1
-    for (int c = j + tid; c < n; c += TRI_NT) {
+    for (int c = j + tid; c < n; c += TS_NT) {
       double2 a = A[(long long)j * ld + c];
       if (pending) {
         a = csub(a, cmul(vp[j], make_double2(wp[c].x, -wp[c].y)));
         a = csub(a, cmul(wp[j], make_double2(vp[c].x, -vp[c].y)));
+        A[(long long)j * ld + c] = a;
       }
-      A[(long long)j * ld + c] = a;
-      if (c == j && false) {}
     }
     __syncthreads();
-    // (b) reflector annihilating column j below the subdiagonal
-    //     (column j = conj(row j) by Hermiticity)
+    // (b) reflector from column j = conj(row j) below the diagonal
     double loc = 0.0;
-    for (int c = j1 + 1 + tid; c < n; c += TRI_NT) {
+    for (int c = j1 + 1 + tid; c < n; c += TS_NT) {
       double2 a = A[(long long)j * ld + c];
       loc += a.x * a.x + a.y * a.y;
     }
-    double xnorm2 = block_sum<TRI_NT>(loc, red);
+    double xnorm2 = block_sum<TS_NT>(loc, red);
     if (tid == 0) {
-      W.d[j] = A[(long long)j * ld + j].x;
       double2 a = A[(long long)j * ld + j1];
-      double2 alpha = make_double2(a.x, -a.y);
       double2 tau, scale;
       double beta;
-      if (xnorm2 == 0.0 && alpha.y == 0.0) {
-        tau = make_double2(0.0, 0.0);
-        beta = alpha.x;
-        scale = make_double2(0.0, 0.0);
-      } else {
-        double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xnorm2);
-        beta = alpha.x >= 0.0 ? -nrm : nrm;
-        tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
-        double2 den = make_double2(alpha.x - beta, alpha.y);
-        double dd = den.x * den.x + den.y * den.y;
-        scale = make_double2(den.x / dd, -den.y / dd);
-      }
-      s_tau = tau;
-      s_scale = scale;
-      s_beta = beta;
+      householder(make_double2(a.x, -a.y), xnorm2, tau, scale, beta);
+      W.d[j] = A[(long long)j * ld + j].x;
       W.e[j] = beta;
       W.e2[j] = beta * beta;
       W.tau[j] = tau;
+      s_tau = tau;
+      s_scale = scale;
     }
     __syncthreads();
     const double2 tau = s_tau, scale = s_scale;
-    for (int c = j1 + tid; c < n; c += TRI_NT) {
+    for (int c = j1 + tid; c < n; c += TS_NT) {
       double2 v;
       if (c == j1) {
         v = make_double2(1.0, 0.0);
       } else {
         double2 a = A[(long long)j * ld + c];
         v = cmul(make_double2(a.x, -a.y), scale);
-        A[(long long)j * ld + c] = v;            // reflector stored in row j
+        A[(long long)j * ld + c] = v;
       }
       vn[c] = v;
     }
     __syncthreads();
-    // (c) fused pass over the trailing block: apply the pending update and
-    //     accumulate p = tau * A v (A Hermitian: (A v)_c = sum_r conj(A[r][c]) v_r)
-    for (int c = j1 + tid; c < n; c += TRI_NT) {
+    // (c) fused pass: pending update + p = tau A v, column c split in 4 row ranges
+    const int rq = (np + TS_SPLIT - 1) / TS_SPLIT;
+    const int r0 = j1 + q * rq, r1 = min(n, r0 + rq);
+    for (int c0 = j1; c0 < n; c0 += TS_COLS) {
+      const int c = c0 + cl;
       double2 acc = make_double2(0.0, 0.0);
-      const double2 wpc = make_double2(wp[c].x, -wp[c].y);
-      const double2 vpc = make_double2(vp[c].x, -vp[c].y);
-#pragma unroll 4
-      for (int r = j1; r < n; ++r) {
-        double2 a = A[(long long)r * ld + c];
-        if (pending) {
-          a = csub(a, cmul(vp[r], wpc));
-          a = csub(a, cmul(wp[r], vpc));
-          A[(long long)r * ld + c] = a;
+      if (c < n) {
+        const double2 wpc = make_double2(wp[c].x, -wp[c].y);
+        const double2 vpc = make_double2(vp[c].x, -vp[c].y);
+#pragma unroll 8
+        for (int r = r0; r < r1; ++r) {
+          double2 a = A[(long long)r * ld + c];
+          if (pending) {
+            a = csub(a, cmul(vp[r], wpc));
+            a = csub(a, cmul(wp[r], vpc));
+            A[(long long)r * ld + c] = a;
+          }
+          acc = cadd(acc, cmulc(a, vn[r]));
         }
-        acc = cadd(acc, cmulc(a, vn[r]));
       }
-      pn[c] = cmul(tau, acc);
+      part[q][cl] = acc;
+      __syncthreads();
+      if (q == 0 && c < n) {
+        double2 s2 = part[0][cl];
+#pragma unroll
+        for (int i = 1; i < TS_SPLIT; ++i) s2 = cadd(s2, part[i][cl]);
+        pn[c] = cmul(tau, s2);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     // (d) w = p - (tau/2)(p^H v) v  -> becomes the pending update
-    double lre = 0.0, lim = 0.0;
-    for (int c = j1 + tid; c < n; c += TRI_NT) {
-      double2 q = cmulc(pn[c], vn[c]);
-      lre += q.x;
-      lim += q.y;
-    }
-    double dre = block_sum<TRI_NT>(lre, red);
-    double dim_ = block_sum<TRI_NT>(lim, red);
-    double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), make_double2(dre, dim_));
-    for (int c = j1 + tid; c < n; c += TRI_NT) {
+    double2 dl = make_double2(0.0, 0.0);
+    for (int c = j1 + tid; c < n; c += TS_NT) dl = cadd(dl, cmulc(pn[c], vn[c]));
+    double2 dot = block_sum2<TS_NT>(dl, red);
+    double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
+    for (int c = j1 + tid; c < n; c += TS_NT) {
       wp[c] = cadd(pn[c], cmul(alpha2, vn[c]));
       vp[c] = vn[c];
     }
@@ -243,9 +375,10 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x) {
 }
 
 constexpr int EV_NT = 256;
-__global__ __launch_bounds__(EV_NT) void eigvals_kernel(DimExpr nexp, int kcap, void* wsbase, int nb, int kc) {
+__global__ __launch_bounds__(EV_NT) void eigvals_kernel(DimExpr nexp, int kcap, void* wsbase, int nb, int kc,
+                                                        const int* kcap_dev) {
   const int b = blockIdx.y;
-  const int n = dim_eval(nexp);
+  const int n = min(dim_eval(nexp, b), nb);
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double sd[EIG_NMAX], se2[EIG_NMAX];
   for (int i = threadIdx.x; i < n; i += EV_NT) {
@@ -255,7 +388,7 @@ __global__ __launch_bounds__(EV_NT) void eigvals_kernel(DimExpr nexp, int kcap, 
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int t = blockIdx.x * (EV_NT / 64) + (threadIdx.x >> 6);
-  const int kmax = min(n, kcap);
+  const int kmax = min(min(n, kcap), kcap_dev ? max(kcap_dev[b], 1) : kcap);
   if (t >= kmax) return;
   // Gershgorin interval
   double glo = 1e300, ghi = -1e300;
@@ -293,39 +426,49 @@ __global__ __launch_bounds__(EV_NT) void eigvals_kernel(DimExpr nexp, int kcap, 
 }
 
 // ------------------------------------------------------------ 3. keep rule
-__global__ void keep_kernel(DimExpr nexp, int kcap, double cutoff, double tau, int* kout, long long kstride,
-                            void* wsbase, int nb, int kc, int batch, int* status, double* sigma_out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int KP_NT = 256;
+__global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, double cutoff, double tau, int* kout,
+                                                     long long kstride, void* wsbase, int nb, int kc, int batch,
+                                                     int* status, double* sigma_out, const int* kcap_dev) {
+  const int b = blockIdx.x;
   if (b >= batch) return;
-  const int n = dim_eval(nexp);
+  const int n = min(dim_eval(nexp, b), nb);
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
-  const int kmax = min(n, kcap);
-  double total = 0.0;
-  for (int i = 0; i < n; ++i) total += W.d[i];
-  const double l0 = W.lam[0];
-  int k = 0;
-  bool bad = !isfinite(l0) || !isfinite(total);
-  if (!bad && l0 > 0.0) {
-    for (int t = 0; t < kmax; ++t) {
-      if (W.lam[t] > tau * l0) k = t + 1;
-      else break;
-    }
-    if (cutoff > 0.0) {
-      double kept = 0.0;
-      for (int t = 0; t < k; ++t) {
-        kept += fmax(W.lam[t], 0.0);
-        if (total - kept <= cutoff * total) { k = t + 1; break; }
+  __shared__ double red[KP_NT / 64];
+  __shared__ int s_k;
+  const int kmax = min(min(n, kcap), kcap_dev ? max(kcap_dev[b], 1) : kcap);
+  double loc = 0.0;
+  for (int i = threadIdx.x; i < n; i += KP_NT) loc += W.d[i];
+  const double total = block_sum<KP_NT>(loc, red);     // trace = sum of all eigenvalues
+  if (threadIdx.x == 0) {
+    const double l0 = W.lam[0];
+    int k = 0;
+    bool bad = !isfinite(l0) || !isfinite(total);
+    if (!bad && l0 > 0.0) {
+      for (int t = 0; t < kmax; ++t) {
+        if (W.lam[t] > tau * l0) k = t + 1;
+        else break;
+      }
+      if (cutoff > 0.0) {
+        double kept = 0.0;
+        for (int t = 0; t < k; ++t) {
+          kept += fmax(W.lam[t], 0.0);
+          if (total - kept <= cutoff * total) { k = t + 1; break; }
+        }
       }
     }
+    if (bad) set_status(status, ST_NONFINITE);
+    if (k < 1) k = 1;
+    s_k = k;
+    kout[b * kstride] = k;
   }
-  if (bad) set_status(status, ST_NONFINITE);
-  if (k < 1) k = 1;
-  for (int t = 0; t < kmax; ++t) {
-    double s = W.lam[t] > 0.0 ? sqrt(W.lam[t]) : 0.0;
-    W.sig[t] = s;
-    if (sigma_out) sigma_out[(long long)b * kcap + t] = t < k ? s : 0.0;
+  __syncthreads();
+  const int k = s_k;
+  for (int t = threadIdx.x; t < kmax; t += KP_NT) {
+    double sg = W.lam[t] > 0.0 ? sqrt(W.lam[t]) : 0.0;
+    W.sig[t] = sg;
+    if (sigma_out) sigma_out[(long long)b * kcap + t] = t < k ? sg : 0.0;
   }
-  kout[b * kstride] = k;
 }
 
 // ------------------------------------------------------------ 4. inverse iteration
@@ -335,43 +478,54 @@ __device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
   return ((double)h / 4294967296.0) - 0.5;
 }
 
+// One lane per eigenvector; its tridiagonal LU factors (with reciprocal
+// pivots) and iterate live in LDS: VPW vectors per workgroup, 5 doubles and
+// one pivot flag per matrix row and vector.
+constexpr int IV_LDS = 63 * 1024;     // dynamic LDS per workgroup (kept under the 64 KB default)
+__host__ __device__ inline int iv_vpw(int nb) {
+  int v = IV_LDS / (nb * 41);
+  return v < 1 ? 1 : (v > 64 ? 64 : v);
+}
+
 __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase,
-                                                     int nb, int kc) {
+                                                     int nb, int kc, int vpw) {
+  extern __shared__ double ivs[];
   const int b = blockIdx.y;
-  const int n = dim_eval(nexp);
+  const int n = min(dim_eval(nexp, b), nb);
   const int k = kin[b * kstride];
-  const int t = blockIdx.x * 64 + threadIdx.x;
-  if (t >= k) return;
+  const int t = threadIdx.x;
+  const int vi = blockIdx.x * vpw + t;
+  if (t >= vpw || vi >= k) return;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
-  const double mu = W.lam[t];
+  // per-lane arrays, interleaved by lane (stride vpw) to spread LDS banks
+  double* D = ivs;
+  double* DL = D + (size_t)nb * vpw;
+  double* DU = DL + (size_t)nb * vpw;
+  double* DU2 = DU + (size_t)nb * vpw;
+  double* X = DU2 + (size_t)nb * vpw;
+  unsigned char* P = (unsigned char*)(X + (size_t)nb * vpw);
+#define IX(i) ((i) * vpw + t)
+  if (n == 1) { W.z[vi] = 1.0; return; }
+  const double mu = W.lam[vi];
   const double tn = fmax(fabs(W.lam[0]), 1e-300);
   const double pivmin = 1e-300 + 2.2e-16 * tn * 1e-3;
-  // strided per-lane arrays: element i of lane t at i*kc + t
-#define IX(i) ((long long)(i) * kc + t)
-  double* DL = W.lu_dl;
-  double* D = W.lu_d;
-  double* DU = W.lu_du;
-  double* DU2 = W.lu_du2;
-  double* X = W.z;
-  int* P = W.piv;
-  if (n == 1) { X[IX(0)] = 1.0; return; }
   for (int i = 0; i < n; ++i) {
     D[IX(i)] = W.d[i] - mu;
-    if (i < n - 1) { DL[IX(i)] = W.e[i]; DU[IX(i)] = W.e[i]; }
+    if (i < n - 1) { DL[IX(i)] = W.e[i]; DU[IX(i)] = W.e[i]; DU2[IX(i)] = 0.0; }
   }
-  // LU with partial pivoting (tridiagonal)
+  // LU with partial pivoting (tridiagonal); pivots stored as reciprocals
   for (int i = 0; i < n - 1; ++i) {
     double di = D[IX(i)], dli = DL[IX(i)];
     if (fabs(di) >= fabs(dli)) {
-      if (di == 0.0) { di = pivmin; D[IX(i)] = di; }
+      if (di == 0.0) di = pivmin;
       double f = dli / di;
+      D[IX(i)] = 1.0 / di;
       DL[IX(i)] = f;
       D[IX(i + 1)] -= f * DU[IX(i)];
-      if (i < n - 2) DU2[IX(i)] = 0.0;
       P[IX(i)] = 0;
     } else {
       double f = di / dli;
-      D[IX(i)] = dli;
+      D[IX(i)] = 1.0 / dli;
       DL[IX(i)] = f;
       double tmp = DU[IX(i)];
       DU[IX(i)] = D[IX(i + 1)];
@@ -383,28 +537,33 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
       P[IX(i)] = 1;
     }
   }
-  if (D[IX(n - 1)] == 0.0) D[IX(n - 1)] = pivmin;
-  for (int i = 0; i < n; ++i) X[IX(i)] = hash_unit(t + 1, i + 7 * b);
+  {
+    double dn = D[IX(n - 1)];
+    D[IX(n - 1)] = 1.0 / (dn == 0.0 ? pivmin : dn);
+  }
+  for (int i = 0; i < n; ++i) X[IX(i)] = hash_unit(vi + 1, i + 7 * b);
   for (int it = 0; it < 3; ++it) {
-    // forward: L
     for (int i = 0; i < n - 1; ++i) {
+      double xi = X[IX(i)], xn = X[IX(i + 1)];
       if (P[IX(i)] == 0) {
-        X[IX(i + 1)] -= DL[IX(i)] * X[IX(i)];
+        X[IX(i + 1)] = xn - DL[IX(i)] * xi;
       } else {
-        double tmp = X[IX(i)];
-        X[IX(i)] = X[IX(i + 1)];
-        X[IX(i + 1)] = tmp - DL[IX(i)] * X[IX(i)];
+        X[IX(i)] = xn;
+        X[IX(i + 1)] = xi - DL[IX(i)] * xn;
       }
     }
-    // backward: U
-    double mx = 0.0;
-    X[IX(n - 1)] /= D[IX(n - 1)];
-    mx = fabs(X[IX(n - 1)]);
-    X[IX(n - 2)] = (X[IX(n - 2)] - DU[IX(n - 2)] * X[IX(n - 1)]) / D[IX(n - 2)];
-    mx = fmax(mx, fabs(X[IX(n - 2)]));
+    double mx;
+    double x2 = X[IX(n - 1)] * D[IX(n - 1)];
+    X[IX(n - 1)] = x2;
+    double x1 = (X[IX(n - 2)] - DU[IX(n - 2)] * x2) * D[IX(n - 2)];
+    X[IX(n - 2)] = x1;
+    mx = fmax(fabs(x1), fabs(x2));
     for (int i = n - 3; i >= 0; --i) {
-      X[IX(i)] = (X[IX(i)] - DU[IX(i)] * X[IX(i + 1)] - DU2[IX(i)] * X[IX(i + 2)]) / D[IX(i)];
-      mx = fmax(mx, fabs(X[IX(i)]));
+      double x0 = (X[IX(i)] - DU[IX(i)] * x1 - DU2[IX(i)] * x2) * D[IX(i)];
+      X[IX(i)] = x0;
+      x2 = x1;
+      x1 = x0;
+      mx = fmax(mx, fabs(x0));
     }
     double sc = mx > 0.0 && isfinite(mx) ? 1.0 / mx : 1.0;
     for (int i = 0; i < n; ++i) X[IX(i)] *= sc;
@@ -412,7 +571,7 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
   double s2 = 0.0;
   for (int i = 0; i < n; ++i) s2 += X[IX(i)] * X[IX(i)];
   double sc = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-  for (int i = 0; i < n; ++i) X[IX(i)] *= sc;
+  for (int i = 0; i < n; ++i) W.z[(long long)i * kc + vi] = X[IX(i)] * sc;
 #undef IX
 }
 
@@ -421,39 +580,38 @@ constexpr int CL_NT = 256;
 __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase,
                                                         int nb, int kc, double reltol) {
   const int b = blockIdx.x;
-  const int n = dim_eval(nexp);
+  const int n = min(dim_eval(nexp, b), nb);
   const int k = kin[b * kstride];
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double red[CL_NT / 64];
   __shared__ double coef[EIG_NMAX];
+  __shared__ double zt[EIG_NMAX];
   const double tn = fabs(W.lam[0]);
   int cs = 0;
   for (int t = 1; t < k; ++t) {
     if (W.lam[t - 1] - W.lam[t] > reltol * tn) { cs = t; continue; }
-    // t belongs to the cluster [cs, t]: orthogonalise twice against [cs, t)
+    // t joins the cluster [cs, t): Gram-Schmidt twice against its members
+    for (int i = threadIdx.x; i < n; i += CL_NT) zt[i] = W.z[(long long)i * kc + t];
+    __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
-      for (int s = cs; s < t; ++s) {
-        double loc = 0.0;
-        for (int i = threadIdx.x; i < n; i += CL_NT) loc += W.z[(long long)i * kc + s] * W.z[(long long)i * kc + t];
-        double dot = block_sum<CL_NT>(loc, red);
-        if (threadIdx.x == 0) coef[s] = dot;
+      for (int s = cs + threadIdx.x; s < t; s += CL_NT) {
+        double d = 0.0;
+        for (int i = 0; i < n; ++i) d += W.z[(long long)i * kc + s] * zt[i];
+        coef[s] = d;
       }
       __syncthreads();
       for (int i = threadIdx.x; i < n; i += CL_NT) {
-        double v = W.z[(long long)i * kc + t];
+        double v = zt[i];
         for (int s = cs; s < t; ++s) v -= coef[s] * W.z[(long long)i * kc + s];
-        W.z[(long long)i * kc + t] = v;
+        zt[i] = v;
       }
       __syncthreads();
     }
     double loc = 0.0;
-    for (int i = threadIdx.x; i < n; i += CL_NT) {
-      double v = W.z[(long long)i * kc + t];
-      loc += v * v;
-    }
+    for (int i = threadIdx.x; i < n; i += CL_NT) loc += zt[i] * zt[i];
     double nrm = sqrt(block_sum<CL_NT>(loc, red));
     double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int i = threadIdx.x; i < n; i += CL_NT) W.z[(long long)i * kc + t] *= sc;
+    for (int i = threadIdx.x; i < n; i += CL_NT) W.z[(long long)i * kc + t] = zt[i] * sc;
     __syncthreads();
   }
 }
@@ -470,10 +628,9 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
                                                        DimExpr nexp, int* kin, long long kstride, void* wsbase,
                                                        int nb, int kc, EmitPack ep) {
   const int b = blockIdx.y;
-  const int n = dim_eval(nexp);
+  const int n = min(dim_eval(nexp, b), nb);
   const int k = kin[b * kstride];
   const int t = blockIdx.x * (BT_NT / 64) + (threadIdx.x >> 6);
-  if (t >= k) return;
   const int lane = threadIdx.x & 63;
   const double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
@@ -481,22 +638,37 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
 #pragma unroll
   for (int q = 0; q < BT_PER_LANE; ++q) {
     int i = lane + 64 * q;
-    v[q] = make_double2(i < n ? W.z[(long long)i * kc + t] : 0.0, 0.0);
+    v[q] = make_double2(i < n && t < k ? W.z[(long long)i * kc + t] : 0.0, 0.0);
   }
+  __shared__ double2 stau[EIG_NMAX];
+  for (int i = threadIdx.x; i < n - 1; i += BT_NT) stau[i] = W.tau[i];
+  __syncthreads();
+  if (t >= k) return;
+  // reflector j lives in row j (columns > j+1) with an implicit 1 at j+1; the
+  // next reflector's row is loaded while the current one is applied
+  double2 un[BT_PER_LANE];
+  auto load_u = [&](int j) {
+#pragma unroll
+    for (int q = 0; q < BT_PER_LANE; ++q) {
+      int i = lane + 64 * q;
+      un[q] = (i > j + 1 && i < n) ? A[(long long)j * ld + i] : make_double2(0.0, 0.0);
+    }
+  };
+  if (n >= 2) load_u(n - 2);
   for (int j = n - 2; j >= 0; --j) {
-    const double2 tau = W.tau[j];
+    double2 u[BT_PER_LANE];
+#pragma unroll
+    for (int q = 0; q < BT_PER_LANE; ++q) u[q] = un[q];
+    if (j > 0) load_u(j - 1);
+    const double2 tau = stau[j];
     if (tau.x == 0.0 && tau.y == 0.0) continue;
     const int j1 = j + 1;
-    double2 u[BT_PER_LANE];
     double dre = 0.0, dim_ = 0.0;
 #pragma unroll
     for (int q = 0; q < BT_PER_LANE; ++q) {
       int i = lane + 64 * q;
-      double2 uu = make_double2(0.0, 0.0);
-      if (i == j1) uu = make_double2(1.0, 0.0);
-      else if (i > j1 && i < n) uu = A[(long long)j * ld + i];
-      u[q] = uu;
-      double2 p = cmulc(uu, v[q]);
+      if (i == j1) u[q] = make_double2(1.0, 0.0);
+      double2 p = cmulc(u[q], v[q]);
       dre += p.x;
       dim_ += p.y;
     }
@@ -530,6 +702,7 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
 // Kept eigenvalues to a caller array (zero beyond the kept count).
 __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long kstride, void* wsbase, int nb, int kc,
                                   double* out, int ldo) {
+  (void)nexp;
   const int b = blockIdx.x;
   const int k = kin[b * kstride];
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
@@ -537,6 +710,8 @@ __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long ks
 }
 
 // ---------------------------------------------------------------- host
+
+ProfHook g_prof;
 
 size_t eig_ws_bytes(int n_bound, int kcap, int batch) {
   int kc = kcap < n_bound ? kcap : n_bound;
@@ -549,17 +724,38 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   if (nb < 1 || nb > EIG_NMAX || sp.batch < 1) return hipErrorInvalidValue;
   const int kc = sp.kcap < nb ? sp.kcap : nb;
   const double tau = sp.tau > 0.0 ? sp.tau : 1e-13;
-  hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TRI_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
-                     sp.n, sp.ws, nb, kc);
-  hipLaunchKernelGGL(eigvals_kernel, dim3((kc + 3) / 4, sp.batch), dim3(EV_NT), 0, s, sp.n, kc, sp.ws, nb, kc);
-  hipLaunchKernelGGL(keep_kernel, dim3((sp.batch + 63) / 64), dim3(64), 0, s, sp.n, kc, sp.cutoff, tau, sp.kout,
-                     sp.kstride, sp.ws, nb, kc, sp.batch, sp.status, sp.sigma_out);
-  hipLaunchKernelGGL(inviter_kernel, dim3((kc + 63) / 64, sp.batch), dim3(64), 0, s, sp.n, sp.kout, sp.kstride,
-                     sp.ws, nb, kc);
+  // profiled class: PROF_TRIDIAG = the streaming reduction (n > 128), the
+  // dominant kernel; PROF_TRIDIAG_LDS = the LDS-resident one (n <= 128)
+  const int cls = nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG;
+  const bool prof = g_prof.what == cls && g_prof.launches < g_prof.max_launches &&
+                    g_prof.slot + sp.batch <= g_prof.max;
+  if (prof) hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
+  int* nl = prof ? g_prof.nlog + g_prof.slot : (int*)nullptr;
+  if (nb <= TL_NMAX)
+    hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
+                       sp.n, sp.ws, nb, kc, nl);
+  else
+    hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TS_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
+                       sp.n, sp.ws, nb, kc, nl);
+  if (prof) {
+    hipEventRecord(g_prof.ev[2 * g_prof.launches + 1], s);
+    g_prof.launches++;
+    g_prof.slot += sp.batch;
+  }
+  hipLaunchKernelGGL(eigvals_kernel, dim3((kc + 3) / 4, sp.batch), dim3(EV_NT), 0, s, sp.n, kc, sp.ws, nb, kc,
+                     sp.kcap_dev);
+  hipLaunchKernelGGL(keep_kernel, dim3(sp.batch), dim3(KP_NT), 0, s, sp.n, kc, sp.cutoff, tau, sp.kout,
+                     sp.kstride, sp.ws, nb, kc, sp.batch, sp.status, sp.sigma_out, sp.kcap_dev);
+  const int vpw = iv_vpw(nb);
+  const size_t ivlds = (size_t)vpw * nb * 41;
+  hipLaunchKernelGGL(inviter_kernel, dim3((kc + vpw - 1) / vpw, sp.batch), dim3(64), ivlds, s, sp.n, sp.kout,
+                     sp.kstride, sp.ws, nb, kc, vpw);
   // inverse-iteration vectors are orthogonal to ~eps*||T||/gap: re-orthogonalise
-  // runs of eigenvalues closer than 1e-8 ||T||
+  // runs of eigenvalues closer than 1e-10 ||T|| (outside them the loss of
+  // orthogonality is <= ~1e-6 and confined to directions whose singular
+  // values are tiny relative to the largest)
   hipLaunchKernelGGL(cluster_kernel, dim3(sp.batch), dim3(CL_NT), 0, s, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc,
-                     1e-8);
+                     1e-10);
   EmitPack ep;
   ep.ne = sp.nemit;
   for (int i = 0; i < sp.nemit && i < 3; ++i) ep.e[i] = sp.emit[i];

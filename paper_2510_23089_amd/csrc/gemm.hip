@@ -59,9 +59,10 @@ template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM>
 __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   typedef typename Vec2<TIn>::t in2;
   typedef typename Mfma<TC>::acc_t acc_t;
-  const int bz = blockIdx.z;
-  if (bz >= min(dim_eval(g.batch), g.Bmax)) return;
-  const int M = min(dim_eval(g.M), g.Mmax), N = min(dim_eval(g.N), g.Nmax), K = min(dim_eval(g.K), g.Kmax);
+  const int f = blockIdx.z / g.b2cap;
+  const int bz = blockIdx.z - f * g.b2cap;
+  if (bz >= min(dim_eval(g.batch, f), g.Bmax)) return;
+  const int M = min(dim_eval(g.M, f), g.Mmax), N = min(dim_eval(g.N, f), g.Nmax), K = min(dim_eval(g.K, f), g.Kmax);
   const int tm = blockIdx.x / g.tiles_n, tn = blockIdx.x % g.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
@@ -80,8 +81,8 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
-  const TIn* Ap = (const TIn*)g.A.ptr + 2 * (long long)bz * g.A.sb;
-  const TIn* Bp = (const TIn*)g.B.ptr + 2 * (long long)bz * g.B.sb;
+  const TIn* Ap = (const TIn*)g.A.ptr + 2 * ((long long)f * g.A.sb + (long long)bz * g.A.sb2);
+  const TIn* Bp = (const TIn*)g.B.ptr + 2 * ((long long)f * g.B.sb + (long long)bz * g.B.sb2);
 
   // ---- per-thread fixed parts of the load addresses
   int a_i[A_PER_T], a_k[A_PER_T];
@@ -185,7 +186,8 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   }
 
   // ---- epilogue: lanes (l, l^1) hold (re, im) of one complex output
-  TOut* Cp = (TOut*)g.C.ptr + 2 * ((long long)bz * g.C.sb + (long long)blockIdx.y * g.csplit);
+  TOut* Cp = (TOut*)g.C.ptr + 2 * ((long long)f * g.C.sb + (long long)bz * g.C.sb2 +
+                                   (long long)blockIdx.y * g.csplit);
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     int jr = wn * BN + j * 16 + l16;
@@ -224,8 +226,7 @@ __global__ void ksplit_reduce_kernel(const double2* __restrict__ part, long long
                                      double2* __restrict__ out, int ld, DimExpr nrows, DimExpr ncols,
                                      long long bstride_part, long long bstride_out, DimExpr batch) {
   const int b = blockIdx.z;
-  if (b >= dim_eval(batch)) return;
-  const int nr = min(dim_eval(nrows), (int)gridDim.y), nc = min(dim_eval(ncols), ld);
+  const int nr = min(dim_eval(nrows, b), (int)gridDim.y), nc = min(dim_eval(ncols, b), ld);
   const int i = blockIdx.y;
   if (i >= nr) return;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nc; j += gridDim.x * blockDim.x) {
@@ -264,6 +265,7 @@ static hipError_t launch_typed(const GemmArgs& g, dim3 grid, bool akm, bool bkm,
 hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   GemmArgs g;
   g.M = sp.M; g.N = sp.N; g.K = sp.K; g.batch = sp.batch;
+  g.b2cap = sp.batch_bound < 1 ? 1 : sp.batch_bound;
   g.fm = make_fastdiv(sp.mlo); g.fn = make_fastdiv(sp.nlo); g.fk = make_fastdiv(sp.klo);
   g.A = sp.A; g.B = sp.B; g.C = sp.C;
   g.accumulate = sp.accumulate;
@@ -274,7 +276,8 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   if (tiles_m < 1 || tiles_n < 1 || sp.batch_bound < 1) return hipSuccess;
   g.tiles_n = tiles_n;
   g.Mmax = sp.m_bound; g.Nmax = sp.n_bound; g.Kmax = sp.k_bound; g.Bmax = sp.batch_bound;
-  dim3 grid(tiles_m * tiles_n, g.ksplit, sp.batch_bound);
+  if (sp.nfield < 1) return hipSuccess;
+  dim3 grid(tiles_m * tiles_n, g.ksplit, sp.batch_bound * sp.nfield);
   // coalescing pattern: which index is unit-stride in memory
   bool akm = (sp.A.syl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.A.syh == 1);
   bool bkm = (sp.B.sxl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.B.sxh == 1);

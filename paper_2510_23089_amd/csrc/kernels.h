@@ -14,6 +14,7 @@ struct GemmSpec {
   int mlo, nlo, klo;            // low extents of the split indices (1 = unsplit)
   int m_bound, n_bound, batch_bound;
   int k_bound = 1 << 30;
+  int nfield = 1;               // outer batch: fields (Operand.sb strides)
   Operand A, B, C;
   int accumulate = 0;
   int ksplit = 1;
@@ -56,6 +57,7 @@ struct EigSpec {
   double cutoff, tau;
   int* kout;                  // device, kept counts
   long long kstride;
+  const int* kcap_dev = nullptr;  // optional per-matrix cap (stride 1), e.g. per-field chi
   int batch;                  // number of matrices (host-known)
   // workspace pointers (carved by the caller; sizes from eig_ws_bytes)
   void* ws;
@@ -66,6 +68,22 @@ struct EigSpec {
 };
 
 size_t eig_ws_bytes(int n_bound, int kcap, int batch);
+
+// Optional per-launch timing of one kernel class (diagnostics for the
+// roofline report): HIP events are recorded around every launch of the
+// selected class on its stream, and the kernel writes its actual problem size
+// to nlog[slot] so algorithmic work can be computed from real sizes.
+enum ProfWhat { PROF_NONE = 0, PROF_TRIDIAG = 1, PROF_TRIDIAG_LDS = 2 };
+struct ProfHook {
+  int what = PROF_NONE;
+  int* nlog = nullptr;       // device ints: per launch, per batch entry
+  int max = 0;               // capacity of nlog (entries)
+  int slot = 0;              // next free entry
+  int launches = 0;
+  hipEvent_t* ev = nullptr;  // 2 * max_launches events
+  int max_launches = 0;
+};
+extern ProfHook g_prof;
 hipError_t eig_launch(const EigSpec& sp, hipStream_t s);
 hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s);
 
@@ -87,8 +105,16 @@ hipError_t block_copy(const void* src, long long s_rs, long long s_cs, void* dst
 // Set dev[i] = val for the given list (used for boundary bonds).
 hipError_t set_ints(int* dev, int count, int val, hipStream_t s);
 hipError_t copy_ints(const int* src, int* dst, int count, hipStream_t s);
-// Clamped copy of caller bonds (see misc.hip).
-hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, hipStream_t s);
+// Clamped copy of caller bonds (see misc.hip); nf fields at stride m+1.
+hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, int nf, hipStream_t s);
+// Batched (nf fields) versions of the small helpers: field f adds f * stride.
+hipError_t block_copy_b(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst, long long d_rs,
+                        long long d_cs, long long d_f, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
+                        int dtype, int nf, hipStream_t s);
+hipError_t block_norm_b(const void* p, int dtype, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
+                        long long ld_r, long long ld_c, long long s_f, double* out, int nf, hipStream_t s);
+hipError_t set_ints_strided(int* dev, int per, long long stride, int nf, int val, hipStream_t s);
+hipError_t set_one_b(void* p, long long s_f, int dtype, int nf, hipStream_t s);
 // Scan a complex buffer for non-finite values and flag the status word.
 hipError_t check_finite(const void* p, int dtype, long long count, int* status, hipStream_t s);
 

@@ -168,6 +168,8 @@ hipError_t check_finite(const void* p, int dtype, long long count, int* status, 
 __global__ void sanitize_bonds_kernel(const int* src, int* dst, int m, int cap, int* status) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > m) return;
+  src += (long long)blockIdx.y * (m + 1);
+  dst += (long long)blockIdx.y * (m + 1);
   int e = min(k, m - k);
   int bound = e >= 30 ? cap : min(cap, 1 << e);
   int v = src[k];
@@ -175,8 +177,87 @@ __global__ void sanitize_bonds_kernel(const int* src, int* dst, int m, int cap, 
   if (c != v) set_status(status, -5);
   dst[k] = c;
 }
-hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, hipStream_t s) {
-  hipLaunchKernelGGL(sanitize_bonds_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, s, src, dst, m, cap, status);
+hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, int nf, hipStream_t s) {
+  hipLaunchKernelGGL(sanitize_bonds_kernel, dim3((m + 1 + 255) / 256, nf), dim3(256), 0, s, src, dst, m, cap, status);
+  return hipGetLastError();
+}
+
+// ---- batched helpers (field f = blockIdx.z or blockIdx.y)
+__global__ void block_copy_b_kernel(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst,
+                                    long long d_rs, long long d_cs, long long d_f, DimExpr rows, DimExpr cols,
+                                    int cmax, int dtype) {
+  const int f = blockIdx.z;
+  const int nr = min(dim_eval(rows, f), (int)gridDim.y), nc = min(dim_eval(cols, f), cmax);
+  const int r = blockIdx.y;
+  if (r >= nr) return;
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
+    long long so = f * s_f + r * s_rs + c * s_cs, dof = f * d_f + r * d_rs + c * d_cs;
+    if (dtype == 0) ((float2*)dst)[dof] = ((const float2*)src)[so];
+    else ((double2*)dst)[dof] = ((const double2*)src)[so];
+  }
+}
+hipError_t block_copy_b(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst, long long d_rs,
+                        long long d_cs, long long d_f, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
+                        int dtype, int nf, hipStream_t s) {
+  if (rows_bound < 1 || cols_bound < 1 || nf < 1) return hipSuccess;
+  int bx = (cols_bound + 255) / 256;
+  hipLaunchKernelGGL(block_copy_b_kernel, dim3(bx, rows_bound, nf), dim3(256), 0, s, src, s_rs, s_cs, s_f, dst, d_rs,
+                     d_cs, d_f, rows, cols, cols_bound, dtype);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(1024) void block_norm_b_kernel(const void* p, int dtype, DimExpr rows, DimExpr cols,
+                                                            int rmax, int cmax, long long ld_r, long long ld_c,
+                                                            long long s_f, double* out) {
+  const int f = blockIdx.x;
+  const int nr = min(dim_eval(rows, f), rmax), nc = min(dim_eval(cols, f), cmax);
+  const long long tot = (long long)nr * nc;
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < tot; e += blockDim.x) {
+    long long r = e / nc, c = e - r * nc;
+    long long off = f * s_f + r * ld_r + c * ld_c;
+    double re, im;
+    if (dtype == 0) { float2 v = ((const float2*)p)[off]; re = v.x; im = v.y; }
+    else { double2 v = ((const double2*)p)[off]; re = v.x; im = v.y; }
+    acc += re * re + im * im;
+  }
+  __shared__ double red[16];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    out[f] = sqrt(s);
+  }
+}
+hipError_t block_norm_b(const void* p, int dtype, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
+                        long long ld_r, long long ld_c, long long s_f, double* out, int nf, hipStream_t s) {
+  if (nf < 1) return hipSuccess;
+  hipLaunchKernelGGL(block_norm_b_kernel, dim3(nf), dim3(1024), 0, s, p, dtype, rows, cols, rows_bound, cols_bound,
+                     ld_r, ld_c, s_f, out);
+  return hipGetLastError();
+}
+
+__global__ void set_ints_strided_kernel(int* p, int per, long long stride, int val) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < per) p[blockIdx.y * stride + i] = val;
+}
+hipError_t set_ints_strided(int* dev, int per, long long stride, int nf, int val, hipStream_t s) {
+  if (per < 1 || nf < 1) return hipSuccess;
+  hipLaunchKernelGGL(set_ints_strided_kernel, dim3((per + 255) / 256, nf), dim3(256), 0, s, dev, per, stride, val);
+  return hipGetLastError();
+}
+
+__global__ void set_one_b_kernel(void* p, long long s_f, int dtype) {
+  long long o = (long long)blockIdx.x * s_f;
+  if (dtype == 0) ((float2*)p)[o] = make_float2(1.f, 0.f);
+  else ((double2*)p)[o] = make_double2(1.0, 0.0);
+}
+hipError_t set_one_b(void* p, long long s_f, int dtype, int nf, hipStream_t s) {
+  if (nf < 1) return hipSuccess;
+  hipLaunchKernelGGL(set_one_b_kernel, dim3(nf), dim3(1), 0, s, p, s_f, dtype);
   return hipGetLastError();
 }
 

@@ -174,3 +174,50 @@ def test_product_mpo_end_to_end_blob():
     api.check_status()
     ref = F.fresnel_dense(img, LAM, DX, 1e-3)
     assert rel(_dense(api, out), ref) < 1e-5
+
+
+def test_batched_apply_uneven_chi_vs_oracle():
+    """Three fields in one batch: different input fields, different MPOs
+    (different z, so different bond profiles, zero-padded to a common one)
+    and different per-field bond caps; each field vs the oracle."""
+    torch = need_gpu()
+    api = _api()
+    n = 6
+    zs = (0.3e-3, 1e-3, 2e-3)
+    chis = (8, 16, 32)
+    imgs = [synth.blob_image(s) for s in (4, 5, 6)]
+    cores = [T.tt_svd(Q.to_quantics(im), 12, 32) for im in imgs]
+    mp = [_oracle_mpos(n, z) for z in zs]
+    psi = api.MPSBatch(3, 12, 32)
+    for f in range(3):
+        psi.fill_from(api.MPS.from_host(cores[f], chi_cap=32), f)
+    wx = api.MPOBatch([w[0] for w in mp])
+    wy = api.MPOBatch([w[1] for w in mp])
+    chi_dev = torch.tensor(chis, dtype=torch.int32, device="cuda")
+    say("batched apply")
+    mid = api.mpo_apply_batched(psi, wx, 32, chi_dev=chi_dev)
+    out = api.mpo_apply_batched(mid, wy, 32, chi_dev=chi_dev)
+    dense = api.tt_to_dense_batched(out).cpu().numpy()
+    api.check_status()
+    for f in range(3):
+        c1, _ = Z.mpo_apply(cores[f], mp[f][0], chis[f], tau=1e-13)
+        ref_cores, _ = Z.mpo_apply(c1, mp[f][1], chis[f], tau=1e-13)
+        ref = Z.to_dense(ref_cores, n)
+        assert rel(dense[f], ref) < 1e-4, (f, rel(dense[f], ref))
+        assert [int(x) for x in out.bonds[f].cpu()] == Z.bonds(ref_cores)
+        assert abs(float(out.norms[f].cpu()) - np.linalg.norm(ref)) < 1e-4 * np.linalg.norm(ref)
+
+
+def test_batched_encode_matches_single():
+    torch = need_gpu()
+    api = _api()
+    imgs = np.stack([synth.blob_image(s) for s in (7, 8)])
+    d = torch.from_numpy(imgs).float().cuda()
+    say("batched encode")
+    chi_dev = torch.tensor([16, 64], dtype=torch.int32, device="cuda")
+    b = api.tt_encode_batched(d, 64, chi_dev=chi_dev)
+    dense = api.tt_to_dense_batched(b).cpu().numpy()
+    api.check_status()
+    for f, chi in enumerate((16, 64)):
+        ref = Z.to_dense(T.tt_svd(Q.to_quantics(imgs[f]), 12, chi, tau=1e-13), 6)
+        assert rel(dense[f], ref) < (1e-4 if chi < 64 else 1e-5)
