@@ -79,7 +79,8 @@ enum qtt_dtype { QTT_C64 = 1, QTT_C128 = 2, QTT_F32 = 3, QTT_F64 = 4 };
 enum qtt_prec { QTT_PREC_FP32 = 0, QTT_PREC_BF16 = 1, QTT_PREC_FP64 = 2 };
 enum qtt_op {
   QTT_OP_ENCODE = 1, QTT_OP_APPLY = 2, QTT_OP_TRUNCATE = 3,
-  QTT_OP_TO_DENSE = 4, QTT_OP_APPLY_BACKWARD = 5
+  QTT_OP_TO_DENSE = 4, QTT_OP_APPLY_BACKWARD = 5, QTT_OP_TO_DENSE_BACKWARD = 6,
+  QTT_OP_LOSS = 7
 };
 
 typedef struct {
@@ -173,7 +174,7 @@ int mpo_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts,
 int tt_encode_batched(const void* img, int img_dtype, int log2_side, const qtt_opts* opts, const int32_t* chi_dev,
                       qtt_mps_batch* out, void* ws, size_t ws_bytes, void* stream);
 int mpo_apply_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt_opts* opts, const int32_t* chi_dev,
-                      qtt_mps_batch* out, void* ws, size_t ws_bytes, void* stream);
+                      qtt_mps_batch* out, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream);
 int tt_to_dense_batched(const qtt_mps_batch* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream);
 
 /* Recompress an MPS in place: QR sweep right to left, then SVD sweep left to
@@ -184,25 +185,55 @@ int tt_truncate(qtt_mps* inout, const qtt_opts* opts, void* ws, size_t ws_bytes,
  * the MPS represents (Sec. 3, decompression in Fig. 6). */
 int tt_to_dense(const qtt_mps* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream);
 
-/* Bytes of the `saved` buffer mpo_apply needs for a later backward call. */
+/* Bytes of the `saved` buffer mpo_apply / mpo_apply_batched need for a later
+ * backward call (capacity bound for chi_zip <= chi_cap; the call itself
+ * checks the exact requirement).  The buffer receives the bonds chosen by the
+ * forward call, the zip-up cores, the carry entering each zip-up site and the
+ * centre entering each sweep step. */
 size_t tt_saved_size(int n_sites, int chi_cap, int d_cap, int prec);
+size_t tt_saved_size_batched(int count, int n_sites, int chi_cap, int d_cap, int prec);
 
-/* Adjoint of mpo_apply.  Given the forward input `in`, the operator W, the
- * options used forward, the `saved` buffer filled by the forward call, the
- * forward output `out` (its cores and bonds) and grad_out (same layout and
- * bonds as out; PyTorch convention for a real loss L: dL/dRe + i dL/dIm),
- * writes grad_in (same layout and bonds as in).  The truncated eigen/SVD
- * steps are differentiated at fixed kept ranks; each site's forward
- * intermediates are recomputed from the saved carries. */
+/* Adjoint of mpo_apply (vector-Jacobian product), for gradient-based inverse
+ * problems such as phase retrieval (the paper's outlook, Sec. 7).  Given the
+ * forward input `in`, the operator W, the options used forward, the `saved`
+ * buffer the forward call filled, the forward output `out` (cores and bonds)
+ * and grad_out (same shape as out; PyTorch convention for a real loss L:
+ * dL/dRe + i dL/dIm), writes grad_in (same shape as in; padding zeroed,
+ * bonds = the forward input bonds).  Each truncation is differentiated at the
+ * forward's kept ranks through the FP64 eigen-decomposition of its Gram
+ * matrix, recomputed from the saved per-site inputs; the contribution of
+ * rotations inside a kept block is omitted (it vanishes for every function of
+ * the decompressed field).  Valid for cotangents of such functions (e.g. the
+ * output of tt_to_dense_backward).  Workspace: tt_workspace_size(
+ * QTT_OP_APPLY_BACKWARD, ...).  The adjoint eigenproblems are at most
+ * 2*chi in size and must not exceed 512. */
 int mpo_apply_backward(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts,
                        const void* saved, size_t saved_bytes,
                        const qtt_mps* out, const qtt_mps* grad_out, qtt_mps* grad_in,
                        void* ws, size_t ws_bytes, void* stream);
+int mpo_apply_backward_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt_opts* opts,
+                               const void* saved, size_t saved_bytes,
+                               const qtt_mps_batch* out, const qtt_mps_batch* grad_out,
+                               qtt_mps_batch* grad_in, void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint of tt_to_dense: grad_dense (device row-major N x N complex, same
- * dtype as the MPS) -> grad (same layout and bonds as in). */
+ * dtype as the MPS; count fields back to back for the batched form) -> grad
+ * (same shape as in; padding zeroed, bonds = the input bonds).  Workspace:
+ * tt_workspace_size(QTT_OP_TO_DENSE_BACKWARD, ...). */
 int tt_to_dense_backward(const qtt_mps* in, const void* grad_dense, qtt_mps* grad,
                          void* ws, size_t ws_bytes, void* stream);
+int tt_to_dense_backward_batched(const qtt_mps_batch* in, const void* grad_dense, qtt_mps_batch* grad,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* Intensity loss of the phase-retrieval objective, per field f of `count`
+ * N x N fields (N = 2^log2_side) stored back to back:
+ *     loss[f] = sum_px (|E|^2 - I_target)^2      (device doubles),
+ * and, if grad is non-NULL, grad = dL/dRe + i dL/dIm = 4 (|E|^2 - I) E in the
+ * field's layout.  dtype QTT_C64 (target float) or QTT_C128 (target double).
+ * Workspace: tt_workspace_size_batched(QTT_OP_LOSS, count, ...) bytes (only
+ * the count matters); fixed-order reduction, so results are reproducible. */
+int tt_intensity_loss(const void* field, const void* target, int dtype, int log2_side, int count,
+                      double* loss, void* grad, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- auxiliary entry points (the building blocks of the calls above) ---- */
 

@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libqtt.so")
 QTT_C64, QTT_C128, QTT_F32, QTT_F64 = 1, 2, 3, 4
 PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
 OP_ENCODE, OP_APPLY, OP_TRUNCATE, OP_TO_DENSE, OP_APPLY_BACKWARD = 1, 2, 3, 4, 5
+OP_TO_DENSE_BACKWARD, OP_LOSS = 6, 7
 
 STATUS = {
     0: "QTT_OK", -1: "QTT_ERR_ARG", -2: "QTT_ERR_SHAPE", -3: "QTT_ERR_DTYPE",
@@ -26,6 +27,7 @@ EXPORTS = [
     "tt_check_status", "tt_last_error", "tt_version",
     "tt_cgemm", "tt_heev_workspace_size", "tt_heev", "tt_prof_begin", "tt_prof_end",
     "tt_workspace_size_batched", "tt_encode_batched", "mpo_apply_batched", "tt_to_dense_batched",
+    "tt_saved_size_batched", "mpo_apply_backward_batched", "tt_to_dense_backward_batched", "tt_intensity_loss",
 ]
 
 
@@ -106,8 +108,18 @@ def load(path=LIB_PATH):
     lib.tt_workspace_size_batched.restype = sz
     lib.tt_encode_batched.argtypes = [vp, i32, i32, P(QttOpts), vp, P(QttMpsBatch), vp, sz, vp]
     lib.tt_encode_batched.restype = i32
-    lib.mpo_apply_batched.argtypes = [P(QttMpsBatch), P(QttMpoBatch), P(QttOpts), vp, P(QttMpsBatch), vp, sz, vp]
+    lib.mpo_apply_batched.argtypes = [P(QttMpsBatch), P(QttMpoBatch), P(QttOpts), vp, P(QttMpsBatch), vp, sz, vp, sz,
+                                      vp]
     lib.mpo_apply_batched.restype = i32
+    lib.tt_saved_size_batched.argtypes = [i32, i32, i32, i32, i32]
+    lib.tt_saved_size_batched.restype = sz
+    lib.mpo_apply_backward_batched.argtypes = [P(QttMpsBatch), P(QttMpoBatch), P(QttOpts), vp, sz, P(QttMpsBatch),
+                                               P(QttMpsBatch), P(QttMpsBatch), vp, sz, vp]
+    lib.mpo_apply_backward_batched.restype = i32
+    lib.tt_to_dense_backward_batched.argtypes = [P(QttMpsBatch), vp, P(QttMpsBatch), vp, sz, vp]
+    lib.tt_to_dense_backward_batched.restype = i32
+    lib.tt_intensity_loss.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
+    lib.tt_intensity_loss.restype = i32
     lib.tt_to_dense_batched.argtypes = [P(QttMpsBatch), vp, i32, vp, sz, vp]
     lib.tt_to_dense_batched.restype = i32
     lib.tt_check_status.argtypes = [vp, vp]
@@ -116,10 +128,6 @@ def load(path=LIB_PATH):
     lib.tt_last_error.restype = ctypes.c_char_p
     lib.tt_version.argtypes = []
     lib.tt_version.restype = ctypes.c_char_p
-    for name in ("tt_apply_workspace_size", "tt_batch_workspace_size", "tt_propagate_batched",
-                 "tt_apply_backward_workspace_size", "tt_refine_workspace_size", "tt_refine"):
-        if hasattr(lib, name):
-            getattr(lib, name).restype = sz if name.endswith("size") else i32
     _lib = lib
     return lib
 

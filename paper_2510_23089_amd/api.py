@@ -80,6 +80,17 @@ class MPS:
         return [int(x) for x in self.bonds.cpu().numpy()]
 
     @classmethod
+    def wrap(cls, cores, bonds, norm=None):
+        """View existing device tensors (cores (m, cap, 2, cap), bonds (m+1,) int32) as an MPS."""
+        obj = cls.__new__(cls)
+        obj.n_sites = int(cores.shape[0])
+        obj.chi_cap = int(cores.shape[1])
+        obj.cores = cores
+        obj.bonds = bonds
+        obj.norm = norm if norm is not None else torch.zeros(1, dtype=torch.float64, device=cores.device)
+        return obj
+
+    @classmethod
     def from_host(cls, cores, chi_cap=None, dtype=torch.complex64, device="cuda"):
         m = len(cores)
         cap = chi_cap or max(max(c.shape[0], c.shape[2]) for c in cores)
@@ -162,19 +173,67 @@ def tt_encode(img, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None
     return out
 
 
-def mpo_apply(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_cap=None):
+def _cap(psi, out, chi, chi_zip):
+    return max(psi.chi_cap, out.chi_cap, int(chi_zip or 0), int(chi))
+
+
+def saved_buffer(psi, mpo, chi, chi_zip=0, out_cap=None):
+    """Device buffer for what a forward application keeps for its adjoint."""
+    lib = L.load()
+    cap = max(psi.chi_cap, int(out_cap or chi), int(chi_zip or 0), int(chi))
+    prec = L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32
+    count = getattr(psi, "count", None)
+    if count is None:
+        nb = lib.tt_saved_size(psi.n_sites, cap, mpo.d_cap, prec)
+    else:
+        nb = lib.tt_saved_size_batched(count, psi.n_sites, cap, mpo.d_cap, prec)
+    return torch.empty(max(int(nb), 256), dtype=torch.uint8, device=psi.cores.device)
+
+
+def mpo_apply(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_cap=None, saved=None):
     lib = L.load()
     prec = psi.prec
     if out is None:
         out = MPS(psi.n_sites, chi_cap or chi, dtype=psi.dtype, device=psi.cores.device)
     o = _opts(chi, chi_zip, cutoff, tau, prec)
-    cap = max(psi.chi_cap, out.chi_cap, int(chi_zip or 0), int(chi))
-    nb = lib.tt_workspace_size(L.OP_APPLY, psi.n_sites, cap, mpo.d_cap, o.prec)
+    nb = lib.tt_workspace_size(L.OP_APPLY, psi.n_sites, _cap(psi, out, chi, chi_zip), mpo.d_cap, o.prec)
     ws = workspace(nb, psi.cores.device)
     si, so, w = psi.cstruct(), out.cstruct(), mpo.cstruct()
-    L.check(lib.mpo_apply(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), ctypes.byref(so), None, 0,
+    sp, sn = (_ptr(saved), saved.numel()) if saved is not None else (None, 0)
+    L.check(lib.mpo_apply(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), ctypes.byref(so), sp, sn,
                           _ptr(ws), nb, _stream()), "mpo_apply")
     return out
+
+
+def mpo_apply_backward(psi, mpo, chi, saved, out, grad_out, chi_zip=0, cutoff=0.0, tau=0.0, grad_in=None):
+    """Vector-Jacobian product of mpo_apply at psi (cotangent grad_out on the
+    output cores); returns the gradient on psi's cores as an MPS."""
+    lib = L.load()
+    if grad_in is None:
+        grad_in = MPS(psi.n_sites, psi.chi_cap, dtype=psi.dtype, device=psi.cores.device)
+    o = _opts(chi, chi_zip, cutoff, tau, psi.prec)
+    nb = lib.tt_workspace_size(L.OP_APPLY_BACKWARD, psi.n_sites, _cap(psi, out, chi, chi_zip), mpo.d_cap, o.prec)
+    ws = workspace(nb, psi.cores.device, key="backward")
+    si, w, so, sg, sgi = psi.cstruct(), mpo.cstruct(), out.cstruct(), grad_out.cstruct(), grad_in.cstruct()
+    L.check(lib.mpo_apply_backward(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), _ptr(saved), saved.numel(),
+                                   ctypes.byref(so), ctypes.byref(sg), ctypes.byref(sgi), _ptr(ws), nb, _stream()),
+            "mpo_apply_backward")
+    return grad_in
+
+
+def tt_to_dense_backward(psi, grad_dense, grad=None):
+    """Gradient on psi's cores of a real loss given its gradient on the dense field."""
+    lib = L.load()
+    if grad is None:
+        grad = MPS(psi.n_sites, psi.chi_cap, dtype=psi.dtype, device=psi.cores.device)
+    prec = L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32
+    nb = lib.tt_workspace_size(L.OP_TO_DENSE_BACKWARD, psi.n_sites, psi.chi_cap, 1, prec)
+    ws = workspace(nb, psi.cores.device, key="dense_bwd")
+    s, sg = psi.cstruct(), grad.cstruct()
+    gd = grad_dense.to(psi.dtype).contiguous()
+    L.check(lib.tt_to_dense_backward(ctypes.byref(s), _ptr(gd), ctypes.byref(sg), _ptr(ws), nb, _stream()),
+            "tt_to_dense_backward")
+    return grad
 
 
 def tt_truncate(psi, chi, cutoff=0.0, tau=0.0):
@@ -230,6 +289,18 @@ class MPSBatch:
         s.bonds = self.bonds.data_ptr()
         s.norms = self.norms.data_ptr()
         return s
+
+    @classmethod
+    def wrap(cls, cores, bonds, norms=None):
+        """View existing device tensors (cores (count, m, cap, 2, cap), bonds (count, m+1)) as a batch."""
+        obj = cls.__new__(cls)
+        obj.count = int(cores.shape[0])
+        obj.n_sites = int(cores.shape[1])
+        obj.chi_cap = int(cores.shape[2])
+        obj.cores = cores
+        obj.bonds = bonds
+        obj.norms = norms if norms is not None else torch.zeros(obj.count, dtype=torch.float64, device=cores.device)
+        return obj
 
     def fill_from(self, psi, index=None):
         """Copy a single MPS (same n_sites, chi_cap <= ours) into one or all fields (device copy)."""
@@ -288,18 +359,71 @@ class MPOBatch:
         return s
 
 
-def mpo_apply_batched(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_dev=None, chi_cap=None):
+def mpo_apply_batched(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_dev=None, chi_cap=None,
+                      saved=None):
     lib = L.load()
     if out is None:
         out = MPSBatch(psi.count, psi.n_sites, chi_cap or chi, dtype=psi.dtype, device=psi.cores.device)
     o = _opts(chi, chi_zip, cutoff, tau, psi.prec)
-    cap = max(psi.chi_cap, out.chi_cap, int(chi_zip or 0), int(chi))
-    nb = lib.tt_workspace_size_batched(L.OP_APPLY, psi.count, psi.n_sites, cap, mpo.d_cap, o.prec)
+    nb = lib.tt_workspace_size_batched(L.OP_APPLY, psi.count, psi.n_sites, _cap(psi, out, chi, chi_zip), mpo.d_cap,
+                                       o.prec)
     ws = workspace(nb, psi.cores.device)
     si, so, w = psi.cstruct(), out.cstruct(), mpo.cstruct()
+    sp, sn = (_ptr(saved), saved.numel()) if saved is not None else (None, 0)
     L.check(lib.mpo_apply_batched(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), _ptr(chi_dev),
-                                  ctypes.byref(so), _ptr(ws), nb, _stream()), "mpo_apply_batched")
+                                  ctypes.byref(so), sp, sn, _ptr(ws), nb, _stream()), "mpo_apply_batched")
     return out
+
+
+def mpo_apply_backward_batched(psi, mpo, chi, saved, out, grad_out, chi_zip=0, cutoff=0.0, tau=0.0, grad_in=None):
+    lib = L.load()
+    if grad_in is None:
+        grad_in = MPSBatch(psi.count, psi.n_sites, psi.chi_cap, dtype=psi.dtype, device=psi.cores.device)
+    o = _opts(chi, chi_zip, cutoff, tau, psi.prec)
+    nb = lib.tt_workspace_size_batched(L.OP_APPLY_BACKWARD, psi.count, psi.n_sites, _cap(psi, out, chi, chi_zip),
+                                       mpo.d_cap, o.prec)
+    ws = workspace(nb, psi.cores.device, key="backward")
+    si, w, so, sg, sgi = psi.cstruct(), mpo.cstruct(), out.cstruct(), grad_out.cstruct(), grad_in.cstruct()
+    L.check(lib.mpo_apply_backward_batched(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), _ptr(saved),
+                                           saved.numel(), ctypes.byref(so), ctypes.byref(sg), ctypes.byref(sgi),
+                                           _ptr(ws), nb, _stream()), "mpo_apply_backward_batched")
+    return grad_in
+
+
+def tt_to_dense_backward_batched(psi, grad_dense, grad=None):
+    lib = L.load()
+    if grad is None:
+        grad = MPSBatch(psi.count, psi.n_sites, psi.chi_cap, dtype=psi.dtype, device=psi.cores.device)
+    prec = L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32
+    nb = lib.tt_workspace_size_batched(L.OP_TO_DENSE_BACKWARD, psi.count, psi.n_sites, psi.chi_cap, 1, prec)
+    ws = workspace(nb, psi.cores.device, key="dense_bwd")
+    s, sg = psi.cstruct(), grad.cstruct()
+    gd = grad_dense.to(psi.dtype).contiguous()
+    L.check(lib.tt_to_dense_backward_batched(ctypes.byref(s), _ptr(gd), ctypes.byref(sg), _ptr(ws), nb, _stream()),
+            "tt_to_dense_backward_batched")
+    return grad
+
+
+def intensity_loss(field, target, with_grad=True):
+    """Per-field loss sum (|E|^2 - I)^2 of (count, N, N) or (N, N) fields and
+    its gradient 4 (|E|^2 - I) E; returns (loss float64 tensor (count,), grad or None)."""
+    lib = L.load()
+    f = field if field.dim() == 3 else field.unsqueeze(0)
+    f = f.contiguous()
+    count, side = int(f.shape[0]), int(f.shape[1])
+    n = side.bit_length() - 1
+    real_t = torch.float64 if f.dtype == torch.complex128 else torch.float32
+    t = target.to(real_t).reshape(f.shape).contiguous()
+    dt = L.QTT_C128 if f.dtype == torch.complex128 else L.QTT_C64
+    loss = torch.empty(count, dtype=torch.float64, device=f.device)
+    grad = torch.empty_like(f) if with_grad else None
+    nb = lib.tt_workspace_size_batched(L.OP_LOSS, count, 2, 1, 1, L.PREC_FP32)
+    ws = workspace(nb, f.device, key="loss")
+    L.check(lib.tt_intensity_loss(_ptr(f), _ptr(t), dt, n, count, _ptr(loss), _ptr(grad), _ptr(ws), nb, _stream()),
+            "tt_intensity_loss")
+    if field.dim() == 2 and grad is not None:
+        grad = grad[0]
+    return loss, grad
 
 
 def tt_encode_batched(imgs, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None, chi_dev=None):

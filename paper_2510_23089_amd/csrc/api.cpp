@@ -125,12 +125,13 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
 }
 
 int gemm(Ctx& c, DimExpr M, int mlo, int mb, DimExpr N, int nlo, int nb, DimExpr K, int klo, const Operand& A,
-         const Operand& B, const Operand& C, DimExpr batch = dx(1), int batch_bound = 1) {
+         const Operand& B, const Operand& C, DimExpr batch = dx(1), int batch_bound = 1, int accumulate = 0) {
   GemmSpec g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.mlo = mlo; g.nlo = nlo; g.klo = klo;
   g.m_bound = mb; g.n_bound = nb; g.batch_bound = batch_bound; g.nfield = c.nf;
   g.A = A; g.B = B; g.C = C;
+  g.accumulate = accumulate;
   g.types = c.gemm_t;
   HIPCHK(gemm_launch(g, c.s));
   return QTT_OK;
@@ -143,7 +144,8 @@ EigEmit emit(void* p, int lo, ll s_hi, ll s_lo, ll s_col, int conj, int pow, int
   return e;
 }
 
-int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kout, std::initializer_list<EigEmit> em) {
+int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kout, std::initializer_list<EigEmit> em,
+        EigSpec* spec_out = nullptr) {
   EigSpec e;
   e.G = c.G; e.ld = c.gld; e.gstride = (ll)c.gld * c.gld;
   e.n = n; e.n_bound = nb;
@@ -159,6 +161,7 @@ int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kou
   e.sigma_out = nullptr;
   if (nb > c.eig_nb) return fail(QTT_ERR_WORKSPACE, "eig size %d exceeds workspace bound %d", nb, c.eig_nb);
   HIPCHK(eig_launch(e, c.s));
+  if (spec_out) *spec_out = e;
   return QTT_OK;
 }
 
@@ -259,6 +262,38 @@ ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   return b;
 }
 
+// What a forward application keeps for its adjoint (caller-owned `saved`
+// buffer): the bonds it chose, the zip-up cores, the carry entering every
+// zip-up site and the centre entering every sweep step.  Slot k of the carries
+// and centres holds all fields (field stride as in the workspace).
+struct SavedBufs {
+  int* inb;
+  int* zbonds;
+  void* Z;
+  void* C;
+  void* N;
+  ll sZ, sC, sCtr;
+};
+
+SavedBufs carve_saved(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
+  Carver dry(nullptr);
+  ApplyBufs t = carve_apply(dry, p, csz, nf);
+  SavedBufs v;
+  v.sZ = t.sZ; v.sC = t.sC; v.sCtr = t.sCtr;
+  v.inb = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
+  v.zbonds = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
+  v.Z = cv.take(nf * v.sZ * csz);
+  v.C = cv.take((size_t)p.m * nf * v.sC * csz);
+  v.N = cv.take((size_t)p.m * nf * v.sCtr * csz);
+  return v;
+}
+
+size_t saved_bytes(const ApplyPlan& p, size_t csz, int nf) {
+  Carver cv(nullptr);
+  carve_saved(cv, p, csz, nf);
+  return cv.off;
+}
+
 // Internal batched views (a single MPS is a batch of one).
 struct MpsB {
   int nf, m, cap, dtype;
@@ -327,7 +362,12 @@ Ctx make_ctx(hipStream_t s, int real, int nf, int m, int* status) {
 
 // ------------------------------------------------------------ zip-up + sweep
 int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out, const ApplyPlan& p, ApplyBufs& b,
-              const int* chi_dev, hipStream_t s) {
+              const int* chi_dev, const SavedBufs* sv, hipStream_t s) {
+  if (sv) {                      // keep bonds and zip cores in the saved buffer
+    b.inb = sv->inb;
+    b.zbonds = sv->zbonds;
+    b.Z = sv->Z;
+  }
   const int m = p.m, nf = in.nf;
   const int real = in.dtype == QTT_C128 ? 1 : 0;
   Ctx c = make_ctx(s, real, nf, m, b.status);
@@ -345,12 +385,18 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
   auto core_z = [&](int k) { return Zc + (size_t)k * zc * 2 * zc * csz; };
   const ll dcap = p.dcap;
   const int bs = c.bs;
+  // carry entering zip-up site k; centre entering sweep step k (k >= 1)
+  auto carry_at = [&](int k) -> void* {
+    return sv ? (char*)sv->C + (size_t)k * nf * b.sC * csz : b.carry[(m - 1 - k) & 1];
+  };
+  auto center_at = [&](int k) -> void* {
+    return sv ? (char*)sv->N + (size_t)k * nf * b.sCtr * csz : b.center[(k - 1) & 1];
+  };
 
   HIPCHK(sanitize_bonds(in.bonds, b.inb, m, (int)ci, b.status, nf, s));
   HIPCHK(set_ints(b.zbonds, nf * bs, 1, s));
   c.kcap_dev = chi_dev;          // per-field caps lower both the zip-up and the sweep caps
-  HIPCHK(set_one_b(b.carry[0], b.sC, real, nf, s));
-  int cur = 0;
+  HIPCHK(set_one_b(carry_at(m - 1), b.sC, real, nf, s));
   // ---- zip-up, right to left
   for (int k = m - 1; k >= 0; --k) {
     const int* ra = b.inb + k;
@@ -358,8 +404,8 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     const int* bet = b.zbonds + k + 1;
     const int Da = p.D[k], Db = p.D[k + 1];
     const bool ident = p.kind[k] == 1;
-    void* carry = b.carry[cur];
-    void* carry_next = b.carry[cur ^ 1];
+    void* carry = carry_at(k);
+    void* carry_next = k > 0 ? carry_at(k - 1) : nullptr;
     // GEMM1: X[(a,s),(b,w)] = A_k[(a,s), a'] C[a', (b,w)]
     {
       Operand A = opd(core_in(k), 2 * ci, ci, 1, 0, 0, sIn);
@@ -418,12 +464,10 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       r = gemm(c, dv(c, 1, kout), 1, p.beta[k], dv(c, 2, bet), 2, (int)qb, dv(c, Da, ra), Da, A2, B2, C2);
       if (r) return r;
     }
-    cur ^= 1;
   }
   // ---- sweep, left to right
   HIPCHK(set_ints_strided(out.bonds, 1, bs, nf, 1, s));
   HIPCHK(set_ints_strided(out.bonds + m, 1, bs, nf, 1, s));
-  int cc = 0;
   const char* center = core_z(0);
   ll sCenter = b.sZ;
   c.kcap_dev = chi_dev;
@@ -433,7 +477,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     const int* bk2 = b.zbonds + k + 2;
     int* kout = out.bonds + k + 1;
     const ll pb = 2ll * p.rout[k], qb = p.beta[k + 1];
-    void* next = b.center[cc];
+    void* next = center_at(k + 1);
     const char* znext = core_z(k + 1);
     // M = center [(r,t), b]: strides (2 zc, zc) rows, 1 cols
     if (qb < pb) {
@@ -476,7 +520,6 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     }
     center = (const char*)next;
     sCenter = b.sCtr;
-    cc ^= 1;
   }
   // last core: out[m-1][r][t][0] = center[r][t][0]
   const int* rl = out.bonds + m - 1;
@@ -494,23 +537,32 @@ size_t apply_bytes(const ApplyPlan& p, size_t csz, int nf) {
   return cv.off;
 }
 
-// Validate and run one (batched) application.  identity: W ignored, every
-// site an identity pass-through of bond 1 (used by tt_truncate).
-int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opts* opts, const MpsB& out,
-                 const int* chi_dev, void* ws, size_t ws_bytes, void* stream, bool identity) {
+// Validated arguments of one (batched) application.
+struct ApplySetup {
+  qtt_opts o;
+  std::vector<int> dbonds, kind;
+  MpoB W;
+  ApplyPlan p;
+  size_t csz;
+};
+
+// Validate the arguments of an application.  identity: W ignored, every site
+// an identity pass-through of bond 1 (used by tt_truncate).
+int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opts* opts, const MpsB& out,
+                bool identity, ApplySetup& su) {
   if (in.m != out.m) return fail(QTT_ERR_SHAPE, "in/out n_sites differ");
   if (in.nf != out.nf) return fail(QTT_ERR_SHAPE, "in/out batch counts differ");
   if (in.dtype != out.dtype) return fail(QTT_ERR_DTYPE, "in/out dtypes differ");
-  if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
   const int m = in.m;
-  qtt_opts o;
+  qtt_opts& o = su.o;
   opts_defaults(opts, out.cap, o);
   if (o.chi_max < 1 || o.chi_max > out.cap) return fail(QTT_ERR_CAPACITY, "chi_max %d outside [1, %d]", o.chi_max, out.cap);
   if (o.chi_zip < 1 || o.chi_zip > 256) return fail(QTT_ERR_CAPACITY, "chi_zip %d outside [1, 256]", o.chi_zip);
   if (o.prec != QTT_PREC_FP32 && o.prec != QTT_PREC_FP64) return fail(QTT_ERR_ARG, "precision %d not supported here", o.prec);
   if ((o.prec == QTT_PREC_FP64) != (in.dtype == QTT_C128)) return fail(QTT_ERR_DTYPE, "precision and dtype disagree");
-  std::vector<int> dbonds(m + 1, 1), kind(m, 1);
-  MpoB W;
+  su.dbonds.assign(m + 1, 1);
+  su.kind.assign(m, 1);
+  MpoB& W = su.W;
   W.nf = in.nf; W.m = m; W.dcap = 1; W.dtype = in.dtype; W.cores = nullptr;
   if (!identity) {
     const int* db;
@@ -533,31 +585,331 @@ int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_op
     if (dcap < 1 || dcap > 512) return fail(QTT_ERR_CAPACITY, "MPO d_cap %d outside [1, 512]", dcap);
     for (int k = 0; k <= m; ++k) {
       if (db[k] < 1 || db[k] > dcap) return fail(QTT_ERR_CAPACITY, "MPO bond %d = %d outside [1, d_cap]", k, db[k]);
-      dbonds[k] = db[k];
+      su.dbonds[k] = db[k];
     }
     for (int k = 0; k < m; ++k) {
-      kind[k] = kd ? kd[k] : 0;
-      if (kind[k] == 1 && dbonds[k] != dbonds[k + 1]) return fail(QTT_ERR_SHAPE, "identity site %d changes the bond", k);
+      su.kind[k] = kd ? kd[k] : 0;
+      if (su.kind[k] == 1 && su.dbonds[k] != su.dbonds[k + 1])
+        return fail(QTT_ERR_SHAPE, "identity site %d changes the bond", k);
     }
     W.dcap = dcap;
   }
-  W.dbonds = dbonds.data();
-  W.kind = kind.data();
-  ApplyPlan p = make_apply_plan(m, in.cap, out.cap, o.chi_max, o.chi_zip, dbonds.data(), kind.data(), W.dcap);
-  size_t csz = in.dtype == QTT_C128 ? 16 : 8;
-  size_t need = apply_bytes(p, csz, in.nf);
-  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
-  Carver cw(ws);
-  ApplyBufs b = carve_apply(cw, p, csz, in.nf);
-  return run_apply(in, W, o, out, p, b, chi_dev, (hipStream_t)stream);
+  W.dbonds = su.dbonds.data();
+  W.kind = su.kind.data();
+  su.p = make_apply_plan(m, in.cap, out.cap, o.chi_max, o.chi_zip, su.dbonds.data(), su.kind.data(), W.dcap);
+  su.csz = in.dtype == QTT_C128 ? 16 : 8;
+  return QTT_OK;
 }
 
-size_t apply_ws(int m, int chi_cap, int d_cap, int prec, bool identity, int nf) {
+int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opts* opts, const MpsB& out,
+                 const int* chi_dev, void* ws, size_t ws_bytes, void* stream, bool identity, void* saved = nullptr,
+                 size_t saved_sz = 0) {
+  if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
+  ApplySetup su;
+  int r = apply_setup(in, W1, Wb, opts, out, identity, su);
+  if (r) return r;
+  size_t need = apply_bytes(su.p, su.csz, in.nf);
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  SavedBufs sv;
+  if (saved) {
+    size_t sneed = saved_bytes(su.p, su.csz, in.nf);
+    if (saved_sz < sneed) return fail(QTT_ERR_WORKSPACE, "saved buffer %zu < required %zu bytes", saved_sz, sneed);
+    Carver cs(saved);
+    sv = carve_saved(cs, su.p, su.csz, in.nf);
+  }
+  Carver cw(ws);
+  ApplyBufs b = carve_apply(cw, su.p, su.csz, in.nf);
+  return run_apply(in, su.W, su.o, out, su.p, b, chi_dev, saved ? &sv : nullptr, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------ adjoint of the application
+// Reverse of the sweep (right to left), then of the zip-up (left to right).
+// Every truncation M -> (V_k, M V_k) (zip-up: B = V_k^H, carry = M V_k; sweep
+// on N^H: U = V_k, R = U^H N) is differentiated with the full FP64 eigen-
+// decomposition G = M^H M = V diag(lam) V^H recomputed from the saved inputs:
+//   Vbar = gV + M^H gC,  Z = F o (V^H Vbar) with F_ji = 1/(lam_i - lam_j) for
+//   discarded j and kept i (0 elsewhere),  P = V Z,
+//   Mbar = (gC + M P) V_k^H + (M V_k) P^H.
+// The kept-kept block is left out: the chain of truncations is invariant
+// under unitary rotations of each kept block, so that block contributes
+// nothing to the gradient of any function of the final field.
+struct BwdBufs {
+  int* status;
+  int* kfull;
+  void *X, *Mb, *Mbar, *Xbar;
+  void* gC[2];
+  void* Zbar;
+  void* Nbar[2];
+  void *R, *Rbar;
+  void *Vall, *Vbar, *Y, *P;
+  double* G;
+  double* part;
+  void* eigws;
+  ll sX, sC, sZ, sCtr, sR, sE;
+  int nmax;
+};
+
+int bwd_nmax(const ApplyPlan& p) {
+  int g = 1;
+  for (int k = 1; k < p.m; ++k) g = std::max(g, 2 * p.beta[k + 1]);
+  for (int k = 0; k < p.m - 1; ++k) g = std::max(g, 2 * p.rout[k]);
+  return g;
+}
+
+BwdBufs carve_bwd(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
+  Carver dry(nullptr);
+  ApplyBufs t = carve_apply(dry, p, csz, nf);
+  BwdBufs b;
+  b.nmax = bwd_nmax(p);
+  b.sX = t.sX; b.sC = t.sC; b.sZ = t.sZ; b.sCtr = t.sCtr; b.sR = t.sR;
+  b.sE = (ll)b.nmax * b.nmax;
+  b.status = (int*)cv.take(256);
+  b.kfull = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
+  b.X = cv.take(nf * b.sX * csz);
+  b.Mb = cv.take(nf * b.sX * csz);
+  b.Mbar = cv.take(nf * b.sX * csz);
+  b.Xbar = cv.take(nf * b.sX * csz);
+  b.gC[0] = cv.take(nf * b.sC * csz);
+  b.gC[1] = cv.take(nf * b.sC * csz);
+  b.Zbar = cv.take(nf * b.sZ * csz);
+  b.Nbar[0] = cv.take(nf * b.sCtr * csz);
+  b.Nbar[1] = cv.take(nf * b.sCtr * csz);
+  b.R = cv.take(nf * b.sR * csz);
+  b.Rbar = cv.take(nf * b.sR * csz);
+  b.Vall = cv.take(nf * b.sE * csz);
+  b.Vbar = cv.take(nf * b.sE * csz);
+  b.Y = cv.take(nf * b.sE * csz);
+  b.P = cv.take(nf * b.sE * csz);
+  b.G = (double*)cv.take((size_t)nf * b.nmax * b.nmax * 16);
+  b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256ull * b.nmax * b.nmax * 16 * nf));
+  b.eigws = cv.take(eig_ws_bytes(b.nmax, b.nmax, nf));
+  return b;
+}
+
+size_t bwd_bytes(const ApplyPlan& p, size_t csz, int nf) {
+  Carver cv(nullptr);
+  carve_bwd(cv, p, csz, nf);
+  return cv.off;
+}
+
+int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const MpsB& gout, const MpsB& gin,
+                       const ApplyPlan& p, const SavedBufs& sv, BwdBufs& b, hipStream_t s) {
+  const int m = p.m, nf = in.nf;
+  const int real = in.dtype == QTT_C128 ? 1 : 0;
+  Ctx c = make_ctx(s, real, nf, m, b.status);
+  c.G = b.G; c.gld = b.nmax; c.part = b.part; c.eigws = b.eigws;
+  c.eig_nb = b.nmax; c.eig_kc = b.nmax;
+  c.kcap_dev = nullptr;
+  const ll ci = in.cap, co = out.cap, zc = p.zc, L = b.nmax;
+  const size_t csz = c.csz;
+  const ll sIn = in.fstride(), sOut = out.fstride(), sW = W.fstride();
+  const int bs = c.bs;
+  auto core_in = [&](int k) { return (char*)in.cores + (size_t)k * ci * 2 * ci * csz; };
+  auto core_gin = [&](int k) { return (char*)gin.cores + (size_t)k * ci * 2 * ci * csz; };
+  auto core_out = [&](int k) { return (char*)out.cores + (size_t)k * co * 2 * co * csz; };
+  auto core_gout = [&](int k) { return (char*)gout.cores + (size_t)k * co * 2 * co * csz; };
+  auto core_z = [&](int k) { return (char*)sv.Z + (size_t)k * zc * 2 * zc * csz; };
+  auto core_zbar = [&](int k) { return (char*)b.Zbar + (size_t)k * zc * 2 * zc * csz; };
+  auto carry_at = [&](int k) { return (char*)sv.C + (size_t)k * nf * b.sC * csz; };
+  auto center_at = [&](int k) { return k == 0 ? core_z(0) : (char*)sv.N + (size_t)k * nf * b.sCtr * csz; };
+  const char* Wc = (const char*)W.cores;
+  const ll dcap = p.dcap;
+  int r;
+
+  HIPCHK(zero_fill(gin.cores, (size_t)nf * sIn * csz, s));
+  HIPCHK(copy_ints(sv.inb, gin.bonds, nf * bs, s));
+  // ---- sweep, reversed.  cbar: gradient of the centre entering step k + 1.
+  const char* cbar = core_gout(m - 1);
+  ll cbar_rs = 2 * co, cbar_ts = co, sCbar = sOut;
+  int nsel = 0;
+  for (int k = m - 2; k >= 0; --k) {
+    const int* rk = out.bonds + k;
+    const int* rk1 = out.bonds + k + 1;
+    const int* bk = sv.zbonds + k + 1;
+    const int* bk2 = sv.zbonds + k + 2;
+    const int nr = 2 * p.rout[k], nr1 = p.rout[k + 1], nbk = p.beta[k + 1], nbk2 = p.beta[k + 2];
+    const char* N = center_at(k);
+    const ll sN = k == 0 ? b.sZ : b.sCtr;
+    const char* U = core_out(k);
+    // R = U^H N
+    r = gemm(c, dv(c, 1, rk1), 1, nr1, dv(c, 1, bk), 1, nbk, dv(c, 2, rk), 1, opd(U, 1, 0, co, 0, 1, sOut),
+             opd(N, zc, 0, 1, 0, 0, sN), opd(b.R, zc, 0, 1, 0, 0, b.sR));
+    if (r) return r;
+    // Rbar = cbar Z_{k+1}^H   (K = (b'', t))
+    r = gemm(c, dv(c, 1, rk1), 1, nr1, dv(c, 1, bk), 1, nbk, dv(c, 2, bk2), 2,
+             opd(cbar, cbar_rs, 0, 1, cbar_ts, 0, sCbar), opd(core_z(k + 1), 1, zc, 2 * zc, 0, 1, b.sZ),
+             opd(b.Rbar, zc, 0, 1, 0, 0, b.sR));
+    if (r) return r;
+    // Zbar_{k+1} = R^H cbar
+    r = gemm(c, dv(c, 1, bk), 1, nbk, dv(c, 2, bk2), 2, 2 * nbk2, dv(c, 1, rk1), 1, opd(b.R, 1, 0, zc, 0, 1, b.sR),
+             opd(cbar, cbar_rs, 0, 1, cbar_ts, 0, sCbar), opd(core_zbar(k + 1), 2 * zc, 0, 1, zc, 0, b.sZ));
+    if (r) return r;
+    // Vbar = gout_k + N Rbar^H   ([p = (r, t)][i], ld L)
+    HIPCHK(block_copy_b(core_gout(k), co, 1, sOut, b.Vbar, L, 1, b.sE, dv(c, 2, rk), dv(c, 1, rk1), nr, nr1, real,
+                        nf, s));
+    r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 1, bk), 1, opd(N, zc, 0, 1, 0, 0, sN),
+             opd(b.Rbar, 1, 0, zc, 0, 1, b.sR), opd(b.Vbar, L, 0, 1, 0, 0, b.sE), dx(1), 1, 1);
+    if (r) return r;
+    // full decomposition of N N^H
+    r = gram(c, opd(N, zc, 0, 1, 0, 0, sN), opd(N, 1, 0, zc, 0, 1, sN), dv(c, 2, rk), 1, nr, dv(c, 1, bk), 1, nbk);
+    if (r) return r;
+    EigSpec es;
+    r = eig(c, dv(c, 2, rk), nr, nr, 0.0, -1.0, b.kfull, {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)}, &es);
+    if (r) return r;
+    // Y = Vall^H Vbar, scaled in place to Z; P = Vall Z
+    r = gemm(c, dv(c, 1, b.kfull), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 2, rk), 1, opd(b.Vall, 1, 0, L, 0, 1, b.sE),
+             opd(b.Vbar, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE));
+    if (r) return r;
+    HIPCHK(eig_adjoint_scale(es, b.Y, L, b.sE, rk1, bs, nr1, real, s));
+    r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 1, b.kfull), 1, opd(b.Vall, L, 0, 1, 0, 0, b.sE),
+             opd(b.Y, L, 0, 1, 0, 0, b.sE), opd(b.P, L, 0, 1, 0, 0, b.sE));
+    if (r) return r;
+    // Rbar += P^H N;  Nbar = U Rbar + P R
+    r = gemm(c, dv(c, 1, rk1), 1, nr1, dv(c, 1, bk), 1, nbk, dv(c, 2, rk), 1, opd(b.P, 1, 0, L, 0, 1, b.sE),
+             opd(N, zc, 0, 1, 0, 0, sN), opd(b.Rbar, zc, 0, 1, 0, 0, b.sR), dx(1), 1, 1);
+    if (r) return r;
+    void* nbar = k == 0 ? (void*)core_zbar(0) : b.Nbar[nsel];
+    const ll sNbar = k == 0 ? b.sZ : b.sCtr;
+    r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, bk), 1, nbk, dv(c, 1, rk1), 1, opd(U, co, 0, 1, 0, 0, sOut),
+             opd(b.Rbar, zc, 0, 1, 0, 0, b.sR), opd(nbar, zc, 0, 1, 0, 0, sNbar));
+    if (r) return r;
+    r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, bk), 1, nbk, dv(c, 1, rk1), 1, opd(b.P, L, 0, 1, 0, 0, b.sE),
+             opd(b.R, zc, 0, 1, 0, 0, b.sR), opd(nbar, zc, 0, 1, 0, 0, sNbar), dx(1), 1, 1);
+    if (r) return r;
+    cbar = (const char*)nbar;
+    cbar_rs = 2 * zc;
+    cbar_ts = zc;
+    sCbar = sNbar;
+    nsel ^= 1;
+  }
+  // ---- zip-up, reversed (left to right).  gcur: gradient of the carry leaving site k.
+  void* gcur = b.gC[0];
+  void* gnext = b.gC[1];
+  for (int k = 0; k < m; ++k) {
+    const int* ra = sv.inb + k;
+    const int* rb = sv.inb + k + 1;
+    const int* bet = sv.zbonds + k + 1;
+    const int* kkp = sv.zbonds + k;
+    const int Da = p.D[k], Db = p.D[k + 1];
+    const bool ident = p.kind[k] == 1;
+    void* Cin = carry_at(k);
+    const ll pb = (ll)p.rin[k] * Da, qb = 2ll * p.beta[k + 1];
+    // recompute X and M exactly as the forward did
+    {
+      Operand A = opd(core_in(k), 2 * ci, ci, 1, 0, 0, sIn);
+      Operand B = opd(Cin, zc * Db, 0, Db, 1, 0, b.sC);
+      Operand C = ident ? opd(b.Mb, 2 * zc * Db, 1, 2, 2 * zc, 0, b.sX) : opd(b.X, zc * 2 * Db, Db, 2 * Db, 1, 0, b.sX);
+      r = gemm(c, dv(c, 2, ra), 2, 2 * p.rin[k], dv(c, Db, bet), Db, Db * p.beta[k + 1], dv(c, 1, rb), 1, A, B, C);
+      if (r) return r;
+    }
+    if (!ident) {
+      Operand A = opd(b.X, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db);
+      Operand B = opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 1, 0, 4 * Db, 2 * Db, 0, sW);
+      Operand C = opd(b.Mb, 2, 0, 2 * zc, 1, 0, b.sX, (ll)Da * zc * 2);
+      r = gemm(c, dv(c, 1, bet), 1, p.beta[k + 1], dx(2 * Da), 2, 2 * Da, dx(2 * Db), 1, A, B, C, dv(c, 1, ra),
+               p.rin[k]);
+      if (r) return r;
+    }
+    const Operand Mrows = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);      // [p = (a, w')][q]
+    const Operand Mbar_v = opd(b.Mbar, 2 * zc * Da, 2 * zc, 2, 1, 0, b.sX);   // [p][q = (b, t)], N split lo 2
+    if (k == 0) {
+      // M[0][0][b][t] = B_0[0][t][b]
+      HIPCHK(block_copy_b(core_zbar(0), zc, 1, b.sZ, b.Mbar, 1, 2, b.sX, dx(2), dv(c, 1, bet), 2, p.beta[1], real, nf,
+                          s));
+    } else {
+      // Vbar[q = 2b + t][i] = conj(Zbar_k[i][t][b]) + (M^H gC)[q][i]
+      for (int t = 0; t < 2; ++t)
+        HIPCHK(block_copy_b(core_zbar(k) + (size_t)t * zc * csz, 1, 2 * zc, b.sZ, (char*)b.Vbar + (size_t)t * L * csz,
+                            2 * L, 1, b.sE, dv(c, 1, bet), dv(c, 1, kkp), p.beta[k + 1], p.beta[k], real, nf, s, 1));
+      r = gemm(c, dv(c, 2, bet), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, Da, ra), Da,
+               opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX), opd(gcur, zc * Da, 1, Da, 0, 0, b.sC),
+               opd(b.Vbar, L, 0, 1, 0, 0, b.sE), dx(1), 1, 1);
+      if (r) return r;
+      // full decomposition of M^H M
+      r = gram(c, opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX), Mrows, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da,
+               pb);
+      if (r) return r;
+      EigSpec es;
+      r = eig(c, dv(c, 2, bet), (int)qb, (int)qb, 0.0, -1.0, b.kfull, {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)},
+              &es);
+      if (r) return r;
+      r = gemm(c, dv(c, 1, b.kfull), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 2, bet), 1,
+               opd(b.Vall, 1, 0, L, 0, 1, b.sE), opd(b.Vbar, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE));
+      if (r) return r;
+      HIPCHK(eig_adjoint_scale(es, b.Y, L, b.sE, kkp, bs, p.beta[k], real, s));
+      r = gemm(c, dv(c, 2, bet), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 1, b.kfull), 1,
+               opd(b.Vall, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE), opd(b.P, L, 0, 1, 0, 0, b.sE));
+      if (r) return r;
+      // gC += M P;  Mbar = gC V^H (V^H is B_k itself) + (M V) P^H
+      r = gemm(c, dv(c, Da, ra), Da, (int)pb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 2, bet), 1, Mrows,
+               opd(b.P, L, 0, 1, 0, 0, b.sE), opd(gcur, zc * Da, 1, Da, 0, 0, b.sC), dx(1), 1, 1);
+      if (r) return r;
+      r = gemm(c, dv(c, Da, ra), Da, (int)pb, dv(c, 2, bet), 2, (int)qb, dv(c, 1, kkp), 1,
+               opd(gcur, zc * Da, 1, Da, 0, 0, b.sC), opd(core_z(k), 2 * zc, 0, 1, zc, 0, b.sZ), Mbar_v);
+      if (r) return r;
+      r = gemm(c, dv(c, Da, ra), Da, (int)pb, dv(c, 2, bet), 2, (int)qb, dv(c, 1, kkp), 1,
+               opd(carry_at(k - 1), zc * Da, 1, Da, 0, 0, b.sC), opd(b.P, 1, 0, 2 * L, L, 1, b.sE), Mbar_v, dx(1), 1,
+               1);
+      if (r) return r;
+    }
+    // Xbar[a][b][(s, w)] = sum_{(w', t)} Mbar[a][w'][b][t] conj(W[w'][t][s][w])
+    if (!ident) {
+      r = gemm(c, dv(c, 1, bet), 1, p.beta[k + 1], dx(2 * Db), 1, 2 * Db, dx(2 * Da), 2,
+               opd(b.Mbar, 2, 0, 2 * zc, 1, 0, b.sX, (ll)Da * zc * 2),
+               opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 4 * Db, 2 * Db, 1, 0, 1, sW),
+               opd(b.Xbar, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db), dv(c, 1, ra), p.rin[k]);
+      if (r) return r;
+    }
+    const Operand XA = ident ? opd(b.Mbar, 2 * zc * Db, 1, 2, 2 * zc, 0, b.sX)
+                             : opd(b.Xbar, zc * 2 * Db, Db, 2 * Db, 1, 0, b.sX);
+    // grad of A_k = Xbar Cin^H
+    r = gemm(c, dv(c, 2, ra), 2, 2 * p.rin[k], dv(c, 1, rb), 1, p.rin[k + 1], dv(c, Db, bet), Db, XA,
+             opd(Cin, Db, 1, zc * Db, 0, 1, b.sC), opd(core_gin(k), 2 * ci, ci, 1, 0, 0, sIn));
+    if (r) return r;
+    // grad of the carry entering site k (= leaving site k + 1) = A_k^H Xbar
+    if (k < m - 1) {
+      r = gemm(c, dv(c, 1, rb), 1, p.rin[k + 1], dv(c, Db, bet), Db, Db * p.beta[k + 1], dv(c, 2, ra), 2,
+               opd(core_in(k), 1, 0, 2 * ci, ci, 1, sIn), XA, opd(gnext, zc * Db, 0, Db, 1, 0, b.sC));
+      if (r) return r;
+    }
+    std::swap(gcur, gnext);
+  }
+  return QTT_OK;
+}
+
+int backward_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opts* opts, const void* saved,
+                    size_t saved_sz, const MpsB& out, const MpsB& gout, const MpsB& gin, void* ws, size_t ws_bytes,
+                    void* stream) {
+  if (!ws || !saved) return fail(QTT_ERR_ARG, "workspace/saved is NULL");
+  if (gout.m != out.m || gout.nf != out.nf || gout.cap != out.cap || gout.dtype != out.dtype)
+    return fail(QTT_ERR_SHAPE, "grad_out must match out (sites, count, chi_cap, dtype)");
+  if (gin.m != in.m || gin.nf != in.nf || gin.cap != in.cap || gin.dtype != in.dtype)
+    return fail(QTT_ERR_SHAPE, "grad_in must match in (sites, count, chi_cap, dtype)");
+  if (gin.cores == in.cores || gout.cores == out.cores) return fail(QTT_ERR_ARG, "gradients must not alias the states");
+  ApplySetup su;
+  int r = apply_setup(in, W1, Wb, opts, out, false, su);
+  if (r) return r;
+  if (bwd_nmax(su.p) > 512) return fail(QTT_ERR_CAPACITY, "adjoint eigenproblem larger than 512");
+  size_t sneed = saved_bytes(su.p, su.csz, in.nf);
+  if (saved_sz < sneed) return fail(QTT_ERR_WORKSPACE, "saved buffer %zu < required %zu bytes", saved_sz, sneed);
+  size_t need = bwd_bytes(su.p, su.csz, in.nf);
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  Carver cs(const_cast<void*>(saved));
+  SavedBufs sv = carve_saved(cs, su.p, su.csz, in.nf);
+  Carver cw(ws);
+  BwdBufs b = carve_bwd(cw, su.p, su.csz, in.nf);
+  return run_apply_backward(in, su.W, out, gout, gin, su.p, sv, b, (hipStream_t)stream);
+}
+
+ApplyPlan capacity_plan(int m, int chi_cap, int d_cap, bool identity) {
   std::vector<int> db(m + 1, identity ? 1 : d_cap);
   db[0] = db[m] = 1;
   std::vector<int> kind(m, identity ? 1 : 0);
-  ApplyPlan p = make_apply_plan(m, chi_cap, chi_cap, chi_cap, chi_cap, db.data(), kind.data(), identity ? 1 : d_cap);
-  return apply_bytes(p, prec == QTT_PREC_FP64 ? 16 : 8, nf);
+  return make_apply_plan(m, chi_cap, chi_cap, chi_cap, chi_cap, db.data(), kind.data(), identity ? 1 : d_cap);
+}
+
+size_t apply_ws(int m, int chi_cap, int d_cap, int prec, bool identity, int nf) {
+  return apply_bytes(capacity_plan(m, chi_cap, d_cap, identity), prec == QTT_PREC_FP64 ? 16 : 8, nf);
 }
 
 // ------------------------------------------------------------ encode
@@ -738,6 +1090,160 @@ int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream
   return QTT_OK;
 }
 
+
+// ------------------------------------------------------------ adjoint of the decompression
+// Forward: E = P_h Q_h with the left half-chain P_(k+1) = P_k A_k (k < h) and
+// the right half-chain Q_k = A_k Q_(k+1) (k >= h).  Backward: Pbar_h =
+// Ebar Q_h^H, Qbar_h = P_h^H Ebar, then each product is undone:
+// Abar_k = P_k^H Pbar_(k+1), Pbar_k = Pbar_(k+1) A_k^H (left) and
+// Abar_k = Qbar_k Q_(k+1)^H, Qbar_(k+1) = A_k^H Qbar_k (right).
+struct DenseBwdBufs {
+  int* status;
+  int* bonds;
+  void* E;
+  void* P;              // P_k (2 <= k <= h) at element offset poff[k] (per field sP)
+  void* Q;              // Q_k (h <= k <= m - 2) at element offset qoff[k] (per field sQ)
+  void* PB[2];
+  void* QB[2];
+  ll sE, sP, sQ, sPB, sQB;
+  std::vector<ll> poff, qoff;
+};
+
+DenseBwdBufs carve_dense_bwd(Carver& cv, int m, int ch, size_t csz, int nf) {
+  DenseBwdBufs b;
+  const int h = m / 2;
+  b.poff.assign(m + 1, 0);
+  b.qoff.assign(m + 1, 0);
+  ll o = 0;
+  for (int k = 2; k <= h; ++k) { b.poff[k] = o; o += ((ll)1 << k) * ch; }
+  b.sP = std::max<ll>(o, 1);
+  o = 0;
+  for (int k = m - 2; k >= h; --k) { b.qoff[k] = o; o += ((ll)1 << (m - k)) * ch; }
+  b.sQ = std::max<ll>(o, 1);
+  b.sE = (ll)1 << m;
+  b.sPB = ((ll)1 << h) * ch;
+  b.sQB = ((ll)1 << (m - h)) * ch;
+  b.status = (int*)cv.take(256);
+  b.bonds = (int*)cv.take((size_t)nf * (m + 1) * sizeof(int));
+  b.E = cv.take(nf * b.sE * csz);
+  b.P = cv.take(nf * b.sP * csz);
+  b.Q = cv.take(nf * b.sQ * csz);
+  b.PB[0] = cv.take(nf * b.sPB * csz);
+  b.PB[1] = cv.take(nf * b.sPB * csz);
+  b.QB[0] = cv.take(nf * b.sQB * csz);
+  b.QB[1] = cv.take(nf * b.sQB * csz);
+  return b;
+}
+
+int dense_backward_impl(const MpsB& in, const void* gdense, const MpsB& g, DenseBwdBufs& b, hipStream_t s) {
+  const int m = in.m, h = m / 2, nf = in.nf;
+  const int real = in.dtype == QTT_C128 ? 1 : 0;
+  Ctx c = make_ctx(s, real, nf, m, b.status);
+  const ll ch = in.cap, cg = g.cap, sIn = in.fstride(), sG = g.fstride();
+  const size_t csz = c.csz;
+  std::vector<int> rb = mps_bounds(m, ch);
+  auto core = [&](int k) { return (char*)in.cores + (size_t)k * ch * 2 * ch * csz; };
+  auto gcore = [&](int k) { return (char*)g.cores + (size_t)k * cg * 2 * cg * csz; };
+  auto pslot = [&](int k) { return (char*)b.P + (size_t)b.poff[k] * csz; };
+  auto qslot = [&](int k) { return (char*)b.Q + (size_t)b.qoff[k] * csz; };
+  HIPCHK(sanitize_bonds(in.bonds, b.bonds, m, (int)ch, b.status, nf, s));
+  const int* bonds = b.bonds;
+  HIPCHK(zero_fill(g.cores, (size_t)nf * sG * csz, s));
+  HIPCHK(copy_ints(bonds, g.bonds, nf * (m + 1), s));
+  for (int f = 0; f < nf; ++f)
+    HIPCHK(quantics_permute((const char*)gdense + (size_t)f * b.sE * csz, real ? QTT_C128 : QTT_C64,
+                            (char*)b.E + (size_t)f * b.sE * csz, real ? QTT_C128 : QTT_C64, m / 2, 0, s));
+  // left half-chain, every P_k kept: P_k = [l][r] with ld pld[k]
+  std::vector<const void*> Pp(h + 1);
+  std::vector<ll> pld(h + 1), psb(h + 1);
+  Pp[1] = core(0); pld[1] = ch; psb[1] = sIn;
+  for (int k = 1; k < h; ++k) {
+    const ll rows = 1ll << k;
+    void* Pn = pslot(k + 1);
+    int r = gemm(c, dx((int)rows), 1, (int)rows, dv(c, 2, bonds + k + 1), 2, 2 * rb[k + 1], dv(c, 1, bonds + k), 1,
+                 opd(Pp[k], pld[k], 0, 1, 0, 0, psb[k]), opd(core(k), 2 * ch, 0, 1, ch, 0, sIn),
+                 opd(Pn, 2 * ch, 0, 1, ch, 0, b.sP));
+    if (r) return r;
+    Pp[k + 1] = Pn; pld[k + 1] = ch; psb[k + 1] = b.sP;
+  }
+  // right half-chain: Q_k = [(r, s)][c] with row stride qrs[k] (per r) and column stride qcs[k]
+  std::vector<const void*> Qp(m);
+  std::vector<ll> qrs(m), qcs(m), qsb(m);
+  Qp[m - 1] = core(m - 1); qrs[m - 1] = 2 * ch; qcs[m - 1] = ch; qsb[m - 1] = sIn;
+  for (int k = m - 2; k >= h; --k) {
+    const ll cols = 1ll << (m - k - 1);
+    void* Qn = qslot(k);
+    int r = gemm(c, dv(c, 2, bonds + k), 2, 2 * rb[k], dx((int)cols), 1, (int)cols, dv(c, 1, bonds + k + 1), 1,
+                 opd(core(k), 2 * ch, ch, 1, 0, 0, sIn), opd(Qp[k + 1], qrs[k + 1], 0, qcs[k + 1], 0, 0, qsb[k + 1]),
+                 opd(Qn, 2 * cols, cols, 1, 0, 0, b.sQ));
+    if (r) return r;
+    Qp[k] = Qn; qrs[k] = 2 * cols; qcs[k] = 1; qsb[k] = b.sQ;
+  }
+  const ll Lh = 1ll << h, Rn = 1ll << (m - h);
+  // Pbar_h = Ebar Q_h^H ([l][r], ld ch); Qbar_h = P_h^H Ebar ([r][c], row stride Rn)
+  int r = gemm(c, dx((int)Lh), 1, (int)Lh, dv(c, 1, bonds + h), 1, rb[h], dx((int)Rn), 1,
+               opd(b.E, Rn, 0, 1, 0, 0, b.sE), opd(Qp[h], qcs[h], 0, qrs[h], 0, 1, qsb[h]),
+               opd(b.PB[0], ch, 0, 1, 0, 0, b.sPB));
+  if (r) return r;
+  r = gemm(c, dv(c, 1, bonds + h), 1, rb[h], dx((int)Rn), 1, (int)Rn, dx((int)Lh), 1,
+           opd(Pp[h], 1, 0, pld[h], 0, 1, psb[h]), opd(b.E, Rn, 0, 1, 0, 0, b.sE), opd(b.QB[0], Rn, 0, 1, 0, 0, b.sQB));
+  if (r) return r;
+  // left chain backwards
+  int ps = 0;
+  for (int k = h - 1; k >= 1; --k) {
+    const ll rows = 1ll << k;
+    const void* PB = b.PB[ps];
+    // Abar_k[r][(b, s)] = P_k^H Pbar_(k+1), Pbar_(k+1) = [(l, s)][b] with ld ch
+    r = gemm(c, dv(c, 1, bonds + k), 1, rb[k], dv(c, 2, bonds + k + 1), 2, 2 * rb[k + 1], dx((int)rows), 1,
+             opd(Pp[k], 1, 0, pld[k], 0, 1, psb[k]), opd(PB, 2 * ch, 0, 1, ch, 0, b.sPB),
+             opd(gcore(k), 2 * cg, 0, 1, cg, 0, sG));
+    if (r) return r;
+    // Pbar_k = Pbar_(k+1) A_k^H  (K = (b, s))
+    r = gemm(c, dx((int)rows), 1, (int)rows, dv(c, 1, bonds + k), 1, rb[k], dv(c, 2, bonds + k + 1), 2,
+             opd(PB, 2 * ch, 0, 1, ch, 0, b.sPB), opd(core(k), 1, ch, 2 * ch, 0, 1, sIn),
+             opd(b.PB[ps ^ 1], ch, 0, 1, 0, 0, b.sPB));
+    if (r) return r;
+    ps ^= 1;
+  }
+  // Pbar_1 = grad of core 0 ([s][b])
+  HIPCHK(block_copy_b(b.PB[ps], ch, 1, b.sPB, gcore(0), cg, 1, sG, dx(2), dv(c, 1, bonds + 1), 2, rb[1], real, nf, s));
+  // right chain forwards: Qbar_k = [(r, s)][c] with row stride 2 * cols_k
+  int qs = 0;
+  for (int k = h; k <= m - 2; ++k) {
+    const ll cols = 1ll << (m - k - 1);
+    const void* QB = b.QB[qs];
+    // Abar_k[(r, s)][b] = Qbar_k Q_(k+1)^H
+    r = gemm(c, dv(c, 2, bonds + k), 2, 2 * rb[k], dv(c, 1, bonds + k + 1), 1, rb[k + 1], dx((int)cols), 1,
+             opd(QB, 2 * cols, cols, 1, 0, 0, b.sQB), opd(Qp[k + 1], qcs[k + 1], 0, qrs[k + 1], 0, 1, qsb[k + 1]),
+             opd(gcore(k), 2 * cg, cg, 1, 0, 0, sG));
+    if (r) return r;
+    // Qbar_(k+1)[b][c] = A_k^H Qbar_k (row stride cols)
+    r = gemm(c, dv(c, 1, bonds + k + 1), 1, rb[k + 1], dx((int)cols), 1, (int)cols, dv(c, 2, bonds + k), 2,
+             opd(core(k), 1, 0, 2 * ch, ch, 1, sIn), opd(QB, 2 * cols, cols, 1, 0, 0, b.sQB),
+             opd(b.QB[qs ^ 1], cols, 0, 1, 0, 0, b.sQB));
+    if (r) return r;
+    qs ^= 1;
+  }
+  // Qbar_(m-1) = grad of core m-1 ([r][s], row stride 2)
+  HIPCHK(block_copy_b(b.QB[qs], 2, 1, b.sQB, gcore(m - 1), 2 * cg, cg, sG, dv(c, 1, bonds + m - 1), dx(2), rb[m - 1], 2,
+                      real, nf, s));
+  return QTT_OK;
+}
+
+int dense_bwd_common(const MpsB& in, const void* gdense, const MpsB& g, void* ws, size_t ws_bytes, void* stream) {
+  if (!gdense || !ws) return fail(QTT_ERR_ARG, "grad_dense/workspace is NULL");
+  if (g.m != in.m || g.nf != in.nf || g.dtype != in.dtype || g.cap != in.cap)
+    return fail(QTT_ERR_SHAPE, "grad must match in (sites, count, chi_cap, dtype)");
+  if (g.cores == in.cores) return fail(QTT_ERR_ARG, "grad must not alias in");
+  size_t csz = in.dtype == QTT_C128 ? 16 : 8;
+  Carver cv(nullptr);
+  carve_dense_bwd(cv, in.m, in.cap, csz, in.nf);
+  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
+  Carver cw(ws);
+  DenseBwdBufs b = carve_dense_bwd(cw, in.m, in.cap, csz, in.nf);
+  return dense_backward_impl(in, gdense, g, b, (hipStream_t)stream);
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -769,14 +1275,28 @@ size_t tt_workspace_size_batched(int op, int count, int n_sites, int chi_cap, in
       carve_dense(cv, n_sites, chi_cap, csz, count);
       return cv.off;
     }
+    case QTT_OP_APPLY_BACKWARD:
+      if (d_cap < 1) return 0;
+      return bwd_bytes(capacity_plan(n_sites, chi_cap, d_cap, false), csz, count);
+    case QTT_OP_TO_DENSE_BACKWARD: {
+      Carver cv(nullptr);
+      carve_dense_bwd(cv, n_sites, chi_cap, csz, count);
+      return cv.off;
+    }
+    case QTT_OP_LOSS:
+      return 256 + intensity_loss_ws(count);
     default:
       return 0;
   }
 }
 
 size_t tt_saved_size(int n_sites, int chi_cap, int d_cap, int prec) {
-  (void)n_sites; (void)chi_cap; (void)d_cap; (void)prec;
-  return 0;
+  return tt_saved_size_batched(1, n_sites, chi_cap, d_cap, prec);
+}
+
+size_t tt_saved_size_batched(int count, int n_sites, int chi_cap, int d_cap, int prec) {
+  if (n_sites < 2 || (n_sites & 1) || chi_cap < 1 || chi_cap > 256 || count < 1 || d_cap < 1) return 0;
+  return saved_bytes(capacity_plan(n_sites, chi_cap, d_cap, false), prec == QTT_PREC_FP64 ? 16 : 8, count);
 }
 
 static int encode_common(const void* img, int img_dtype, int log2_side, const qtt_opts* opts, const MpsB& out,
@@ -820,27 +1340,33 @@ int tt_encode_batched(const void* img, int img_dtype, int log2_side, const qtt_o
 int mpo_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts, qtt_mps* out, void* saved,
               size_t saved_bytes, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
-  (void)saved; (void)saved_bytes;
   int r;
   if ((r = check_mps(in, "in"))) return r;
   if ((r = check_mps(out, "out"))) return r;
   if (in->cores == out->cores) return fail(QTT_ERR_ARG, "in and out must not alias");
   if (!W) return fail(QTT_ERR_ARG, "MPO is NULL");
-  return apply_common(view(in), W, nullptr, opts, view(out), nullptr, ws, ws_bytes, stream, false);
+  return apply_common(view(in), W, nullptr, opts, view(out), nullptr, ws, ws_bytes, stream, false, saved,
+                      saved_bytes);
+}
+
+static MpoB mpob_view(const qtt_mpo_batch* W) {
+  MpoB wb;
+  wb.nf = W->count; wb.m = W->n_sites; wb.dcap = W->d_cap; wb.dtype = W->dtype;
+  wb.cores = W->cores; wb.dbonds = W->d_bonds; wb.kind = W->site_kind;
+  return wb;
 }
 
 int mpo_apply_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt_opts* opts, const int32_t* chi_dev,
-                      qtt_mps_batch* out, void* ws, size_t ws_bytes, void* stream) {
+                      qtt_mps_batch* out, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream) {
   g_err.clear();
   int r;
   if ((r = check_mpsb(in, "in"))) return r;
   if ((r = check_mpsb(out, "out"))) return r;
   if (in->cores == out->cores) return fail(QTT_ERR_ARG, "in and out must not alias");
   if (!W) return fail(QTT_ERR_ARG, "MPO batch is NULL");
-  MpoB wb;
-  wb.nf = W->count; wb.m = W->n_sites; wb.dcap = W->d_cap; wb.dtype = W->dtype;
-  wb.cores = W->cores; wb.dbonds = W->d_bonds; wb.kind = W->site_kind;
-  return apply_common(view(in), nullptr, &wb, opts, view(out), chi_dev, ws, ws_bytes, stream, false);
+  MpoB wb = mpob_view(W);
+  return apply_common(view(in), nullptr, &wb, opts, view(out), chi_dev, ws, ws_bytes, stream, false, saved,
+                      saved_bytes);
 }
 
 int tt_truncate(qtt_mps* inout, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream) {
@@ -882,15 +1408,63 @@ int tt_to_dense_batched(const qtt_mps_batch* in, void* out, int out_dtype, void*
 int mpo_apply_backward(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts, const void* saved,
                        size_t saved_bytes, const qtt_mps* out, const qtt_mps* grad_out, qtt_mps* grad_in, void* ws,
                        size_t ws_bytes, void* stream) {
-  (void)in; (void)W; (void)opts; (void)saved; (void)saved_bytes; (void)out; (void)grad_out; (void)grad_in;
-  (void)ws; (void)ws_bytes; (void)stream;
-  return fail(QTT_ERR_ARG, "mpo_apply_backward: not available in this build");
+  g_err.clear();
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if ((r = check_mps(out, "out"))) return r;
+  if ((r = check_mps(grad_out, "grad_out"))) return r;
+  if ((r = check_mps(grad_in, "grad_in"))) return r;
+  if (!W) return fail(QTT_ERR_ARG, "MPO is NULL");
+  return backward_common(view(in), W, nullptr, opts, saved, saved_bytes, view(out), view(grad_out), view(grad_in), ws,
+                         ws_bytes, stream);
+}
+
+int mpo_apply_backward_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt_opts* opts,
+                               const void* saved, size_t saved_bytes, const qtt_mps_batch* out,
+                               const qtt_mps_batch* grad_out, qtt_mps_batch* grad_in, void* ws, size_t ws_bytes,
+                               void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mpsb(in, "in"))) return r;
+  if ((r = check_mpsb(out, "out"))) return r;
+  if ((r = check_mpsb(grad_out, "grad_out"))) return r;
+  if ((r = check_mpsb(grad_in, "grad_in"))) return r;
+  if (!W) return fail(QTT_ERR_ARG, "MPO batch is NULL");
+  MpoB wb = mpob_view(W);
+  return backward_common(view(in), nullptr, &wb, opts, saved, saved_bytes, view(out), view(grad_out), view(grad_in),
+                         ws, ws_bytes, stream);
 }
 
 int tt_to_dense_backward(const qtt_mps* in, const void* grad_dense, qtt_mps* grad, void* ws, size_t ws_bytes,
                          void* stream) {
-  (void)in; (void)grad_dense; (void)grad; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(QTT_ERR_ARG, "tt_to_dense_backward: not available in this build");
+  g_err.clear();
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if ((r = check_mps(grad, "grad"))) return r;
+  return dense_bwd_common(view(in), grad_dense, view(grad), ws, ws_bytes, stream);
+}
+
+int tt_to_dense_backward_batched(const qtt_mps_batch* in, const void* grad_dense, qtt_mps_batch* grad, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mpsb(in, "in"))) return r;
+  if ((r = check_mpsb(grad, "grad"))) return r;
+  return dense_bwd_common(view(in), grad_dense, view(grad), ws, ws_bytes, stream);
+}
+
+int tt_intensity_loss(const void* field, const void* target, int dtype, int log2_side, int count, double* loss,
+                      void* grad, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  if (!field || !target || !loss || !ws) return fail(QTT_ERR_ARG, "NULL argument");
+  if (dtype != QTT_C64 && dtype != QTT_C128) return fail(QTT_ERR_DTYPE, "field dtype must be C64 or C128");
+  if (log2_side < 1 || log2_side > 15) return fail(QTT_ERR_SHAPE, "log2_side %d outside [1, 15]", log2_side);
+  if (count < 1) return fail(QTT_ERR_ARG, "count %d < 1", count);
+  if (ws_bytes < 256 + intensity_loss_ws(count)) return fail(QTT_ERR_WORKSPACE, "workspace too small");
+  const long long per = 1ll << (2 * log2_side);
+  HIPCHK(intensity_loss(field, target, dtype == QTT_C128 ? 1 : 0, per, count, loss, grad, (char*)ws + 256,
+                        (hipStream_t)stream));
+  return QTT_OK;
 }
 
 int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void* B, int ldb, int conj_b, void* C,

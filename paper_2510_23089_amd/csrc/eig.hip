@@ -709,6 +709,38 @@ __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long ks
   for (int t = threadIdx.x; t < ldo; t += blockDim.x) out[(long long)b * ldo + t] = t < k ? W.lam[t] : 0.0;
 }
 
+// Adjoint scaling (see kernels.h): one block per (row j, matrix b).
+__global__ void adj_scale_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase, int nb, int kc, void* Y,
+                                 long long ldy, long long s_batch, const int* kk, long long kk_stride, int kk_bound,
+                                 int dtype) {
+  const int b = blockIdx.y;
+  const int j = blockIdx.x;
+  const int n = min(dim_eval(nexp, b), nb);
+  const int kfull = min(kin[b * kstride], n);
+  const int kkb = min(kk[b * kk_stride], kk_bound);
+  EigWs W = eig_ws_carve(wsbase, b, nb, kc);
+  if (j >= n) return;
+  const double lj = W.lam[j < kc ? j : 0];
+  const double eps = 1e-15 * fabs(W.lam[0]) + 1e-300;
+  for (int i = threadIdx.x; i < kkb; i += blockDim.x) {
+    double f = 0.0;
+    if (j >= kkb && j < kfull) {
+      const double d = W.lam[i] - lj;
+      f = d / (d * d + eps * eps);
+    }
+    long long o = (long long)b * s_batch + (long long)j * ldy + i;
+    // rows outside [kk, kept) are stored as exact zeros (never read, so
+    // stale or non-finite contents cannot leak through a 0 * x product)
+    if (dtype == 0) {
+      float2 v = f != 0.0 ? ((float2*)Y)[o] : make_float2(0.f, 0.f);
+      ((float2*)Y)[o] = make_float2((float)(v.x * f), (float)(v.y * f));
+    } else {
+      double2 v = f != 0.0 ? ((double2*)Y)[o] : make_double2(0.0, 0.0);
+      ((double2*)Y)[o] = make_double2(v.x * f, v.y * f);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- host
 
 ProfHook g_prof;
@@ -723,7 +755,9 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   const int nb = sp.n_bound;
   if (nb < 1 || nb > EIG_NMAX || sp.batch < 1) return hipErrorInvalidValue;
   const int kc = sp.kcap < nb ? sp.kcap : nb;
-  const double tau = sp.tau > 0.0 ? sp.tau : 1e-13;
+  // tau == 0 selects the default; a negative tau keeps every computed pair
+  // (full decompositions for the adjoint)
+  const double tau = sp.tau == 0.0 ? 1e-13 : sp.tau;
   // profiled class: PROF_TRIDIAG = the streaming reduction (n > 128), the
   // dominant kernel; PROF_TRIDIAG_LDS = the LDS-resident one (n <= 128)
   const int cls = nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG;
@@ -761,6 +795,16 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   for (int i = 0; i < sp.nemit && i < 3; ++i) ep.e[i] = sp.emit[i];
   hipLaunchKernelGGL(backtr_kernel, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s, (const double2*)sp.G, sp.ld,
                      sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep);
+  return hipGetLastError();
+}
+
+hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long long s_batch, const int* kk,
+                             long long kk_stride, int kk_bound, int dtype, hipStream_t s) {
+  const int nb = sp.n_bound;
+  const int kc = sp.kcap < nb ? sp.kcap : nb;
+  if (kc < nb) return hipErrorInvalidValue;      // needs the full decomposition
+  hipLaunchKernelGGL(adj_scale_kernel, dim3(nb, sp.batch), dim3(64), 0, s, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc,
+                     Y, ldy, s_batch, kk, kk_stride, kk_bound, dtype);
   return hipGetLastError();
 }
 

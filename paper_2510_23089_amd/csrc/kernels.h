@@ -86,6 +86,12 @@ struct ProfHook {
 extern ProfHook g_prof;
 hipError_t eig_launch(const EigSpec& sp, hipStream_t s);
 hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s);
+// Eigenvector-adjoint scaling after a full decomposition (sp.kcap = n, every
+// pair kept): Y[j][i] (row j = eigenvector index, column i < kk[f]) becomes
+//   Y[j][i] / (lam_i - lam_j)  for kk[f] <= j < kept, and 0 otherwise,
+// with lam from the decomposition just run (regularised denominator).
+hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long long s_batch, const int* kk,
+                             long long kk_stride, int kk_bound, int dtype, hipStream_t s);
 
 // ---------------------------------------------------------------- misc
 // Quantics permutation of a row-major N x N image into the flat quantics
@@ -110,7 +116,15 @@ hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status,
 // Batched (nf fields) versions of the small helpers: field f adds f * stride.
 hipError_t block_copy_b(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst, long long d_rs,
                         long long d_cs, long long d_f, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
-                        int dtype, int nf, hipStream_t s);
+                        int dtype, int nf, hipStream_t s, int conj = 0);
+// Zero a buffer (bytes a multiple of 16) with a plain kernel.
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t s);
+// Phase-retrieval loss per field, L_f = sum (|E|^2 - I)^2, and its gradient
+// 4 (|E|^2 - I) E (NULL grad skips it).  dtype 0: complex64 field and float
+// target; 1: complex128 and double.  part: intensity_loss_ws(nf) bytes.
+size_t intensity_loss_ws(int nf);
+hipError_t intensity_loss(const void* field, const void* target, int dtype, long long per, int nf, double* loss,
+                          void* grad, void* part, hipStream_t s);
 hipError_t block_norm_b(const void* p, int dtype, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
                         long long ld_r, long long ld_c, long long s_f, double* out, int nf, hipStream_t s);
 hipError_t set_ints_strided(int* dev, int per, long long stride, int nf, int val, hipStream_t s);

@@ -2,6 +2,8 @@
 // Sec. 3 (row-major image <-> bit-interleaved vector), block copies, FP64
 // Frobenius norms and the non-finite scan.
 #include "common.h"
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace qtt {
@@ -185,24 +187,110 @@ hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status,
 // ---- batched helpers (field f = blockIdx.z or blockIdx.y)
 __global__ void block_copy_b_kernel(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst,
                                     long long d_rs, long long d_cs, long long d_f, DimExpr rows, DimExpr cols,
-                                    int cmax, int dtype) {
+                                    int cmax, int dtype, int conj) {
   const int f = blockIdx.z;
   const int nr = min(dim_eval(rows, f), (int)gridDim.y), nc = min(dim_eval(cols, f), cmax);
   const int r = blockIdx.y;
   if (r >= nr) return;
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += gridDim.x * blockDim.x) {
     long long so = f * s_f + r * s_rs + c * s_cs, dof = f * d_f + r * d_rs + c * d_cs;
-    if (dtype == 0) ((float2*)dst)[dof] = ((const float2*)src)[so];
-    else ((double2*)dst)[dof] = ((const double2*)src)[so];
+    if (dtype == 0) {
+      float2 v = ((const float2*)src)[so];
+      if (conj) v.y = -v.y;
+      ((float2*)dst)[dof] = v;
+    } else {
+      double2 v = ((const double2*)src)[so];
+      if (conj) v.y = -v.y;
+      ((double2*)dst)[dof] = v;
+    }
   }
 }
 hipError_t block_copy_b(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst, long long d_rs,
                         long long d_cs, long long d_f, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
-                        int dtype, int nf, hipStream_t s) {
+                        int dtype, int nf, hipStream_t s, int conj) {
   if (rows_bound < 1 || cols_bound < 1 || nf < 1) return hipSuccess;
   int bx = (cols_bound + 255) / 256;
   hipLaunchKernelGGL(block_copy_b_kernel, dim3(bx, rows_bound, nf), dim3(256), 0, s, src, s_rs, s_cs, s_f, dst, d_rs,
-                     d_cs, d_f, rows, cols, cols_bound, dtype);
+                     d_cs, d_f, rows, cols, cols_bound, dtype, conj);
+  return hipGetLastError();
+}
+
+// Zero `bytes` bytes (a multiple of 16) with vector stores; a plain kernel,
+// so it is safe inside captured graphs.
+__global__ void zero_fill_kernel(uint4* p, long long n16) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16; i += (long long)gridDim.x * blockDim.x)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+hipError_t zero_fill(void* p, size_t bytes, hipStream_t s) {
+  long long n16 = (long long)(bytes / 16);
+  if (n16 < 1) return hipSuccess;
+  int blocks = (int)std::min<long long>((n16 + 255) / 256, 4096);
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, s, (uint4*)p, n16);
+  return hipGetLastError();
+}
+
+// Intensity loss of the phase-retrieval problem, per field f:
+//   L_f = sum_px (|E|^2 - I)^2,  grad = dL/dRe + i dL/dIm = 4 (|E|^2 - I) E.
+// Two passes: per-block partial sums (fixed order), then one block per field.
+constexpr int IL_NT = 256;
+constexpr int IL_BLOCKS = 256;
+template <typename C, typename R>
+__global__ __launch_bounds__(IL_NT) void intensity_loss_kernel(const C* field, const R* target, long long per,
+                                                               C* grad, double* part) {
+  const int f = blockIdx.y;
+  const C* e = field + f * per;
+  const R* t = target + f * per;
+  C* g = grad ? grad + f * per : nullptr;
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)IL_NT + threadIdx.x; i < per; i += (long long)IL_BLOCKS * IL_NT) {
+    C v = e[i];
+    double re = v.x, im = v.y;
+    double d = re * re + im * im - (double)t[i];
+    acc += d * d;
+    if (g) {
+      C o;
+      o.x = (decltype(o.x))(4.0 * d * re);
+      o.y = (decltype(o.y))(4.0 * d * im);
+      g[i] = o;
+    }
+  }
+  __shared__ double red[IL_NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sm = 0.0;
+    for (int i = 0; i < IL_NT / 64; ++i) sm += red[i];
+    part[(long long)f * IL_BLOCKS + blockIdx.x] = sm;
+  }
+}
+__global__ __launch_bounds__(IL_BLOCKS) void loss_reduce_kernel(const double* part, double* out) {
+  const int f = blockIdx.x;
+  double v = part[(long long)f * IL_BLOCKS + threadIdx.x];
+  __shared__ double red[IL_BLOCKS / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sm = 0.0;
+    for (int i = 0; i < IL_BLOCKS / 64; ++i) sm += red[i];
+    out[f] = sm;
+  }
+}
+size_t intensity_loss_ws(int nf) { return (size_t)nf * IL_BLOCKS * sizeof(double); }
+hipError_t intensity_loss(const void* field, const void* target, int dtype, long long per, int nf, double* loss,
+                          void* grad, void* part, hipStream_t s) {
+  if (nf < 1 || per < 1) return hipSuccess;
+  dim3 g(IL_BLOCKS, nf);
+  if (dtype == 0)
+    hipLaunchKernelGGL((intensity_loss_kernel<float2, float>), g, dim3(IL_NT), 0, s, (const float2*)field,
+                       (const float*)target, per, (float2*)grad, (double*)part);
+  else
+    hipLaunchKernelGGL((intensity_loss_kernel<double2, double>), g, dim3(IL_NT), 0, s, (const double2*)field,
+                       (const double*)target, per, (double2*)grad, (double*)part);
+  hipLaunchKernelGGL(loss_reduce_kernel, dim3(nf), dim3(IL_BLOCKS), 0, s, (const double*)part, loss);
   return hipGetLastError();
 }
 

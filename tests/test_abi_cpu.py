@@ -89,3 +89,51 @@ def test_argument_errors_before_enqueue(lib):
     # tt_heev / tt_cgemm shape checks
     assert lib.tt_heev(fake, 1000, 1, 4, 0.0, 0.0, fake, fake, fake, fake, 1 << 30, None) == -2
     assert lib.tt_cgemm(0, 4, 4, fake, 4, 0, fake, 4, 0, fake, 4, L.PREC_FP32, None) == -2
+
+
+def test_adjoint_argument_errors(lib):
+    """The adjoint entry points validate on the host like the forward ones."""
+    from paper_2510_23089_amd import _lib as L
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.tt_saved_size(12, 32, 8, L.PREC_FP32) > 0
+    assert lib.tt_saved_size_batched(4, 12, 32, 8, L.PREC_FP32) > 3 * lib.tt_saved_size(12, 32, 8, L.PREC_FP32)
+    assert lib.tt_workspace_size(L.OP_APPLY_BACKWARD, 12, 32, 8, L.PREC_FP32) > 0
+    assert lib.tt_workspace_size(L.OP_TO_DENSE_BACKWARD, 12, 32, 1, L.PREC_FP32) > 0
+    assert lib.tt_workspace_size_batched(L.OP_LOSS, 3, 2, 1, 1, L.PREC_FP32) > 256
+    s = L.QttMps(12, 32, L.QTT_C64, 0x1000, 0x2000, 0)
+    out = L.QttMps(12, 32, L.QTT_C64, 0x5000, 0x6000, 0)
+    go = L.QttMps(12, 32, L.QTT_C64, 0x7000, 0x6000, 0)
+    gi = L.QttMps(12, 32, L.QTT_C64, 0x9000, 0x2000, 0)
+    o = L.QttOpts(16, 0, 0.0, 0.0, L.PREC_FP32)
+    bonds = (ctypes.c_int32 * 13)(*([1] + [2] * 11 + [1]))
+    w = L.QttMpo(12, 2, L.QTT_C64, 0x3000, ctypes.cast(bonds, ctypes.c_void_p), None)
+    args = (ctypes.byref(s), ctypes.byref(w), ctypes.byref(o))
+    # no saved buffer
+    rc = lib.mpo_apply_backward(*args, None, 0, ctypes.byref(out), ctypes.byref(go), ctypes.byref(gi), fake, 1 << 30,
+                                None)
+    assert rc == -1
+    # saved buffer too small
+    rc = lib.mpo_apply_backward(*args, fake, 16, ctypes.byref(out), ctypes.byref(go), ctypes.byref(gi), fake, 1 << 30,
+                                None)
+    assert rc == -4 and b"saved" in lib.tt_last_error()
+    # grad_in aliasing the input
+    rc = lib.mpo_apply_backward(*args, fake, 1 << 40, ctypes.byref(out), ctypes.byref(go), ctypes.byref(s), fake,
+                                1 << 30, None)
+    assert rc == -1
+    # grad_out of a different capacity than out
+    go2 = L.QttMps(12, 16, L.QTT_C64, 0x7000, 0x6000, 0)
+    rc = lib.mpo_apply_backward(*args, fake, 1 << 40, ctypes.byref(out), ctypes.byref(go2), ctypes.byref(gi), fake,
+                                1 << 30, None)
+    assert rc == -2
+    # forward with a too-small saved buffer
+    rc = lib.mpo_apply(ctypes.byref(s), ctypes.byref(w), ctypes.byref(o), ctypes.byref(out), fake, 16, fake, 1 << 30,
+                       None)
+    assert rc == -4
+    # decompression adjoint: dtype mismatch, aliasing
+    g64 = L.QttMps(12, 32, L.QTT_C128, 0x9000, 0x2000, 0)
+    assert lib.tt_to_dense_backward(ctypes.byref(s), fake, ctypes.byref(g64), fake, 1 << 30, None) == -2
+    assert lib.tt_to_dense_backward(ctypes.byref(s), fake, ctypes.byref(s), fake, 1 << 30, None) == -1
+    # loss: bad dtype, bad side, small workspace
+    assert lib.tt_intensity_loss(fake, fake, L.QTT_F32, 4, 1, fake, None, fake, 1 << 20, None) == -3
+    assert lib.tt_intensity_loss(fake, fake, L.QTT_C64, 0, 1, fake, None, fake, 1 << 20, None) == -2
+    assert lib.tt_intensity_loss(fake, fake, L.QTT_C64, 4, 1, fake, None, fake, 8, None) == -4
