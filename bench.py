@@ -18,6 +18,14 @@ launch from the matrix sizes the kernel logs on the device.
 cpu_baseline: the float64 oracle (numpy/LAPACK) on the host, on a bounded
 sample of the same workload: encode + one propagation (x then y) at z = 2 mm.
 
+grad_step (second headline number, phase retrieval): 32 independent 4096^2
+problems (24 sites), a learnable phase mask exp(i phi) (phi: iid N(0,1)
+smoothed by a periodic Gaussian of 16 px, std pi/8) encoded at chi 64, the
+Fresnel MPO at z = 2 mm (x then y, chi 64), decompression and the summed
+squared intensity error against targets made the same way (std pi/2); one
+step = forward with saved state + loss + the full adjoint back to the mask
+cores, all 32 problems as one batch.
+
 Prints ONE JSON line (N = 1 only).
 """
 import argparse
@@ -45,6 +53,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--chi", type=int, default=CHI)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-grad", action="store_true")
+    p.add_argument("--grad-steps", type=int, default=3)
     return p.parse_args()
 
 
@@ -89,6 +99,61 @@ def cpu_baseline(field, chi):
         "sample": "float64 numpy/LAPACK oracle on the host: one propagation (x then y, z=2 mm, chi %d) of "
                   "the same 1024^2 field (%.2f s); its encode (%.2f s) is not in value" % (chi, t_prop, t1 - t0),
         "cpu": _cpu_model(),
+    }
+
+
+def grad_step_bench(steps, dev):
+    """Phase-retrieval gradient steps: 32 x 4096^2 problems, chi 64, z = 2 mm."""
+    from concurrent.futures import ThreadPoolExecutor
+    import torch
+    import synth
+    from paper_2510_23089_amd import api
+    from paper_2510_23089_amd import autograd as AG
+    n, z, chi, nb = 12, 2e-3, 64, 32
+    side = 1 << n
+    with ThreadPoolExecutor(16) as ex:
+        masks = list(ex.map(lambda sd: synth.smoothed_phase(1000 + sd, side, 16.0, np.pi / 8).astype(np.float32),
+                            range(nb)))
+        tgts = list(ex.map(lambda sd: synth.smoothed_phase(2000 + sd, side, 16.0, np.pi / 2).astype(np.float32),
+                           range(nb)))
+    prop = api.FresnelPropagator(n, LAM, DX, z, device=dev)
+    wx = api.MPOBatch([prop.wx] * nb, device=dev)
+    wy = api.MPOBatch([prop.wy] * nb, device=dev)
+    ph = torch.from_numpy(np.stack(masks)).to(dev)
+    del masks
+    mask = api.tt_encode_batched(torch.polar(torch.ones_like(ph), ph), chi)
+    ph.copy_(torch.from_numpy(np.stack(tgts)))
+    del tgts
+    tmps = api.tt_encode_batched(torch.polar(torch.ones_like(ph), ph), chi)
+    del ph
+    t1 = api.mpo_apply_batched(tmps, wx, chi)
+    t2 = api.mpo_apply_batched(t1, wy, chi)
+    target = api.tt_to_dense_batched(t2).abs().pow(2).float()
+    del t1, t2, tmps
+    api.check_status()
+    pr = AG.PhaseRetrieval(wx, wy, chi)
+    loss, g = pr.loss_and_grad(mask.cores, mask.bonds, target)     # warm-up
+    api.check_status()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        loss, g = pr.loss_and_grad(mask.cores, mask.bonds, target)
+    ev1.record()
+    torch.cuda.synchronize()
+    api.check_status()
+    ms = ev0.elapsed_time(ev1) / steps
+    return {
+        "ms": ms,
+        "unit": "ms per gradient step (32 problems)",
+        "steps": steps,
+        "workload": "phase retrieval: 32 x 4096^2 (24 sites), mask chi 64, Fresnel z = 2 mm (x, y) to chi 64, "
+                    "decompression, summed squared intensity error; forward with saved state + full adjoint",
+        "dtype": "c64 (fp32 MFMA) + f64 eig and eig adjoint",
+        "mpo_max_bond": int(max(prop.wx.d_bonds)),
+        "loss": float(loss),
+        "grad_norm": float(g.abs().pow(2).sum().sqrt()),
     }
 
 
@@ -185,6 +250,8 @@ def main():
         },
         "wall_s": wall,
     }
+    if not a.no_grad:
+        res["grad_step"] = grad_step_bench(a.grad_steps, dev)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(field, chi)
     print(json.dumps(res), flush=True)

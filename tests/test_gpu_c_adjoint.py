@@ -4,8 +4,10 @@ central finite differences of the GPU's own FP64 forward.
 
 Both sides start from the same cores and the same (oracle-built) MPO cores,
 so the truncations are identical; the compared quantity is the gradient on
-the input cores, which is gauge invariant.  Bars: FP64 path 1e-7, FP32 path
-1e-3 relative L2 over all entries.
+the input cores, which is gauge invariant.  Bars (relative L2 over all
+entries): linear functional through two truncated applications 1e-10 (FP64)
+and 1e-4 (FP32); phase-retrieval loss gradient 1e-8 (FP64) and 2e-4 (FP32),
+the FP32 bar being tighter than the 1e-3 proposed for this adjoint.
 """
 import numpy as np
 import pytest
@@ -130,7 +132,7 @@ def test_apply_backward_linear_functional_vs_oracle(prec, n, chi, z):
     assert g_in.host_bonds() == psi.host_bonds()
     err = _rel_list(got, ref)
     say("  rel err", err)
-    assert err < (1e-3 if prec == "fp32" else 1e-7)
+    assert err < (1e-4 if prec == "fp32" else 1e-10)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -162,7 +164,7 @@ def test_phase_retrieval_gradient_vs_oracle(prec):
     assert abs(float(loss) - loss_ref) < lt * loss_ref
     err = _rel_list(got, gref)
     say("  rel err", err)
-    assert err < (1e-3 if prec == "fp32" else 1e-7)
+    assert err < (2e-4 if prec == "fp32" else 1e-8)
 
 
 def test_phase_retrieval_fd_on_gpu_fp64():
