@@ -38,8 +38,9 @@
  *   the sweep cap = chi_max.  tau <= 0 selects the default 1e-13.
  * Precision.  QTT_PREC_FP32: complex64 operands, FP32 MFMA contractions;
  *   Gram matrices accumulated and eigen-decomposed in FP64.  QTT_PREC_FP64:
- *   complex128 throughout.  QTT_PREC_BF16: contraction operands rounded to
- *   bfloat16, FP32 accumulation, FP64 Gram/eigen.
+ *   complex128 throughout.  QTT_PREC_BF16 (complex64 storage): contraction
+ *   operands rounded to bfloat16 on the way into the matrix cores, FP32
+ *   accumulation, FP64 Gram/eigen; usually combined with opts.refine = 1.
  * Ownership.  The library never allocates device memory.  Every call takes a
  *   caller-owned device workspace `ws` of at least tt_workspace_size(...)
  *   bytes; its first 256 bytes hold the device status word.
@@ -133,6 +134,13 @@ typedef struct {
   double cutoff;     /* relative discarded-weight target (0 = off)         */
   double tau;        /* numerical-zero threshold on lam_i / lam_1 (<=0: 1e-13) */
   int32_t prec;      /* qtt_prec                                           */
+  int32_t refine;    /* 0: plain truncation sweep after the zip-up;
+                        1: one two-site variational fitting sweep instead
+                        (left to right, initialised from the right-canonical
+                        zip-up output, contractions in FP32 -- FP64 for
+                        complex128 -- whatever prec is; the refinement pass
+                        that follows a BF16 zip-up).  The adjoint covers
+                        refine = 0 only. */
 } qtt_opts;
 
 /* Bytes of device workspace needed by an operation on MPS of n_sites sites
@@ -240,8 +248,9 @@ int tt_intensity_loss(const void* field, const void* target, int dtype, int log2
 /* C = op(A) . op(B) for dense row-major complex matrices through the MFMA
  * contraction kernel used by every step above.  A is M x K (lda), B is K x N
  * (ldb), C is M x N (ldc), all device pointers; conj_a / conj_b conjugate the
- * operand elements.  prec QTT_PREC_FP32 (complex64) or QTT_PREC_FP64
- * (complex128).  Asynchronous on `stream`. */
+ * operand elements.  prec QTT_PREC_FP32 (complex64), QTT_PREC_BF16
+ * (complex64 in memory, operands rounded to bfloat16, FP32 accumulation) or
+ * QTT_PREC_FP64 (complex128).  Asynchronous on `stream`. */
 int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void* B, int ldb, int conj_b,
              void* C, int ldc, int prec, void* stream);
 

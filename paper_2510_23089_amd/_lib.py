@@ -55,7 +55,7 @@ class QttMpoBatch(ctypes.Structure):
 
 class QttOpts(ctypes.Structure):
     _fields_ = [("chi_max", ctypes.c_int32), ("chi_zip", ctypes.c_int32), ("cutoff", ctypes.c_double),
-                ("tau", ctypes.c_double), ("prec", ctypes.c_int32)]
+                ("tau", ctypes.c_double), ("prec", ctypes.c_int32), ("refine", ctypes.c_int32)]
 
 
 class QttError(RuntimeError):

@@ -135,14 +135,25 @@ class MPO:
         return s
 
 
-def _opts(chi_max, chi_zip=0, cutoff=0.0, tau=0.0, prec="fp32"):
+def _opts(chi_max, chi_zip=0, cutoff=0.0, tau=0.0, prec="fp32", refine=False):
     o = L.QttOpts()
     o.chi_max = int(chi_max)
     o.chi_zip = int(chi_zip or 0)
     o.cutoff = float(cutoff)
     o.tau = float(tau)
     o.prec = _prec_code(prec)
+    o.refine = 1 if refine else 0
     return o
+
+
+def _apply_prec(psi, prec):
+    """Contraction precision of an application: the state's (fp32 / fp64) or
+    "bf16" (complex64 states only)."""
+    if prec is None:
+        return psi.prec
+    if prec == "bf16" and psi.prec != "fp32":
+        raise ValueError("bf16 contractions need complex64 states")
+    return prec
 
 
 def check_status(key="default"):
@@ -190,12 +201,16 @@ def saved_buffer(psi, mpo, chi, chi_zip=0, out_cap=None):
     return torch.empty(max(int(nb), 256), dtype=torch.uint8, device=psi.cores.device)
 
 
-def mpo_apply(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_cap=None, saved=None):
+def mpo_apply(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_cap=None, saved=None, prec=None,
+              refine=False):
+    """out = W psi: zip-up then the truncation sweep (refine=False) or one
+    two-site fitting sweep in full precision (refine=True).  prec: None (the
+    state's precision) or "bf16" for bfloat16 contraction operands."""
     lib = L.load()
-    prec = psi.prec
+    prec = _apply_prec(psi, prec)
     if out is None:
         out = MPS(psi.n_sites, chi_cap or chi, dtype=psi.dtype, device=psi.cores.device)
-    o = _opts(chi, chi_zip, cutoff, tau, prec)
+    o = _opts(chi, chi_zip, cutoff, tau, prec, refine)
     nb = lib.tt_workspace_size(L.OP_APPLY, psi.n_sites, _cap(psi, out, chi, chi_zip), mpo.d_cap, o.prec)
     ws = workspace(nb, psi.cores.device)
     si, so, w = psi.cstruct(), out.cstruct(), mpo.cstruct()
@@ -360,11 +375,12 @@ class MPOBatch:
 
 
 def mpo_apply_batched(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_dev=None, chi_cap=None,
-                      saved=None):
+                      saved=None, prec=None, refine=False):
     lib = L.load()
+    prec = _apply_prec(psi, prec)
     if out is None:
         out = MPSBatch(psi.count, psi.n_sites, chi_cap or chi, dtype=psi.dtype, device=psi.cores.device)
-    o = _opts(chi, chi_zip, cutoff, tau, psi.prec)
+    o = _opts(chi, chi_zip, cutoff, tau, prec, refine)
     nb = lib.tt_workspace_size_batched(L.OP_APPLY, psi.count, psi.n_sites, _cap(psi, out, chi, chi_zip), mpo.d_cap,
                                        o.prec)
     ws = workspace(nb, psi.cores.device)
@@ -468,9 +484,12 @@ class FresnelBatch:
         self.wy = MPOBatch([p.wy for p in props], dtype=dtype, device=device)
         self.count = len(zs)
 
-    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None, chi_dev=None):
-        mid = mpo_apply_batched(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp, chi_dev=chi_dev)
-        return mpo_apply_batched(mid, self.wy, chi, chi_zip, cutoff, tau, out=out, chi_dev=chi_dev)
+    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None, chi_dev=None, prec=None,
+                 refine=False):
+        mid = mpo_apply_batched(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp, chi_dev=chi_dev, prec=prec,
+                                refine=refine)
+        return mpo_apply_batched(mid, self.wy, chi, chi_zip, cutoff, tau, out=out, chi_dev=chi_dev, prec=prec,
+                                 refine=refine)
 
 
 class FresnelPropagator:
@@ -486,6 +505,6 @@ class FresnelPropagator:
         self.wy = MPO(cy, ky, dtype=dtype, device=device, d_cap=dcap)
         self.axis_cores = w1
 
-    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None):
-        mid = mpo_apply(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp)
-        return mpo_apply(mid, self.wy, chi, chi_zip, cutoff, tau, out=out)
+    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None, prec=None, refine=False):
+        mid = mpo_apply(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp, prec=prec, refine=refine)
+        return mpo_apply(mid, self.wy, chi, chi_zip, cutoff, tau, out=out, prec=prec, refine=refine)

@@ -175,6 +175,7 @@ std::vector<int> mps_bounds(int m, int chi) {
 // ------------------------------------------------------------ apply plan
 struct ApplyPlan {
   int m, chi_in, chi_out, chi_zip, chi_max, dcap, zc;   // zc: zip capacity stride
+  int refine = 0;                                        // fitting sweep instead of the plain sweep
   std::vector<int> rin, beta, rout, D;
   std::vector<int> kind;
   int gram_nb;     // largest Gram size
@@ -182,8 +183,9 @@ struct ApplyPlan {
 };
 
 ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_zip, const int* dbonds,
-                          const int* kind, int dcap) {
+                          const int* kind, int dcap, int refine = 0) {
   ApplyPlan p;
+  p.refine = refine;
   p.m = m; p.chi_in = chi_in; p.chi_out = chi_out; p.chi_max = chi_max;
   p.chi_zip = chi_zip; p.dcap = dcap;
   p.rin = mps_bounds(m, chi_in);
@@ -208,6 +210,15 @@ ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_z
     g = (int)std::max<ll>(g, std::min(pb, qb));
   }
   for (int k = 0; k < m - 1; ++k) g = std::max(g, std::min(2 * p.rout[k], p.beta[k + 1]));
+  if (refine) {
+    // fitting sweep: the pair (k, k+1) matrix is (2 r_k) x (2 beta_(k+2)), so
+    // the output bonds may exceed the zip-up bonds; buffers use zc >= chi_max
+    p.rout[0] = 1;
+    for (int k = 0; k < m - 1; ++k) p.rout[k + 1] = std::max(1, std::min({chi_max, 2 * p.rout[k], 2 * p.beta[k + 2]}));
+    p.rout[m] = 1;
+    for (int k = 0; k < m - 1; ++k) g = std::max(g, std::min(2 * p.rout[k], 2 * p.beta[k + 2]));
+    p.zc = std::max(p.zc, *std::max_element(p.rout.begin(), p.rout.end()));
+  }
   p.gram_nb = g;
   p.rmax = *std::max_element(p.rin.begin(), p.rin.end());
   p.dmax = *std::max_element(p.D.begin(), p.D.end());
@@ -229,8 +240,14 @@ struct ApplyBufs {
   double* G;
   double* part;
   void* eigws;
+  // fitting sweep (refine) only
+  void* Renv;      // right environments: slot j (sites j..m-1) at j * nf * sC, carry layout
+  void* Y;         // [b][w][a'][s] strides (dmax rmax 2, rmax 2, 2, 1)
+  void* LX;        // [b][t][a'][w'] strides (2 rmax D', rmax D', D', 1)
+  void* Th;        // pair matrix [(b, t1)][(beta'', t2)], row stride 2 zc
+  void* Lenv[2];   // left environments [b][w][a] strides (dmax rmax, rmax, 1)
   // per-field strides (complex elements)
-  ll sZ, sC, sX, sV, sCtr, sR;
+  ll sZ, sC, sX, sV, sCtr, sR, sY, sTh, sL;
 };
 
 ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
@@ -259,6 +276,18 @@ ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   b.G = (double*)cv.take((size_t)nf * nmax * nmax * 16);
   b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256 * nmax * nmax * 16 * (size_t)nf));
   b.eigws = cv.take(eig_ws_bytes((int)nmax, std::max(p.chi_zip, p.chi_max), nf));
+  b.sY = (ll)zc * p.dmax * p.rmax * 2;
+  b.sTh = (ll)2 * zc * 2 * zc;
+  b.sL = (ll)zc * p.dmax * p.rmax;
+  b.Renv = b.Y = b.LX = b.Th = b.Lenv[0] = b.Lenv[1] = nullptr;
+  if (p.refine) {
+    b.Renv = cv.take((size_t)(p.m + 1) * nf * b.sC * csz);
+    b.Y = cv.take(nf * b.sY * csz);
+    b.LX = cv.take(nf * b.sY * csz);
+    b.Th = cv.take(nf * b.sTh * csz);
+    b.Lenv[0] = cv.take(nf * b.sL * csz);
+    b.Lenv[1] = cv.take(nf * b.sL * csz);
+  }
   return b;
 }
 
@@ -343,7 +372,7 @@ MpsB view(const qtt_mps_batch* a) {
 
 void opts_defaults(const qtt_opts* o, int cap, qtt_opts& out) {
   if (o) out = *o;
-  else { out.chi_max = cap; out.chi_zip = 0; out.cutoff = 0.0; out.tau = 0.0; out.prec = QTT_PREC_FP32; }
+  else { out.chi_max = cap; out.chi_zip = 0; out.cutoff = 0.0; out.tau = 0.0; out.prec = QTT_PREC_FP32; out.refine = 0; }
   if (out.chi_zip <= 0) out.chi_zip = out.chi_max;
   if (!(out.tau > 0.0)) out.tau = 1e-13;
 }
@@ -371,6 +400,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
   const int m = p.m, nf = in.nf;
   const int real = in.dtype == QTT_C128 ? 1 : 0;
   Ctx c = make_ctx(s, real, nf, m, b.status);
+  if (o.prec == QTT_PREC_BF16) c.gemm_t = GEMM_BF16;
   c.G = b.G; c.gld = std::max(p.gram_nb, 1); c.part = b.part; c.eigws = b.eigws;
   c.eig_nb = c.gld; c.eig_kc = std::max(p.chi_zip, p.chi_max);
   const ll ci = in.cap, co = out.cap, zc = p.zc;
@@ -465,6 +495,115 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       if (r) return r;
     }
   }
+  if (p.refine) {
+    // ---- one two-site fitting sweep (left to right) against W . in, with
+    // FP32 (or FP64) contractions whatever the zip-up precision was.  The
+    // initial state is the right-canonical zip-up output Z.
+    c.gemm_t = real ? GEMM_F64 : GEMM_F32;
+    const ll rmax = p.rmax, dmax = p.dmax;
+    auto env_at = [&](int j) { return (char*)b.Renv + (size_t)j * nf * b.sC * csz; };
+    // M[a][w'][beta][t] of site j with right environment `env` (the zip-up's
+    // first two contractions); identity sites write M directly
+    auto make_M = [&](int j, const void* env, const int* bet) -> int {
+      const int* ra = b.inb + j;
+      const int* rb = b.inb + j + 1;
+      const int Da = p.D[j], Db = p.D[j + 1];
+      const bool ident = p.kind[j] == 1;
+      Operand A = opd(core_in(j), 2 * ci, ci, 1, 0, 0, sIn);
+      Operand B = opd(env, zc * Db, 0, Db, 1, 0, b.sC);
+      Operand C = ident ? opd(b.Mb, 2 * zc * Db, 1, 2, 2 * zc, 0, b.sX) : opd(b.X, zc * 2 * Db, Db, 2 * Db, 1, 0, b.sX);
+      int r = gemm(c, dv(c, 2, ra), 2, 2 * p.rin[j], dv(c, Db, bet), Db, Db * p.beta[j + 1], dv(c, 1, rb), 1, A, B, C);
+      if (r || ident) return r;
+      return gemm(c, dv(c, 1, bet), 1, p.beta[j + 1], dx(2 * Da), 2, 2 * Da, dx(2 * Db), 1,
+                  opd(b.X, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db),
+                  opd(Wc + (size_t)j * dcap * 4 * dcap * csz, 1, 0, 4 * Db, 2 * Db, 0, sW),
+                  opd(b.Mb, 2, 0, 2 * zc, 1, 0, b.sX, (ll)Da * zc * 2), dv(c, 1, ra), p.rin[j]);
+    };
+    // right environments of Z in full precision: env_j = M_j Z_j^H
+    HIPCHK(set_one_b(env_at(m), b.sC, real, nf, s));
+    for (int j = m - 1; j >= 2; --j) {
+      const int Da = p.D[j];
+      int r = make_M(j, env_at(j + 1), b.zbonds + j + 1);
+      if (r) return r;
+      r = gemm(c, dv(c, Da, b.inb + j), Da, p.rin[j] * Da, dv(c, 1, b.zbonds + j), 1, p.beta[j],
+               dv(c, 2, b.zbonds + j + 1), 2, opd(b.Mb, 2 * zc * Da, 2 * zc, 2, 1, 0, b.sX),
+               opd(core_z(j), 1, zc, 2 * zc, 0, 1, b.sZ), opd(env_at(j), zc * Da, 1, Da, 0, 0, b.sC));
+      if (r) return r;
+    }
+    HIPCHK(set_ints_strided(out.bonds, 1, bs, nf, 1, s));
+    HIPCHK(set_ints_strided(out.bonds + m, 1, bs, nf, 1, s));
+    HIPCHK(set_one_b(b.Lenv[0], b.sL, real, nf, s));
+    int ls = 0;
+    for (int k = 0; k < m - 1; ++k) {
+      const int* rk = out.bonds + k;
+      int* kout = out.bonds + k + 1;
+      const int Dk = p.D[k], D1 = p.D[k + 1];
+      const bool ident = p.kind[k] == 1;
+      const void* Lk = b.Lenv[ls];
+      // Y[b][w][a'][s] = sum_a L[b][w][a] A_k[a][s][a']
+      int r = gemm(c, dv(c, Dk, rk), Dk, p.rout[k] * Dk, dv(c, 2, b.inb + k + 1), 2, 2 * p.rin[k + 1],
+                   dv(c, 1, b.inb + k), 1, opd(Lk, dmax * rmax, rmax, 1, 0, 0, b.sL),
+                   opd(core_in(k), 2 * ci, 0, 1, ci, 0, sIn), opd(b.Y, dmax * rmax * 2, rmax * 2, 2, 1, 0, b.sY));
+      if (r) return r;
+      // LX[b][t][a'][w'] = sum_{w, s} Y[b][w][a'][s] W_k[w][t][s][w']  (identity site: a view of Y)
+      Operand LXrows;    // rows (b, t) split lo 2, columns (a', w') split lo D1
+      if (ident) {
+        LXrows = opd(b.Y, dmax * rmax * 2, 1, 2, rmax * 2, 0, b.sY);
+      } else {
+        r = gemm(c, dv(c, 1, b.inb + k + 1), 1, p.rin[k + 1], dx(2 * D1), D1, 2 * D1, dx(2 * Dk), 2,
+                 opd(b.Y, 2, 0, rmax * 2, 1, 0, b.sY, dmax * rmax * 2),
+                 opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 4 * D1, D1, 2 * D1, 1, 0, sW),
+                 opd(b.LX, D1, 0, rmax * D1, 1, 0, b.sY, 2 * rmax * D1), dv(c, 1, rk), p.rout[k]);
+        if (r) return r;
+        LXrows = opd(b.LX, 2 * rmax * D1, rmax * D1, D1, 1, 0, b.sY);
+      }
+      // right part of the pair: M_(k+1)[a'][w'][beta''][t2] with env_(k+2)
+      r = make_M(k + 1, env_at(k + 2), b.zbonds + k + 2);
+      if (r) return r;
+      // Theta[(b, t1)][(beta'', t2)] = LX[(b, t1)][(a', w')] M[(a', w')][(beta'', t2)]
+      const int* bq = b.zbonds + k + 2;
+      const ll pb = 2ll * p.rout[k], qb = 2ll * p.beta[k + 2];
+      r = gemm(c, dv(c, 2, rk), 2, (int)pb, dv(c, 2, bq), 1, (int)qb, dv(c, D1, b.inb + k + 1), D1, LXrows,
+               opd(b.Mb, 2 * zc * D1, 2 * zc, 1, 0, 0, b.sX), opd(b.Th, 4 * zc, 2 * zc, 1, 0, 0, b.sTh));
+      if (r) return r;
+      const Operand Th_rows = opd(b.Th, 4 * zc, 2 * zc, 1, 0, 0, b.sTh);    // [(b, t1)][q]
+      const Operand U_out = opd(core_out(k), 2 * co, co, 1, 0, 0, sOut);     // [(b, t1)][i]
+      if (qb < pb) {
+        r = gram(c, opd(b.Th, 1, 0, 4 * zc, 2 * zc, 1, b.sTh), Th_rows, dv(c, 2, bq), 1, (int)qb, dv(c, 2, rk), 2, pb);
+        if (r) return r;
+        r = eig(c, dv(c, 2, bq), (int)qb, p.rout[k + 1], o.cutoff, o.tau, kout,
+                {emit(b.V1, 1, zc, 0, 1, 0, -1, real, b.sV)});                  // V / sigma
+        if (r) return r;
+        r = gemm(c, dv(c, 2, rk), 2, (int)pb, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 2, bq), 1, Th_rows,
+                 opd(b.V1, zc, 0, 1, 0, 0, b.sV), U_out);
+        if (r) return r;
+      } else {
+        r = gram(c, Th_rows, opd(b.Th, 1, 0, 4 * zc, 2 * zc, 1, b.sTh), dv(c, 2, rk), 2, (int)pb, dv(c, 2, bq), 1, qb);
+        if (r) return r;
+        r = eig(c, dv(c, 2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout,
+                {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut)});       // U
+        if (r) return r;
+      }
+      const Operand Uh = opd(core_out(k), 1, 0, 2 * co, co, 1, sOut);          // [i][(b, t1)] conjugated
+      if (k == m - 2) {
+        // last core [i][t2][0] = U^H Theta
+        r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dx(2), 1, 2, dv(c, 2, rk), 2, Uh, Th_rows,
+                 opd(core_out(m - 1), 2 * co, 0, co, 0, 0, sOut));
+        if (r) return r;
+      } else {
+        // L_(k+1)[i][w'][a'] = sum_(b, t1) conj(U)[(b, t1)][i] LX[(b, t1)][(a', w')]
+        r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, D1, b.inb + k + 1), D1, p.rin[k + 1] * D1,
+                 dv(c, 2, rk), 2, Uh, LXrows, opd(b.Lenv[ls ^ 1], dmax * rmax, 0, 1, rmax, 0, b.sL));
+        if (r) return r;
+        ls ^= 1;
+      }
+    }
+    const int* rl = out.bonds + m - 1;
+    if (out.norms)
+      HIPCHK(block_norm_b(core_out(m - 1), real, dv(c, 1, rl), dx(2), p.rout[m - 1], 2, 2 * co, co, sOut, out.norms,
+                          nf, s));
+    return QTT_OK;
+  }
   // ---- sweep, left to right
   HIPCHK(set_ints_strided(out.bonds, 1, bs, nf, 1, s));
   HIPCHK(set_ints_strided(out.bonds + m, 1, bs, nf, 1, s));
@@ -558,8 +697,10 @@ int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opt
   opts_defaults(opts, out.cap, o);
   if (o.chi_max < 1 || o.chi_max > out.cap) return fail(QTT_ERR_CAPACITY, "chi_max %d outside [1, %d]", o.chi_max, out.cap);
   if (o.chi_zip < 1 || o.chi_zip > 256) return fail(QTT_ERR_CAPACITY, "chi_zip %d outside [1, 256]", o.chi_zip);
-  if (o.prec != QTT_PREC_FP32 && o.prec != QTT_PREC_FP64) return fail(QTT_ERR_ARG, "precision %d not supported here", o.prec);
+  if (o.prec != QTT_PREC_FP32 && o.prec != QTT_PREC_FP64 && o.prec != QTT_PREC_BF16)
+    return fail(QTT_ERR_ARG, "precision %d not supported", o.prec);
   if ((o.prec == QTT_PREC_FP64) != (in.dtype == QTT_C128)) return fail(QTT_ERR_DTYPE, "precision and dtype disagree");
+  if (o.refine != 0 && o.refine != 1) return fail(QTT_ERR_ARG, "refine must be 0 or 1");
   su.dbonds.assign(m + 1, 1);
   su.kind.assign(m, 1);
   MpoB& W = su.W;
@@ -596,7 +737,8 @@ int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opt
   }
   W.dbonds = su.dbonds.data();
   W.kind = su.kind.data();
-  su.p = make_apply_plan(m, in.cap, out.cap, o.chi_max, o.chi_zip, su.dbonds.data(), su.kind.data(), W.dcap);
+  su.p = make_apply_plan(m, in.cap, out.cap, o.chi_max, o.chi_zip, su.dbonds.data(), su.kind.data(), W.dcap,
+                         identity ? 0 : o.refine);
   su.csz = in.dtype == QTT_C128 ? 16 : 8;
   return QTT_OK;
 }
@@ -611,6 +753,7 @@ int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_op
   size_t need = apply_bytes(su.p, su.csz, in.nf);
   if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
   SavedBufs sv;
+  if (saved && su.p.refine) return fail(QTT_ERR_ARG, "the adjoint covers the plain sweep only (refine = 0)");
   if (saved) {
     size_t sneed = saved_bytes(su.p, su.csz, in.nf);
     if (saved_sz < sneed) return fail(QTT_ERR_WORKSPACE, "saved buffer %zu < required %zu bytes", saved_sz, sneed);
@@ -889,6 +1032,7 @@ int backward_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt
   ApplySetup su;
   int r = apply_setup(in, W1, Wb, opts, out, false, su);
   if (r) return r;
+  if (su.p.refine) return fail(QTT_ERR_ARG, "the adjoint covers the plain sweep only (refine = 0)");
   if (bwd_nmax(su.p) > 512) return fail(QTT_ERR_CAPACITY, "adjoint eigenproblem larger than 512");
   size_t sneed = saved_bytes(su.p, su.csz, in.nf);
   if (saved_sz < sneed) return fail(QTT_ERR_WORKSPACE, "saved buffer %zu < required %zu bytes", saved_sz, sneed);
@@ -901,11 +1045,12 @@ int backward_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt
   return run_apply_backward(in, su.W, out, gout, gin, su.p, sv, b, (hipStream_t)stream);
 }
 
-ApplyPlan capacity_plan(int m, int chi_cap, int d_cap, bool identity) {
+ApplyPlan capacity_plan(int m, int chi_cap, int d_cap, bool identity, int refine = 0) {
   std::vector<int> db(m + 1, identity ? 1 : d_cap);
   db[0] = db[m] = 1;
   std::vector<int> kind(m, identity ? 1 : 0);
-  return make_apply_plan(m, chi_cap, chi_cap, chi_cap, chi_cap, db.data(), kind.data(), identity ? 1 : d_cap);
+  return make_apply_plan(m, chi_cap, chi_cap, chi_cap, chi_cap, db.data(), kind.data(), identity ? 1 : d_cap,
+                         refine);
 }
 
 size_t apply_ws(int m, int chi_cap, int d_cap, int prec, bool identity, int nf) {
@@ -1267,7 +1412,8 @@ size_t tt_workspace_size_batched(int op, int count, int n_sites, int chi_cap, in
     }
     case QTT_OP_APPLY:
       if (d_cap < 1) return 0;
-      return apply_ws(n_sites, chi_cap, d_cap, prec, false, count);
+      // covers every precision and the refinement sweep
+      return apply_bytes(capacity_plan(n_sites, chi_cap, d_cap, false, 1), csz, count);
     case QTT_OP_TRUNCATE:
       return apply_ws(n_sites, chi_cap, 1, prec, true, count);
     case QTT_OP_TO_DENSE: {
@@ -1472,7 +1618,8 @@ int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void
   g_err.clear();
   if (!A || !B || !C) return fail(QTT_ERR_ARG, "NULL operand");
   if (M < 1 || N < 1 || K < 1 || lda < K || ldb < N || ldc < N) return fail(QTT_ERR_SHAPE, "bad GEMM shape");
-  if (prec != QTT_PREC_FP32 && prec != QTT_PREC_FP64) return fail(QTT_ERR_ARG, "precision %d not supported", prec);
+  if (prec != QTT_PREC_FP32 && prec != QTT_PREC_FP64 && prec != QTT_PREC_BF16)
+    return fail(QTT_ERR_ARG, "precision %d not supported", prec);
   GemmSpec g;
   g.M = dx(M); g.N = dx(N); g.K = dx(K); g.batch = dx(1);
   g.mlo = g.nlo = g.klo = 1;
@@ -1480,7 +1627,7 @@ int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void
   g.A = opd(A, lda, 0, 1, 0, conj_a);
   g.B = opd(B, ldb, 0, 1, 0, conj_b);
   g.C = opd(C, ldc, 0, 1, 0);
-  g.types = prec == QTT_PREC_FP64 ? GEMM_F64 : GEMM_F32;
+  g.types = prec == QTT_PREC_FP64 ? GEMM_F64 : (prec == QTT_PREC_BF16 ? GEMM_BF16 : GEMM_F32);
   HIPCHK(gemm_launch(g, (hipStream_t)stream));
   return QTT_OK;
 }

@@ -13,7 +13,9 @@
 // Tiles: 64x64 complex outputs per 256-thread workgroup, 16 complex of depth
 // per LDS stage, 4 waves in a 2x2 arrangement, each wave a 32x64 real block
 // made of 16x16 MFMA tiles (v_mfma_f32_16x16x4f32 for FP32,
-// v_mfma_f64_16x16x4f64 for FP64 Gram matrices and the FP64 path).  Global
+// v_mfma_f64_16x16x4f64 for FP64 Gram matrices and the FP64 path, or
+// v_mfma_f32_16x16x16bf16_1k when the operands are rounded to bfloat16 with
+// FP32 accumulation -- the BF16 precision form).  Global
 // loads of the next stage are issued into registers before the MFMAs of the
 // current stage (software pipelining).  Dimensions are read from the device
 // (DimExpr), so tiles beyond the actual bond dimensions exit at once.
@@ -24,6 +26,16 @@ namespace qtt {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+// Round an FP32 value to the nearest bfloat16 (ties to even) and return it
+// as FP32 (low 16 bits zero); finite inputs only.
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(x) >> 16); }
 
 template <typename TC> struct Mfma;
 template <> struct Mfma<float> {
@@ -55,7 +67,7 @@ __device__ __forceinline__ long long split_off(const FastDiv& f, uint32_t x, lon
   return (long long)h * sh + (long long)l * sl;
 }
 
-template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM>
+template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM, bool BF = false>
 __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   typedef typename Vec2<TIn>::t in2;
   typedef typename Mfma<TC>::acc_t acc_t;
@@ -133,12 +145,14 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < A_PER_T; ++r) {
       TC re = (TC)ra[r].x, im = (TC)ra[r].y;
+      if constexpr (BF) { re = round_bf16(re); im = round_bf16(im); }
       As[2 * a_k[r]][a_i[r]] = re;
       As[2 * a_k[r] + 1][a_i[r]] = g.A.conj ? -im : im;
     }
 #pragma unroll
     for (int r = 0; r < B_PER_T; ++r) {
       TC re = (TC)rb[r].x, im = (TC)rb[r].y;
+      if constexpr (BF) { re = round_bf16(re); im = round_bf16(im); }
       Bs[b_k[r]][2 * b_j[r]] = re;
       Bs[b_k[r]][2 * b_j[r] + 1] = g.B.conj ? -im : im;
     }
@@ -165,6 +179,36 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
       store_stage();
       __syncthreads();
       if (k0 + BKC < kend) load_stage(k0 + BKC);
+      if constexpr (BF) {
+        // 16 real k per MFMA: lane group lq supplies real k = 16 ks + 4 lq + v
+#pragma unroll
+        for (int ks = 0; ks < BKC / 8; ++ks) {
+          shortx4 af[MI], bf[NJ];
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              af[i][v] = bf16_bits(As[16 * ks + 4 * lq + v][wm * (BM / 2) + i * 16 + l16]);
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            const int jr = wn * BN + j * 16 + l16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int kc = 8 * ks + 2 * lq + (v >> 1);
+              const int part = v & 1;
+              TC x = Bs[kc][jr ^ part];
+              if (part && !(jr & 1)) x = -x;
+              bf[j][v] = bf16_bits((float)x);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+        }
+        continue;
+      }
 #pragma unroll
       for (int ks = 0; ks < BKC / 2; ++ks) {
         TC af[MI], bf[NJ];
@@ -253,12 +297,12 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-template <typename TIn, typename TC, typename TOut>
+template <typename TIn, typename TC, typename TOut, bool BF = false>
 static hipError_t launch_typed(const GemmArgs& g, dim3 grid, bool akm, bool bkm, hipStream_t s) {
-  if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true>), grid, dim3(NT), 0, s, g);
-  else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false>), grid, dim3(NT), 0, s, g);
-  else if (bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, true>), grid, dim3(NT), 0, s, g);
-  else hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, false>), grid, dim3(NT), 0, s, g);
+  if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true, BF>), grid, dim3(NT), 0, s, g);
+  else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false, BF>), grid, dim3(NT), 0, s, g);
+  else if (bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, true, BF>), grid, dim3(NT), 0, s, g);
+  else hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, false, BF>), grid, dim3(NT), 0, s, g);
   return hipGetLastError();
 }
 
@@ -285,6 +329,7 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
     case GEMM_F32: return launch_typed<float, float, float>(g, grid, akm, bkm, s);
     case GEMM_F32_GRAM64: return launch_typed<float, double, double>(g, grid, akm, bkm, s);
     case GEMM_F64: return launch_typed<double, double, double>(g, grid, akm, bkm, s);
+    case GEMM_BF16: return launch_typed<float, float, float, true>(g, grid, akm, bkm, s);
   }
   return hipErrorInvalidValue;
 }
