@@ -41,6 +41,10 @@
  *   complex128 throughout.  QTT_PREC_BF16 (complex64 storage): contraction
  *   operands rounded to bfloat16 on the way into the matrix cores, FP32
  *   accumulation, FP64 Gram/eigen; usually combined with opts.refine = 1.
+ *   QTT_PREC_BF16X3 (complex64 storage): every operand split into two
+ *   bfloat16 terms hi + lo and each product formed as hi.hi + hi.lo + lo.hi
+ *   on the bfloat16 matrix cores with FP32 accumulation (close to FP32
+ *   accuracy).
  * Ownership.  The library never allocates device memory.  Every call takes a
  *   caller-owned device workspace `ws` of at least tt_workspace_size(...)
  *   bytes; its first 256 bytes hold the device status word.
@@ -77,7 +81,7 @@ enum qtt_status {
 };
 
 enum qtt_dtype { QTT_C64 = 1, QTT_C128 = 2, QTT_F32 = 3, QTT_F64 = 4 };
-enum qtt_prec { QTT_PREC_FP32 = 0, QTT_PREC_BF16 = 1, QTT_PREC_FP64 = 2 };
+enum qtt_prec { QTT_PREC_FP32 = 0, QTT_PREC_BF16 = 1, QTT_PREC_FP64 = 2, QTT_PREC_BF16X3 = 3 };
 enum qtt_op {
   QTT_OP_ENCODE = 1, QTT_OP_APPLY = 2, QTT_OP_TRUNCATE = 3,
   QTT_OP_TO_DENSE = 4, QTT_OP_APPLY_BACKWARD = 5, QTT_OP_TO_DENSE_BACKWARD = 6,
@@ -248,9 +252,9 @@ int tt_intensity_loss(const void* field, const void* target, int dtype, int log2
 /* C = op(A) . op(B) for dense row-major complex matrices through the MFMA
  * contraction kernel used by every step above.  A is M x K (lda), B is K x N
  * (ldb), C is M x N (ldc), all device pointers; conj_a / conj_b conjugate the
- * operand elements.  prec QTT_PREC_FP32 (complex64), QTT_PREC_BF16
- * (complex64 in memory, operands rounded to bfloat16, FP32 accumulation) or
- * QTT_PREC_FP64 (complex128).  Asynchronous on `stream`. */
+ * operand elements.  prec QTT_PREC_FP32 (complex64), QTT_PREC_BF16 /
+ * QTT_PREC_BF16X3 (complex64 in memory, bfloat16 matrix cores, FP32
+ * accumulation) or QTT_PREC_FP64 (complex128).  Asynchronous on `stream`. */
 int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void* B, int ldb, int conj_b,
              void* C, int ldc, int prec, void* stream);
 

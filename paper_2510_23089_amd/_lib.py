@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqtt.so")
 
 QTT_C64, QTT_C128, QTT_F32, QTT_F64 = 1, 2, 3, 4
-PREC_FP32, PREC_BF16, PREC_FP64 = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_FP64, PREC_BF16X3 = 0, 1, 2, 3
 OP_ENCODE, OP_APPLY, OP_TRUNCATE, OP_TO_DENSE, OP_APPLY_BACKWARD = 1, 2, 3, 4, 5
 OP_TO_DENSE_BACKWARD, OP_LOSS = 6, 7
 

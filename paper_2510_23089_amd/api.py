@@ -35,7 +35,7 @@ def workspace(nbytes, device=None, key="default"):
 
 
 def _prec_code(prec):
-    return {"fp32": L.PREC_FP32, "bf16": L.PREC_BF16, "fp64": L.PREC_FP64}[prec]
+    return {"fp32": L.PREC_FP32, "bf16": L.PREC_BF16, "fp64": L.PREC_FP64, "bf16x3": L.PREC_BF16X3}[prec]
 
 
 def _ctype(prec):
@@ -151,8 +151,8 @@ def _apply_prec(psi, prec):
     "bf16" (complex64 states only)."""
     if prec is None:
         return psi.prec
-    if prec == "bf16" and psi.prec != "fp32":
-        raise ValueError("bf16 contractions need complex64 states")
+    if prec in ("bf16", "bf16x3") and psi.prec != "fp32":
+        raise ValueError("bfloat16 contractions need complex64 states")
     return prec
 
 

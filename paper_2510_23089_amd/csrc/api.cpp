@@ -401,6 +401,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
   const int real = in.dtype == QTT_C128 ? 1 : 0;
   Ctx c = make_ctx(s, real, nf, m, b.status);
   if (o.prec == QTT_PREC_BF16) c.gemm_t = GEMM_BF16;
+  if (o.prec == QTT_PREC_BF16X3) c.gemm_t = GEMM_BF16X3;
   c.G = b.G; c.gld = std::max(p.gram_nb, 1); c.part = b.part; c.eigws = b.eigws;
   c.eig_nb = c.gld; c.eig_kc = std::max(p.chi_zip, p.chi_max);
   const ll ci = in.cap, co = out.cap, zc = p.zc;
@@ -697,7 +698,7 @@ int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opt
   opts_defaults(opts, out.cap, o);
   if (o.chi_max < 1 || o.chi_max > out.cap) return fail(QTT_ERR_CAPACITY, "chi_max %d outside [1, %d]", o.chi_max, out.cap);
   if (o.chi_zip < 1 || o.chi_zip > 256) return fail(QTT_ERR_CAPACITY, "chi_zip %d outside [1, 256]", o.chi_zip);
-  if (o.prec != QTT_PREC_FP32 && o.prec != QTT_PREC_FP64 && o.prec != QTT_PREC_BF16)
+  if (o.prec != QTT_PREC_FP32 && o.prec != QTT_PREC_FP64 && o.prec != QTT_PREC_BF16 && o.prec != QTT_PREC_BF16X3)
     return fail(QTT_ERR_ARG, "precision %d not supported", o.prec);
   if ((o.prec == QTT_PREC_FP64) != (in.dtype == QTT_C128)) return fail(QTT_ERR_DTYPE, "precision and dtype disagree");
   if (o.refine != 0 && o.refine != 1) return fail(QTT_ERR_ARG, "refine must be 0 or 1");
@@ -1618,7 +1619,7 @@ int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void
   g_err.clear();
   if (!A || !B || !C) return fail(QTT_ERR_ARG, "NULL operand");
   if (M < 1 || N < 1 || K < 1 || lda < K || ldb < N || ldc < N) return fail(QTT_ERR_SHAPE, "bad GEMM shape");
-  if (prec != QTT_PREC_FP32 && prec != QTT_PREC_FP64 && prec != QTT_PREC_BF16)
+  if (prec != QTT_PREC_FP32 && prec != QTT_PREC_FP64 && prec != QTT_PREC_BF16 && prec != QTT_PREC_BF16X3)
     return fail(QTT_ERR_ARG, "precision %d not supported", prec);
   GemmSpec g;
   g.M = dx(M); g.N = dx(N); g.K = dx(K); g.batch = dx(1);
@@ -1627,7 +1628,9 @@ int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void
   g.A = opd(A, lda, 0, 1, 0, conj_a);
   g.B = opd(B, ldb, 0, 1, 0, conj_b);
   g.C = opd(C, ldc, 0, 1, 0);
-  g.types = prec == QTT_PREC_FP64 ? GEMM_F64 : (prec == QTT_PREC_BF16 ? GEMM_BF16 : GEMM_F32);
+  g.types = prec == QTT_PREC_FP64 ? GEMM_F64
+            : prec == QTT_PREC_BF16 ? GEMM_BF16
+            : prec == QTT_PREC_BF16X3 ? GEMM_BF16X3 : GEMM_F32;
   HIPCHK(gemm_launch(g, (hipStream_t)stream));
   return QTT_OK;
 }

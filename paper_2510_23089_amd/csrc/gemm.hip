@@ -14,8 +14,9 @@
 // per LDS stage, 4 waves in a 2x2 arrangement, each wave a 32x64 real block
 // made of 16x16 MFMA tiles (v_mfma_f32_16x16x4f32 for FP32,
 // v_mfma_f64_16x16x4f64 for FP64 Gram matrices and the FP64 path, or
-// v_mfma_f32_16x16x16bf16_1k when the operands are rounded to bfloat16 with
-// FP32 accumulation -- the BF16 precision form).  Global
+// v_mfma_f32_16x16x16bf16_1k for the BF16 precision forms: operands rounded
+// to bfloat16, or split into two bfloat16 terms with three products, always
+// with FP32 accumulation).  Global
 // loads of the next stage are issued into registers before the MFMAs of the
 // current stage (software pipelining).  Dimensions are read from the device
 // (DimExpr), so tiles beyond the actual bond dimensions exit at once.
@@ -67,7 +68,10 @@ __device__ __forceinline__ long long split_off(const FastDiv& f, uint32_t x, lon
   return (long long)h * sh + (long long)l * sl;
 }
 
-template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM, bool BF = false>
+// BF: 0 = no bfloat16; 1 = operands rounded to bfloat16 (one MFMA per
+// step); 3 = operands split as x = hi + lo with hi, lo bfloat16 and the
+// product formed as hi.hi + hi.lo + lo.hi (three MFMAs, close to FP32).
+template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM, int BF = 0>
 __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   typedef typename Vec2<TIn>::t in2;
   typedef typename Mfma<TC>::acc_t acc_t;
@@ -145,14 +149,14 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < A_PER_T; ++r) {
       TC re = (TC)ra[r].x, im = (TC)ra[r].y;
-      if constexpr (BF) { re = round_bf16(re); im = round_bf16(im); }
+      if constexpr (BF == 1) { re = round_bf16(re); im = round_bf16(im); }
       As[2 * a_k[r]][a_i[r]] = re;
       As[2 * a_k[r] + 1][a_i[r]] = g.A.conj ? -im : im;
     }
 #pragma unroll
     for (int r = 0; r < B_PER_T; ++r) {
       TC re = (TC)rb[r].x, im = (TC)rb[r].y;
-      if constexpr (BF) { re = round_bf16(re); im = round_bf16(im); }
+      if constexpr (BF == 1) { re = round_bf16(re); im = round_bf16(im); }
       Bs[b_k[r]][2 * b_j[r]] = re;
       Bs[b_k[r]][2 * b_j[r] + 1] = g.B.conj ? -im : im;
     }
@@ -179,16 +183,15 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
       store_stage();
       __syncthreads();
       if (k0 + BKC < kend) load_stage(k0 + BKC);
-      if constexpr (BF) {
+      if constexpr (BF != 0) {
         // 16 real k per MFMA: lane group lq supplies real k = 16 ks + 4 lq + v
 #pragma unroll
         for (int ks = 0; ks < BKC / 8; ++ks) {
-          shortx4 af[MI], bf[NJ];
+          float ax[MI][4], bx[NJ][4];
 #pragma unroll
           for (int i = 0; i < MI; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-              af[i][v] = bf16_bits(As[16 * ks + 4 * lq + v][wm * (BM / 2) + i * 16 + l16]);
+            for (int v = 0; v < 4; ++v) ax[i][v] = As[16 * ks + 4 * lq + v][wm * (BM / 2) + i * 16 + l16];
 #pragma unroll
           for (int j = 0; j < NJ; ++j) {
             const int jr = wn * BN + j * 16 + l16;
@@ -196,16 +199,42 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
             for (int v = 0; v < 4; ++v) {
               const int kc = 8 * ks + 2 * lq + (v >> 1);
               const int part = v & 1;
-              TC x = Bs[kc][jr ^ part];
-              if (part && !(jr & 1)) x = -x;
-              bf[j][v] = bf16_bits((float)x);
+              float x = Bs[kc][jr ^ part];
+              bx[j][v] = (part && !(jr & 1)) ? -x : x;
             }
+          }
+          shortx4 ah[MI], bh[NJ];
+#pragma unroll
+          for (int i = 0; i < MI; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ah[i][v] = bf16_bits(round_bf16(ax[i][v]));
+#pragma unroll
+          for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bh[j][v] = bf16_bits(round_bf16(bx[j][v]));
+          if constexpr (BF == 3) {
+            shortx4 al[MI], bl[NJ];
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) al[i][v] = bf16_bits(round_bf16(ax[i][v] - round_bf16(ax[i][v])));
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) bl[j][v] = bf16_bits(round_bf16(bx[j][v] - round_bf16(bx[j][v])));
+#pragma unroll
+            for (int i = 0; i < MI; ++i)
+#pragma unroll
+              for (int j = 0; j < NJ; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+              }
           }
 #pragma unroll
           for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bf[j], acc[i][j], 0, 0, 0);
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
         continue;
       }
@@ -297,7 +326,7 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-template <typename TIn, typename TC, typename TOut, bool BF = false>
+template <typename TIn, typename TC, typename TOut, int BF = 0>
 static hipError_t launch_typed(const GemmArgs& g, dim3 grid, bool akm, bool bkm, hipStream_t s) {
   if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true, BF>), grid, dim3(NT), 0, s, g);
   else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false, BF>), grid, dim3(NT), 0, s, g);
@@ -329,7 +358,8 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
     case GEMM_F32: return launch_typed<float, float, float>(g, grid, akm, bkm, s);
     case GEMM_F32_GRAM64: return launch_typed<float, double, double>(g, grid, akm, bkm, s);
     case GEMM_F64: return launch_typed<double, double, double>(g, grid, akm, bkm, s);
-    case GEMM_BF16: return launch_typed<float, float, float, true>(g, grid, akm, bkm, s);
+    case GEMM_BF16: return launch_typed<float, float, float, 1>(g, grid, akm, bkm, s);
+    case GEMM_BF16X3: return launch_typed<float, float, float, 3>(g, grid, akm, bkm, s);
   }
   return hipErrorInvalidValue;
 }

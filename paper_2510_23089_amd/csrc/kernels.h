@@ -6,7 +6,9 @@
 namespace qtt {
 
 // GEMM_BF16: complex64 operands rounded to bfloat16, FP32 accumulation.
-enum GemmTypes { GEMM_F32 = 0, GEMM_F32_GRAM64 = 1, GEMM_F64 = 2, GEMM_BF16 = 3 };
+// GEMM_BF16X3: operands split into two bfloat16 terms (hi + lo), products
+// hi.hi + hi.lo + lo.hi on the bfloat16 matrix cores, FP32 accumulation.
+enum GemmTypes { GEMM_F32 = 0, GEMM_F32_GRAM64 = 1, GEMM_F64 = 2, GEMM_BF16 = 3, GEMM_BF16X3 = 4 };
 
 // C(M,N) = op(A)(M,K) . op(B)(K,N), batched.  Sizes are device expressions;
 // *_bound are host upper bounds used only to size the launch grid.
