@@ -347,10 +347,12 @@ class MPOBatch:
             prof = np.maximum(prof, [1] + [int(c.shape[3]) for c in h])
         self.d_bonds = prof.astype(np.int32)
         self.d_cap = int(prof.max())
-        kind = kinds[0]
-        if kind is not None and all(k is not None and np.array_equal(k, kind) for k in kinds):
-            ok = all(prof[k] == prof[k + 1] for k in range(m) if kind[k] == 1)
-            self.site_kind = np.array(kind, dtype=np.int32) if ok else None
+        # a site is a pass-through (kind 1) for the batch when it is one for
+        # every member (its padded bond profile then stays equal across it)
+        if all(k is not None for k in kinds):
+            kind = np.array([int(all(int(k[j]) == 1 for k in kinds)) for j in range(m)], dtype=np.int32)
+            ok = all(prof[j] == prof[j + 1] for j in range(m) if kind[j] == 1)
+            self.site_kind = kind if ok and kind.any() else None
         else:
             self.site_kind = None
         stride = self.d_cap * 4 * self.d_cap

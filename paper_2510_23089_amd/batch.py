@@ -1,0 +1,103 @@
+"""Batches of fields of uneven size and bond cap in one lockstep pass.
+
+A field of side 2^k inside a batch of side 2^K (k <= K) is stored
+zero-padded in the top-left 2^k x 2^k block of the 2^K grid.  In quantics
+order (most significant bit first) its first 2(K - k) sites are then the
+state |0> with bond 1, and its propagator is the Fresnel MPO of its own
+2^k grid (periodic on that grid) on the remaining sites with identity
+(pass-through) cores on the padded ones: every member is processed exactly
+as it would be alone, while all members advance site by site together.  Per
+field bond caps go to the device as one int per field.
+
+The whole pipeline (encode, x then y application, optional refinement, and
+decompression) is a fixed sequence of stream-ordered library calls with no
+host synchronisation, so it can be captured once in a HIP graph and replayed.
+"""
+import numpy as np
+import torch
+
+from . import api
+from . import mpo_build as B
+
+
+def padded_axis_mpos(k, K, lam, dx, z, rel=1e-12):
+    """(x cores, x kinds, y cores, y kinds) of a 2^k field in a 2^K batch."""
+    w1 = B.fresnel_axis(k, lam, dx, z, rel)
+    pad = [B.identity_core(1)] * (2 * (K - k))
+    cx, kx = B.embed(w1, "x")
+    cy, ky = B.embed(w1, "y")
+    return (pad + cx, [1] * len(pad) + kx, pad + cy, [1] * len(pad) + ky)
+
+
+class UnevenBatch:
+    """Encode + propagate (x then y) + decompress a batch of square fields of
+    sides 2^ks[i] with bond caps chis[i], all at distance z."""
+
+    def __init__(self, ks, chis, lam, dx, z, device="cuda", prec="fp32", refine=False, rel=1e-12):
+        self.ks = [int(k) for k in ks]
+        self.chis = [int(c) for c in chis]
+        self.count = len(self.ks)
+        self.K = max(self.ks)
+        self.m = 2 * self.K
+        self.chi = max(self.chis)
+        self.prec, self.refine = prec, refine
+        self.device = torch.device(device)
+        per_k = {}
+        for k in sorted(set(self.ks)):
+            cx, kx, cy, ky = padded_axis_mpos(k, self.K, lam, dx, z, rel)
+            per_k[k] = (api.MPO(cx, kx, dtype=torch.complex64, device="cpu"),
+                        api.MPO(cy, ky, dtype=torch.complex64, device="cpu"))
+        self.wx = api.MPOBatch([per_k[k][0] for k in self.ks], device=device)
+        self.wy = api.MPOBatch([per_k[k][1] for k in self.ks], device=device)
+        self.chi_dev = torch.tensor(self.chis, dtype=torch.int32, device=device)
+        side = 1 << self.K
+        self.images = torch.zeros((self.count, side, side), dtype=torch.complex64, device=device)
+        self.psi = api.MPSBatch(self.count, self.m, self.chi, device=device)
+        self.mid = api.MPSBatch(self.count, self.m, self.chi, device=device)
+        self.out = api.MPSBatch(self.count, self.m, self.chi, device=device)
+        self.dense = torch.empty_like(self.images)
+        self.graph = None
+
+    def load(self, fields):
+        """Copy host fields (list of 2^k x 2^k arrays) into the padded device batch."""
+        self.images.zero_()
+        for i, f in enumerate(fields):
+            n = f.shape[0]
+            assert n == 1 << self.ks[i]
+            self.images[i, :n, :n].copy_(torch.from_numpy(np.asarray(f)).to(torch.complex64))
+
+    def run(self):
+        """The pipeline on the current stream (capturable)."""
+        api.tt_encode_batched(self.images, self.chi, out=self.psi, chi_dev=self.chi_dev)
+        api.mpo_apply_batched(self.psi, self.wx, self.chi, out=self.mid, chi_dev=self.chi_dev, prec=self.prec,
+                              refine=self.refine)
+        api.mpo_apply_batched(self.mid, self.wy, self.chi, out=self.out, chi_dev=self.chi_dev, prec=self.prec,
+                              refine=self.refine)
+        api.tt_to_dense_batched(self.out, out=self.dense)
+        return self.dense
+
+    def capture(self):
+        """Record run() in a HIP graph (after one eager run that sizes every
+        workspace), then replay() re-issues the whole batch in one launch."""
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        torch.cuda.synchronize(self.device)
+        # the graph records raw workspace addresses: hold the buffers it uses
+        self._held = list(api._WS_CACHE.values())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.dense
+
+    def field(self, i):
+        """Dense result of member i on its own 2^k grid (device view)."""
+        n = 1 << self.ks[i]
+        return self.dense[i, :n, :n]

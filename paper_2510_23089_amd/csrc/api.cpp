@@ -1102,9 +1102,8 @@ int encode_impl(const void* img, int img_dtype, int n, const qtt_opts& o, const 
   auto core_out = [&](int k) { return outc + (size_t)k * co * 2 * co * c.csz; };
   std::vector<int> rb = mps_bounds(m, chi);
   const size_t isz = img_dtype == QTT_C128 ? 16 : (img_dtype == QTT_F32 ? 4 : 8);
-  for (int f = 0; f < nf; ++f)
-    HIPCHK(quantics_permute((const char*)img + (size_t)f * (b.sq * isz), img_dtype,
-                            (char*)b.v + (size_t)f * b.sq * c.csz, real ? QTT_C128 : QTT_C64, n, 0, s));
+  (void)isz;
+  HIPCHK(quantics_permute(img, img_dtype, b.v, real ? QTT_C128 : QTT_C64, n, 0, s, nf, b.sq, b.sq));
   HIPCHK(set_ints_strided(out.bonds, 1, c.bs, nf, 1, s));
   HIPCHK(set_ints_strided(out.bonds + m, 1, c.bs, nf, 1, s));
   const void* Rcur = b.v;
@@ -1230,9 +1229,8 @@ int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream
                opd(P, pld, 0, 1, 0, 0, sP), opd(Q, qrs, 0, qcs, 0, 0, sQ), opd(b.E, Rn, 0, 1, 0, 0, b.sE));
   if (r) return r;
   const size_t osz = out_dtype == QTT_C128 ? 16 : 8;
-  for (int f = 0; f < nf; ++f)
-    HIPCHK(quantics_permute((char*)b.E + (size_t)f * b.sE * c.csz, real ? QTT_C128 : QTT_C64,
-                            (char*)out + (size_t)f * b.sE * osz, out_dtype, m / 2, 1, s));
+  (void)osz;
+  HIPCHK(quantics_permute(b.E, real ? QTT_C128 : QTT_C64, out, out_dtype, m / 2, 1, s, nf, b.sE, b.sE));
   return QTT_OK;
 }
 
@@ -1296,9 +1294,8 @@ int dense_backward_impl(const MpsB& in, const void* gdense, const MpsB& g, Dense
   const int* bonds = b.bonds;
   HIPCHK(zero_fill(g.cores, (size_t)nf * sG * csz, s));
   HIPCHK(copy_ints(bonds, g.bonds, nf * (m + 1), s));
-  for (int f = 0; f < nf; ++f)
-    HIPCHK(quantics_permute((const char*)gdense + (size_t)f * b.sE * csz, real ? QTT_C128 : QTT_C64,
-                            (char*)b.E + (size_t)f * b.sE * csz, real ? QTT_C128 : QTT_C64, m / 2, 0, s));
+  HIPCHK(quantics_permute(gdense, real ? QTT_C128 : QTT_C64, b.E, real ? QTT_C128 : QTT_C64, m / 2, 0, s, nf, b.sE,
+                          b.sE));
   // left half-chain, every P_k kept: P_k = [l][r] with ld pld[k]
   std::vector<const void*> Pp(h + 1);
   std::vector<ll> pld(h + 1), psb(h + 1);

@@ -100,8 +100,9 @@ hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long lon
 // Quantics permutation of a row-major N x N image into the flat quantics
 // vector (dir = 0) or back (dir = 1).  src/dst element types given by the
 // qtt_dtype codes; the quantics side is always complex (float or double).
+// nf fields at element strides s_src / s_dst (one launch).
 hipError_t quantics_permute(const void* src, int src_dtype, void* dst, int dst_dtype, int log2_side,
-                            int dir, hipStream_t s);
+                            int dir, hipStream_t s, int nf = 1, long long s_src = 0, long long s_dst = 0);
 // Frobenius norm of a (rows x cols) complex block (strides ld_r, ld_c), FP64 result.
 hipError_t block_norm(const void* p, int dtype, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
                       long long ld_r, long long ld_c, double* out, hipStream_t s);

@@ -44,7 +44,10 @@ __device__ __forceinline__ void store_elem(void* p, int dtype, long long i, doub
 // dir 1: dst[a*N + b] = src[q]
 // The quantics index interleaves a_1 b_1 a_2 b_2 ... (a bits at odd positions
 // counted from the least significant bit, b bits at even positions).
-__global__ void quantics_kernel(const void* src, int sdt, void* dst, int ddt, int n, long long total, int dir) {
+__global__ void quantics_kernel(const void* src, int sdt, void* dst, int ddt, int n, long long total, int dir,
+                                long long s_src, long long s_dst) {
+  // field blockIdx.y: element offsets f * s_src / f * s_dst
+  const long long fs = blockIdx.y * s_src, fd = blockIdx.y * s_dst;
   for (long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x; o < total;
        o += (long long)gridDim.x * blockDim.x) {
     long long in;
@@ -57,18 +60,20 @@ __global__ void quantics_kernel(const void* src, int sdt, void* dst, int ddt, in
       in = (long long)((spread_even(a) << 1) | spread_even(b));
     }
     double re, im;
-    load_elem(src, sdt, in, re, im);
-    store_elem(dst, ddt, o, re, im);
+    load_elem(src, sdt, fs + in, re, im);
+    store_elem(dst, ddt, fd + o, re, im);
   }
 }
 
 hipError_t quantics_permute(const void* src, int src_dtype, void* dst, int dst_dtype, int log2_side, int dir,
-                            hipStream_t s) {
+                            hipStream_t s, int nf, long long s_src, long long s_dst) {
   long long total = 1ll << (2 * log2_side);
   long long blocks = (total + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(quantics_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, src_dtype, dst, dst_dtype,
-                     log2_side, total, dir);
+  long long cap = std::max<long long>(1, 65536 / std::max(nf, 1));
+  if (blocks > cap) blocks = cap;
+  if (nf < 1) return hipSuccess;
+  hipLaunchKernelGGL(quantics_kernel, dim3((unsigned)blocks, nf), dim3(256), 0, s, src, src_dtype, dst, dst_dtype,
+                     log2_side, total, dir, s_src, s_dst);
   return hipGetLastError();
 }
 
