@@ -18,6 +18,14 @@ launch from the matrix sizes the kernel logs on the device.
 cpu_baseline: the float64 oracle (numpy/LAPACK) on the host, on a bounded
 sample of the same workload: encode + one propagation (x then y) at z = 2 mm.
 
+batched (the uneven-batch precision form): 256 fields with side 2^k, k
+uniform in {8..11}, and bond caps uniform in {16, 32, 64, 128} (seeded draws),
+aperture fields of the same recipe; zero-padded into one 2048^2 batch, encoded,
+propagated (x then y, z = 2 mm) and decompressed in one HIP-graph replay,
+with split-bfloat16 contractions and the full-precision fitting sweep; beside
+it the same batch with plain FP32 contractions and sweep, and a per-field
+FP32 baseline (fields processed one at a time) on a sample of the batch.
+
 grad_step (second headline number, phase retrieval): 32 independent 4096^2
 problems (24 sites), a learnable phase mask exp(i phi) (phi: iid N(0,1)
 smoothed by a periodic Gaussian of 16 px, std pi/8) encoded at chi 64, the
@@ -54,6 +62,7 @@ def parse():
     p.add_argument("--chi", type=int, default=CHI)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true")
+    p.add_argument("--no-batched", action="store_true")
     p.add_argument("--grad-steps", type=int, default=3)
     return p.parse_args()
 
@@ -100,6 +109,92 @@ def cpu_baseline(field, chi):
                   "the same 1024^2 field (%.2f s); its encode (%.2f s) is not in value" % (chi, t_prop, t1 - t0),
         "cpu": _cpu_model(),
     }
+
+
+def batched_bench(dev, replays=3, sample=16):
+    """256 uneven fields in one graph replay; per-field FP32 baseline on a sample."""
+    from concurrent.futures import ThreadPoolExecutor
+    import torch
+    import synth
+    from paper_2510_23089_amd import api
+    from paper_2510_23089_amd import batch as BT
+    z = 2e-3
+    specs = synth.batch_specs(0, 256, 8, 11, (16, 32, 64, 128))
+    ks = [k for k, _, _ in specs]
+    chis = [c for _, c, _ in specs]
+    with ThreadPoolExecutor(16) as ex:
+        fields = list(ex.map(lambda sp: synth.aperture_field(sp[2], n=1 << sp[0]).astype(np.complex64), specs))
+    px = sum(4 ** k for k in ks)
+    res = {"fields": len(ks), "pixels": px, "z_mm": 2.0, "sides": sorted(set(1 << k for k in ks)),
+           "chis": sorted(set(chis))}
+
+    def timed(run, reps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            run()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    outs = {}
+    for name, prec, refine in (("bf16x3_fit_graph", "bf16x3", True), ("fp32_graph", "fp32", False)):
+        b = BT.UnevenBatch(ks, chis, LAM, DX, z, device=dev, prec=prec, refine=refine)
+        b.load(fields)
+        b.capture()
+        ms = timed(b.replay, replays)
+        api.check_status()
+        outs[name] = [b.field(i).clone() for i in range(sample)]
+        res[name] = {"ms_per_batch": ms, "fields_per_s": len(ks) / (ms / 1e3),
+                     "propagations_per_s": len(ks) / (ms / 1e3)}
+        del b
+        api._WS_CACHE.clear()
+        torch.cuda.empty_cache()
+    # per-field FP32 baseline (one field at a time, each with its own MPO)
+    props = {}
+    tot = 0.0
+    for i in range(sample):
+        k, chi = ks[i], chis[i]
+        if k not in props:
+            props[k] = api.FresnelPropagator(k, LAM, DX, z, device=dev)
+        img = torch.from_numpy(fields[i]).to(dev)
+
+        def one():
+            psi = api.tt_encode(img, chi)
+            out = props[k](psi, chi)
+            return api.tt_to_dense(out)
+        one()
+        tot += timed(one, 1)
+        d = one()
+        outs.setdefault("per_field", []).append(d.clone())
+    api.check_status()
+    px_s = sum(4 ** ks[i] for i in range(sample))
+    res["per_field_fp32_sample"] = {"fields": sample, "ms_total": tot, "fields_per_s": sample / (tot / 1e3),
+                                    "pixel_share_of_batch": px_s / px}
+    # accuracy against the exact propagation (float64 FFT on the host; the
+    # truncation to chi dominates both forms' error, and the two must agree)
+    errs = {"bf16x3_fit_graph": [], "fp32_graph": [], "per_field": []}
+    for i in range(sample):
+        n = 1 << ks[i]
+        f = np.fft.fftfreq(n, d=DX)
+        t = np.exp(-1j * np.pi * LAM * z * f * f)
+        exact = np.fft.ifft2(np.fft.fft2(fields[i].astype(np.complex128)) * (t[:, None] * t[None, :]))
+        nrm = np.linalg.norm(exact)
+        for key in errs:
+            errs[key].append(float(np.linalg.norm(outs[key][i].cpu().numpy() - exact) / nrm))
+    res["error_vs_exact"] = {
+        "sample": sample,
+        "per_field_fp32": errs["per_field"],
+        "max_abs_gap_bf16x3_fit_minus_per_field": max(abs(a - b) for a, b in zip(errs["bf16x3_fit_graph"],
+                                                                              errs["per_field"])),
+        "max_abs_gap_fp32_batched_minus_per_field": max(abs(a - b) for a, b in zip(errs["fp32_graph"],
+                                                                                errs["per_field"])),
+        "mean_bf16x3_fit": float(np.mean(errs["bf16x3_fit_graph"])),
+        "mean_per_field_fp32": float(np.mean(errs["per_field"])),
+    }
+    return res
 
 
 def grad_step_bench(steps, dev):
@@ -250,6 +345,8 @@ def main():
         },
         "wall_s": wall,
     }
+    if not a.no_batched:
+        res["batched"] = batched_bench(dev)
     if not a.no_grad:
         res["grad_step"] = grad_step_bench(a.grad_steps, dev)
     if not a.no_cpu_baseline:

@@ -76,7 +76,8 @@ def test_uneven_batch_vs_oracle_per_field():
         n = 1 << k
         got = dense[i].cpu().numpy()
         assert rel(got[:n, :n], ref) < 1e-4
-        assert np.abs(got[n:, :]).max() == 0 and np.abs(got[:, n:]).max() == 0
+        if n < got.shape[0]:
+            assert np.abs(got[n:, :]).max() == 0 and np.abs(got[:, n:]).max() == 0
         # the padded sites stay bond 1
         b = [int(x) for x in out.bonds[i].cpu()]
         assert b[:2 * (K - k) + 1] == [1] * (2 * (K - k) + 1)
@@ -86,8 +87,10 @@ def test_uneven_batch_vs_oracle_per_field():
 def test_uneven_batch_lossless_vs_fft():
     torch = need_gpu()
     from paper_2510_23089_amd import api
+    # caps at least the largest zip-up bond a 2k-site member can need
+    # (left of the centre the zip-up state is not yet in Schmidt form)
     ks = [2, 4, 3, 4]
-    chis = [4, 16, 8, 16]
+    chis = [8, 64, 32, 64]
     z = 10e-6
     fields = [synth.random_field(20 + i, 1 << k) for i, k in enumerate(ks)]
     _, _, dense = _run_batch(api, torch, fields, ks, chis, z)
