@@ -144,11 +144,15 @@ def batched_bench(dev, replays=3, sample=16):
         b = BT.UnevenBatch(ks, chis, LAM, DX, z, device=dev, prec=prec, refine=refine)
         b.load(fields)
         b.capture()
+        ms_untuned = timed(b.replay, replays)
+        n_tuned = b.tune()
+        b.capture()
         ms = timed(b.replay, replays)
         api.check_status()
         outs[name] = [b.field(i).clone() for i in range(sample)]
         res[name] = {"ms_per_batch": ms, "fields_per_s": len(ks) / (ms / 1e3),
-                     "propagations_per_s": len(ks) / (ms / 1e3)}
+                     "propagations_per_s": len(ks) / (ms / 1e3), "ms_per_batch_untuned": ms_untuned,
+                     "tuned_shapes": n_tuned}
         del b
         api._WS_CACHE.clear()
         torch.cuda.empty_cache()

@@ -282,6 +282,27 @@ int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int*
 int tt_prof_begin(int what, int* nlog, int max_entries, int max_launches);
 int tt_prof_end(int* launches, int* entries, double* total_ms);
 
+/* ---- tile autotuner of the contraction kernel ----
+ * The contraction kernel has several output-tile variants (64x64, 32x64,
+ * 32x32 complex per workgroup).  tt_autotune_record(1) starts collecting the
+ * call shapes (element types, host bounds of the output, grid depth, operand
+ * access pattern) of every contraction enqueued afterwards; (0) stops.
+ * tt_autotune_run times every variant on synthetic operands of each recorded
+ * shape on `stream` (synchronises; needs tt_autotune_workspace_size() bytes
+ * of device memory) and from then on every contraction of that shape uses
+ * the fastest.  Variants differ only in how the output is partitioned, so
+ * results are bit-identical whatever is chosen.  tt_autotune_export writes
+ * up to max_entries 6-int entries (types, m, n, depth, pattern, variant) and
+ * returns the table size; tt_autotune_import loads such entries (invalid
+ * ones are skipped and reported).  Host state, not thread-safe; choices are
+ * read when a call is enqueued, so capture graphs after tuning. */
+int tt_autotune_record(int on);
+size_t tt_autotune_workspace_size(void);
+int tt_autotune_run(void* ws, size_t ws_bytes, void* stream, int* n_tuned);
+int tt_autotune_export(int32_t* entries, int max_entries);
+int tt_autotune_import(const int32_t* entries, int n);
+int tt_autotune_clear(void);
+
 /* Synchronise `stream`, read the device status word in ws, reset it to 0 and
  * return it (QTT_OK or a negative qtt_status). */
 int tt_check_status(void* ws, void* stream);

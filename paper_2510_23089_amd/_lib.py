@@ -28,6 +28,8 @@ EXPORTS = [
     "tt_cgemm", "tt_heev_workspace_size", "tt_heev", "tt_prof_begin", "tt_prof_end",
     "tt_workspace_size_batched", "tt_encode_batched", "mpo_apply_batched", "tt_to_dense_batched",
     "tt_saved_size_batched", "mpo_apply_backward_batched", "tt_to_dense_backward_batched", "tt_intensity_loss",
+    "tt_autotune_record", "tt_autotune_workspace_size", "tt_autotune_run", "tt_autotune_export",
+    "tt_autotune_import", "tt_autotune_clear",
 ]
 
 
@@ -122,6 +124,18 @@ def load(path=LIB_PATH):
     lib.tt_intensity_loss.restype = i32
     lib.tt_to_dense_batched.argtypes = [P(QttMpsBatch), vp, i32, vp, sz, vp]
     lib.tt_to_dense_batched.restype = i32
+    lib.tt_autotune_record.argtypes = [i32]
+    lib.tt_autotune_record.restype = i32
+    lib.tt_autotune_workspace_size.argtypes = []
+    lib.tt_autotune_workspace_size.restype = sz
+    lib.tt_autotune_run.argtypes = [vp, sz, vp, P(ctypes.c_int)]
+    lib.tt_autotune_run.restype = i32
+    lib.tt_autotune_export.argtypes = [vp, i32]
+    lib.tt_autotune_export.restype = i32
+    lib.tt_autotune_import.argtypes = [vp, i32]
+    lib.tt_autotune_import.restype = i32
+    lib.tt_autotune_clear.argtypes = []
+    lib.tt_autotune_clear.restype = i32
     lib.tt_check_status.argtypes = [vp, vp]
     lib.tt_check_status.restype = i32
     lib.tt_last_error.argtypes = []

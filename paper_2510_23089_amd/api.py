@@ -510,3 +510,48 @@ class FresnelPropagator:
     def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None, prec=None, refine=False):
         mid = mpo_apply(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp, prec=prec, refine=refine)
         return mpo_apply(mid, self.wy, chi, chi_zip, cutoff, tau, out=out, prec=prec, refine=refine)
+
+
+# ------------------------------------------------------------------ autotuner
+def autotune(run, device=None, path=None):
+    """Record the contraction shapes of run() (called once), time every tile
+    variant for each on this device and keep the fastest.  Optionally save the
+    table as JSON to `path`.  Returns the number of shapes tuned."""
+    import json
+    lib = L.load()
+    L.check(lib.tt_autotune_record(1), "tt_autotune_record")
+    try:
+        run()
+        torch.cuda.synchronize(device)
+    finally:
+        L.check(lib.tt_autotune_record(0), "tt_autotune_record")
+    nb = int(lib.tt_autotune_workspace_size())
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=device or "cuda")
+    n = ctypes.c_int(0)
+    L.check(lib.tt_autotune_run(_ptr(ws), ws.numel(), _stream(), ctypes.byref(n)), "tt_autotune_run")
+    if path is not None:
+        with open(path, "w") as fh:
+            json.dump(autotune_table(), fh)
+    return n.value
+
+
+def autotune_table():
+    """The current tuning table as a list of [types, m, n, depth, pattern, variant]."""
+    lib = L.load()
+    cnt = lib.tt_autotune_export(None, 0)
+    buf = (ctypes.c_int32 * (6 * max(cnt, 1)))()
+    cnt = lib.tt_autotune_export(ctypes.cast(buf, ctypes.c_void_p), cnt)
+    return [list(buf[6 * i:6 * i + 6]) for i in range(cnt)]
+
+
+def autotune_load(table_or_path):
+    """Load a table saved by autotune(path=...) (or the list itself)."""
+    import json
+    lib = L.load()
+    table = table_or_path
+    if isinstance(table_or_path, str):
+        with open(table_or_path) as fh:
+            table = json.load(fh)
+    flat = [int(x) for e in table for x in e]
+    buf = (ctypes.c_int32 * max(len(flat), 1))(*flat)
+    L.check(lib.tt_autotune_import(ctypes.cast(buf, ctypes.c_void_p), len(table)), "tt_autotune_import")

@@ -76,6 +76,10 @@ class UnevenBatch:
         api.tt_to_dense_batched(self.out, out=self.dense)
         return self.dense
 
+    def tune(self, path=None):
+        """Autotune the contraction tiles on this batch's call shapes (before capture)."""
+        return api.autotune(self.run, device=self.device, path=path)
+
     def capture(self):
         """Record run() in a HIP graph (after one eager run that sizes every
         workspace), then replay() re-issues the whole batch in one launch."""

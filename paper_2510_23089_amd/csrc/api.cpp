@@ -1698,6 +1698,45 @@ int tt_prof_end(int* launches, int* entries, double* total_ms) {
   return QTT_OK;
 }
 
+int tt_autotune_record(int on) {
+  g_err.clear();
+  autotune_record(on != 0);
+  return QTT_OK;
+}
+
+size_t tt_autotune_workspace_size(void) { return autotune_ws_bytes() + 256; }
+
+int tt_autotune_run(void* ws, size_t ws_bytes, void* stream, int* n_tuned) {
+  g_err.clear();
+  const size_t need = autotune_ws_bytes();
+  if (!ws && need > 0) return fail(QTT_ERR_ARG, "workspace is NULL");
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  if (need > 0) HIPCHK(zero_fill(ws, need / 16 * 16, s));
+  HIPCHK(autotune_run(ws, ws_bytes, s, n_tuned));
+  return QTT_OK;
+}
+
+int tt_autotune_export(int32_t* entries, int max_entries) {
+  g_err.clear();
+  if (max_entries < 0) return fail(QTT_ERR_ARG, "max_entries < 0");
+  return autotune_export(entries, max_entries);
+}
+
+int tt_autotune_import(const int32_t* entries, int n) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && !entries)) return fail(QTT_ERR_ARG, "bad entries");
+  int bad = autotune_import(entries, n);
+  if (bad) return fail(QTT_ERR_ARG, "%d invalid entries ignored", bad);
+  return QTT_OK;
+}
+
+int tt_autotune_clear(void) {
+  g_err.clear();
+  autotune_clear();
+  return QTT_OK;
+}
+
 int tt_check_status(void* ws, void* stream) {
   g_err.clear();
   if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");

@@ -20,6 +20,9 @@
 // loads of the next stage are issued into registers before the MFMAs of the
 // current stage (software pipelining).  Dimensions are read from the device
 // (DimExpr), so tiles beyond the actual bond dimensions exit at once.
+#include <map>
+#include <set>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -56,11 +59,14 @@ template <typename T> struct Vec2;
 template <> struct Vec2<float> { typedef float2 t; };
 template <> struct Vec2<double> { typedef double2 t; };
 
-constexpr int BM = 64, BN = 64, BKC = 16;   // complex tile sizes
+constexpr int BKC = 16;                     // complex depth per LDS stage
 constexpr int PADA = 4, PADB = 4;
 constexpr int NT = 256;
-constexpr int A_PER_T = BM * BKC / NT;      // complex elements of A per thread per stage
-constexpr int B_PER_T = BKC * BN / NT;
+// Output tile variants (complex rows x complex columns per workgroup); the
+// autotuner picks one per call shape, 64 x 64 by default.
+constexpr int N_TILES = 3;
+constexpr int TILE_M[N_TILES] = {64, 32, 32};
+constexpr int TILE_N[N_TILES] = {64, 64, 32};
 
 __device__ __forceinline__ long long split_off(const FastDiv& f, uint32_t x, long long sh, long long sl) {
   uint32_t h = fdiv(f, x);
@@ -71,8 +77,10 @@ __device__ __forceinline__ long long split_off(const FastDiv& f, uint32_t x, lon
 // BF: 0 = no bfloat16; 1 = operands rounded to bfloat16 (one MFMA per
 // step); 3 = operands split as x = hi + lo with hi, lo bfloat16 and the
 // product formed as hi.hi + hi.lo + lo.hi (three MFMAs, close to FP32).
-template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM, int BF = 0>
+template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM, int BF, int BM, int BN>
 __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
+  constexpr int A_PER_T = BM * BKC / NT;      // complex elements of A per thread per stage
+  constexpr int B_PER_T = BKC * BN / NT;
   typedef typename Vec2<TIn>::t in2;
   typedef typename Mfma<TC>::acc_t acc_t;
   const int f = blockIdx.z / g.b2cap;
@@ -326,13 +334,74 @@ FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-template <typename TIn, typename TC, typename TOut, int BF = 0>
-static hipError_t launch_typed(const GemmArgs& g, dim3 grid, bool akm, bool bkm, hipStream_t s) {
-  if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true, BF>), grid, dim3(NT), 0, s, g);
-  else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false, BF>), grid, dim3(NT), 0, s, g);
-  else if (bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, true, BF>), grid, dim3(NT), 0, s, g);
-  else hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, false, BF>), grid, dim3(NT), 0, s, g);
+template <typename TIn, typename TC, typename TOut, int BF, int BM, int BN>
+static hipError_t launch_tile(const GemmArgs& g, dim3 grid, bool akm, bool bkm, hipStream_t s) {
+  if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+  else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+  else if (bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, true, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+  else hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, false, BF, BM, BN>), grid, dim3(NT), 0, s, g);
   return hipGetLastError();
+}
+
+template <typename TIn, typename TC, typename TOut, int BF = 0>
+static hipError_t launch_typed(const GemmArgs& g, dim3 grid, bool akm, bool bkm, int tile, hipStream_t s) {
+  switch (tile) {
+    case 1: return launch_tile<TIn, TC, TOut, BF, 32, 64>(g, grid, akm, bkm, s);
+    case 2: return launch_tile<TIn, TC, TOut, BF, 32, 32>(g, grid, akm, bkm, s);
+    default: return launch_tile<TIn, TC, TOut, BF, 64, 64>(g, grid, akm, bkm, s);
+  }
+}
+
+// ---------------------------------------------------------------- autotuner
+// Per call shape (element types, host bounds of M and N, grid depth = inner
+// batch x fields, operand access pattern) the tile variant measured fastest
+// on this device.  Shapes are collected while recording is on; tuning times
+// every variant on synthetic operands of that shape (K = TUNE_K).
+namespace {
+struct TileKey {
+  int types, mb, nb, zb, pat;
+  bool operator<(const TileKey& o) const {
+    if (types != o.types) return types < o.types;
+    if (mb != o.mb) return mb < o.mb;
+    if (nb != o.nb) return nb < o.nb;
+    if (zb != o.zb) return zb < o.zb;
+    return pat < o.pat;
+  }
+};
+std::map<TileKey, int> g_tiles;
+std::set<TileKey> g_seen;
+bool g_record = false;
+constexpr int TUNE_K = 64;
+constexpr int TUNE_ZMAX = 2048;      // grid depth used for timing (larger grids all saturate)
+}  // namespace
+
+static TileKey make_key(const GemmSpec& sp, bool akm, bool bkm) {
+  TileKey k;
+  k.types = sp.types;
+  k.mb = sp.m_bound;
+  k.nb = sp.n_bound;
+  k.zb = (sp.batch_bound < 1 ? 1 : sp.batch_bound) * (sp.nfield < 1 ? 1 : sp.nfield) * (sp.ksplit < 1 ? 1 : sp.ksplit);
+  k.pat = (akm ? 1 : 0) | (bkm ? 2 : 0);
+  return k;
+}
+
+static hipError_t launch_variant(const GemmArgs& g0, int types, bool akm, bool bkm, int tile, int m_bound,
+                                 int n_bound, int zdim, int ksplit, hipStream_t s) {
+  GemmArgs g = g0;
+  const int bm = TILE_M[tile], bn = TILE_N[tile];
+  int tiles_m = (m_bound + bm - 1) / bm;
+  int tiles_n = (n_bound + bn - 1) / bn;
+  if (tiles_m < 1 || tiles_n < 1 || zdim < 1) return hipSuccess;
+  g.tiles_n = tiles_n;
+  dim3 grid(tiles_m * tiles_n, ksplit, zdim);
+  switch (types) {
+    case GEMM_F32: return launch_typed<float, float, float>(g, grid, akm, bkm, tile, s);
+    case GEMM_F32_GRAM64: return launch_typed<float, double, double>(g, grid, akm, bkm, tile, s);
+    case GEMM_F64: return launch_typed<double, double, double>(g, grid, akm, bkm, tile, s);
+    case GEMM_BF16: return launch_typed<float, float, float, 1>(g, grid, akm, bkm, tile, s);
+    case GEMM_BF16X3: return launch_typed<float, float, float, 3>(g, grid, akm, bkm, tile, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
@@ -344,24 +413,123 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   g.accumulate = sp.accumulate;
   g.ksplit = sp.ksplit < 1 ? 1 : sp.ksplit;
   g.csplit = sp.csplit;
-  int tiles_m = (sp.m_bound + BM - 1) / BM;
-  int tiles_n = (sp.n_bound + BN - 1) / BN;
-  if (tiles_m < 1 || tiles_n < 1 || sp.batch_bound < 1) return hipSuccess;
-  g.tiles_n = tiles_n;
+  if (sp.m_bound < 1 || sp.n_bound < 1 || sp.batch_bound < 1 || sp.nfield < 1) return hipSuccess;
   g.Mmax = sp.m_bound; g.Nmax = sp.n_bound; g.Kmax = sp.k_bound; g.Bmax = sp.batch_bound;
-  if (sp.nfield < 1) return hipSuccess;
-  dim3 grid(tiles_m * tiles_n, g.ksplit, sp.batch_bound * sp.nfield);
   // coalescing pattern: which index is unit-stride in memory
   bool akm = (sp.A.syl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.A.syh == 1);
   bool bkm = (sp.B.sxl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.B.sxh == 1);
-  switch (sp.types) {
-    case GEMM_F32: return launch_typed<float, float, float>(g, grid, akm, bkm, s);
-    case GEMM_F32_GRAM64: return launch_typed<float, double, double>(g, grid, akm, bkm, s);
-    case GEMM_F64: return launch_typed<double, double, double>(g, grid, akm, bkm, s);
-    case GEMM_BF16: return launch_typed<float, float, float, 1>(g, grid, akm, bkm, s);
-    case GEMM_BF16X3: return launch_typed<float, float, float, 3>(g, grid, akm, bkm, s);
+  TileKey key = make_key(sp, akm, bkm);
+  if (g_record) g_seen.insert(key);
+  auto it = g_tiles.find(key);
+  const int tile = it == g_tiles.end() ? 0 : it->second;
+  return launch_variant(g, sp.types, akm, bkm, tile, sp.m_bound, sp.n_bound, sp.batch_bound * sp.nfield, g.ksplit,
+                        s);
+}
+
+void autotune_record(bool on) {
+  g_record = on;
+  if (on) g_seen.clear();
+}
+
+size_t autotune_ws_bytes() {
+  size_t need = 0;
+  for (const TileKey& k : g_seen) {
+    const size_t esz = k.types == GEMM_F64 ? 16 : 8;
+    const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
+    const size_t z = std::min(k.zb, TUNE_ZMAX);
+    size_t a = z * k.mb * TUNE_K * esz, b = z * TUNE_K * k.nb * esz;
+    size_t c = z * k.mb * k.nb * csz;
+    need = std::max(need, ((a + 255) / 256 + (b + 255) / 256 + (c + 255) / 256) * 256);
   }
-  return hipErrorInvalidValue;
+  return need;
+}
+
+hipError_t autotune_run(void* ws, size_t ws_bytes, hipStream_t s, int* n_tuned) {
+  int tuned = 0;
+  if (ws_bytes < autotune_ws_bytes()) return hipErrorInvalidValue;
+  hipEvent_t e0, e1;
+  hipError_t err = hipEventCreate(&e0);
+  if (err != hipSuccess) return err;
+  err = hipEventCreate(&e1);
+  if (err != hipSuccess) { hipEventDestroy(e0); return err; }
+  for (const TileKey& k : g_seen) {
+    const size_t esz = k.types == GEMM_F64 ? 16 : 8;
+    const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
+    char* base = (char*)ws;
+    const int zt = std::min(k.zb, TUNE_ZMAX);
+    (void)csz;
+    const size_t a = ((size_t)zt * k.mb * TUNE_K * esz + 255) / 256 * 256;
+    const size_t b = ((size_t)zt * TUNE_K * k.nb * esz + 255) / 256 * 256;
+    // plain row-major operands with the recorded access pattern: A [z][M][K]
+    // (K unit stride if pat bit 0) or [z][K][M]; B likewise
+    GemmArgs g;
+    g.M = DimExpr{k.mb, nullptr, nullptr, 0};
+    g.N = DimExpr{k.nb, nullptr, nullptr, 0};
+    g.K = DimExpr{TUNE_K, nullptr, nullptr, 0};
+    g.batch = DimExpr{1, nullptr, nullptr, 0};
+    g.b2cap = 1;
+    g.fm = make_fastdiv(1); g.fn = make_fastdiv(1); g.fk = make_fastdiv(1);
+    const bool akm = k.pat & 1, bkm = (k.pat >> 1) & 1;
+    g.A = Operand{base, akm ? TUNE_K : 1, 0, akm ? 1 : k.mb, 0, (long long)k.mb * TUNE_K, 0, 0};
+    g.B = Operand{base + a, bkm ? 1 : k.nb, 0, bkm ? TUNE_K : 1, 0, (long long)TUNE_K * k.nb, 0, 0};
+    g.C = Operand{base + a + b, k.nb, 0, 1, 0, (long long)k.mb * k.nb, 0, 0};
+    g.accumulate = 0;
+    g.ksplit = 1;
+    g.csplit = 0;
+    g.Mmax = k.mb; g.Nmax = k.nb; g.Kmax = TUNE_K; g.Bmax = 1;
+    float best = 1e30f;
+    int best_t = 0;
+    for (int t = 0; t < N_TILES; ++t) {
+      // warm-up, then the mean of three launches
+      err = launch_variant(g, k.types, akm, bkm, t, k.mb, k.nb, zt, 1, s);
+      if (err != hipSuccess) break;
+      hipEventRecord(e0, s);
+      for (int r = 0; r < 3; ++r) launch_variant(g, k.types, akm, bkm, t, k.mb, k.nb, zt, 1, s);
+      hipEventRecord(e1, s);
+      err = hipEventSynchronize(e1);
+      if (err != hipSuccess) break;
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) { best = ms; best_t = t; }
+    }
+    if (err != hipSuccess) break;
+    g_tiles[k] = best_t;
+    ++tuned;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (n_tuned) *n_tuned = tuned;
+  return err;
+}
+
+int autotune_export(int* out, int max_entries) {
+  int n = 0;
+  for (const auto& kv : g_tiles) {
+    if (n < max_entries && out) {
+      int* e = out + 6 * n;
+      e[0] = kv.first.types; e[1] = kv.first.mb; e[2] = kv.first.nb; e[3] = kv.first.zb; e[4] = kv.first.pat;
+      e[5] = kv.second;
+    }
+    ++n;
+  }
+  return n;
+}
+
+int autotune_import(const int* entries, int n) {
+  int bad = 0;
+  for (int i = 0; i < n; ++i) {
+    const int* e = entries + 6 * i;
+    if (e[5] < 0 || e[5] >= N_TILES || e[1] < 1 || e[2] < 1 || e[3] < 1) { ++bad; continue; }
+    TileKey k;
+    k.types = e[0]; k.mb = e[1]; k.nb = e[2]; k.zb = e[3]; k.pat = e[4];
+    g_tiles[k] = e[5];
+  }
+  return bad;
+}
+
+void autotune_clear() {
+  g_tiles.clear();
+  g_seen.clear();
 }
 
 hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,

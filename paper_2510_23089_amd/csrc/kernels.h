@@ -27,6 +27,15 @@ struct GemmSpec {
 
 FastDiv make_fastdiv(uint32_t d);
 hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s);
+// Tile autotuner (host state, not thread-safe): record the call shapes of a
+// run, time every tile variant on synthetic operands of each shape, use the
+// fastest from then on; export / import the table as 6-int entries.
+void autotune_record(bool on);
+size_t autotune_ws_bytes();
+hipError_t autotune_run(void* ws, size_t ws_bytes, hipStream_t s, int* n_tuned);
+int autotune_export(int* out, int max_entries);
+int autotune_import(const int* entries, int n);
+void autotune_clear();
 hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,
                          DimExpr nrows, DimExpr ncols, int rows_bound, int cols_bound,
                          long long bstride_part, long long bstride_out, DimExpr batch, int batch_bound,

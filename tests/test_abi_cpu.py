@@ -137,3 +137,22 @@ def test_adjoint_argument_errors(lib):
     assert lib.tt_intensity_loss(fake, fake, L.QTT_F32, 4, 1, fake, None, fake, 1 << 20, None) == -3
     assert lib.tt_intensity_loss(fake, fake, L.QTT_C64, 0, 1, fake, None, fake, 1 << 20, None) == -2
     assert lib.tt_intensity_loss(fake, fake, L.QTT_C64, 4, 1, fake, None, fake, 8, None) == -4
+
+
+def test_autotune_table_host_side(lib):
+    """The tuning table is host state: import/export/clear need no device."""
+    import ctypes as C
+    assert lib.tt_autotune_clear() == 0
+    assert lib.tt_autotune_export(None, 0) == 0
+    good = (C.c_int32 * 12)(0, 64, 32, 8, 1, 2, 2, 128, 64, 16, 3, 0)
+    assert lib.tt_autotune_import(C.cast(good, C.c_void_p), 2) == 0
+    assert lib.tt_autotune_export(None, 0) == 2
+    out = (C.c_int32 * 12)()
+    assert lib.tt_autotune_export(C.cast(out, C.c_void_p), 2) == 2
+    assert sorted([tuple(out[0:6]), tuple(out[6:12])]) == sorted([tuple(good[0:6]), tuple(good[6:12])])
+    bad = (C.c_int32 * 6)(0, 64, 32, 8, 1, 7)          # variant out of range
+    assert lib.tt_autotune_import(C.cast(bad, C.c_void_p), 1) == -1
+    assert lib.tt_autotune_clear() == 0
+    assert lib.tt_autotune_export(None, 0) == 0
+    assert lib.tt_autotune_record(0) == 0
+    assert lib.tt_autotune_workspace_size() >= 256

@@ -131,3 +131,32 @@ def test_graph_replay_matches_eager(prec, refine):
     torch.cuda.synchronize()
     assert torch.equal(g2, e2)
     api.check_status()
+
+
+def test_autotune_keeps_results_bit_identical():
+    torch = need_gpu()
+    from paper_2510_23089_amd import api
+    from paper_2510_23089_amd import batch as BT
+    from paper_2510_23089_amd import _lib as L
+    lib = L.load()
+    L.check(lib.tt_autotune_clear(), "clear")
+    ks = [4, 6, 5]
+    chis = [8, 32, 16]
+    b = BT.UnevenBatch(ks, chis, LAM, DX, 50e-6, prec="bf16x3", refine=True)
+    b.load([synth.aperture_field(50 + i, n=1 << k) for i, k in enumerate(ks)])
+    before = b.run().clone()
+    n = b.tune()
+    assert n > 0
+    table = api.autotune_table()
+    assert len(table) == n and all(0 <= e[5] < 3 for e in table)
+    after = b.run().clone()
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+    # export / import round trip
+    L.check(lib.tt_autotune_clear(), "clear")
+    assert api.autotune_table() == []
+    api.autotune_load(table)
+    assert sorted(api.autotune_table()) == sorted(table)
+    b.capture()
+    assert torch.equal(b.replay().clone(), before)
+    api.check_status()
