@@ -290,8 +290,9 @@ int tt_prof_end(int* launches, int* entries, double* total_ms);
  * tt_autotune_run times every variant on synthetic operands of each recorded
  * shape on `stream` (synchronises; needs tt_autotune_workspace_size() bytes
  * of device memory) and from then on every contraction of that shape uses
- * the fastest.  Variants differ only in how the output is partitioned, so
- * results are bit-identical whatever is chosen.  tt_autotune_export writes
+ * the fastest (outputs larger than 512 x 512 keep the 64x64 tile).
+ * Variants differ only in how the output is partitioned, so results are
+ * bit-identical whatever is chosen.  tt_autotune_export writes
  * up to max_entries 6-int entries (types, m, n, depth, pattern, variant) and
  * returns the table size; tt_autotune_import loads such entries (invalid
  * ones are skipped and reported).  Host state, not thread-safe; choices are

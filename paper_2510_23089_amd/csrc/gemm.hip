@@ -373,6 +373,18 @@ std::set<TileKey> g_seen;
 bool g_record = false;
 constexpr int TUNE_K = 64;
 constexpr int TUNE_ZMAX = 2048;      // grid depth used for timing (larger grids all saturate)
+constexpr int TUNE_MN_MAX = 512 * 512;          // larger outputs keep the 64 x 64 tile
+constexpr size_t TUNE_BYTES = 256ull << 20;     // synthetic operands per shape
+
+// Grid depth used to time shape k (0: not tuned).
+int tune_depth(const TileKey& k) {
+  if ((long long)k.mb * k.nb > TUNE_MN_MAX) return 0;
+  const size_t esz = k.types == GEMM_F64 ? 16 : 8;
+  const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
+  const size_t per = (size_t)k.mb * TUNE_K * esz + (size_t)TUNE_K * k.nb * esz + (size_t)k.mb * k.nb * csz + 768;
+  size_t z = std::min<size_t>({(size_t)k.zb, (size_t)TUNE_ZMAX, TUNE_BYTES / per});
+  return (int)z;
+}
 }  // namespace
 
 static TileKey make_key(const GemmSpec& sp, bool akm, bool bkm) {
@@ -436,7 +448,8 @@ size_t autotune_ws_bytes() {
   for (const TileKey& k : g_seen) {
     const size_t esz = k.types == GEMM_F64 ? 16 : 8;
     const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
-    const size_t z = std::min(k.zb, TUNE_ZMAX);
+    const size_t z = (size_t)tune_depth(k);
+    if (z == 0) continue;
     size_t a = z * k.mb * TUNE_K * esz, b = z * TUNE_K * k.nb * esz;
     size_t c = z * k.mb * k.nb * csz;
     need = std::max(need, ((a + 255) / 256 + (b + 255) / 256 + (c + 255) / 256) * 256);
@@ -456,8 +469,9 @@ hipError_t autotune_run(void* ws, size_t ws_bytes, hipStream_t s, int* n_tuned) 
     const size_t esz = k.types == GEMM_F64 ? 16 : 8;
     const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
     char* base = (char*)ws;
-    const int zt = std::min(k.zb, TUNE_ZMAX);
+    const int zt = tune_depth(k);
     (void)csz;
+    if (zt == 0) continue;
     const size_t a = ((size_t)zt * k.mb * TUNE_K * esz + 255) / 256 * 256;
     const size_t b = ((size_t)zt * TUNE_K * k.nb * esz + 255) / 256 * 256;
     // plain row-major operands with the recorded access pattern: A [z][M][K]
