@@ -65,6 +65,10 @@ struct EigWs {
   double *lu_dl, *lu_d, *lu_du, *lu_du2, *z;
   int* piv;
   int* clus;
+  // exchange area of the multi-workgroup reduction: reflector and partial
+  // products of two consecutive steps, tau, and the two step counters
+  double2 *xv, *xp, *xt;
+  int* xflag;
 };
 
 __host__ __device__ inline size_t eig_ws_per_matrix(int nb, int kc) {
@@ -73,7 +77,8 @@ __host__ __device__ inline size_t eig_ws_per_matrix(int nb, int kc) {
   s += (size_t)nb * sizeof(double2);             // tau
   s += 5 * (size_t)nb * kc * sizeof(double);     // LU (4) + z
   s += (size_t)nb * kc * sizeof(int);            // pivots
-  s += (size_t)kc * sizeof(int);                 // cluster starts
+  s += ((size_t)kc * sizeof(int) + 15) / 16 * 16;  // cluster starts
+  s += 4 * (size_t)nb * sizeof(double2) + 2 * sizeof(double2) + 4 * sizeof(int);   // exchange area
   return (s + 255) / 256 * 256;
 }
 
@@ -92,7 +97,11 @@ __host__ __device__ inline EigWs eig_ws_carve(void* base, int b, int nb, int kc)
   w.lu_du2 = (double*)p; p += (size_t)nb * kc * sizeof(double);
   w.z = (double*)p; p += (size_t)nb * kc * sizeof(double);
   w.piv = (int*)p; p += (size_t)nb * kc * sizeof(int);
-  w.clus = (int*)p;
+  w.clus = (int*)p; p += ((size_t)kc * sizeof(int) + 15) / 16 * 16;
+  w.xv = (double2*)p; p += 2 * (size_t)nb * sizeof(double2);
+  w.xp = (double2*)p; p += 2 * (size_t)nb * sizeof(double2);
+  w.xt = (double2*)p; p += 2 * sizeof(double2);
+  w.xflag = (int*)p;
   return w;
 }
 
@@ -347,6 +356,152 @@ __global__ __launch_bounds__(TS_NT) void tridiag_kernel(double2* Gall, int ld, l
     }
     W.d[n - 1] = a.x;
   }
+}
+
+// (c) 128 < n <= 512 when the batch fits the chip: the matrix is split by
+//     column blocks over G workgroups (CB columns each, 128 KB of LDS), so
+//     the whole reduction runs out of LDS.  Step k: the owner of column k
+//     forms the reflector and publishes it; every workgroup forms its part of
+//     p = tau A v from its own columns (A Hermitian: (A v)_c uses column c)
+//     and publishes it; every workgroup then forms w and applies the rank-2
+//     update to its own columns.  Two device-scope flag exchanges per step;
+//     exchange buffers alternate between steps.  Every wait is bounded: a
+//     workgroup that spins too long flags QTT_ERR_NOCONVERGE and exits, so
+//     the grid always drains.  The launch keeps G * batch at or below the
+//     number of compute units, so all workgroups are resident together.
+constexpr int MW_NT = 1024;
+constexpr int MW_LDS = 8192;                  // complex doubles of owned columns (128 KB)
+constexpr long long MW_SPIN = 1ll << 20;
+
+__device__ bool mw_wait(int* flag, int target, int* status) {
+  long long it = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (++it > MW_SPIN) {
+      set_status(status, ST_NOCONVERGE);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+__global__ void mw_reset_kernel(void* wsbase, int nb, int kc) {
+  EigWs W = eig_ws_carve(wsbase, blockIdx.x, nb, kc);
+  if (threadIdx.x < 4) W.xflag[threadIdx.x] = 0;
+}
+
+template <int CB>
+__global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
+                                                            void* wsbase, int nb, int kc, int* status, int* nlog) {
+  constexpr int TPC = MW_NT / CB;             // threads per owned column
+  const int g = blockIdx.x, G = gridDim.x, b = blockIdx.y;
+  const int n = min(dim_eval(nexp, b), nb);
+  double2* A = Gall + (long long)b * gstride;
+  EigWs W = eig_ws_carve(wsbase, b, nb, kc);
+  __shared__ double2 Ac[MW_LDS];              // owned columns, Ac[cl * n + r]
+  __shared__ double2 sv[EIG_NMAX], sp[EIG_NMAX];
+  __shared__ double red[2 * MW_NT / 64];
+  __shared__ double2 s_tau, s_scale;
+  __shared__ int s_ok;
+  const int tid = threadIdx.x;
+  const int c0 = g * CB;
+  const int cn = max(0, min(CB, n - c0));
+  if (nlog && g == 0 && tid == 0) nlog[b] = n;
+  for (int e = tid; e < n * CB; e += MW_NT) {
+    const int r = e / CB, cl = e - r * CB;
+    if (cl < cn) Ac[cl * n + r] = A[(long long)r * ld + c0 + cl];
+  }
+  __syncthreads();
+  const int mc = tid / TPC, lt = tid - (tid / TPC) * TPC;
+  for (int k = 0; k < n - 1; ++k) {
+    const int k1 = k + 1;
+    const int buf = k & 1;
+    double2* xv = W.xv + (long long)buf * nb;
+    double2* xp = W.xp + (long long)buf * nb;
+    // ---- A: the owner of column k forms and publishes the reflector
+    if (g == k / CB) {
+      const int lc = k - c0;
+      double loc = 0.0;
+      for (int r = k1 + 1 + tid; r < n; r += MW_NT) {
+        double2 x = Ac[lc * n + r];
+        loc += x.x * x.x + x.y * x.y;
+      }
+      const double xnorm2 = block_sum<MW_NT>(loc, red);
+      if (tid == 0) {
+        double2 tau, scale;
+        double beta;
+        householder(Ac[lc * n + k1], xnorm2, tau, scale, beta);
+        W.d[k] = Ac[lc * n + k].x;
+        W.e[k] = beta;
+        W.e2[k] = beta * beta;
+        W.tau[k] = tau;
+        W.xt[buf] = tau;
+        s_scale = scale;
+      }
+      __syncthreads();
+      const double2 scale = s_scale;
+      for (int r = k1 + tid; r < n; r += MW_NT) {
+        const double2 v = r == k1 ? make_double2(1.0, 0.0) : cmul(Ac[lc * n + r], scale);
+        xv[r] = v;
+        if (r > k1) A[(long long)k * ld + r] = v;    // reflector kept for the back-transformation
+      }
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) __hip_atomic_store(W.xflag, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // ---- B: p_c = tau sum_r conj(A[r][c]) v_r for the owned columns c > k
+    if (tid == 0) s_ok = mw_wait(W.xflag, k + 1, status);
+    __syncthreads();
+    if (!s_ok) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int r = k1 + tid; r < n; r += MW_NT) sv[r] = xv[r];
+    if (tid == 0) s_tau = W.xt[buf];
+    __syncthreads();
+    const double2 tau = s_tau;
+    {
+      const int c = c0 + mc;
+      const bool act = mc < cn && c > k;
+      double2 acc = make_double2(0.0, 0.0);
+      if (act)
+        for (int r = k1 + lt; r < n; r += TPC) acc = cadd(acc, cmulc(Ac[mc * n + r], sv[r]));
+#pragma unroll
+      for (int o = 1; o < TPC; o <<= 1) {
+        acc.x += __shfl_xor(acc.x, o);
+        acc.y += __shfl_xor(acc.y, o);
+      }
+      if (act && lt == 0) xp[c] = cmul(tau, acc);
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) __hip_atomic_fetch_add(W.xflag + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // ---- C: w = p - (tau/2)(p^H v) v, rank-2 update of the owned columns
+    if (tid == 0) s_ok = mw_wait(W.xflag + 1, G * (k + 1), status);
+    __syncthreads();
+    if (!s_ok) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int r = k1 + tid; r < n; r += MW_NT) sp[r] = xp[r];
+    __syncthreads();
+    double2 dl = make_double2(0.0, 0.0);
+    for (int r = k1 + tid; r < n; r += MW_NT) dl = cadd(dl, cmulc(sp[r], sv[r]));
+    const double2 dot = block_sum2<MW_NT>(dl, red);
+    const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
+    for (int r = k1 + tid; r < n; r += MW_NT) sp[r] = cadd(sp[r], cmul(alpha2, sv[r]));
+    __syncthreads();
+    {
+      const int c = c0 + mc;
+      if (mc < cn && c > k) {
+        const double2 wc = make_double2(sp[c].x, -sp[c].y), vc = make_double2(sv[c].x, -sv[c].y);
+        for (int r = k1 + lt; r < n; r += TPC) {
+          double2 a = Ac[mc * n + r];
+          a = csub(a, cmul(sv[r], wc));
+          a = csub(a, cmul(sp[r], vc));
+          Ac[mc * n + r] = a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (n >= 1 && g == (n - 1) / CB && tid == 0) W.d[n - 1] = Ac[(n - 1 - c0) * n + (n - 1)].x;
 }
 
 // ------------------------------------------------------------ 2. eigenvalues
@@ -745,6 +900,19 @@ __global__ void adj_scale_kernel(DimExpr nexp, int* kin, long long kstride, void
 
 ProfHook g_prof;
 
+// Compute units of the current device (queried once per device).
+static int compute_units() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] == 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    cached[dev] = prop.multiProcessorCount;
+  }
+  return cached[dev];
+}
+
 size_t eig_ws_bytes(int n_bound, int kcap, int batch) {
   int kc = kcap < n_bound ? kcap : n_bound;
   if (kc < 1) kc = 1;
@@ -765,12 +933,23 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
                     g_prof.slot + sp.batch <= g_prof.max;
   if (prof) hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
   int* nl = prof ? g_prof.nlog + g_prof.slot : (int*)nullptr;
-  if (nb <= TL_NMAX)
+  const int cb = nb <= 256 ? 32 : 16;
+  const int groups = (nb + cb - 1) / cb;
+  if (nb <= TL_NMAX) {
     hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
                        sp.n, sp.ws, nb, kc, nl);
-  else
+  } else if ((long long)groups * sp.batch <= compute_units()) {
+    hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(64), 0, s, sp.ws, nb, kc);
+    if (cb == 32)
+      hipLaunchKernelGGL(tridiag_mwg_kernel<32>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
+    else
+      hipLaunchKernelGGL(tridiag_mwg_kernel<16>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
+  } else {
     hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TS_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
                        sp.n, sp.ws, nb, kc, nl);
+  }
   if (prof) {
     hipEventRecord(g_prof.ev[2 * g_prof.launches + 1], s);
     g_prof.launches++;
