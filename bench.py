@@ -10,10 +10,12 @@ distances advancing as one batch -- and each result is decompressed to the
 decompression included).  Inputs are resident in HBM before the timed region;
 the host float64 MPO construction is setup.
 
-The dominant kernel (qtt::tridiag_kernel, the streaming Householder
-tridiagonalisation of Gram matrices larger than 128 in the FP64 eigensolver) is timed live with HIP events around each of its launches during
-the timed steps, and reports the algorithmic FP64 work (16/3) n^3 of each
-launch from the matrix sizes the kernel logs on the device.
+The dominant kernel (qtt::tridiag_mwg_kernel<32>, the Householder
+tridiagonalisation of the FP64 Gram matrices larger than 128, split over
+eight LDS-resident workgroups per matrix) is timed live with HIP events
+around each of its launches during the timed steps, and reports the
+algorithmic FP64 work (16/3) n^3 of each launch from the matrix sizes the
+kernel logs on the device.
 
 cpu_baseline: the float64 oracle (numpy/LAPACK) on the host, on a bounded
 sample of the same workload: encode + one propagation (x then y) at z = 2 mm.
@@ -335,7 +337,8 @@ def main():
                                "encode + 3 propagations + 3 decompressions per step",
                    "global_batch": 1, "chi": chi, "sites": m},
         "roofline": {
-            "kernel": "qtt::tridiag_kernel (streaming Householder reduction, FP64 Gram eigensolver, n > 128)",
+            "kernel": "qtt::tridiag_mwg_kernel<32> (Householder reduction over 8 LDS-resident workgroups, "
+                      "FP64 Gram eigensolver, 128 < n <= 256)",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,

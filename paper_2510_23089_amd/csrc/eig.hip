@@ -5,11 +5,15 @@
 // squared singular values decide the kept rank (Sec. 4: each bond is a
 // Schmidt cut) and the eigenvectors give the kept singular subspace.  Stages,
 // one kernel each, all stream-ordered with device-side sizes:
-//   1. tridiag   Householder reduction to real tridiagonal form, one
-//                workgroup per matrix; the rank-2 update of step j is fused
-//                with the matrix-vector product of step j+1 so the trailing
-//                matrix is streamed once per step (column-per-thread, rows
-//                read coalesced).  Reflectors are kept in the upper triangle.
+//   1. tridiag   Householder reduction to real tridiagonal form.  n <= 128:
+//                one workgroup per matrix with the packed triangle in LDS.
+//                128 < n <= 512: column blocks spread over several
+//                workgroups (all LDS-resident) exchanging the reflector and
+//                the partial products through device-coherent atomics when
+//                the batch fits the chip; otherwise one workgroup per matrix
+//                streaming the trailing matrix from L2 once per step (the
+//                rank-2 update of step j fused with the product of step j+1).
+//                Reflectors are kept in the upper triangle.
 //   2. eigvals   the top min(n, cap) eigenvalues, one wave per eigenvalue:
 //                64-way multisection on Sturm counts (division-free
 //                three-term recurrence with exponent rescaling), so a wave
@@ -375,7 +379,7 @@ constexpr long long MW_SPIN = 1ll << 20;
 
 __device__ bool mw_wait(int* flag, int target, int* status) {
   long long it = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if (++it > MW_SPIN) {
       set_status(status, ST_NOCONVERGE);
       return false;
@@ -384,6 +388,25 @@ __device__ bool mw_wait(int* flag, int target, int* status) {
   }
   return true;
 }
+
+// Exchange-area accesses: relaxed device-scope atomics on 64-bit halves, so
+// the data travels through the device-coherent level without whole-cache
+// write-back / invalidate fences; ordering comes from waiting for the
+// stores' completion before the flag is raised, and from the loads being
+// issued only after the flag was seen.
+__device__ __forceinline__ void xstore(double2* p, double2 v) {
+  unsigned long long* q = (unsigned long long*)p;
+  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 xload(const double2* p) {
+  unsigned long long* q = (unsigned long long*)p;
+  double2 v;
+  v.x = __longlong_as_double((long long)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  v.y = __longlong_as_double((long long)__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  return v;
+}
+__device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0); }
 
 __global__ void mw_reset_kernel(void* wsbase, int nb, int kc) {
   EigWs W = eig_ws_carve(wsbase, blockIdx.x, nb, kc);
@@ -435,27 +458,26 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
         W.e[k] = beta;
         W.e2[k] = beta * beta;
         W.tau[k] = tau;
-        W.xt[buf] = tau;
+        xstore(W.xt + buf, tau);
         s_scale = scale;
       }
       __syncthreads();
       const double2 scale = s_scale;
       for (int r = k1 + tid; r < n; r += MW_NT) {
         const double2 v = r == k1 ? make_double2(1.0, 0.0) : cmul(Ac[lc * n + r], scale);
-        xv[r] = v;
+        xstore(xv + r, v);
         if (r > k1) A[(long long)k * ld + r] = v;    // reflector kept for the back-transformation
       }
-      __threadfence();
+      stores_done();
       __syncthreads();
-      if (tid == 0) __hip_atomic_store(W.xflag, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (tid == 0) __hip_atomic_store(W.xflag, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     // ---- B: p_c = tau sum_r conj(A[r][c]) v_r for the owned columns c > k
     if (tid == 0) s_ok = mw_wait(W.xflag, k + 1, status);
     __syncthreads();
     if (!s_ok) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int r = k1 + tid; r < n; r += MW_NT) sv[r] = xv[r];
-    if (tid == 0) s_tau = W.xt[buf];
+    for (int r = k1 + tid; r < n; r += MW_NT) sv[r] = xload(xv + r);
+    if (tid == 0) s_tau = xload(W.xt + buf);
     __syncthreads();
     const double2 tau = s_tau;
     {
@@ -469,17 +491,16 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
         acc.x += __shfl_xor(acc.x, o);
         acc.y += __shfl_xor(acc.y, o);
       }
-      if (act && lt == 0) xp[c] = cmul(tau, acc);
+      if (act && lt == 0) xstore(xp + c, cmul(tau, acc));
     }
-    __threadfence();
+    stores_done();
     __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(W.xflag + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0) __hip_atomic_fetch_add(W.xflag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // ---- C: w = p - (tau/2)(p^H v) v, rank-2 update of the owned columns
     if (tid == 0) s_ok = mw_wait(W.xflag + 1, G * (k + 1), status);
     __syncthreads();
     if (!s_ok) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int r = k1 + tid; r < n; r += MW_NT) sp[r] = xp[r];
+    for (int r = k1 + tid; r < n; r += MW_NT) sp[r] = xload(xp + r);
     __syncthreads();
     double2 dl = make_double2(0.0, 0.0);
     for (int r = k1 + tid; r < n; r += MW_NT) dl = cadd(dl, cmulc(sp[r], sv[r]));
@@ -931,15 +952,16 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   const int cls = nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG;
   const bool prof = g_prof.what == cls && g_prof.launches < g_prof.max_launches &&
                     g_prof.slot + sp.batch <= g_prof.max;
-  if (prof) hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
-  int* nl = prof ? g_prof.nlog + g_prof.slot : (int*)nullptr;
   const int cb = nb <= 256 ? 32 : 16;
   const int groups = (nb + cb - 1) / cb;
+  const bool mwg = nb > TL_NMAX && (long long)groups * sp.batch <= compute_units();
+  if (mwg) hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(64), 0, s, sp.ws, nb, kc);
+  if (prof) hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
+  int* nl = prof ? g_prof.nlog + g_prof.slot : (int*)nullptr;
   if (nb <= TL_NMAX) {
     hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
                        sp.n, sp.ws, nb, kc, nl);
-  } else if ((long long)groups * sp.batch <= compute_units()) {
-    hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(64), 0, s, sp.ws, nb, kc);
+  } else if (mwg) {
     if (cb == 32)
       hipLaunchKernelGGL(tridiag_mwg_kernel<32>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
                          sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
