@@ -364,15 +364,18 @@ __global__ __launch_bounds__(TS_NT) void tridiag_kernel(double2* Gall, int ld, l
 
 // (c) 128 < n <= 512 when the batch fits the chip: the matrix is split by
 //     column blocks over G workgroups (CB columns each, 128 KB of LDS), so
-//     the whole reduction runs out of LDS.  Step k: the owner of column k
-//     forms the reflector and publishes it; every workgroup forms its part of
-//     p = tau A v from its own columns (A Hermitian: (A v)_c uses column c)
-//     and publishes it; every workgroup then forms w and applies the rank-2
-//     update to its own columns.  Two device-scope flag exchanges per step;
-//     exchange buffers alternate between steps.  Every wait is bounded: a
-//     workgroup that spins too long flags QTT_ERR_NOCONVERGE and exits, so
-//     the grid always drains.  The launch keeps G * batch at or below the
-//     number of compute units, so all workgroups are resident together.
+//     the whole reduction runs out of LDS.  Every workgroup also keeps a copy
+//     of the next column to be reduced.  Step k: every workgroup forms the
+//     reflector of column k from its copy (the same arithmetic everywhere),
+//     forms its part of p = tau A v from its own columns (A Hermitian:
+//     (A v)_c uses column c) and publishes it -- the owner of column k + 1
+//     publishes that column as well; after one exchange every workgroup holds
+//     p and column k + 1, forms w, and updates its own columns and its copy of
+//     column k + 1.  One device-scope exchange per step; exchange buffers
+//     alternate between steps.  Every wait is bounded: a workgroup that
+//     spins too long flags QTT_ERR_NOCONVERGE and exits, so the grid always
+//     drains.  The launch keeps G * batch at or below the number of compute
+//     units, so all workgroups are resident together.
 constexpr int MW_NT = 1024;
 constexpr int MW_LDS = 8192;                  // complex doubles of owned columns (128 KB)
 constexpr long long MW_SPIN = 1ll << 20;
@@ -422,7 +425,7 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
   double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 Ac[MW_LDS];              // owned columns, Ac[cl * n + r]
-  __shared__ double2 sv[EIG_NMAX], sp[EIG_NMAX];
+  __shared__ double2 sv[EIG_NMAX], sp[EIG_NMAX], scol[EIG_NMAX];
   __shared__ double red[2 * MW_NT / 64];
   __shared__ double2 s_tau, s_scale;
   __shared__ int s_ok;
@@ -434,52 +437,45 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
     const int r = e / CB, cl = e - r * CB;
     if (cl < cn) Ac[cl * n + r] = A[(long long)r * ld + c0 + cl];
   }
+  // every workgroup keeps its own copy of the next column to be reduced
+  for (int r = tid; r < n; r += MW_NT) scol[r] = A[(long long)r * ld];
   __syncthreads();
   const int mc = tid / TPC, lt = tid - (tid / TPC) * TPC;
   for (int k = 0; k < n - 1; ++k) {
     const int k1 = k + 1;
     const int buf = k & 1;
-    double2* xv = W.xv + (long long)buf * nb;
+    double2* xc = W.xv + (long long)buf * nb;
     double2* xp = W.xp + (long long)buf * nb;
-    // ---- A: the owner of column k forms and publishes the reflector
-    if (g == k / CB) {
-      const int lc = k - c0;
-      double loc = 0.0;
-      for (int r = k1 + 1 + tid; r < n; r += MW_NT) {
-        double2 x = Ac[lc * n + r];
-        loc += x.x * x.x + x.y * x.y;
-      }
-      const double xnorm2 = block_sum<MW_NT>(loc, red);
-      if (tid == 0) {
-        double2 tau, scale;
-        double beta;
-        householder(Ac[lc * n + k1], xnorm2, tau, scale, beta);
-        W.d[k] = Ac[lc * n + k].x;
+    // ---- A: reflector of column k, formed redundantly (and identically) by every workgroup
+    double loc = 0.0;
+    for (int r = k1 + 1 + tid; r < n; r += MW_NT) {
+      double2 x = scol[r];
+      loc += x.x * x.x + x.y * x.y;
+    }
+    const double xnorm2 = block_sum<MW_NT>(loc, red);
+    if (tid == 0) {
+      double2 tau, scale;
+      double beta;
+      householder(scol[k1], xnorm2, tau, scale, beta);
+      if (g == 0) {
+        W.d[k] = scol[k].x;
         W.e[k] = beta;
         W.e2[k] = beta * beta;
         W.tau[k] = tau;
-        xstore(W.xt + buf, tau);
-        s_scale = scale;
       }
-      __syncthreads();
-      const double2 scale = s_scale;
-      for (int r = k1 + tid; r < n; r += MW_NT) {
-        const double2 v = r == k1 ? make_double2(1.0, 0.0) : cmul(Ac[lc * n + r], scale);
-        xstore(xv + r, v);
-        if (r > k1) A[(long long)k * ld + r] = v;    // reflector kept for the back-transformation
-      }
-      stores_done();
-      __syncthreads();
-      if (tid == 0) __hip_atomic_store(W.xflag, k + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_tau = tau;
+      s_scale = scale;
     }
-    // ---- B: p_c = tau sum_r conj(A[r][c]) v_r for the owned columns c > k
-    if (tid == 0) s_ok = mw_wait(W.xflag, k + 1, status);
     __syncthreads();
-    if (!s_ok) return;
-    for (int r = k1 + tid; r < n; r += MW_NT) sv[r] = xload(xv + r);
-    if (tid == 0) s_tau = xload(W.xt + buf);
+    const double2 tau = s_tau, scale = s_scale;
+    for (int r = k1 + tid; r < n; r += MW_NT) {
+      const double2 v = r == k1 ? make_double2(1.0, 0.0) : cmul(scol[r], scale);
+      sv[r] = v;
+      if (g == 0 && r > k1) A[(long long)k * ld + r] = v;   // reflector kept for the back-transformation
+    }
     __syncthreads();
-    const double2 tau = s_tau;
+    // ---- B: p_c = tau sum_r conj(A[r][c]) v_r for the owned columns c > k;
+    //         the owner of column k + 1 also publishes that column
     {
       const int c = c0 + mc;
       const bool act = mc < cn && c > k;
@@ -493,14 +489,20 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
       }
       if (act && lt == 0) xstore(xp + c, cmul(tau, acc));
     }
+    if (k1 >= c0 && k1 < c0 + cn)
+      for (int r = k1 + tid; r < n; r += MW_NT) xstore(xc + r, Ac[(k1 - c0) * n + r]);
     stores_done();
     __syncthreads();
     if (tid == 0) __hip_atomic_fetch_add(W.xflag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // ---- C: w = p - (tau/2)(p^H v) v, rank-2 update of the owned columns
+    // ---- C: w = p - (tau/2)(p^H v) v; rank-2 update of the owned columns
+    //         and of the copy of column k + 1
     if (tid == 0) s_ok = mw_wait(W.xflag + 1, G * (k + 1), status);
     __syncthreads();
     if (!s_ok) return;
-    for (int r = k1 + tid; r < n; r += MW_NT) sp[r] = xload(xp + r);
+    for (int r = k1 + tid; r < n; r += MW_NT) {
+      sp[r] = xload(xp + r);
+      scol[r] = xload(xc + r);
+    }
     __syncthreads();
     double2 dl = make_double2(0.0, 0.0);
     for (int r = k1 + tid; r < n; r += MW_NT) dl = cadd(dl, cmulc(sp[r], sv[r]));
@@ -519,10 +521,17 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
           Ac[mc * n + r] = a;
         }
       }
+      const double2 wk = make_double2(sp[k1].x, -sp[k1].y), vk = make_double2(sv[k1].x, -sv[k1].y);
+      for (int r = k1 + tid; r < n; r += MW_NT) {
+        double2 a = scol[r];
+        a = csub(a, cmul(sv[r], wk));
+        a = csub(a, cmul(sp[r], vk));
+        scol[r] = a;
+      }
     }
     __syncthreads();
   }
-  if (n >= 1 && g == (n - 1) / CB && tid == 0) W.d[n - 1] = Ac[(n - 1 - c0) * n + (n - 1)].x;
+  if (n >= 1 && g == 0 && tid == 0) W.d[n - 1] = scol[n - 1].x;
 }
 
 // ------------------------------------------------------------ 2. eigenvalues
