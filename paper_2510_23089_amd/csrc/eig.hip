@@ -115,6 +115,7 @@ __host__ __device__ inline EigWs eig_ws_carve(void* base, int b, int nb, int kc)
 //     matrix-vector product and the rank-2 update.
 constexpr int TL_NMAX = 128;
 constexpr int TL_NT = 1024;
+constexpr int TL_ROWS = TL_NT / 8;           // rows per pass (8 threads per row)
 constexpr int TL_TRI = TL_NMAX * (TL_NMAX + 1) / 2;
 
 __device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1) >> 1) + c; }   // r >= c
@@ -200,8 +201,8 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
     __syncthreads();
     if (tau.x == 0.0 && tau.y == 0.0) continue;
     // p = tau A v over the trailing block (A Hermitian, lower triangle stored)
-    {
-      const int r = j1 + rl;
+    for (int rb = j1; rb < n; rb += TL_ROWS) {
+      const int r = rb + rl;
       double2 acc = make_double2(0.0, 0.0);
       if (r < n) {
         for (int c = j1 + sl; c < n; c += 8) {
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
     for (int r = j1 + tid; r < n; r += TL_NT) P[r] = cadd(P[r], cmul(alpha2, V[r]));
     __syncthreads();
     // rank-2 update of the lower trailing triangle: A -= v w^H + w v^H
-    {
-      const int r = j1 + rl;
+    for (int rb = j1; rb < n; rb += TL_ROWS) {
+      const int r = rb + rl;
       if (r < n) {
         const double2 vr = V[r], wr = P[r];
         for (int c = j1 + sl; c <= r; c += 8) {
