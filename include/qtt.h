@@ -247,6 +247,34 @@ int tt_to_dense_backward_batched(const qtt_mps_batch* in, const void* grad_dense
 int tt_intensity_loss(const void* field, const void* target, int dtype, int log2_side, int count,
                       double* loss, void* grad, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- fields too large to densify ----
+ * tt_encode_separable: E0[a][b] = vec_a[a] * vec_b[b] on a 2^n x 2^n grid
+ * (n = log2_side, even) without forming the 2-D array: each vector is
+ * encoded as a 1-D MPS of n sites by sequential SVD (cap c1 = the largest
+ * integer with c1^2 <= out->chi_cap, keep rule with tau = 1e-13) and the two
+ * are interleaved in quantics order (Sec. 3): the site of bit p of a carries
+ * core_a(p) x identity, the site of bit p of b identity x core_b(p), so every
+ * bond is a product of the factors' bonds.  vec_dtype F32/F64/C64/C128 (the
+ * MPS dtype decides the compute precision).  out->norm is not written and
+ * the result is left-orthonormal except for its last two cores.  Workspace:
+ * tt_encode_separable_workspace_size(log2_side, chi_cap, prec).
+ * tt_eval_points: out[p] = the field at pixel (rows[p], cols[p]) for count
+ * points (device int arrays; device output of the MPS dtype), all points
+ * contracted site by site together.  Workspace: tt_eval_points_workspace_size.
+ * tt_to_dense_block: the aligned 2^log2_block square block (block_row,
+ * block_col) of the field (row-major, out_dtype C64/C128): the high bits are
+ * contracted into a boundary vector, the remaining sites decompressed.
+ * Workspace: tt_to_dense_block_workspace_size. */
+size_t tt_encode_separable_workspace_size(int log2_side, int chi_cap, int prec);
+int tt_encode_separable(const void* vec_a, const void* vec_b, int vec_dtype, int log2_side, qtt_mps* out,
+                        void* ws, size_t ws_bytes, void* stream);
+size_t tt_eval_points_workspace_size(int n_sites, int chi_cap, int count, int prec);
+int tt_eval_points(const qtt_mps* in, const int32_t* rows, const int32_t* cols, int count, void* out,
+                   void* ws, size_t ws_bytes, void* stream);
+size_t tt_to_dense_block_workspace_size(int n_sites, int chi_cap, int log2_block, int prec);
+int tt_to_dense_block(const qtt_mps* in, int log2_block, int block_row, int block_col, void* out, int out_dtype,
+                      void* ws, size_t ws_bytes, void* stream);
+
 /* ---- auxiliary entry points (the building blocks of the calls above) ---- */
 
 /* C = op(A) . op(B) for dense row-major complex matrices through the MFMA

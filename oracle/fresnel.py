@@ -59,3 +59,14 @@ def gaussian_beam_exact(n_side, w0, lam, dx, z, ca, cb):
     b = (np.arange(n_side)[None, :] - cb) * dx
     r2 = a * a + b * b
     return np.exp(-r2 / (w * w * q)) / q
+
+
+def gaussian_beam_exact_1d(n_side, w0, lam, dx, z, c):
+    """1-D closed form of the same propagation: q^-1/2 exp(-u^2 / (w0^2 q)),
+    u = (index - c) dx, for the factor exp(-u^2 / w0^2) of a separable beam
+    (each axis contributes q^-1/2, their product the 2-D q^-1)."""
+    w = w0 * dx
+    zr = np.pi * w * w / lam
+    q = 1.0 + 1j * z / zr
+    u = (np.arange(n_side) - c) * dx
+    return np.exp(-u * u / (w * w * q)) / np.sqrt(q)

@@ -30,6 +30,8 @@ EXPORTS = [
     "tt_saved_size_batched", "mpo_apply_backward_batched", "tt_to_dense_backward_batched", "tt_intensity_loss",
     "tt_autotune_record", "tt_autotune_workspace_size", "tt_autotune_run", "tt_autotune_export",
     "tt_autotune_import", "tt_autotune_clear",
+    "tt_encode_separable_workspace_size", "tt_encode_separable", "tt_eval_points_workspace_size", "tt_eval_points",
+    "tt_to_dense_block_workspace_size", "tt_to_dense_block",
 ]
 
 
@@ -136,6 +138,18 @@ def load(path=LIB_PATH):
     lib.tt_autotune_import.restype = i32
     lib.tt_autotune_clear.argtypes = []
     lib.tt_autotune_clear.restype = i32
+    lib.tt_encode_separable_workspace_size.argtypes = [i32, i32, i32]
+    lib.tt_encode_separable_workspace_size.restype = sz
+    lib.tt_encode_separable.argtypes = [vp, vp, i32, i32, P(QttMps), vp, sz, vp]
+    lib.tt_encode_separable.restype = i32
+    lib.tt_eval_points_workspace_size.argtypes = [i32, i32, i32, i32]
+    lib.tt_eval_points_workspace_size.restype = sz
+    lib.tt_eval_points.argtypes = [P(QttMps), vp, vp, i32, vp, vp, sz, vp]
+    lib.tt_eval_points.restype = i32
+    lib.tt_to_dense_block_workspace_size.argtypes = [i32, i32, i32, i32]
+    lib.tt_to_dense_block_workspace_size.restype = sz
+    lib.tt_to_dense_block.argtypes = [P(QttMps), i32, i32, i32, vp, i32, vp, sz, vp]
+    lib.tt_to_dense_block.restype = i32
     lib.tt_check_status.argtypes = [vp, vp]
     lib.tt_check_status.restype = i32
     lib.tt_last_error.argtypes = []

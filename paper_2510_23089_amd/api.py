@@ -275,6 +275,77 @@ def tt_to_dense(psi, out=None):
     return out
 
 
+def tt_encode_separable(vec_a, vec_b, chi_cap, prec="fp32", out=None):
+    """Field vec_a[a] * vec_b[b] (two device vectors of length 2^n, n even)
+    as a 2n-site MPS without forming the 2-D array."""
+    lib = L.load()
+    N = int(vec_a.numel())
+    n = N.bit_length() - 1
+    assert (1 << n) == N and int(vec_b.numel()) == N
+    dt = {torch.float32: L.QTT_F32, torch.float64: L.QTT_F64,
+          torch.complex64: L.QTT_C64, torch.complex128: L.QTT_C128}[vec_a.dtype]
+    vb = vec_b.to(vec_a.dtype).contiguous()
+    va = vec_a.contiguous()
+    if out is None:
+        out = MPS(2 * n, chi_cap, dtype=_ctype(prec), device=vec_a.device)
+    nb = lib.tt_encode_separable_workspace_size(n, out.chi_cap, _prec_code(prec))
+    ws = workspace(nb, vec_a.device, key="separable")
+    s = out.cstruct()
+    L.check(lib.tt_encode_separable(_ptr(va), _ptr(vb), dt, n, ctypes.byref(s), _ptr(ws), nb, _stream()),
+            "tt_encode_separable")
+    return out
+
+
+def tt_eval_points(psi, rows, cols):
+    """Field values at pixels (rows[p], cols[p]) (device int32 tensors)."""
+    lib = L.load()
+    count = int(rows.numel())
+    r = rows.to(torch.int32).contiguous()
+    c = cols.to(torch.int32).contiguous()
+    out = torch.empty(count, dtype=psi.dtype, device=psi.cores.device)
+    prec = L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32
+    nb = lib.tt_eval_points_workspace_size(psi.n_sites, psi.chi_cap, count, prec)
+    ws = workspace(nb, psi.cores.device, key="points")
+    s = psi.cstruct()
+    L.check(lib.tt_eval_points(ctypes.byref(s), _ptr(r), _ptr(c), count, _ptr(out), _ptr(ws), nb, _stream()),
+            "tt_eval_points")
+    return out
+
+
+def tt_to_dense_block(psi, log2_block, block_row, block_col, out=None):
+    """The aligned 2^log2_block square block (block_row, block_col) of the field."""
+    lib = L.load()
+    side = 1 << log2_block
+    if out is None:
+        out = torch.empty((side, side), dtype=psi.dtype, device=psi.cores.device)
+    dt = L.QTT_C128 if out.dtype == torch.complex128 else L.QTT_C64
+    prec = L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32
+    nb = lib.tt_to_dense_block_workspace_size(psi.n_sites, psi.chi_cap, log2_block, prec)
+    ws = workspace(nb, psi.cores.device, key="block")
+    s = psi.cstruct()
+    L.check(lib.tt_to_dense_block(ctypes.byref(s), log2_block, block_row, block_col, _ptr(out), dt, _ptr(ws), nb,
+                                  _stream()), "tt_to_dense_block")
+    return out
+
+
+def tt_to_dense_window(psi, row0, col0, rows, cols, log2_block=None):
+    """An arbitrary rows x cols window at (row0, col0), assembled from the
+    aligned blocks that cover it (nothing outside those blocks is formed)."""
+    n = psi.n_sites // 2
+    if log2_block is None:
+        log2_block = max(1, min(n, max(rows, cols).bit_length() - 1))
+    side = 1 << log2_block
+    out = torch.empty((rows, cols), dtype=psi.dtype, device=psi.cores.device)
+    for br in range(row0 // side, (row0 + rows - 1) // side + 1):
+        for bc in range(col0 // side, (col0 + cols - 1) // side + 1):
+            blk = tt_to_dense_block(psi, log2_block, br, bc)
+            r0, c0 = br * side, bc * side
+            ra, rb = max(row0, r0), min(row0 + rows, r0 + side)
+            ca, cb = max(col0, c0), min(col0 + cols, c0 + side)
+            out[ra - row0:rb - row0, ca - col0:cb - col0] = blk[ra - r0:rb - r0, ca - c0:cb - c0]
+    return out
+
+
 class MPSBatch:
     """count MPS of one shape in one allocation: cores (count, m, chi_cap, 2, chi_cap)."""
 

@@ -1089,8 +1089,10 @@ EncBufs carve_encode(Carver& cv, int m, int chi, size_t csz, int nf) {
 }
 
 // img: nf images of N x N (field stride N^2 elements of img_dtype)
+// dir 0: a 2^n x 2^n image, quantics-permuted; dir 2: a flat vector of
+// length 2^(2n) taken as is (a 1-D signal of 2n bits).
 int encode_impl(const void* img, int img_dtype, int n, const qtt_opts& o, const MpsB& out, EncBufs& b,
-                const int* chi_dev, hipStream_t s) {
+                const int* chi_dev, hipStream_t s, int dir = 0) {
   const int m = 2 * n, nf = out.nf;
   const int real = out.dtype == QTT_C128 ? 1 : 0;
   const int chi = o.chi_max;
@@ -1103,7 +1105,7 @@ int encode_impl(const void* img, int img_dtype, int n, const qtt_opts& o, const 
   std::vector<int> rb = mps_bounds(m, chi);
   const size_t isz = img_dtype == QTT_C128 ? 16 : (img_dtype == QTT_F32 ? 4 : 8);
   (void)isz;
-  HIPCHK(quantics_permute(img, img_dtype, b.v, real ? QTT_C128 : QTT_C64, n, 0, s, nf, b.sq, b.sq));
+  HIPCHK(quantics_permute(img, img_dtype, b.v, real ? QTT_C128 : QTT_C64, n, dir, s, nf, b.sq, b.sq));
   HIPCHK(set_ints_strided(out.bonds, 1, c.bs, nf, 1, s));
   HIPCHK(set_ints_strided(out.bonds + m, 1, c.bs, nf, 1, s));
   const void* Rcur = b.v;
@@ -1180,8 +1182,13 @@ DenseBufs carve_dense(Carver& cv, int m, int chi, size_t csz, int nf) {
 }
 
 // out: nf dense N x N fields (stride N^2 elements of out_dtype)
-int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream_t s) {
-  const int m = in.m, h = m / 2, nf = in.nf;
+// Decompression of sites off..m-1.  off = 0: the whole MPS (core 0 has left
+// bond 1).  off > 0: `boundary` is the row vector (1 x bond off, stride ch,
+// per-field stride bsf) of the first off sites contracted at fixed bits, so
+// the result is the 2^((m-off)/2) square block those bits select.
+int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream_t s, int off = 0,
+               const void* boundary = nullptr, ll bsf = 0) {
+  const int m = in.m, mp = m - off, h = mp / 2, nf = in.nf;
   const int real = in.dtype == QTT_C128 ? 1 : 0;
   Ctx c = make_ctx(s, real, nf, m, b.status);
   const ll ch = in.cap, sIn = in.fstride();
@@ -1190,15 +1197,16 @@ int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream
   auto core = [&](int k) { return inc + (size_t)k * ch * 2 * ch * c.csz; };
   HIPCHK(sanitize_bonds(in.bonds, b.bonds, m, (int)ch, b.status, nf, s));
   const int* bonds = b.bonds;
-  // left: P_1 = core 0 as [s][b] (row stride ch); P_{k+1}[(l,s)][b] = P_k[l][r] A_k[r][s][b]
-  const void* P = core(0);
-  ll pld = ch, sP = sIn;
+  // left: P_(k+1)[(l, s)][b] = P_k[l][r] A_(off+k)[r][s][b], rows 2^(k+1)
+  const void* P = off ? boundary : core(0);
+  ll pld = ch, sP = off ? bsf : sIn;
   int psel = 0;
-  for (int k = 1; k < h; ++k) {
+  for (int k = off ? 0 : 1; k < h; ++k) {
     const ll rows = 1ll << k;
+    const int g = off + k;
     void* Pn = b.P[psel];
-    int r = gemm(c, dx((int)rows), 1, (int)rows, dv(c, 2, bonds + k + 1), 2, 2 * rb[k + 1], dv(c, 1, bonds + k), 1,
-                 opd(P, pld, 0, 1, 0, 0, sP), opd(core(k), 2 * ch, 0, 1, ch, 0, sIn),
+    int r = gemm(c, dx((int)rows), 1, (int)rows, dv(c, 2, bonds + g + 1), 2, 2 * rb[g + 1], dv(c, 1, bonds + g), 1,
+                 opd(P, pld, 0, 1, 0, 0, sP), opd(core(g), 2 * ch, 0, 1, ch, 0, sIn),
                  opd(Pn, 2 * ch, 0, 1, ch, 0, b.sP));
     if (r) return r;
     P = Pn;
@@ -1206,11 +1214,11 @@ int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream
     sP = b.sP;
     psel ^= 1;
   }
-  // right: Q_{m-1}[r][s] = core m-1 [r][s][0]; Q_k[(r,s)][c] = A_k[(r,s)][b] Q_{k+1}[b][c]
+  // right: Q_(m-1)[r][s] = core m-1 [r][s][0]; Q_k[(r,s)][c] = A_k[(r,s)][b] Q_(k+1)[b][c]
   const void* Q = core(m - 1);
-  ll qrs = 2 * ch, qcs = ch, sQ = sIn;   // row / column strides of Q_{k+1}
+  ll qrs = 2 * ch, qcs = ch, sQ = sIn;   // row / column strides of Q_(k+1)
   int qsel = 0;
-  for (int k = m - 2; k >= h; --k) {
+  for (int k = m - 2; k >= off + h; --k) {
     const ll cols = 1ll << (m - k - 1);
     void* Qn = b.Q[qsel];
     int r = gemm(c, dv(c, 2, bonds + k), 2, 2 * rb[k], dx((int)cols), 1, (int)cols, dv(c, 1, bonds + k + 1), 1,
@@ -1224,16 +1232,63 @@ int dense_impl(const MpsB& in, void* out, int out_dtype, DenseBufs& b, hipStream
     qsel ^= 1;
   }
   // E[l][c] = P_h[l][r] Q_h[r][c]
-  const ll L = 1ll << h, Rn = 1ll << (m - h);
-  int r = gemm(c, dx((int)L), 1, (int)L, dx((int)Rn), 1, (int)Rn, dv(c, 1, bonds + h), 1,
+  const ll L = 1ll << h, Rn = 1ll << (mp - h);
+  int r = gemm(c, dx((int)L), 1, (int)L, dx((int)Rn), 1, (int)Rn, dv(c, 1, bonds + off + h), 1,
                opd(P, pld, 0, 1, 0, 0, sP), opd(Q, qrs, 0, qcs, 0, 0, sQ), opd(b.E, Rn, 0, 1, 0, 0, b.sE));
   if (r) return r;
-  const size_t osz = out_dtype == QTT_C128 ? 16 : 8;
-  (void)osz;
-  HIPCHK(quantics_permute(b.E, real ? QTT_C128 : QTT_C64, out, out_dtype, m / 2, 1, s, nf, b.sE, b.sE));
+  HIPCHK(quantics_permute(b.E, real ? QTT_C128 : QTT_C64, out, out_dtype, mp / 2, 1, s, nf, b.sE, b.sE));
   return QTT_OK;
 }
 
+// ------------------------------------------------------------ point evaluation
+// Every point's row vector is carried site by site: one contraction of all
+// rows with the core (both bit values), then the half each point's bit picks.
+struct EvalBufs {
+  int* status;
+  int* bonds;
+  void* L[2];
+  void* C;
+  int* pts;                  // two ints (row, col) for the block boundary
+  ll ldl, ldc;
+};
+
+EvalBufs carve_eval(Carver& cv, int m, int cap, int count, size_t csz) {
+  EvalBufs b;
+  b.ldl = cap;
+  b.ldc = 2ll * cap;
+  b.status = (int*)cv.take(256);
+  b.bonds = (int*)cv.take((size_t)(m + 1) * sizeof(int));
+  b.L[0] = cv.take((size_t)count * b.ldl * csz);
+  b.L[1] = cv.take((size_t)count * b.ldl * csz);
+  b.C = cv.take((size_t)count * b.ldc * csz);
+  b.pts = (int*)cv.take(2 * sizeof(int));
+  return b;
+}
+
+// Contract sites 0..nsite-1 at each point's bits; returns the buffer that
+// holds the row vectors (count x bond nsite, stride ldl).
+int eval_rows(const MpsB& in, const int* rows, const int* cols, int count, int nsite, EvalBufs& b, hipStream_t s,
+              void** result) {
+  const int m = in.m, n = m / 2;
+  const int real = in.dtype == QTT_C128 ? 1 : 0;
+  Ctx c = make_ctx(s, real, 1, m, b.status);
+  const ll ch = in.cap;
+  std::vector<int> rb = mps_bounds(m, ch);
+  auto core = [&](int k) { return (char*)in.cores + (size_t)k * ch * 2 * ch * c.csz; };
+  HIPCHK(sanitize_bonds(in.bonds, b.bonds, m, (int)ch, b.status, 1, s));
+  HIPCHK(unit_rows(b.L[0], b.ldl, count, (int)ch, real, s));
+  int cur = 0;
+  for (int k = 0; k < nsite; ++k) {
+    // C[p][(r', s)] = L[p][r] A_k[r][s][r']
+    int r = gemm(c, dx(count), 1, count, dv(c, 2, b.bonds + k + 1), 2, 2 * rb[k + 1], dv(c, 1, b.bonds + k), 1,
+                 opd(b.L[cur], b.ldl, 0, 1, 0), opd(core(k), 2 * ch, 0, 1, ch), opd(b.C, b.ldc, 0, 2, 1));
+    if (r) return r;
+    HIPCHK(select_bit(b.C, b.ldc, b.L[cur ^ 1], b.ldl, rows, cols, count, k, n, b.bonds + k + 1, (int)ch, real, s));
+    cur ^= 1;
+  }
+  *result = b.L[cur];
+  return QTT_OK;
+}
 
 // ------------------------------------------------------------ adjoint of the decompression
 // Forward: E = P_h Q_h with the left half-chain P_(k+1) = P_k A_k (k < h) and
@@ -1609,6 +1664,141 @@ int tt_intensity_loss(const void* field, const void* target, int dtype, int log2
   HIPCHK(intensity_loss(field, target, dtype == QTT_C128 ? 1 : 0, per, count, loss, grad, (char*)ws + 256,
                         (hipStream_t)stream));
   return QTT_OK;
+}
+
+// ---- separable encode, point evaluation, block decompression
+static int sep_cap(int chi_cap) {
+  int c = 1;
+  while ((c + 1) * (c + 1) <= chi_cap) ++c;
+  return c;
+}
+
+size_t tt_encode_separable_workspace_size(int log2_side, int chi_cap, int prec) {
+  if (log2_side < 2 || (log2_side & 1) || log2_side > 30 || chi_cap < 1 || chi_cap > 256) return 0;
+  const size_t csz = prec == QTT_PREC_FP64 ? 16 : 8;
+  const int c1 = sep_cap(chi_cap), n = log2_side;
+  Carver cv(nullptr);
+  cv.take(256);
+  for (int i = 0; i < 2; ++i) {
+    cv.take((size_t)n * c1 * 2 * c1 * csz);
+    cv.take((size_t)(n + 1) * sizeof(int));
+  }
+  carve_encode(cv, n, c1, csz, 1);
+  return cv.off;
+}
+
+int tt_encode_separable(const void* vec_a, const void* vec_b, int vec_dtype, int log2_side, qtt_mps* out, void* ws,
+                        size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if (!vec_a || !vec_b || !ws) return fail(QTT_ERR_ARG, "NULL argument");
+  if ((r = check_mps(out, "out"))) return r;
+  if (log2_side < 2 || (log2_side & 1) || log2_side > 30)
+    return fail(QTT_ERR_SHAPE, "log2_side %d must be even and in [2, 30]", log2_side);
+  if (out->n_sites != 2 * log2_side) return fail(QTT_ERR_SHAPE, "out has %d sites, need %d", out->n_sites, 2 * log2_side);
+  if (vec_dtype < QTT_C64 || vec_dtype > QTT_F64) return fail(QTT_ERR_DTYPE, "bad vector dtype %d", vec_dtype);
+  const int real = out->dtype == QTT_C128 ? 1 : 0;
+  const size_t csz = real ? 16 : 8;
+  const size_t need = tt_encode_separable_workspace_size(log2_side, out->chi_cap, real ? QTT_PREC_FP64 : QTT_PREC_FP32);
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  const int c1 = sep_cap(out->chi_cap), n = log2_side;
+  Carver cw(ws);
+  int* status = (int*)cw.take(256);
+  MpsB f[2];
+  for (int i = 0; i < 2; ++i) {
+    f[i].nf = 1; f[i].m = n; f[i].cap = c1; f[i].dtype = out->dtype;
+    f[i].cores = cw.take((size_t)n * c1 * 2 * c1 * csz);
+    f[i].bonds = (int*)cw.take((size_t)(n + 1) * sizeof(int));
+    f[i].norms = nullptr;
+  }
+  EncBufs eb = carve_encode(cw, n, c1, csz, 1);
+  eb.status = status;          // report eigensolver failures in the workspace head
+  qtt_opts o;
+  opts_defaults(nullptr, c1, o);
+  o.prec = real ? QTT_PREC_FP64 : QTT_PREC_FP32;
+  hipStream_t s = (hipStream_t)stream;
+  const void* vecs[2] = {vec_a, vec_b};
+  for (int i = 0; i < 2; ++i) {
+    r = encode_impl(vecs[i], vec_dtype, n / 2, o, f[i], eb, nullptr, s, 2);
+    if (r) return r;
+  }
+  HIPCHK(interleave(f[0].cores, f[0].bonds, c1, f[1].cores, f[1].bonds, c1, out->cores, out->bonds, out->chi_cap, n,
+                    real, status, s));
+  (void)eb;
+  return QTT_OK;
+}
+
+size_t tt_eval_points_workspace_size(int n_sites, int chi_cap, int count, int prec) {
+  if (n_sites < 2 || (n_sites & 1) || chi_cap < 1 || chi_cap > 256 || count < 1) return 0;
+  Carver cv(nullptr);
+  carve_eval(cv, n_sites, chi_cap, count, prec == QTT_PREC_FP64 ? 16 : 8);
+  return cv.off;
+}
+
+int tt_eval_points(const qtt_mps* in, const int32_t* rows, const int32_t* cols, int count, void* out, void* ws,
+                   size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if (!rows || !cols || !out || !ws) return fail(QTT_ERR_ARG, "NULL argument");
+  if (count < 1) return fail(QTT_ERR_ARG, "count %d < 1", count);
+  const int real = in->dtype == QTT_C128 ? 1 : 0;
+  const size_t csz = real ? 16 : 8;
+  Carver cv(nullptr);
+  carve_eval(cv, in->n_sites, in->chi_cap, count, csz);
+  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
+  Carver cw(ws);
+  EvalBufs b = carve_eval(cw, in->n_sites, in->chi_cap, count, csz);
+  void* res = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  r = eval_rows(view(in), rows, cols, count, in->n_sites, b, s, &res);
+  if (r) return r;
+  HIPCHK(gather_col0(res, b.ldl, out, count, real, s));
+  return QTT_OK;
+}
+
+size_t tt_to_dense_block_workspace_size(int n_sites, int chi_cap, int log2_block, int prec) {
+  if (n_sites < 2 || (n_sites & 1) || chi_cap < 1 || chi_cap > 256) return 0;
+  if (log2_block < 1 || 2 * log2_block > n_sites) return 0;
+  const size_t csz = prec == QTT_PREC_FP64 ? 16 : 8;
+  Carver cv(nullptr);
+  carve_eval(cv, n_sites, chi_cap, 1, csz);
+  carve_dense(cv, 2 * log2_block, chi_cap, csz, 1);
+  cv.take((size_t)(n_sites + 1) * sizeof(int));
+  return cv.off;
+}
+
+int tt_to_dense_block(const qtt_mps* in, int log2_block, int block_row, int block_col, void* out, int out_dtype,
+                      void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if (!out || !ws) return fail(QTT_ERR_ARG, "NULL argument");
+  if (out_dtype != QTT_C64 && out_dtype != QTT_C128) return fail(QTT_ERR_DTYPE, "out dtype must be C64 or C128");
+  const int n = in->n_sites / 2;
+  if (log2_block < 1 || log2_block > n) return fail(QTT_ERR_SHAPE, "log2_block %d outside [1, %d]", log2_block, n);
+  const long long nblk = 1ll << (n - log2_block);
+  if (block_row < 0 || block_col < 0 || block_row >= nblk || block_col >= nblk)
+    return fail(QTT_ERR_SHAPE, "block (%d, %d) outside the %lld x %lld grid of blocks", block_row, block_col, nblk, nblk);
+  const int real = in->dtype == QTT_C128 ? 1 : 0;
+  const size_t csz = real ? 16 : 8;
+  const size_t need = tt_to_dense_block_workspace_size(in->n_sites, in->chi_cap, log2_block,
+                                                       real ? QTT_PREC_FP64 : QTT_PREC_FP32);
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  Carver cw(ws);
+  EvalBufs eb = carve_eval(cw, in->n_sites, in->chi_cap, 1, csz);
+  DenseBufs db = carve_dense(cw, 2 * log2_block, in->chi_cap, csz, 1);
+  db.status = eb.status;
+  db.bonds = (int*)cw.take((size_t)(in->n_sites + 1) * sizeof(int));   // bonds of the whole MPS
+  hipStream_t s = (hipStream_t)stream;
+  const MpsB v = view(in);
+  if (log2_block == n) return dense_impl(v, out, out_dtype, db, s);
+  const int off = 2 * (n - log2_block);
+  HIPCHK(fill_point(eb.pts, eb.pts + 1, (int)((long long)block_row << log2_block), (int)((long long)block_col << log2_block), s));
+  void* bnd = nullptr;
+  r = eval_rows(v, eb.pts, eb.pts + 1, 1, off, eb, s, &bnd);
+  if (r) return r;
+  return dense_impl(v, out, out_dtype, db, s, off, bnd, 0);
 }
 
 int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void* B, int ldb, int conj_b, void* C,

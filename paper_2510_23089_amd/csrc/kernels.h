@@ -142,6 +142,18 @@ hipError_t block_norm_b(const void* p, int dtype, DimExpr rows, DimExpr cols, in
                         long long ld_r, long long ld_c, long long s_f, double* out, int nf, hipStream_t s);
 hipError_t set_ints_strided(int* dev, int per, long long stride, int nf, int val, hipStream_t s);
 hipError_t set_one_b(void* p, long long s_f, int dtype, int nf, hipStream_t s);
+// Separable fields: interleave two 1-D MPS of n_per_axis sites (capacities
+// ucap, vcap; device bonds ub, vb) into a 2 n_per_axis site MPS (capacity
+// ocap, bonds ob).  dtype 0 complex64, 1 complex128.
+hipError_t interleave(const void* U, const int* ub, int ucap, const void* V, const int* vb, int vcap, void* out,
+                      int* ob, int ocap, int n_per_axis, int dtype, int* status, hipStream_t s);
+// Point evaluation helpers: Lnext[p][r] = C[p][2 r + bit of point p at site];
+// the final value is column 0; unit_rows sets every row to e_0.
+hipError_t select_bit(const void* C, long long ldc, void* Lnext, long long ldl, const int* rows, const int* cols,
+                      int count, int site, int n, const int* rbond, int cap, int dtype, hipStream_t s);
+hipError_t gather_col0(const void* Lf, long long ldl, void* out, int count, int dtype, hipStream_t s);
+hipError_t unit_rows(void* L, long long ldl, int count, int cap, int dtype, hipStream_t s);
+hipError_t fill_point(int* rows, int* cols, int row, int col, hipStream_t s);
 // Scan a complex buffer for non-finite values and flag the status word.
 hipError_t check_finite(const void* p, int dtype, long long count, int* status, hipStream_t s);
 

@@ -51,7 +51,9 @@ __global__ void quantics_kernel(const void* src, int sdt, void* dst, int ddt, in
   for (long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x; o < total;
        o += (long long)gridDim.x * blockDim.x) {
     long long in;
-    if (dir == 0) {
+    if (dir == 2) {
+      in = o;                                  // flat copy (1-D vectors)
+    } else if (dir == 0) {
       uint32_t q = (uint32_t)o;
       uint32_t a = compact_even(q >> 1), b = compact_even(q);
       in = ((long long)a << n) | b;
@@ -361,6 +363,136 @@ __global__ void set_one_kernel(void* p, int dtype) {
 }
 hipError_t set_one(void* p, int dtype, hipStream_t s) {
   hipLaunchKernelGGL(set_one_kernel, dim3(1), dim3(1), 0, s, p, dtype);
+  return hipGetLastError();
+}
+
+// ---- separable fields: interleave two 1-D MPS (Sec. 3 quantics order)
+// Output site 2p (bit p of a) has bonds (ru_p rv_p) -> (ru_(p+1) rv_p) and
+// core U_p x identity; site 2p+1 (bit p of b) has (ru_(p+1) rv_p) ->
+// (ru_(p+1) rv_(p+1)) and core identity x V_p.  Bond pairs are flattened
+// as iu * rv + iv.  Products beyond the output capacity flag the status.
+template <typename T>
+__global__ void interleave_kernel(const T* U, const int* ub, int ucap, const T* V, const int* vb, int vcap, T* out,
+                                  int* ob, int ocap, int* status) {
+  const int j = blockIdx.y, p = j >> 1;
+  const bool is_a = (j & 1) == 0;
+  const int rul = ub[p], rur = ub[p + 1], rvl = vb[p], rvr = vb[p + 1];
+  const int L = is_a ? rul * rvl : rur * rvl;
+  const int R = is_a ? rur * rvl : rur * rvr;
+  if (L > ocap || R > ocap) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) set_status(status, -5);
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ob[j + 1] = R;
+    if (j == 0) ob[0] = 1;
+  }
+  const T* Up = U + (long long)p * ucap * 2 * ucap;
+  const T* Vp = V + (long long)p * vcap * 2 * vcap;
+  T* O = out + (long long)j * ocap * 2 * ocap;
+  const long long tot = (long long)L * 2 * R;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int l = (int)(e / (2 * R)), rem = (int)(e - (long long)l * 2 * R), s = rem / R, r = rem - s * R;
+    T val;
+    val.x = 0;
+    val.y = 0;
+    if (is_a) {
+      const int iu = l / rvl, iv = l - iu * rvl, ju = r / rvl, jv = r - ju * rvl;
+      if (iv == jv) val = Up[(long long)iu * 2 * ucap + s * ucap + ju];
+    } else {
+      const int iu = l / rvl, iv = l - iu * rvl, ju = r / rvr, jv = r - ju * rvr;
+      if (iu == ju) val = Vp[(long long)iv * 2 * vcap + s * vcap + jv];
+    }
+    O[(long long)l * 2 * ocap + s * ocap + r] = val;
+  }
+}
+hipError_t interleave(const void* U, const int* ub, int ucap, const void* V, const int* vb, int vcap, void* out,
+                      int* ob, int ocap, int n_per_axis, int dtype, int* status, hipStream_t s) {
+  dim3 g(256, 2 * n_per_axis);
+  if (dtype == 0)
+    hipLaunchKernelGGL(interleave_kernel<float2>, g, dim3(256), 0, s, (const float2*)U, ub, ucap, (const float2*)V,
+                       vb, vcap, (float2*)out, ob, ocap, status);
+  else
+    hipLaunchKernelGGL(interleave_kernel<double2>, g, dim3(256), 0, s, (const double2*)U, ub, ucap,
+                       (const double2*)V, vb, vcap, (double2*)out, ob, ocap, status);
+  return hipGetLastError();
+}
+
+// ---- point evaluation: after contracting site k for every point, keep the
+// half of C[p][(r', s)] selected by the point's bit at site k.
+// Site 2q is bit q (most significant first) of the row a, site 2q+1 of b.
+template <typename T>
+__global__ void select_bit_kernel(const T* C, long long ldc, T* Lnext, long long ldl, const int* rows,
+                                  const int* cols, int count, int site, int n, const int* rbond, int cap) {
+  const int p = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (p >= count) return;
+  const int q = site >> 1;
+  const int coord = (site & 1) ? cols[p] : rows[p];
+  const int bit = (coord >> (n - 1 - q)) & 1;
+  const int rr = min(rbond[0], cap);
+  for (int r = threadIdx.x & 63; r < rr; r += 64) Lnext[(long long)p * ldl + r] = C[(long long)p * ldc + 2 * r + bit];
+}
+hipError_t select_bit(const void* C, long long ldc, void* Lnext, long long ldl, const int* rows, const int* cols,
+                      int count, int site, int n, const int* rbond, int cap, int dtype, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  dim3 g((count + 3) / 4);
+  if (dtype == 0)
+    hipLaunchKernelGGL(select_bit_kernel<float2>, g, dim3(256), 0, s, (const float2*)C, ldc, (float2*)Lnext, ldl,
+                       rows, cols, count, site, n, rbond, cap);
+  else
+    hipLaunchKernelGGL(select_bit_kernel<double2>, g, dim3(256), 0, s, (const double2*)C, ldc, (double2*)Lnext, ldl,
+                       rows, cols, count, site, n, rbond, cap);
+  return hipGetLastError();
+}
+
+// Point p's value: column 0 of its final row vector.
+template <typename T>
+__global__ void gather_col0_kernel(const T* Lf, long long ldl, T* out, int count) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < count) out[p] = Lf[(long long)p * ldl];
+}
+hipError_t gather_col0(const void* Lf, long long ldl, void* out, int count, int dtype, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(gather_col0_kernel<float2>, dim3((count + 255) / 256), dim3(256), 0, s, (const float2*)Lf, ldl,
+                       (float2*)out, count);
+  else
+    hipLaunchKernelGGL(gather_col0_kernel<double2>, dim3((count + 255) / 256), dim3(256), 0, s, (const double2*)Lf,
+                       ldl, (double2*)out, count);
+  return hipGetLastError();
+}
+
+// Row vector e_0 (complex 1 at column 0, zeros to the capacity) per point.
+template <typename T>
+__global__ void unit_rows_kernel(T* L, long long ldl, int count, int cap) {
+  const long long tot = (long long)count * cap;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const long long p = e / cap;
+    const int r = (int)(e - p * cap);
+    T v;
+    v.x = r == 0 ? 1 : 0;
+    v.y = 0;
+    L[p * ldl + r] = v;
+  }
+}
+hipError_t unit_rows(void* L, long long ldl, int count, int cap, int dtype, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  long long tot = (long long)count * cap;
+  int blocks = (int)std::min<long long>((tot + 255) / 256, 8192);
+  if (dtype == 0)
+    hipLaunchKernelGGL(unit_rows_kernel<float2>, dim3(blocks), dim3(256), 0, s, (float2*)L, ldl, count, cap);
+  else
+    hipLaunchKernelGGL(unit_rows_kernel<double2>, dim3(blocks), dim3(256), 0, s, (double2*)L, ldl, count, cap);
+  return hipGetLastError();
+}
+
+// Write the bit pattern of a block's fixed high bits as point coordinates.
+__global__ void fill_point_kernel(int* rows, int* cols, int row, int col) {
+  rows[0] = row;
+  cols[0] = col;
+}
+hipError_t fill_point(int* rows, int* cols, int row, int col, hipStream_t s) {
+  hipLaunchKernelGGL(fill_point_kernel, dim3(1), dim3(1), 0, s, rows, cols, row, col);
   return hipGetLastError();
 }
 

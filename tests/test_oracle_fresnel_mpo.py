@@ -153,3 +153,18 @@ def test_axis_embedding_is_kronecker():
     uy = M.mpo_dense(wy)
     assert np.allclose(Q.from_quantics(ux @ v, n), u @ e0, atol=1e-12)
     assert np.allclose(Q.from_quantics(uy @ v, n), e0 @ u.T, atol=1e-12)
+
+
+@pytest.mark.parametrize("n_side,w0,z", [(4096, 300.0, 2e-3), (16384, 2000.0, 10e-3), (1024, 60.0, 8e-3)])
+def test_gaussian_beam_closed_form_1d(n_side, w0, z):
+    """1-D factor: the FFT propagation of exp(-(u - c)^2 / w0^2) against the
+    q^-1/2 closed form, and the 2-D closed form is the product of two."""
+    c = n_side / 2
+    u = np.arange(n_side) - c
+    g = np.exp(-(u * u) / (w0 * w0)).astype(np.complex128)
+    got = F.fresnel_1d(g, LAM, DX, z)
+    ref = F.gaussian_beam_exact_1d(n_side, w0, LAM, DX, z, c)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-9
+    if n_side <= 1024:
+        two = F.gaussian_beam_exact(n_side, w0, LAM, DX, z, c, c)
+        assert np.allclose(np.outer(ref, ref), two, rtol=0, atol=1e-13)
