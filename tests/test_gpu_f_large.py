@@ -46,7 +46,7 @@ def test_eval_points_and_blocks_vs_dense(prec):
     torch = need_gpu()
     api = _api()
     n = 5
-    e0 = synth.aperture_field(3, n=1 << n)
+    e0 = synth.random_field(3, 1 << n)         # nonzero everywhere: every block has a reference
     cores = T.tt_svd(Q.to_quantics(e0), 2 * n, 16, tau=1e-13)
     ref = Z.to_dense(cores, n)
     dt = torch.complex64 if prec == "fp32" else torch.complex128
@@ -76,11 +76,13 @@ def _exact_factor(vec, z):
 
 
 def test_large_separable_propagation_16384():
-    """16384^2 field (28 sites), chi 256, two distances as one batch."""
+    """16384^2 field (28 sites), chi 256, the shortest, a middle and the
+    longest of the eight log-spaced distances as one batch (the 10 mm MPO has
+    bond 88)."""
     torch = need_gpu()
     api = _api()
     n, chi = 14, 256
-    zs = (0.1e-3, 1e-3)
+    zs = (0.1e-3, 1e-3, 10e-3)
     ua, vb = synth.grating_beam_1d(1 << n)
     say("encode")
     psi = api.tt_encode_separable(torch.from_numpy(ua).to(torch.complex64).cuda(),
@@ -115,5 +117,6 @@ def test_large_separable_propagation_16384():
         e_win = rel(win, np.outer(ex_a[lo:lo + 4096], ex_b[lo:lo + 4096]))
         say("z=%.1e mm: sampled rel err %.3e, window rel err %.3e, max bond %d" %
             (z * 1e3, e_pts, e_win, max(int(x) for x in out.bonds[f].cpu())))
-        assert e_pts < 1e-3
-        assert e_win < 1e-3
+        # FP32 contractions, no truncation at these ranks (measured ~2e-6)
+        assert e_pts < 2e-5
+        assert e_win < 2e-5
