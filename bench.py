@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--copy-probe", type=int, default=0,
+                   help="after the run, copy this many MiB device to device (calibrates HBM byte counters)")
     p.add_argument("--grad-steps", type=int, default=3)
     return p.parse_args()
 
@@ -352,6 +354,14 @@ def main():
         },
         "wall_s": wall,
     }
+    if a.copy_probe > 0:
+        src = torch.ones(a.copy_probe << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_probe_mib"] = a.copy_probe
+        del src, dst
     if not a.no_batched:
         res["batched"] = batched_bench(dev)
     if not a.no_grad:
