@@ -54,6 +54,10 @@ ZS = (0.5e-3, 2e-3, 8e-3)
 N_LOG2 = 10
 CHI = 128
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
+# Memory traffic of the dominant kernel per launch, from two rocprofv3 counter
+# passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
+# copy); valid only while eig.hip is the source the counters were taken on.
+TRAFFIC = {"eig_sha256_prefix": "dcd29ed25c6c58e7", "bytes_per_launch": (25.54 + 6.58) * 1e6}
 
 
 def parse():
@@ -260,6 +264,17 @@ def grad_step_bench(steps, dev):
     }
 
 
+def _traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2510_23089_amd", "csrc", "eig.hip")
+    try:
+        with open(path, "rb") as fh:
+            h = hashlib.sha256(fh.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return TRAFFIC["bytes_per_launch"] if h == TRAFFIC["eig_sha256_prefix"] else None
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -346,7 +361,8 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": _traffic(),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "launches": launches.value,
             "avg_launch_ms": avg_launch_s * 1e3,
             "kernel_share_of_step": kms.value / (ms * a.steps),
