@@ -288,8 +288,9 @@ int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void
 
 /* Batched Hermitian eigen-decomposition with the keep rule of the truncation
  * steps (Sec. 4: squared singular values of a bond cut are the eigenvalues of
- * its Gram matrix).  G: device, batch x n x n complex128 row-major Hermitian
- * (overwritten).  Writes, per matrix b: kept[b] (device int) from the keep
+ * its Gram matrix).  G: device, batch x n x n complex128 row-major Hermitian;
+ * only the lower triangle (with the diagonal) is referenced; the upper
+ * triangle is overwritten.  Writes, per matrix b: kept[b] (device int) from the keep
  * rule with cap kcap / cutoff / tau, evals[b*kcap + i] (device double, the
  * kept eigenvalues in descending order, zero beyond kept[b]) and
  * evecs[b*n*kcap + p*kcap + i] (device complex128, eigenvector i).  n <= 512.

@@ -100,6 +100,8 @@ struct Ctx {
 DimExpr dv(const Ctx& c, int k, const int* p0 = nullptr, const int* p1 = nullptr) { return dx(k, p0, p1, c.bs); }
 
 // Hermitian Gram matrices (one per field) into ctx.G: G = op(A) . op(B).
+// Only the tiles touching the lower triangle are computed: the eigensolver
+// references the lower triangle alone.
 int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb, DimExpr K, int klo, ll kb) {
   int ks = ksplit_for(c.gld, kb, c.nf);
   GemmSpec g;
@@ -108,6 +110,7 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
   g.m_bound = nb; g.n_bound = nb; g.batch_bound = 1; g.nfield = c.nf;
   g.A = A; g.B = B;
   g.types = c.gram_t;
+  g.lower = 1;
   // the result is a plain n x n matrix: address it through the same (hi, lo)
   // split as the M and N indices
   const ll ld = c.gld, gs = ld * ld;

@@ -54,6 +54,7 @@ struct GemmArgs {
   FastDiv fm, fn, fk;     // low extents of the split M, N, K indices
   Operand A, B, C;        // A: (M, K); B: (K, N); C: (M, N)
   int accumulate;         // C += A.B instead of C = A.B
+  int lower;              // Hermitian result: tiles wholly above the diagonal are skipped
   int ksplit;             // >1: blockIdx.y selects a K chunk; C gets batch stride csplit
   long long csplit;       // complex-element stride between K-chunk partial results
   int tiles_n;            // tile-grid width used to decode blockIdx.x

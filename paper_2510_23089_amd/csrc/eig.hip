@@ -13,7 +13,9 @@
 //                the batch fits the chip; otherwise one workgroup per matrix
 //                streaming the trailing matrix from L2 once per step (the
 //                rank-2 update of step j fused with the product of step j+1).
-//                Reflectors are kept in the upper triangle.
+//                Only the lower triangle of G is referenced (the streaming
+//                form first completes the matrix from it); reflectors are
+//                kept in the upper triangle.
 //   2. eigvals   the top min(n, cap) eigenvalues, one wave per eigenvalue:
 //                64-way multisection on Sturm counts (division-free
 //                three-term recurrence with exponent rescaling), so a wave
@@ -69,10 +71,10 @@ struct EigWs {
   double *lu_dl, *lu_d, *lu_du, *lu_du2, *z;
   int* piv;
   int* clus;
-  // exchange area of the multi-workgroup reduction: reflector and partial
-  // products of two consecutive steps, tau, and the two step counters
-  double2 *xv, *xp, *xt;
-  int* xflag;
+  // exchange area of the multi-workgroup reduction: the next column and the
+  // partial products of two consecutive steps, as tagged 64-bit words
+  // (four per complex value)
+  double2 *xv, *xp;
 };
 
 __host__ __device__ inline size_t eig_ws_per_matrix(int nb, int kc) {
@@ -82,7 +84,7 @@ __host__ __device__ inline size_t eig_ws_per_matrix(int nb, int kc) {
   s += 5 * (size_t)nb * kc * sizeof(double);     // LU (4) + z
   s += (size_t)nb * kc * sizeof(int);            // pivots
   s += ((size_t)kc * sizeof(int) + 15) / 16 * 16;  // cluster starts
-  s += 4 * (size_t)nb * sizeof(double2) + 2 * sizeof(double2) + 4 * sizeof(int);   // exchange area
+  s += 8 * (size_t)nb * sizeof(double2);        // exchange area
   return (s + 255) / 256 * 256;
 }
 
@@ -102,10 +104,8 @@ __host__ __device__ inline EigWs eig_ws_carve(void* base, int b, int nb, int kc)
   w.z = (double*)p; p += (size_t)nb * kc * sizeof(double);
   w.piv = (int*)p; p += (size_t)nb * kc * sizeof(int);
   w.clus = (int*)p; p += ((size_t)kc * sizeof(int) + 15) / 16 * 16;
-  w.xv = (double2*)p; p += 2 * (size_t)nb * sizeof(double2);
-  w.xp = (double2*)p; p += 2 * (size_t)nb * sizeof(double2);
-  w.xt = (double2*)p; p += 2 * sizeof(double2);
-  w.xflag = (int*)p;
+  w.xv = (double2*)p; p += 4 * (size_t)nb * sizeof(double2);
+  w.xp = (double2*)p; p += 4 * (size_t)nb * sizeof(double2);
   return w;
 }
 
@@ -131,6 +131,45 @@ __device__ double2 block_sum2(double2 v, double* red) {
 #pragma unroll
   for (int i = 0; i < NT / 64; ++i) { s.x += red[2 * i]; s.y += red[2 * i + 1]; }
   return s;
+}
+
+// Cross-lane sums through DPP moves (a few cycles each) instead of LDS
+// permutes.  row16_sum: every lane gets the sum over its 16-lane row (lanes
+// of one row may differ in the last bit: the association depends on the
+// quad).  wave_sum_u: the wave's sum from rows 0..3 in a fixed order,
+// identical in every lane.  seg_sum<TPC>: sum over aligned segments of TPC
+// lanes (32 or 64), valid in the segment's last lane.
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xf, false);
+  return __hiloint2double(h2, l2);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_d<0xB1, 0xf>(v);      // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E, 0xf>(v);      // quad_perm [2,3,0,1]
+  v += dpp_d<0x124, 0xf>(v);     // row_ror:4
+  v += dpp_d<0x128, 0xf>(v);     // row_ror:8
+  return v;
+}
+__device__ __forceinline__ double lane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ double wave_sum_u(double v) {
+  v = row16_sum(v);
+  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
+}
+template <int TPC>
+__device__ __forceinline__ double seg_sum(double v) {
+  static_assert(TPC == 32 || TPC == 64, "segments of 32 or 64 lanes");
+  if constexpr (TPC == 64) {
+    return wave_sum_u(v);
+  } else {
+    v = row16_sum(v);
+    return v + dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  }
 }
 
 __device__ void householder(double2 alpha, double xnorm2, double2& tau, double2& scale, double& beta) {
@@ -364,175 +403,246 @@ __global__ __launch_bounds__(TS_NT) void tridiag_kernel(double2* Gall, int ld, l
 }
 
 // (c) 128 < n <= 512 when the batch fits the chip: the matrix is split by
-//     column blocks over G workgroups (CB columns each, 128 KB of LDS), so
-//     the whole reduction runs out of LDS.  Every workgroup also keeps a copy
-//     of the next column to be reduced.  Step k: every workgroup forms the
-//     reflector of column k from its copy (the same arithmetic everywhere),
-//     forms its part of p = tau A v from its own columns (A Hermitian:
-//     (A v)_c uses column c) and publishes it -- the owner of column k + 1
-//     publishes that column as well; after one exchange every workgroup holds
-//     p and column k + 1, forms w, and updates its own columns and its copy of
-//     column k + 1.  One device-scope exchange per step; exchange buffers
-//     alternate between steps.  Every wait is bounded: a workgroup that
-//     spins too long flags QTT_ERR_NOCONVERGE and exits, so the grid always
+//     column blocks over G workgroups (CB columns each, up to 128 KB of
+//     LDS), so the whole reduction runs out of LDS.  Every workgroup also
+//     keeps a copy of the next column to be reduced (one row per thread, in
+//     registers).  Step k: every workgroup forms the reflector of column k
+//     from its copy (the same arithmetic everywhere, in the waves that hold
+//     its rows), forms its part of p = tau A v from its own columns (A
+//     Hermitian: (A v)_c uses column c) and publishes it -- the owner of
+//     column k + 1 publishes that column as well; every workgroup then
+//     gathers p and column k + 1, forms w, and updates its own columns and
+//     its copy of column k + 1.
+//     Exchange: every published complex value travels as four 64-bit words,
+//     each a 32-bit half of the payload under the 32-bit step tag k + 1,
+//     written and read with relaxed device-scope atomics; a reader takes a
+//     value once all four words carry the tag, so no flag, fence or
+//     store-completion wait sits on the critical path.  One lane per wave
+//     polls until its own value has arrived before the whole wave reads
+//     (all lanes polling at once floods the few memory channels the area
+//     maps to).  Exchange buffers alternate between steps (a writer cannot
+//     get two steps ahead of a reader: step k + 1 needs every workgroup's
+//     step-k + 1 products, which each publishes only after it has read step
+//     k) and are cleared before the launch.  Three barriers per step; the
+//     cross-lane sums use DPP.  Every wait is bounded: a workgroup that
+//     polls too long flags QTT_ERR_NOCONVERGE and exits, so the grid always
 //     drains.  The launch keeps G * batch at or below the number of compute
 //     units, so all workgroups are resident together.
 constexpr int MW_NT = 1024;
 constexpr int MW_LDS = 8192;                  // complex doubles of owned columns (128 KB)
 constexpr long long MW_SPIN = 1ll << 20;
+static_assert(MW_NT >= 2 * EIG_NMAX, "one thread per row for p and one for the column");
 
-__device__ bool mw_wait(int* flag, int target, int* status) {
-  long long it = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-    if (++it > MW_SPIN) {
-      set_status(status, ST_NOCONVERGE);
-      return false;
+typedef unsigned long long u64;
+__device__ __forceinline__ void tag_store(u64* q, double2 v, unsigned tag) {
+  const u64 t = (u64)tag << 32;
+  const u64 bx = (u64)__double_as_longlong(v.x), by = (u64)__double_as_longlong(v.y);
+  __hip_atomic_store(q + 0, t | (bx & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, t | (bx >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 2, t | (by & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 3, t | (by >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ bool tag_ready(const u64* q, unsigned tag) {
+  u64* w = (u64*)q;
+  const u64 w0 = __hip_atomic_load(w + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const u64 w3 = __hip_atomic_load(w + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (unsigned)(w0 >> 32) == tag && (unsigned)(w3 >> 32) == tag;
+}
+// Poll four words until all carry `tag`; false after the spin limit.
+__device__ __forceinline__ bool tag_load(const u64* q, unsigned tag, double2& v) {
+  u64* w = (u64*)q;
+  for (long long it = 0;; ++it) {
+    const u64 w0 = __hip_atomic_load(w + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 w1 = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 w2 = __hip_atomic_load(w + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 w3 = __hip_atomic_load(w + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((unsigned)(w0 >> 32) == tag && (unsigned)(w1 >> 32) == tag && (unsigned)(w2 >> 32) == tag &&
+        (unsigned)(w3 >> 32) == tag) {
+      v.x = __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+      v.y = __longlong_as_double((long long)((w3 << 32) | (w2 & 0xffffffffull)));
+      return true;
     }
+    if (it >= MW_SPIN) return false;
     __builtin_amdgcn_s_sleep(1);
   }
-  return true;
 }
 
-// Exchange-area accesses: relaxed device-scope atomics on 64-bit halves, so
-// the data travels through the device-coherent level without whole-cache
-// write-back / invalidate fences; ordering comes from waiting for the
-// stores' completion before the flag is raised, and from the loads being
-// issued only after the flag was seen.
-__device__ __forceinline__ void xstore(double2* p, double2 v) {
-  unsigned long long* q = (unsigned long long*)p;
-  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double2 xload(const double2* p) {
-  unsigned long long* q = (unsigned long long*)p;
-  double2 v;
-  v.x = __longlong_as_double((long long)__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  v.y = __longlong_as_double((long long)__hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  return v;
-}
-__device__ __forceinline__ void stores_done() { __builtin_amdgcn_s_waitcnt(0); }
-
+// Clear the exchange words (tags 0) of every matrix in the batch.
 __global__ void mw_reset_kernel(void* wsbase, int nb, int kc) {
   EigWs W = eig_ws_carve(wsbase, blockIdx.x, nb, kc);
-  if (threadIdx.x < 4) W.xflag[threadIdx.x] = 0;
+  u64* x = (u64*)W.xv;
+  const long long words = 16ll * nb;          // xv and xp: 2 buffers x nb values x 4 words each
+  for (long long i = threadIdx.x; i < words; i += blockDim.x) x[i] = 0;
 }
 
 template <int CB>
 __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
                                                             void* wsbase, int nb, int kc, int* status, int* nlog) {
   constexpr int TPC = MW_NT / CB;             // threads per owned column
-  const int g = blockIdx.x, G = gridDim.x, b = blockIdx.y;
+  constexpr int NW = MW_NT / 64;
+  const int g = blockIdx.x, b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
   double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 Ac[MW_LDS];              // owned columns, Ac[cl * n + r]
-  __shared__ double2 sv[EIG_NMAX], sp[EIG_NMAX], scol[EIG_NMAX];
-  __shared__ double red[2 * MW_NT / 64];
-  __shared__ double2 s_tau, s_scale;
-  __shared__ int s_ok;
-  const int tid = threadIdx.x;
+  __shared__ double2 sv[EIG_NMAX], sp[EIG_NMAX], sx[EIG_NMAX];
+  __shared__ double rnorm[NW];
+  __shared__ double2 rdot[NW];
+  __shared__ double2 s_alpha, s_tau;
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int c0 = g * CB;
   const int cn = max(0, min(CB, n - c0));
-  if (nlog && g == 0 && tid == 0) nlog[b] = n;
-  for (int e = tid; e < n * CB; e += MW_NT) {
-    const int r = e / CB, cl = e - r * CB;
-    if (cl < cn) Ac[cl * n + r] = A[(long long)r * ld + c0 + cl];
-  }
-  // every workgroup keeps its own copy of the next column to be reduced
-  for (int r = tid; r < n; r += MW_NT) scol[r] = A[(long long)r * ld];
-  __syncthreads();
   const int mc = tid / TPC, lt = tid - (tid / TPC) * TPC;
+  if (nlog && g == 0 && tid == 0) nlog[b] = n;
+  if (tid == 0) s_bad = 0;
+  // owned columns from the lower triangle only: workgroup 0 writes the
+  // reflectors into the upper triangle while others may still be loading
+  for (int e = tid; e < n * CB; e += MW_NT) {
+    const int r = e / CB, cl = e - r * CB, c = c0 + cl;
+    if (cl < cn) {
+      if (r >= c) {
+        Ac[cl * n + r] = A[(long long)r * ld + c];
+      } else {
+        const double2 u = A[(long long)c * ld + r];
+        Ac[cl * n + r] = make_double2(u.x, -u.y);
+      }
+    }
+  }
+  // thread r keeps row r of the column being reduced
+  double2 cr = make_double2(0.0, 0.0);
+  if (tid < n) cr = A[(long long)tid * ld];
+  {
+    const double loc = wave_sum_u(tid >= 2 && tid < n ? cr.x * cr.x + cr.y * cr.y : 0.0);
+    if (lane == 0) rnorm[wv] = loc;
+    if (tid == 1) s_alpha = cr;
+  }
+  __syncthreads();
   for (int k = 0; k < n - 1; ++k) {
     const int k1 = k + 1;
     const int buf = k & 1;
-    double2* xc = W.xv + (long long)buf * nb;
-    double2* xp = W.xp + (long long)buf * nb;
-    // ---- A: reflector of column k, formed redundantly (and identically) by every workgroup
-    double loc = 0.0;
-    for (int r = k1 + 1 + tid; r < n; r += MW_NT) {
-      double2 x = scol[r];
-      loc += x.x * x.x + x.y * x.y;
-    }
-    const double xnorm2 = block_sum<MW_NT>(loc, red);
-    if (tid == 0) {
-      double2 tau, scale;
-      double beta;
-      householder(scol[k1], xnorm2, tau, scale, beta);
-      if (g == 0) {
-        W.d[k] = scol[k].x;
-        W.e[k] = beta;
-        W.e2[k] = beta * beta;
-        W.tau[k] = tau;
-      }
-      s_tau = tau;
-      s_scale = scale;
-    }
-    __syncthreads();
-    const double2 tau = s_tau, scale = s_scale;
-    for (int r = k1 + tid; r < n; r += MW_NT) {
-      const double2 v = r == k1 ? make_double2(1.0, 0.0) : cmul(scol[r], scale);
-      sv[r] = v;
-      if (g == 0 && r > k1) A[(long long)k * ld + r] = v;   // reflector kept for the back-transformation
-    }
-    __syncthreads();
-    // ---- B: p_c = tau sum_r conj(A[r][c]) v_r for the owned columns c > k;
-    //         the owner of column k + 1 also publishes that column
-    {
-      const int c = c0 + mc;
-      const bool act = mc < cn && c > k;
-      double2 acc = make_double2(0.0, 0.0);
-      if (act)
-        for (int r = k1 + lt; r < n; r += TPC) acc = cadd(acc, cmulc(Ac[mc * n + r], sv[r]));
+    u64* xc = (u64*)W.xv + (size_t)buf * nb * 4;
+    u64* xp = (u64*)W.xp + (size_t)buf * nb * 4;
+    // ---- A: reflector of column k, formed (identically) by the waves that
+    //         hold rows k + 1 .. n - 1; the others take tau after the barrier
+    double2 scale = make_double2(0.0, 0.0);
+    if (wv * 64 + 63 >= k1 && wv * 64 < n) {
+      double xnorm2 = 0.0;
 #pragma unroll
-      for (int o = 1; o < TPC; o <<= 1) {
-        acc.x += __shfl_xor(acc.x, o);
-        acc.y += __shfl_xor(acc.y, o);
-      }
-      if (act && lt == 0) xstore(xp + c, cmul(tau, acc));
-    }
-    if (k1 >= c0 && k1 < c0 + cn)
-      for (int r = k1 + tid; r < n; r += MW_NT) xstore(xc + r, Ac[(k1 - c0) * n + r]);
-    stores_done();
-    __syncthreads();
-    if (tid == 0) __hip_atomic_fetch_add(W.xflag + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // ---- C: w = p - (tau/2)(p^H v) v; rank-2 update of the owned columns
-    //         and of the copy of column k + 1
-    if (tid == 0) s_ok = mw_wait(W.xflag + 1, G * (k + 1), status);
-    __syncthreads();
-    if (!s_ok) return;
-    for (int r = k1 + tid; r < n; r += MW_NT) {
-      sp[r] = xload(xp + r);
-      scol[r] = xload(xc + r);
-    }
-    __syncthreads();
-    double2 dl = make_double2(0.0, 0.0);
-    for (int r = k1 + tid; r < n; r += MW_NT) dl = cadd(dl, cmulc(sp[r], sv[r]));
-    const double2 dot = block_sum2<MW_NT>(dl, red);
-    const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
-    for (int r = k1 + tid; r < n; r += MW_NT) sp[r] = cadd(sp[r], cmul(alpha2, sv[r]));
-    __syncthreads();
-    {
-      const int c = c0 + mc;
-      if (mc < cn && c > k) {
-        const double2 wc = make_double2(sp[c].x, -sp[c].y), vc = make_double2(sv[c].x, -sv[c].y);
-        for (int r = k1 + lt; r < n; r += TPC) {
-          double2 a = Ac[mc * n + r];
-          a = csub(a, cmul(sv[r], wc));
-          a = csub(a, cmul(sp[r], vc));
-          Ac[mc * n + r] = a;
+      for (int i = 0; i < NW; ++i) xnorm2 += rnorm[i];
+      double2 tau;
+      double beta;
+      householder(s_alpha, xnorm2, tau, scale, beta);
+      if (tid == k1) {
+        s_tau = tau;
+        if (g == 0) {
+          W.e[k] = beta;
+          W.e2[k] = beta * beta;
+          W.tau[k] = tau;
         }
       }
-      const double2 wk = make_double2(sp[k1].x, -sp[k1].y), vk = make_double2(sv[k1].x, -sv[k1].y);
-      for (int r = k1 + tid; r < n; r += MW_NT) {
-        double2 a = scol[r];
-        a = csub(a, cmul(sv[r], wk));
-        a = csub(a, cmul(sp[r], vk));
-        scol[r] = a;
-      }
+    }
+    if (g == 0 && tid == k) W.d[k] = cr.x;
+    if (tid >= k1 && tid < n) {
+      const double2 v = tid == k1 ? make_double2(1.0, 0.0) : cmul(cr, scale);
+      sv[tid] = v;
+      if (g == 0 && tid > k1) A[(long long)k * ld + tid] = v;   // reflector kept for the back-transformation
     }
     __syncthreads();
+    const double2 tau = s_tau;
+    // ---- B: p_c = tau sum_r conj(A[r][c]) v_r for the owned columns c > k;
+    //         the owner of column k + 1 also publishes that column.  Thread
+    //         (mc, lt) always handles the rows r = lt (mod TPC) of column mc.
+    const int c = c0 + mc;
+    const bool act = mc < cn && c > k;
+    const int rbeg = k1 + ((lt - k1) & (TPC - 1));
+    {
+      double2 acc = make_double2(0.0, 0.0);
+      if (act)
+        for (int r = rbeg; r < n; r += TPC) acc = cadd(acc, cmulc(Ac[mc * n + r], sv[r]));
+      acc.x = seg_sum<TPC>(acc.x);
+      acc.y = seg_sum<TPC>(acc.y);
+      if (act && lt == TPC - 1) tag_store(xp + (size_t)c * 4, cmul(tau, acc), (unsigned)k1);
+    }
+    if (k1 >= c0 && k1 < c0 + cn) {
+      const int r = k1 + tid;
+      if (r < n) tag_store(xc + (size_t)r * 4, Ac[(k1 - c0) * n + r], (unsigned)k1);
+    }
+    // ---- C: gather p (thread r) and column k + 1 (thread EIG_NMAX + r);
+    //         partial sums of p^H v on the way
+    {
+      const u64* q = nullptr;
+      if (tid < EIG_NMAX) {
+        if (tid >= k1 && tid < n) q = xp + (size_t)tid * 4;
+      } else {
+        const int r = tid - EIG_NMAX;
+        if (r >= k1 && r < n) q = xc + (size_t)r * 4;
+      }
+      const unsigned long long need = __ballot(q != nullptr);
+      if (need) {
+        const int leader = __ffsll((long long)need) - 1;
+        for (long long it = 0;; ++it) {
+          int got = 0;
+          if (lane == leader) got = tag_ready(q, (unsigned)k1);
+          if (__shfl(got, leader) || it >= MW_SPIN) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      double2 dl = make_double2(0.0, 0.0);
+      if (q) {
+        double2 x = make_double2(0.0, 0.0);
+        if (!tag_load(q, (unsigned)k1, x)) {
+          set_status(status, ST_NOCONVERGE);
+          s_bad = 1;
+        }
+        if (tid < EIG_NMAX) {
+          sp[tid] = x;
+          dl = cmulc(x, sv[tid]);
+        } else {
+          sx[tid - EIG_NMAX] = x;
+        }
+      }
+      dl.x = wave_sum_u(dl.x);
+      dl.y = wave_sum_u(dl.y);
+      if (lane == 0) rdot[wv] = dl;
+    }
+    __syncthreads();
+    if (s_bad) return;
+    double2 dot = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < NW; ++i) dot = cadd(dot, rdot[i]);
+    // w = p + alpha2 v,  alpha2 = -(tau/2)(p^H v)
+    const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
+    if (act) {
+      const double2 wcc = cadd(sp[c], cmul(alpha2, sv[c]));
+      const double2 wc = make_double2(wcc.x, -wcc.y), vc = make_double2(sv[c].x, -sv[c].y);
+      for (int r = rbeg; r < n; r += TPC) {
+        const double2 vr = sv[r];
+        const double2 wr = cadd(sp[r], cmul(alpha2, vr));
+        double2 a = Ac[mc * n + r];
+        a = csub(a, cmul(vr, wc));
+        a = csub(a, cmul(wr, vc));
+        Ac[mc * n + r] = a;
+      }
+    }
+    double loc = 0.0;
+    if (tid >= k1 && tid < n) {
+      const double2 wkk = cadd(sp[k1], cmul(alpha2, sv[k1]));
+      const double2 wk = make_double2(wkk.x, -wkk.y), vk = make_double2(sv[k1].x, -sv[k1].y);
+      const double2 vr = sv[tid];
+      const double2 wr = cadd(sp[tid], cmul(alpha2, vr));
+      double2 a = sx[tid];
+      a = csub(a, cmul(vr, wk));
+      a = csub(a, cmul(wr, vk));
+      cr = a;
+      if (tid >= k1 + 2) loc = a.x * a.x + a.y * a.y;
+      if (tid == k1 + 1) s_alpha = a;
+    }
+    loc = wave_sum_u(loc);
+    if (lane == 0) rnorm[wv] = loc;
+    __syncthreads();
   }
-  if (n >= 1 && g == 0 && tid == 0) W.d[n - 1] = scol[n - 1].x;
+  if (n >= 1 && g == 0 && tid == n - 1) W.d[n - 1] = cr.x;
 }
 
 // ------------------------------------------------------------ 2. eigenvalues
@@ -965,7 +1075,13 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   const int cb = nb <= 256 ? 32 : 16;
   const int groups = (nb + cb - 1) / cb;
   const bool mwg = nb > TL_NMAX && (long long)groups * sp.batch <= compute_units();
-  if (mwg) hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(64), 0, s, sp.ws, nb, kc);
+  if (mwg) hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc);
+  if (nb > TL_NMAX && !mwg) {
+    // the streaming reduction updates the full matrix in place: complete it
+    // from the lower triangle first
+    hipError_t fe = hermitian_fill(sp.G, sp.ld, sp.gstride, sp.n, nb, sp.batch, s);
+    if (fe != hipSuccess) return fe;
+  }
   if (prof) hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
   int* nl = prof ? g_prof.nlog + g_prof.slot : (int*)nullptr;
   if (nb <= TL_NMAX) {

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   const int tm = blockIdx.x / g.tiles_n, tn = blockIdx.x % g.tiles_n;
   const int m0 = tm * BM, n0 = tn * BN;
   if (m0 >= M || n0 >= N) return;
+  if (g.lower && m0 + BM <= n0) return;
   int kbeg = 0, kend = K;
   if (g.ksplit > 1) {
     int chunk = (K + g.ksplit - 1) / g.ksplit;
@@ -423,6 +424,7 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   g.fm = make_fastdiv(sp.mlo); g.fn = make_fastdiv(sp.nlo); g.fk = make_fastdiv(sp.klo);
   g.A = sp.A; g.B = sp.B; g.C = sp.C;
   g.accumulate = sp.accumulate;
+  g.lower = sp.lower;
   g.ksplit = sp.ksplit < 1 ? 1 : sp.ksplit;
   g.csplit = sp.csplit;
   if (sp.m_bound < 1 || sp.n_bound < 1 || sp.batch_bound < 1 || sp.nfield < 1) return hipSuccess;
@@ -488,6 +490,7 @@ hipError_t autotune_run(void* ws, size_t ws_bytes, hipStream_t s, int* n_tuned) 
     g.B = Operand{base + a, bkm ? 1 : k.nb, 0, bkm ? TUNE_K : 1, 0, (long long)TUNE_K * k.nb, 0, 0};
     g.C = Operand{base + a + b, k.nb, 0, 1, 0, (long long)k.mb * k.nb, 0, 0};
     g.accumulate = 0;
+    g.lower = 0;
     g.ksplit = 1;
     g.csplit = 0;
     g.Mmax = k.mb; g.Nmax = k.nb; g.Kmax = TUNE_K; g.Bmax = 1;

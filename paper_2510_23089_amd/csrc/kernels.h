@@ -20,6 +20,7 @@ struct GemmSpec {
   int nfield = 1;               // outer batch: fields (Operand.sb strides)
   Operand A, B, C;
   int accumulate = 0;
+  int lower = 0;                // Hermitian result: only tiles touching the lower triangle
   int ksplit = 1;
   long long csplit = 0;
   int types = GEMM_F32;
@@ -130,6 +131,9 @@ hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status,
 hipError_t block_copy_b(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst, long long d_rs,
                         long long d_cs, long long d_f, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
                         int dtype, int nf, hipStream_t s, int conj = 0);
+// Complete Hermitian matrices from their lower triangle: G[i][j] =
+// conj(G[j][i]) for i < j < n (n a device value per matrix, ld, stride gs).
+hipError_t hermitian_fill(double* G, int ld, long long gs, DimExpr n, int n_bound, int nf, hipStream_t s);
 // Zero a buffer (bytes a multiple of 16) with a plain kernel.
 hipError_t zero_fill(void* p, size_t bytes, hipStream_t s);
 // Phase-retrieval loss per field, L_f = sum (|E|^2 - I)^2, and its gradient

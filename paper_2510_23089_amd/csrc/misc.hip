@@ -222,6 +222,23 @@ hipError_t block_copy_b(const void* src, long long s_rs, long long s_cs, long lo
   return hipGetLastError();
 }
 
+__global__ void hermitian_fill_kernel(double2* G, int ld, long long gs, DimExpr nexp, int nb) {
+  const int f = blockIdx.y;
+  const int n = min(dim_eval(nexp, f), nb);
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  double2* A = G + f * gs;
+  for (int j = i + 1 + threadIdx.x; j < n; j += blockDim.x) {
+    double2 v = A[(long long)j * ld + i];
+    A[(long long)i * ld + j] = make_double2(v.x, -v.y);
+  }
+}
+hipError_t hermitian_fill(double* G, int ld, long long gs, DimExpr n, int n_bound, int nf, hipStream_t s) {
+  if (n_bound < 2 || nf < 1) return hipSuccess;
+  hipLaunchKernelGGL(hermitian_fill_kernel, dim3(n_bound, nf), dim3(256), 0, s, (double2*)G, ld, gs, n, n_bound);
+  return hipGetLastError();
+}
+
 // Zero `bytes` bytes (a multiple of 16) with vector stores; a plain kernel,
 // so it is safe inside captured graphs.
 __global__ void zero_fill_kernel(uint4* p, long long n16) {
