@@ -70,11 +70,13 @@ struct Carver {
   }
 };
 
-constexpr size_t PART_BYTES = 32ull << 20;   // Gram K-split partials (all fields)
+constexpr size_t PART_BYTES = 96ull << 20;   // Gram K-split partials (all fields)
 
 int ksplit_for(int nb, ll kb, int nf) {
-  int tiles = ((nb + 63) / 64) * ((nb + 63) / 64) * std::max(nf, 1);
-  ll want = std::max<ll>(1, 256 / std::max(tiles, 1));
+  // lower-triangle tiles only; aim at about two workgroups per compute unit
+  const int t = (nb + 63) / 64;
+  int tiles = t * (t + 1) / 2 * std::max(nf, 1);
+  ll want = std::max<ll>(1, 512 / std::max(tiles, 1));
   ll bykb = std::max<ll>(1, kb / 256);
   ll bymem = std::max<ll>(1, (ll)(PART_BYTES / (16ull * (size_t)nb * nb * std::max(nf, 1))));
   return (int)std::min<ll>({want, bykb, bymem, 256});
@@ -119,7 +121,7 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
     g.ksplit = ks;
     g.csplit = gs;
     HIPCHK(gemm_launch(g, c.s));
-    HIPCHK(ksplit_reduce(c.part, gs, ks, c.G, c.gld, n, n, nb, nb, (ll)ks * gs, gs, dx(1), c.nf, c.s));
+    HIPCHK(ksplit_reduce(c.part, gs, ks, c.G, c.gld, n, n, nb, nb, (ll)ks * gs, gs, c.nf, 1, c.s));
   } else {
     g.C = opd(c.G, nlo * ld, ld, nlo, 1, 0, gs);
     HIPCHK(gemm_launch(g, c.s));

@@ -303,14 +303,16 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   }
 }
 
-// Sum of K-chunk partial results: out[i][j] = sum_c part[c][i][j], i, j < n.
+// Sum of K-chunk partial results: out[i][j] = sum_c part[c][i][j], i, j < n
+// (j <= i only when `lower`).
 __global__ void ksplit_reduce_kernel(const double2* __restrict__ part, long long cstride, int nsplit,
                                      double2* __restrict__ out, int ld, DimExpr nrows, DimExpr ncols,
-                                     long long bstride_part, long long bstride_out, DimExpr batch) {
+                                     long long bstride_part, long long bstride_out, int lower) {
   const int b = blockIdx.z;
-  const int nr = min(dim_eval(nrows, b), (int)gridDim.y), nc = min(dim_eval(ncols, b), ld);
+  const int nr = min(dim_eval(nrows, b), (int)gridDim.y);
   const int i = blockIdx.y;
   if (i >= nr) return;
+  const int nc = min(min(dim_eval(ncols, b), ld), lower ? i + 1 : ld);
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nc; j += gridDim.x * blockDim.x) {
     double2 s = make_double2(0.0, 0.0);
     const double2* p = part + b * bstride_part + (long long)i * ld + j;
@@ -551,13 +553,13 @@ void autotune_clear() {
 
 hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,
                          DimExpr nrows, DimExpr ncols, int rows_bound, int cols_bound,
-                         long long bstride_part, long long bstride_out, DimExpr batch, int batch_bound,
+                         long long bstride_part, long long bstride_out, int batch_bound, int lower,
                          hipStream_t s) {
   int bx = (cols_bound + 255) / 256;
   if (bx < 1 || rows_bound < 1 || batch_bound < 1) return hipSuccess;
   hipLaunchKernelGGL(ksplit_reduce_kernel, dim3(bx, rows_bound, batch_bound), dim3(256), 0, s,
                      (const double2*)part, cstride, nsplit, (double2*)out, ld, nrows, ncols,
-                     bstride_part, bstride_out, batch);
+                     bstride_part, bstride_out, lower);
   return hipGetLastError();
 }
 

@@ -37,9 +37,10 @@ hipError_t autotune_run(void* ws, size_t ws_bytes, hipStream_t s, int* n_tuned);
 int autotune_export(int* out, int max_entries);
 int autotune_import(const int* entries, int n);
 void autotune_clear();
+// Sum K-chunk partials into out (only j <= i when lower).
 hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,
                          DimExpr nrows, DimExpr ncols, int rows_bound, int cols_bound,
-                         long long bstride_part, long long bstride_out, DimExpr batch, int batch_bound,
+                         long long bstride_part, long long bstride_out, int batch_bound, int lower,
                          hipStream_t s);
 
 // ---------------------------------------------------------------- eigensolver
