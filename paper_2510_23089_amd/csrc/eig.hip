@@ -110,12 +110,8 @@ __host__ __device__ inline EigWs eig_ws_carve(void* base, int b, int nb, int kc)
 }
 
 // ------------------------------------------------------------ 1. tridiag
-// (a) n <= 128: the packed lower triangle (n(n+1)/2 complex doubles, <= 132 KB)
-//     lives in LDS for the whole reduction; 1024 threads, 8 per row for the
-//     matrix-vector product and the rank-2 update.
 constexpr int TL_NMAX = 128;
 constexpr int TL_NT = 1024;
-constexpr int TL_ROWS = TL_NT / 8;           // rows per pass (8 threads per row)
 constexpr int TL_TRI = TL_NMAX * (TL_NMAX + 1) / 2;
 
 __device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1) >> 1) + c; }   // r >= c
@@ -187,8 +183,22 @@ __device__ void householder(double2 alpha, double xnorm2, double2& tau, double2&
   }
 }
 
+// (a) n <= 128: the packed lower triangle (n(n+1)/2 complex doubles, <= 132 KB)
+//     lives in LDS for the whole reduction; 1024 threads, 8 per row (row
+//     r = tid / 8) for the matrix-vector product and the rank-2 update.
+//     Lane 0 of row r updates the entry of the next column in that row and
+//     forms the partial sums of its norm, the waves holding rows j + 1 ..
+//     n - 1 form the reflector redundantly, and the cross-lane sums use DPP:
+//     three barriers per step.
+__device__ __forceinline__ double seg8_sum(double v) {   // valid in lanes 4..7 of each 8
+  v += dpp_d<0xB1, 0xf>(v);      // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E, 0xf>(v);      // quad_perm [2,3,0,1]
+  return v + dpp_d<0x114, 0xf>(v);   // row_shr:4
+}
+
 __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
                                                             void* wsbase, int nb, int kc, int* nlog) {
+  constexpr int NW = TL_NT / 64;
   const int b = blockIdx.x;
   const int n = min(dim_eval(nexp, b), min(nb, TL_NMAX));
   if (nlog && threadIdx.x == 0) nlog[b] = n;
@@ -196,9 +206,11 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 L[TL_TRI];
   __shared__ double2 V[TL_NMAX], P[TL_NMAX];
-  __shared__ double red[2 * TL_NT / 64];
-  __shared__ double2 s_tau, s_scale;
-  const int tid = threadIdx.x;
+  __shared__ double rnorm[NW];
+  __shared__ double2 rdot[NW];
+  __shared__ double2 s_tau;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = tid >> 3, sl = tid & 7;       // row and lane within the row's 8 threads
   {
     // packed lower triangle, all loads independent: element e -> (r, c)
     const int T = n * (n + 1) / 2;
@@ -209,74 +221,84 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
       L[e] = A[(long long)r * ld + (e - tri(r, 0))];
     }
   }
+  {
+    double loc = 0.0;
+    if (sl == 0 && r >= 2 && r < n) {
+      const double2 x = A[(long long)r * ld];
+      loc = x.x * x.x + x.y * x.y;
+    }
+    loc = wave_sum_u(loc);
+    if (lane == 0) rnorm[wv] = loc;
+  }
   __syncthreads();
-  const int rl = tid >> 3, sl = tid & 7;      // row slot and lane within the row's 8 threads
   for (int j = 0; j < n - 1; ++j) {
     const int j1 = j + 1;
-    double loc = 0.0;
-    for (int r = j1 + 1 + tid; r < n; r += TL_NT) {
-      double2 x = L[tri(r, j)];
-      loc += x.x * x.x + x.y * x.y;
-    }
-    double xnorm2 = block_sum<TL_NT>(loc, red);
-    if (tid == 0) {
-      double2 tau, scale;
+    // ---- reflector of column j (waves holding rows j1 .. n-1)
+    double2 scale = make_double2(0.0, 0.0);
+    if (wv * 64 + 63 >= 8 * j1 && wv * 64 < 8 * n) {
+      double xnorm2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < NW; ++i) xnorm2 += rnorm[i];
+      double2 tau;
       double beta;
       householder(L[tri(j1, j)], xnorm2, tau, scale, beta);
-      W.d[j] = L[tri(j, j)].x;
-      W.e[j] = beta;
-      W.e2[j] = beta * beta;
-      W.tau[j] = tau;
-      s_tau = tau;
-      s_scale = scale;
+      if (tid == 8 * j1) {
+        s_tau = tau;
+        W.d[j] = L[tri(j, j)].x;
+        W.e[j] = beta;
+        W.e2[j] = beta * beta;
+        W.tau[j] = tau;
+      }
     }
-    __syncthreads();
-    const double2 tau = s_tau, scale = s_scale;
-    for (int r = j1 + tid; r < n; r += TL_NT) {
-      double2 v = r == j1 ? make_double2(1.0, 0.0) : cmul(L[tri(r, j)], scale);
+    if (sl == 0 && r >= j1 && r < n) {
+      const double2 v = r == j1 ? make_double2(1.0, 0.0) : cmul(L[tri(r, j)], scale);
       V[r] = v;
       if (r > j1) A[(long long)j * ld + r] = v;   // reflector kept for the back-transformation
     }
     __syncthreads();
-    if (tau.x == 0.0 && tau.y == 0.0) continue;
-    // p = tau A v over the trailing block (A Hermitian, lower triangle stored)
-    for (int rb = j1; rb < n; rb += TL_ROWS) {
-      const int r = rb + rl;
+    const double2 tau = s_tau;
+    // ---- p = tau A v over the trailing block (A Hermitian, lower triangle stored)
+    {
       double2 acc = make_double2(0.0, 0.0);
-      if (r < n) {
+      if (r >= j1 && r < n) {
         for (int c = j1 + sl; c < n; c += 8) {
-          double2 a = c <= r ? L[tri(r, c)] : make_double2(L[tri(c, r)].x, -L[tri(c, r)].y);
+          const double2 a = c <= r ? L[tri(r, c)] : make_double2(L[tri(c, r)].x, -L[tri(c, r)].y);
           acc = cadd(acc, cmul(a, V[c]));
         }
       }
+      acc.x = seg8_sum(acc.x);
+      acc.y = seg8_sum(acc.y);
+      double2 dl = make_double2(0.0, 0.0);
+      if (sl == 7 && r >= j1 && r < n) {
+        const double2 p = cmul(tau, acc);
+        P[r] = p;
+        dl = cmulc(p, V[r]);
+      }
+      dl.x = wave_sum_u(dl.x);
+      dl.y = wave_sum_u(dl.y);
+      if (lane == 0) rdot[wv] = dl;
+    }
+    __syncthreads();
+    // ---- rank-2 update of the lower trailing triangle: A -= v w^H + w v^H,
+    //      w = p + alpha2 v, alpha2 = -(tau/2)(p^H v)
+    double2 dot = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
-        acc.x += __shfl_xor(acc.x, o);
-        acc.y += __shfl_xor(acc.y, o);
-      }
-      if (r < n && sl == 0) P[r] = cmul(tau, acc);
-    }
-    __syncthreads();
-    // w = p - (tau/2)(p^H v) v, kept in P
-    double2 dl = make_double2(0.0, 0.0);
-    for (int r = j1 + tid; r < n; r += TL_NT) dl = cadd(dl, cmulc(P[r], V[r]));
-    double2 dot = block_sum2<TL_NT>(dl, red);
+    for (int i = 0; i < NW; ++i) dot = cadd(dot, rdot[i]);
     const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
-    for (int r = j1 + tid; r < n; r += TL_NT) P[r] = cadd(P[r], cmul(alpha2, V[r]));
-    __syncthreads();
-    // rank-2 update of the lower trailing triangle: A -= v w^H + w v^H
-    for (int rb = j1; rb < n; rb += TL_ROWS) {
-      const int r = rb + rl;
-      if (r < n) {
-        const double2 vr = V[r], wr = P[r];
-        for (int c = j1 + sl; c <= r; c += 8) {
-          double2 a = L[tri(r, c)];
-          a = csub(a, cmul(vr, make_double2(P[c].x, -P[c].y)));
-          a = csub(a, cmul(wr, make_double2(V[c].x, -V[c].y)));
-          L[tri(r, c)] = a;
-        }
+    double loc = 0.0;
+    if (r >= j1 && r < n) {
+      const double2 vr = V[r], wr = cadd(P[r], cmul(alpha2, vr));
+      for (int c = j1 + sl; c <= r; c += 8) {
+        const double2 vc = V[c], wc = cadd(P[c], cmul(alpha2, vc));
+        double2 a = L[tri(r, c)];
+        a = csub(a, cmul(vr, make_double2(wc.x, -wc.y)));
+        a = csub(a, cmul(wr, make_double2(vc.x, -vc.y)));
+        L[tri(r, c)] = a;
+        if (c == j1 && r >= j1 + 2) loc = a.x * a.x + a.y * a.y;
       }
     }
+    loc = wave_sum_u(loc);
+    if (lane == 0) rnorm[wv] = loc;
     __syncthreads();
   }
   if (tid == 0 && n >= 1) W.d[n - 1] = L[tri(n - 1, n - 1)].x;
