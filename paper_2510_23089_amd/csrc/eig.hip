@@ -669,26 +669,41 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
 
 // ------------------------------------------------------------ 2. eigenvalues
 // Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x.
+// Steps run in blocks of eight whose d and e2 loads are all issued before the
+// recurrence, so the LDS latency is paid once per block; the exponent
+// rescaling follows each block (the same points as a step-by-step loop that
+// rescales after every eighth step).
+__device__ __forceinline__ void sturm_step(double d, double e2, double x, double& p0, double& p1, int& sprev,
+                                           int& cnt) {
+  const double p2 = fma(d - x, p1, -e2 * p0);
+  const int s = p2 > 0.0 ? 1 : (p2 < 0.0 ? -1 : -sprev);
+  cnt += (s != sprev);
+  sprev = s;
+  p0 = p1;
+  p1 = p2;
+}
 __device__ int sturm_count(const double* d, const double* e2, int n, double x) {
   double p0 = 1.0, p1 = d[0] - x;
   int sprev = p1 > 0.0 ? 1 : -1;
   int cnt = sprev < 0 ? 1 : 0;
-  for (int i = 1; i < n; ++i) {
-    double p2 = fma(d[i] - x, p1, -e2[i - 1] * p0);
-    int s = p2 > 0.0 ? 1 : (p2 < 0.0 ? -1 : -sprev);
-    cnt += (s != sprev);
-    sprev = s;
-    p0 = p1;
-    p1 = p2;
-    if ((i & 7) == 0) {
-      double m = fmax(fabs(p0), fabs(p1));
-      if (m > 0x1p+600 || (m < 0x1p-600 && m > 0.0)) {
-        int ex = ilogb(m);
-        p0 = ldexp(p0, -ex);
-        p1 = ldexp(p1, -ex);
-      }
+  int i = 1;
+  for (; i + 8 <= n; i += 8) {
+    double dd[8], ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dd[u] = d[i + u];
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sturm_step(dd[u], ee[u], x, p0, p1, sprev, cnt);
+    const double m = fmax(fabs(p0), fabs(p1));
+    if (m > 0x1p+600 || (m < 0x1p-600 && m > 0.0)) {
+      const int ex = ilogb(m);
+      p0 = ldexp(p0, -ex);
+      p1 = ldexp(p1, -ex);
     }
   }
+  for (; i < n; ++i) sturm_step(d[i], e2[i - 1], x, p0, p1, sprev, cnt);
   return cnt;
 }
 
@@ -798,8 +813,11 @@ __device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
 
 // One lane per eigenvector; its tridiagonal LU factors (with reciprocal
 // pivots) and iterate live in LDS: VPW vectors per workgroup, 5 doubles and
-// one pivot flag per matrix row and vector.
-constexpr int IV_LDS = 63 * 1024;     // dynamic LDS per workgroup (kept under the 64 KB default)
+// one pivot flag per matrix row and vector.  Every recurrence carries its
+// running values in registers and reads its LDS inputs in blocks of eight
+// issued ahead of the arithmetic, so the LDS latency stays off the chain.
+constexpr int IV_LDS = 55 * 1024;     // dynamic LDS per workgroup (with the static part under 64 KB)
+constexpr int IV_B = 8;               // recurrence steps per prefetched block
 __host__ __device__ inline int iv_vpw(int nb) {
   int v = IV_LDS / (nb * 41);
   return v < 1 ? 1 : (v > 64 ? 64 : v);
@@ -808,13 +826,20 @@ __host__ __device__ inline int iv_vpw(int nb) {
 __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase,
                                                      int nb, int kc, int vpw) {
   extern __shared__ double ivs[];
+  __shared__ double sd[EIG_NMAX], se[EIG_NMAX];
   const int b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
   const int k = kin[b * kstride];
   const int t = threadIdx.x;
   const int vi = blockIdx.x * vpw + t;
-  if (t >= vpw || vi >= k) return;
+  if (blockIdx.x * vpw >= k) return;          // whole workgroup idle
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
+  for (int i = t; i < n; i += 64) {
+    sd[i] = W.d[i];
+    se[i] = i < n - 1 ? W.e[i] : 0.0;
+  }
+  __syncthreads();
+  if (t >= vpw || vi >= k) return;
   // per-lane arrays, interleaved by lane (stride vpw) to spread LDS banks
   double* D = ivs;
   double* DL = D + (size_t)nb * vpw;
@@ -823,73 +848,127 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
   double* X = DU2 + (size_t)nb * vpw;
   unsigned char* P = (unsigned char*)(X + (size_t)nb * vpw);
 #define IX(i) ((i) * vpw + t)
-  if (n == 1) { W.z[vi] = 1.0; return; }
+  if (n == 1) { W.z[(long long)vi * nb] = 1.0; return; }
   const double mu = W.lam[vi];
   const double tn = fmax(fabs(W.lam[0]), 1e-300);
   const double pivmin = 1e-300 + 2.2e-16 * tn * 1e-3;
-  for (int i = 0; i < n; ++i) {
-    D[IX(i)] = W.d[i] - mu;
-    if (i < n - 1) { DL[IX(i)] = W.e[i]; DU[IX(i)] = W.e[i]; DU2[IX(i)] = 0.0; }
-  }
-  // LU with partial pivoting (tridiagonal); pivots stored as reciprocals
-  for (int i = 0; i < n - 1; ++i) {
-    double di = D[IX(i)], dli = DL[IX(i)];
-    if (fabs(di) >= fabs(dli)) {
-      if (di == 0.0) di = pivmin;
-      double f = dli / di;
-      D[IX(i)] = 1.0 / di;
-      DL[IX(i)] = f;
-      D[IX(i + 1)] -= f * DU[IX(i)];
-      P[IX(i)] = 0;
-    } else {
-      double f = di / dli;
-      D[IX(i)] = 1.0 / dli;
-      DL[IX(i)] = f;
-      double tmp = DU[IX(i)];
-      DU[IX(i)] = D[IX(i + 1)];
-      D[IX(i + 1)] = tmp - f * D[IX(i + 1)];
-      if (i < n - 2) {
-        DU2[IX(i)] = DU[IX(i + 1)];
-        DU[IX(i + 1)] = -f * DU[IX(i + 1)];
-      }
-      P[IX(i)] = 1;
+  // LU with partial pivoting (tridiagonal); pivots stored as reciprocals.
+  // Step i sees the running diagonal entry dcur = U[i][i] and superdiagonal
+  // ducur = U[i][i+1]; rows i + 1 and beyond are still untouched.
+  double dcur = sd[0] - mu, ducur = se[0];
+  for (int i0 = 0; i0 < n - 1; i0 += IV_B) {
+    double dl[IV_B], dn[IV_B], en[IV_B];
+#pragma unroll
+    for (int u = 0; u < IV_B; ++u) {
+      const int i = min(i0 + u, n - 2);
+      dl[u] = se[i];
+      dn[u] = sd[i + 1] - mu;
+      en[u] = i < n - 2 ? se[i + 1] : 0.0;
     }
-  }
-  {
-    double dn = D[IX(n - 1)];
-    D[IX(n - 1)] = 1.0 / (dn == 0.0 ? pivmin : dn);
-  }
-  for (int i = 0; i < n; ++i) X[IX(i)] = hash_unit(vi + 1, i + 7 * b);
-  for (int it = 0; it < 3; ++it) {
-    for (int i = 0; i < n - 1; ++i) {
-      double xi = X[IX(i)], xn = X[IX(i + 1)];
-      if (P[IX(i)] == 0) {
-        X[IX(i + 1)] = xn - DL[IX(i)] * xi;
+#pragma unroll
+    for (int u = 0; u < IV_B; ++u) {
+      const int i = i0 + u;
+      if (i >= n - 1) break;
+      double di = dcur;
+      if (fabs(di) >= fabs(dl[u])) {
+        if (di == 0.0) di = pivmin;
+        const double f = dl[u] / di;
+        D[IX(i)] = 1.0 / di;
+        DL[IX(i)] = f;
+        DU[IX(i)] = ducur;
+        DU2[IX(i)] = 0.0;
+        P[IX(i)] = 0;
+        dcur = dn[u] - f * ducur;
+        ducur = en[u];
       } else {
-        X[IX(i)] = xn;
-        X[IX(i + 1)] = xi - DL[IX(i)] * xn;
+        const double f = di / dl[u];
+        D[IX(i)] = 1.0 / dl[u];
+        DL[IX(i)] = f;
+        DU[IX(i)] = dn[u];
+        DU2[IX(i)] = en[u];
+        P[IX(i)] = 1;
+        dcur = ducur - f * dn[u];
+        ducur = -f * en[u];
       }
     }
-    double mx;
-    double x2 = X[IX(n - 1)] * D[IX(n - 1)];
+  }
+  D[IX(n - 1)] = 1.0 / (dcur == 0.0 ? pivmin : dcur);
+  for (int i = 0; i < n; ++i) X[IX(i)] = hash_unit(vi + 1, i + 7 * b);
+  double sc = 1.0;                            // scale of the stored iterate
+  for (int it = 0; it < 3; ++it) {
+    // forward: L y = P x (row interchanges), x scaled on load
+    double xcur = X[IX(0)] * sc;
+    for (int i0 = 0; i0 < n - 1; i0 += IV_B) {
+      double xn[IV_B], dl[IV_B];
+      unsigned char pv[IV_B];
+#pragma unroll
+      for (int u = 0; u < IV_B; ++u) {
+        const int i = min(i0 + u, n - 2);
+        xn[u] = X[IX(i + 1)] * sc;
+        dl[u] = DL[IX(i)];
+        pv[u] = P[IX(i)];
+      }
+#pragma unroll
+      for (int u = 0; u < IV_B; ++u) {
+        const int i = i0 + u;
+        if (i >= n - 1) break;
+        if (pv[u] == 0) {
+          X[IX(i)] = xcur;
+          xcur = xn[u] - dl[u] * xcur;
+        } else {
+          X[IX(i)] = xn[u];
+          xcur = xcur - dl[u] * xn[u];
+        }
+      }
+    }
+    X[IX(n - 1)] = xcur;
+    // backward: U x = y
+    double x2 = xcur * D[IX(n - 1)];
     X[IX(n - 1)] = x2;
     double x1 = (X[IX(n - 2)] - DU[IX(n - 2)] * x2) * D[IX(n - 2)];
     X[IX(n - 2)] = x1;
-    mx = fmax(fabs(x1), fabs(x2));
-    for (int i = n - 3; i >= 0; --i) {
-      double x0 = (X[IX(i)] - DU[IX(i)] * x1 - DU2[IX(i)] * x2) * D[IX(i)];
-      X[IX(i)] = x0;
-      x2 = x1;
-      x1 = x0;
-      mx = fmax(mx, fabs(x0));
+    double mx = fmax(fabs(x1), fabs(x2));
+    for (int i0 = n - 3; i0 >= 0; i0 -= IV_B) {
+      double xv[IV_B], du[IV_B], du2[IV_B], dd[IV_B];
+#pragma unroll
+      for (int u = 0; u < IV_B; ++u) {
+        const int i = max(i0 - u, 0);
+        xv[u] = X[IX(i)];
+        du[u] = DU[IX(i)];
+        du2[u] = DU2[IX(i)];
+        dd[u] = D[IX(i)];
+      }
+#pragma unroll
+      for (int u = 0; u < IV_B; ++u) {
+        const int i = i0 - u;
+        if (i < 0) break;
+        const double x0 = (xv[u] - du[u] * x1 - du2[u] * x2) * dd[u];
+        X[IX(i)] = x0;
+        x2 = x1;
+        x1 = x0;
+        mx = fmax(mx, fabs(x0));
+      }
     }
-    double sc = mx > 0.0 && isfinite(mx) ? 1.0 / mx : 1.0;
-    for (int i = 0; i < n; ++i) X[IX(i)] *= sc;
+    sc = mx > 0.0 && isfinite(mx) ? 1.0 / mx : 1.0;
   }
   double s2 = 0.0;
-  for (int i = 0; i < n; ++i) s2 += X[IX(i)] * X[IX(i)];
-  double sc = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-  for (int i = 0; i < n; ++i) W.z[(long long)i * kc + vi] = X[IX(i)] * sc;
+  for (int i0 = 0; i0 < n; i0 += IV_B) {
+    double xv[IV_B];
+#pragma unroll
+    for (int u = 0; u < IV_B; ++u) xv[u] = X[IX(min(i0 + u, n - 1))] * sc;
+#pragma unroll
+    for (int u = 0; u < IV_B; ++u)
+      if (i0 + u < n) s2 += xv[u] * xv[u];
+  }
+  const double scn = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  for (int i0 = 0; i0 < n; i0 += IV_B) {
+    double xv[IV_B];
+#pragma unroll
+    for (int u = 0; u < IV_B; ++u) xv[u] = X[IX(min(i0 + u, n - 1))] * sc;
+#pragma unroll
+    for (int u = 0; u < IV_B; ++u)
+      if (i0 + u < n) W.z[(long long)vi * nb + i0 + u] = xv[u] * scn;
+  }
 #undef IX
 }
 
@@ -904,23 +983,30 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
   __shared__ double red[CL_NT / 64];
   __shared__ double coef[EIG_NMAX];
   __shared__ double zt[EIG_NMAX];
+  __shared__ double slam[EIG_NMAX];
   const double tn = fabs(W.lam[0]);
+  int joins = 0;
+  for (int t = threadIdx.x; t < k; t += CL_NT) {
+    slam[t] = W.lam[t];
+    if (t > 0 && !(W.lam[t - 1] - W.lam[t] > reltol * tn)) joins = 1;
+  }
+  if (!__syncthreads_or(joins)) return;       // no clusters: nothing to do
   int cs = 0;
   for (int t = 1; t < k; ++t) {
-    if (W.lam[t - 1] - W.lam[t] > reltol * tn) { cs = t; continue; }
+    if (slam[t - 1] - slam[t] > reltol * tn) { cs = t; continue; }
     // t joins the cluster [cs, t): Gram-Schmidt twice against its members
-    for (int i = threadIdx.x; i < n; i += CL_NT) zt[i] = W.z[(long long)i * kc + t];
+    for (int i = threadIdx.x; i < n; i += CL_NT) zt[i] = W.z[(long long)t * nb + i];
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
       for (int s = cs + threadIdx.x; s < t; s += CL_NT) {
         double d = 0.0;
-        for (int i = 0; i < n; ++i) d += W.z[(long long)i * kc + s] * zt[i];
+        for (int i = 0; i < n; ++i) d += W.z[(long long)s * nb + i] * zt[i];
         coef[s] = d;
       }
       __syncthreads();
       for (int i = threadIdx.x; i < n; i += CL_NT) {
         double v = zt[i];
-        for (int s = cs; s < t; ++s) v -= coef[s] * W.z[(long long)i * kc + s];
+        for (int s = cs; s < t; ++s) v -= coef[s] * W.z[(long long)s * nb + i];
         zt[i] = v;
       }
       __syncthreads();
@@ -929,7 +1015,7 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
     for (int i = threadIdx.x; i < n; i += CL_NT) loc += zt[i] * zt[i];
     double nrm = sqrt(block_sum<CL_NT>(loc, red));
     double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int i = threadIdx.x; i < n; i += CL_NT) W.z[(long long)i * kc + t] = zt[i] * sc;
+    for (int i = threadIdx.x; i < n; i += CL_NT) W.z[(long long)t * nb + i] = zt[i] * sc;
     __syncthreads();
   }
 }
@@ -956,30 +1042,26 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
 #pragma unroll
   for (int q = 0; q < BT_PER_LANE; ++q) {
     int i = lane + 64 * q;
-    v[q] = make_double2(i < n && t < k ? W.z[(long long)i * kc + t] : 0.0, 0.0);
+    v[q] = make_double2(i < n && t < k ? W.z[(long long)t * nb + i] : 0.0, 0.0);
   }
   __shared__ double2 stau[EIG_NMAX];
   for (int i = threadIdx.x; i < n - 1; i += BT_NT) stau[i] = W.tau[i];
   __syncthreads();
   if (t >= k) return;
-  // reflector j lives in row j (columns > j+1) with an implicit 1 at j+1; the
-  // next reflector's row is loaded while the current one is applied
-  double2 un[BT_PER_LANE];
-  auto load_u = [&](int j) {
+  // reflector j lives in row j (columns > j+1) with an implicit 1 at j+1;
+  // three rows rotate through registers, each loaded two applications
+  // before its own
+  double2 u0[BT_PER_LANE], u1[BT_PER_LANE], u2[BT_PER_LANE];
+  auto load_u = [&](double2* u, int j) {
 #pragma unroll
     for (int q = 0; q < BT_PER_LANE; ++q) {
       int i = lane + 64 * q;
-      un[q] = (i > j + 1 && i < n) ? A[(long long)j * ld + i] : make_double2(0.0, 0.0);
+      u[q] = (j >= 0 && i > j + 1 && i < n) ? A[(long long)j * ld + i] : make_double2(0.0, 0.0);
     }
   };
-  if (n >= 2) load_u(n - 2);
-  for (int j = n - 2; j >= 0; --j) {
-    double2 u[BT_PER_LANE];
-#pragma unroll
-    for (int q = 0; q < BT_PER_LANE; ++q) u[q] = un[q];
-    if (j > 0) load_u(j - 1);
+  auto apply_u = [&](double2* u, int j) {
     const double2 tau = stau[j];
-    if (tau.x == 0.0 && tau.y == 0.0) continue;
+    if (tau.x == 0.0 && tau.y == 0.0) return;
     const int j1 = j + 1;
     double dre = 0.0, dim_ = 0.0;
 #pragma unroll
@@ -990,11 +1072,24 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
       dre += p.x;
       dim_ += p.y;
     }
-    dre = wave_sum(dre);
-    dim_ = wave_sum(dim_);
+    dre = wave_sum_u(dre);
+    dim_ = wave_sum_u(dim_);
     const double2 f = cmul(tau, make_double2(dre, dim_));
 #pragma unroll
     for (int q = 0; q < BT_PER_LANE; ++q) v[q] = csub(v[q], cmul(f, u[q]));
+  };
+  load_u(u0, n - 2);
+  load_u(u1, n - 3);
+  load_u(u2, n - 4);
+  for (int j = n - 2; j >= 0; j -= 3) {
+    apply_u(u0, j);
+    load_u(u0, j - 3);
+    if (j - 1 < 0) break;
+    apply_u(u1, j - 1);
+    load_u(u1, j - 4);
+    if (j - 2 < 0) break;
+    apply_u(u2, j - 2);
+    load_u(u2, j - 5);
   }
   const double sg = W.sig[t];
   for (int e = 0; e < ep.ne; ++e) {
