@@ -668,24 +668,18 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
 }
 
 // ------------------------------------------------------------ 2. eigenvalues
-// Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x.
-// Steps run in blocks of eight whose d and e2 loads are all issued before the
-// recurrence, so the LDS latency is paid once per block; the exponent
-// rescaling follows each block (the same points as a step-by-step loop that
-// rescales after every eighth step).
-__device__ __forceinline__ void sturm_step(double d, double e2, double x, double& p0, double& p1, int& sprev,
-                                           int& cnt) {
-  const double p2 = fma(d - x, p1, -e2 * p0);
-  const int s = p2 > 0.0 ? 1 : (p2 < 0.0 ? -1 : -sprev);
-  cnt += (s != sprev);
-  sprev = s;
-  p0 = p1;
-  p1 = p2;
-}
+// Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x:
+// the sign changes along p_0 = 1, p_1, ..., p_n of the three-term recurrence
+// p_i = (d_i - x) p_{i-1} - e2_{i-1} p_{i-2} (division-free), taken from the
+// sign bits; an exact zero takes the sign opposite to its predecessor's (so
+// a run of underflowed zeros, e.g. for the zero matrix, still counts every
+// eigenvalue at or below x).  Steps run in
+// blocks of eight whose d and e2 loads are all issued before the
+// recurrence; the exponent rescaling follows each block.
 __device__ int sturm_count(const double* d, const double* e2, int n, double x) {
   double p0 = 1.0, p1 = d[0] - x;
-  int sprev = p1 > 0.0 ? 1 : -1;
-  int cnt = sprev < 0 ? 1 : 0;
+  unsigned sprev = p1 > 0.0 ? 0u : 1u;
+  int cnt = (int)sprev;
   int i = 1;
   for (; i + 8 <= n; i += 8) {
     double dd[8], ee[8];
@@ -695,7 +689,14 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x) {
       ee[u] = e2[i + u - 1];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) sturm_step(dd[u], ee[u], x, p0, p1, sprev, cnt);
+    for (int u = 0; u < 8; ++u) {
+      const double p2 = fma(dd[u] - x, p1, -ee[u] * p0);
+      const unsigned sg = p2 == 0.0 ? (sprev ^ 1u) : (unsigned)__double2hiint(p2) >> 31;
+      cnt += (int)(sg ^ sprev);
+      sprev = sg;
+      p0 = p1;
+      p1 = p2;
+    }
     const double m = fmax(fabs(p0), fabs(p1));
     if (m > 0x1p+600 || (m < 0x1p-600 && m > 0.0)) {
       const int ex = ilogb(m);
@@ -703,7 +704,14 @@ __device__ int sturm_count(const double* d, const double* e2, int n, double x) {
       p1 = ldexp(p1, -ex);
     }
   }
-  for (; i < n; ++i) sturm_step(d[i], e2[i - 1], x, p0, p1, sprev, cnt);
+  for (; i < n; ++i) {
+    const double p2 = fma(d[i] - x, p1, -e2[i - 1] * p0);
+    const unsigned sg = p2 == 0.0 ? (sprev ^ 1u) : (unsigned)__double2hiint(p2) >> 31;
+    cnt += (int)(sg ^ sprev);
+    sprev = sg;
+    p0 = p1;
+    p1 = p2;
+  }
   return cnt;
 }
 
@@ -805,22 +813,37 @@ __global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, dou
 }
 
 // ------------------------------------------------------------ 4. inverse iteration
-__device__ __forceinline__ double hash_unit(unsigned a, unsigned b) {
-  unsigned h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u;
-  h ^= h >> 15; h *= 0x2C1B3C6Du; h ^= h >> 12; h *= 0x297A2D39u; h ^= h >> 15;
-  return ((double)h / 4294967296.0) - 0.5;
-}
 
 // One lane per eigenvector; its tridiagonal LU factors (with reciprocal
 // pivots) and iterate live in LDS: VPW vectors per workgroup, 5 doubles and
-// one pivot flag per matrix row and vector.  Every recurrence carries its
-// running values in registers and reads its LDS inputs in blocks of eight
-// issued ahead of the arithmetic, so the LDS latency stays off the chain.
+// one pivot flag per matrix row and vector.  Only a few lanes of each wave
+// are busy, so every instruction costs a full wave slot: the recurrences are
+// branch-free (pivot choice by selects, one reciprocal per step from
+// v_rcp_f64 and two Newton steps), carry their running values in registers
+// and read their LDS inputs in blocks of eight issued ahead of the
+// arithmetic.  The start vector comes from a per-vector xorshift stream,
+// generated inside the first forward pass.
 constexpr int IV_LDS = 55 * 1024;     // dynamic LDS per workgroup (with the static part under 64 KB)
 constexpr int IV_B = 8;               // recurrence steps per prefetched block
+constexpr int IV_ITERS = 3;           // inverse-iteration solves
 __host__ __device__ inline int iv_vpw(int nb) {
   int v = IV_LDS / (nb * 41);
   return v < 1 ? 1 : (v > 64 ? 64 : v);
+}
+
+// 1/p to full double precision for normal p (hardware estimate, two Newton steps)
+__device__ __forceinline__ double recip(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  r = fma(r, fma(-p, r, 1.0), r);
+  return fma(r, fma(-p, r, 1.0), r);
+}
+
+// xorshift64 stream -> uniform in [-0.5, 0.5)
+__device__ __forceinline__ double xs_next(unsigned long long& st) {
+  st ^= st << 13;
+  st ^= st >> 7;
+  st ^= st << 17;
+  return (double)(st >> 11) * 0x1p-53 - 0.5;
 }
 
 __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase,
@@ -852,9 +875,10 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
   const double mu = W.lam[vi];
   const double tn = fmax(fabs(W.lam[0]), 1e-300);
   const double pivmin = 1e-300 + 2.2e-16 * tn * 1e-3;
-  // LU with partial pivoting (tridiagonal); pivots stored as reciprocals.
-  // Step i sees the running diagonal entry dcur = U[i][i] and superdiagonal
-  // ducur = U[i][i+1]; rows i + 1 and beyond are still untouched.
+  // LU with partial pivoting (tridiagonal); pivots stored as reciprocals,
+  // pivots smaller than pivmin raised to it.  Step i sees the running
+  // diagonal entry dcur = U[i][i] and superdiagonal ducur = U[i][i+1]; rows
+  // i + 1 and beyond are still untouched.
   double dcur = sd[0] - mu, ducur = se[0];
   for (int i0 = 0; i0 < n - 1; i0 += IV_B) {
     double dl[IV_B], dn[IV_B], en[IV_B];
@@ -869,42 +893,40 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
     for (int u = 0; u < IV_B; ++u) {
       const int i = i0 + u;
       if (i >= n - 1) break;
-      double di = dcur;
-      if (fabs(di) >= fabs(dl[u])) {
-        if (di == 0.0) di = pivmin;
-        const double f = dl[u] / di;
-        D[IX(i)] = 1.0 / di;
-        DL[IX(i)] = f;
-        DU[IX(i)] = ducur;
-        DU2[IX(i)] = 0.0;
-        P[IX(i)] = 0;
-        dcur = dn[u] - f * ducur;
-        ducur = en[u];
-      } else {
-        const double f = di / dl[u];
-        D[IX(i)] = 1.0 / dl[u];
-        DL[IX(i)] = f;
-        DU[IX(i)] = dn[u];
-        DU2[IX(i)] = en[u];
-        P[IX(i)] = 1;
-        dcur = ducur - f * dn[u];
-        ducur = -f * en[u];
-      }
+      const bool piv = fabs(dcur) < fabs(dl[u]);
+      const double di = fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur;
+      const double r = recip(piv ? dl[u] : di);
+      const double f = (piv ? di : dl[u]) * r;
+      D[IX(i)] = r;
+      DL[IX(i)] = f;
+      DU[IX(i)] = piv ? dn[u] : ducur;
+      DU2[IX(i)] = piv ? en[u] : 0.0;
+      P[IX(i)] = piv ? 1 : 0;
+      dcur = fma(-f, piv ? dn[u] : ducur, piv ? ducur : dn[u]);
+      ducur = piv ? -f * en[u] : en[u];
     }
   }
-  D[IX(n - 1)] = 1.0 / (dcur == 0.0 ? pivmin : dcur);
-  for (int i = 0; i < n; ++i) X[IX(i)] = hash_unit(vi + 1, i + 7 * b);
+  D[IX(n - 1)] = recip(fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur);
+  unsigned long long st = 0x9E3779B97F4A7C15ull ^ ((unsigned long long)(vi + 1) * 0xD1B54A32D192ED03ull) ^
+                          ((unsigned long long)(b + 1) * 0x94D049BB133111EBull);
   double sc = 1.0;                            // scale of the stored iterate
-  for (int it = 0; it < 3; ++it) {
-    // forward: L y = P x (row interchanges), x scaled on load
-    double xcur = X[IX(0)] * sc;
+  double ss = 0.0;                            // sum of squares of the last solution
+  // three solves: with the shift accurate to ~eps ||T||, components along
+  // eigenvalues at a gap g shrink by ~(eps ||T|| / g) per solve (gaps below
+  // 1e-10 ||T|| are left to the cluster pass); across an exact split of T
+  // (e_i = 0, as for zero-padded fields) the shrink per solve is the pivot
+  // floor, and three solves take such components below the FP32 range
+  for (int it = 0; it < IV_ITERS; ++it) {
+    // forward: L y = P x (row interchanges); the stored x is scaled on load
+    // (the first pass draws x from the start stream instead)
+    double xcur = it == 0 ? xs_next(st) : X[IX(0)] * sc;
     for (int i0 = 0; i0 < n - 1; i0 += IV_B) {
       double xn[IV_B], dl[IV_B];
       unsigned char pv[IV_B];
 #pragma unroll
       for (int u = 0; u < IV_B; ++u) {
         const int i = min(i0 + u, n - 2);
-        xn[u] = X[IX(i + 1)] * sc;
+        xn[u] = it == 0 ? 0.0 : X[IX(i + 1)] * sc;
         dl[u] = DL[IX(i)];
         pv[u] = P[IX(i)];
       }
@@ -912,13 +934,10 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
       for (int u = 0; u < IV_B; ++u) {
         const int i = i0 + u;
         if (i >= n - 1) break;
-        if (pv[u] == 0) {
-          X[IX(i)] = xcur;
-          xcur = xn[u] - dl[u] * xcur;
-        } else {
-          X[IX(i)] = xn[u];
-          xcur = xcur - dl[u] * xn[u];
-        }
+        const double x1 = it == 0 ? xs_next(st) : xn[u];
+        const bool p = pv[u] != 0;
+        X[IX(i)] = p ? x1 : xcur;
+        xcur = fma(-dl[u], p ? x1 : xcur, p ? xcur : x1);
       }
     }
     X[IX(n - 1)] = xcur;
@@ -928,6 +947,7 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
     double x1 = (X[IX(n - 2)] - DU[IX(n - 2)] * x2) * D[IX(n - 2)];
     X[IX(n - 2)] = x1;
     double mx = fmax(fabs(x1), fabs(x2));
+    ss = x1 * x1 + x2 * x2;
     for (int i0 = n - 3; i0 >= 0; i0 -= IV_B) {
       double xv[IV_B], du[IV_B], du2[IV_B], dd[IV_B];
 #pragma unroll
@@ -947,33 +967,72 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
         x2 = x1;
         x1 = x0;
         mx = fmax(mx, fabs(x0));
+        ss = fma(x0, x0, ss);
       }
     }
     sc = mx > 0.0 && isfinite(mx) ? 1.0 / mx : 1.0;
   }
-  double s2 = 0.0;
+  // unit vector: x * sc has sum of squares ss * sc^2
+  const double s2 = ss * sc * sc;
+  const double f = s2 > 0.0 ? sc / sqrt(s2) : 0.0;
   for (int i0 = 0; i0 < n; i0 += IV_B) {
     double xv[IV_B];
 #pragma unroll
-    for (int u = 0; u < IV_B; ++u) xv[u] = X[IX(min(i0 + u, n - 1))] * sc;
+    for (int u = 0; u < IV_B; ++u) xv[u] = X[IX(min(i0 + u, n - 1))];
 #pragma unroll
     for (int u = 0; u < IV_B; ++u)
-      if (i0 + u < n) s2 += xv[u] * xv[u];
-  }
-  const double scn = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-  for (int i0 = 0; i0 < n; i0 += IV_B) {
-    double xv[IV_B];
-#pragma unroll
-    for (int u = 0; u < IV_B; ++u) xv[u] = X[IX(min(i0 + u, n - 1))] * sc;
-#pragma unroll
-    for (int u = 0; u < IV_B; ++u)
-      if (i0 + u < n) W.z[(long long)vi * nb + i0 + u] = xv[u] * scn;
+      if (i0 + u < n) W.z[(long long)vi * nb + i0 + u] = xv[u] * f;
   }
 #undef IX
 }
 
 // ------------------------------------------------------------ 5. clusters
-constexpr int CL_NT = 256;
+// Runs of kept eigenvalues closer than reltol * |lambda_1| form clusters;
+// each cluster's vectors get classical Gram-Schmidt twice, member by member
+// (the first member stays).  A cluster whose vectors fit in LDS is
+// orthogonalised there and written back once; a larger one works on the
+// eigenvector scratch in place.  Dots: one wave per earlier member, lanes
+// over rows, DPP sums.
+constexpr int CL_NT = 1024;
+constexpr int CL_LDS = 12 * 1024;             // doubles of cluster vectors held in LDS (96 KB)
+
+template <bool IN_LDS>
+__device__ void cluster_gs(double* Z, int ldz, int m, int n, double* coef, double* red) {
+  constexpr int NW = CL_NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j = 1; j < m; ++j) {
+    double* zj = Z + (long long)j * ldz;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int s0 = 0; s0 < j; s0 += NW) {
+        const int s = s0 + wv;
+        double d = 0.0;
+        if (s < j)
+          for (int i = lane; i < n; i += 64) d = fma(Z[(long long)s * ldz + i], zj[i], d);
+        d = wave_sum_u(d);
+        if (s < j && lane == 0) coef[s] = d;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += CL_NT) {
+        double v = zj[i];
+        for (int s = 0; s < j; ++s) v = fma(-coef[s], Z[(long long)s * ldz + i], v);
+        zj[i] = v;
+      }
+      __syncthreads();
+    }
+    double loc = 0.0;
+    for (int i = tid; i < n; i += CL_NT) loc = fma(zj[i], zj[i], loc);
+    loc = wave_sum_u(loc);
+    if (lane == 0) red[wv] = loc;
+    __syncthreads();
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) nrm2 += red[i];
+    const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+    for (int i = tid; i < n; i += CL_NT) zj[i] *= sc;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase,
                                                         int nb, int kc, double reltol) {
   const int b = blockIdx.x;
@@ -982,8 +1041,8 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double red[CL_NT / 64];
   __shared__ double coef[EIG_NMAX];
-  __shared__ double zt[EIG_NMAX];
   __shared__ double slam[EIG_NMAX];
+  __shared__ double zs[CL_LDS];
   const double tn = fabs(W.lam[0]);
   int joins = 0;
   for (int t = threadIdx.x; t < k; t += CL_NT) {
@@ -992,31 +1051,28 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
   }
   if (!__syncthreads_or(joins)) return;       // no clusters: nothing to do
   int cs = 0;
-  for (int t = 1; t < k; ++t) {
-    if (slam[t - 1] - slam[t] > reltol * tn) { cs = t; continue; }
-    // t joins the cluster [cs, t): Gram-Schmidt twice against its members
-    for (int i = threadIdx.x; i < n; i += CL_NT) zt[i] = W.z[(long long)t * nb + i];
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int s = cs + threadIdx.x; s < t; s += CL_NT) {
-        double d = 0.0;
-        for (int i = 0; i < n; ++i) d += W.z[(long long)s * nb + i] * zt[i];
-        coef[s] = d;
+  for (int t = 1; t <= k; ++t) {
+    if (t < k && !(slam[t - 1] - slam[t] > reltol * tn)) continue;
+    const int m = t - cs;                     // cluster [cs, t)
+    if (m > 1) {
+      double* zg = W.z + (long long)cs * nb;
+      if ((long long)m * n <= CL_LDS) {
+        for (int e = threadIdx.x; e < m * n; e += CL_NT) {
+          const int j = e / n, i = e - j * n;
+          zs[e] = zg[(long long)j * nb + i];
+        }
+        __syncthreads();
+        cluster_gs<true>(zs, n, m, n, coef, red);
+        for (int e = threadIdx.x; e < m * n; e += CL_NT) {
+          const int j = e / n, i = e - j * n;
+          if (j > 0) zg[(long long)j * nb + i] = zs[e];
+        }
+        __syncthreads();
+      } else {
+        cluster_gs<false>(zg, nb, m, n, coef, red);
       }
-      __syncthreads();
-      for (int i = threadIdx.x; i < n; i += CL_NT) {
-        double v = zt[i];
-        for (int s = cs; s < t; ++s) v -= coef[s] * W.z[(long long)s * nb + i];
-        zt[i] = v;
-      }
-      __syncthreads();
     }
-    double loc = 0.0;
-    for (int i = threadIdx.x; i < n; i += CL_NT) loc += zt[i] * zt[i];
-    double nrm = sqrt(block_sum<CL_NT>(loc, red));
-    double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    for (int i = threadIdx.x; i < n; i += CL_NT) W.z[(long long)t * nb + i] = zt[i] * sc;
-    __syncthreads();
+    cs = t;
   }
 }
 
