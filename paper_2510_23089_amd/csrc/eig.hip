@@ -187,9 +187,9 @@ __device__ void householder(double2 alpha, double xnorm2, double2& tau, double2&
 //     lives in LDS for the whole reduction; 1024 threads, 8 per row (row
 //     r = tid / 8) for the matrix-vector product and the rank-2 update.
 //     Lane 0 of row r updates the entry of the next column in that row and
-//     forms the partial sums of its norm, the waves holding rows j + 1 ..
-//     n - 1 form the reflector redundantly, and the cross-lane sums use DPP:
-//     three barriers per step.
+//     forms the partial sums of its norm, the (at most two) waves whose
+//     thread indices cover rows j + 1 .. n - 1 form the reflector
+//     redundantly, and the cross-lane sums use DPP: three barriers per step.
 __device__ __forceinline__ double seg8_sum(double v) {   // valid in lanes 4..7 of each 8
   v += dpp_d<0xB1, 0xf>(v);      // quad_perm [1,0,3,2]
   v += dpp_d<0x4E, 0xf>(v);      // quad_perm [2,3,0,1]
@@ -233,27 +233,27 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
   __syncthreads();
   for (int j = 0; j < n - 1; ++j) {
     const int j1 = j + 1;
-    // ---- reflector of column j (waves holding rows j1 .. n-1)
-    double2 scale = make_double2(0.0, 0.0);
-    if (wv * 64 + 63 >= 8 * j1 && wv * 64 < 8 * n) {
+    // ---- reflector of column j: threads tid in [j1, n) form and write it
+    //      (two waves at most compute the Householder scalars)
+    if (wv * 64 + 63 >= j1 && wv * 64 < n) {
       double xnorm2 = 0.0;
 #pragma unroll
       for (int i = 0; i < NW; ++i) xnorm2 += rnorm[i];
-      double2 tau;
+      double2 tau, scale;
       double beta;
       householder(L[tri(j1, j)], xnorm2, tau, scale, beta);
-      if (tid == 8 * j1) {
+      if (tid == j1) {
         s_tau = tau;
         W.d[j] = L[tri(j, j)].x;
         W.e[j] = beta;
         W.e2[j] = beta * beta;
         W.tau[j] = tau;
       }
-    }
-    if (sl == 0 && r >= j1 && r < n) {
-      const double2 v = r == j1 ? make_double2(1.0, 0.0) : cmul(L[tri(r, j)], scale);
-      V[r] = v;
-      if (r > j1) A[(long long)j * ld + r] = v;   // reflector kept for the back-transformation
+      if (tid >= j1 && tid < n) {
+        const double2 v = tid == j1 ? make_double2(1.0, 0.0) : cmul(L[tri(tid, j)], scale);
+        V[tid] = v;
+        if (tid > j1) A[(long long)j * ld + tid] = v;   // reflector kept for the back-transformation
+      }
     }
     __syncthreads();
     const double2 tau = s_tau;
@@ -261,9 +261,16 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
     {
       double2 acc = make_double2(0.0, 0.0);
       if (r >= j1 && r < n) {
-        for (int c = j1 + sl; c < n; c += 8) {
-          const double2 a = c <= r ? L[tri(r, c)] : make_double2(L[tri(c, r)].x, -L[tri(c, r)].y);
-          acc = cadd(acc, cmul(a, V[c]));
+        // stored part of row r (c <= r), then the rest of the row read as
+        // the conjugate of column r (c > r); no per-element select
+        const int rb = tri(r, 0);
+        int c = j1 + sl;
+#pragma unroll 4
+        for (; c <= r; c += 8) acc = cadd(acc, cmul(L[rb + c], V[c]));
+#pragma unroll 4
+        for (; c < n; c += 8) {
+          const double2 a = L[tri(c, r)];
+          acc = cadd(acc, cmul(make_double2(a.x, -a.y), V[c]));
         }
       }
       acc.x = seg8_sum(acc.x);
@@ -288,6 +295,7 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
     double loc = 0.0;
     if (r >= j1 && r < n) {
       const double2 vr = V[r], wr = cadd(P[r], cmul(alpha2, vr));
+#pragma unroll 2
       for (int c = j1 + sl; c <= r; c += 8) {
         const double2 vc = V[c], wc = cadd(P[c], cmul(alpha2, vc));
         double2 a = L[tri(r, c)];
