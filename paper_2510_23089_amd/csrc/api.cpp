@@ -73,10 +73,11 @@ struct Carver {
 constexpr size_t PART_BYTES = 96ull << 20;   // Gram K-split partials (all fields)
 
 int ksplit_for(int nb, ll kb, int nf) {
-  // lower-triangle tiles only; aim at about two workgroups per compute unit
+  // lower-triangle tiles only; aim at about eight workgroups per compute
+  // unit, each K chunk at least 256 deep; partials are nb x nb per chunk
   const int t = (nb + 63) / 64;
   int tiles = t * (t + 1) / 2 * std::max(nf, 1);
-  ll want = std::max<ll>(1, 512 / std::max(tiles, 1));
+  ll want = std::max<ll>(1, 2048 / std::max(tiles, 1));
   ll bykb = std::max<ll>(1, kb / 256);
   ll bymem = std::max<ll>(1, (ll)(PART_BYTES / (16ull * (size_t)nb * nb * std::max(nf, 1))));
   return (int)std::min<ll>({want, bykb, bymem, 256});
@@ -103,9 +104,10 @@ DimExpr dv(const Ctx& c, int k, const int* p0 = nullptr, const int* p1 = nullptr
 
 // Hermitian Gram matrices (one per field) into ctx.G: G = op(A) . op(B).
 // Only the tiles touching the lower triangle are computed: the eigensolver
-// references the lower triangle alone.
+// references the lower triangle alone.  K-split partials are nb x nb.
 int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb, DimExpr K, int klo, ll kb) {
-  int ks = ksplit_for(c.gld, kb, c.nf);
+  const ll ld = c.gld, gs = ld * ld;
+  const ll gsp = (ll)nb * nb;
   GemmSpec g;
   g.M = n; g.N = n; g.K = K; g.batch = dx(1);
   g.mlo = nlo; g.nlo = nlo; g.klo = klo;
@@ -113,15 +115,28 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
   g.A = A; g.B = B;
   g.types = c.gram_t;
   g.lower = 1;
+  // B = A^H over the same data: a few rows against a long K streams through
+  // the dedicated kernel instead of mostly-padding MFMA tiles
+  const bool herm = B.ptr == A.ptr && B.conj != A.conj && B.sxh == A.syh && B.sxl == A.syl && B.syh == A.sxh &&
+                    B.syl == A.sxl && B.sb == A.sb && B.sb2 == A.sb2;
+  if (herm && nb <= GRAM_SKINNY_N) {
+    ll want = std::max<ll>(1, 2048 / std::max(c.nf, 1));
+    ll byk = std::max<ll>(1, kb / 1024);
+    ll bymem = std::max<ll>(1, (ll)(PART_BYTES / (16ull * (size_t)gsp * std::max(c.nf, 1))));
+    const int ns = (int)std::min<ll>({want, byk, bymem, 4096});
+    HIPCHK(gram_skinny(g, ns, c.part, nb, c.s));
+    HIPCHK(ksplit_reduce(c.part, gsp, ns, nb, c.G, c.gld, n, n, nb, nb, (ll)ns * gsp, gs, c.nf, 1, c.s));
+    return QTT_OK;
+  }
+  int ks = ksplit_for(nb, kb, c.nf);
   // the result is a plain n x n matrix: address it through the same (hi, lo)
   // split as the M and N indices
-  const ll ld = c.gld, gs = ld * ld;
   if (ks > 1) {
-    g.C = opd(c.part, nlo * ld, ld, nlo, 1, 0, (ll)ks * gs);
+    g.C = opd(c.part, nlo * nb, nb, nlo, 1, 0, (ll)ks * gsp);
     g.ksplit = ks;
-    g.csplit = gs;
+    g.csplit = gsp;
     HIPCHK(gemm_launch(g, c.s));
-    HIPCHK(ksplit_reduce(c.part, gs, ks, c.G, c.gld, n, n, nb, nb, (ll)ks * gs, gs, c.nf, 1, c.s));
+    HIPCHK(ksplit_reduce(c.part, gsp, ks, nb, c.G, c.gld, n, n, nb, nb, (ll)ks * gsp, gs, c.nf, 1, c.s));
   } else {
     g.C = opd(c.G, nlo * ld, ld, nlo, 1, 0, gs);
     HIPCHK(gemm_launch(g, c.s));

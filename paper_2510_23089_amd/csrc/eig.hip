@@ -129,45 +129,6 @@ __device__ double2 block_sum2(double2 v, double* red) {
   return s;
 }
 
-// Cross-lane sums through DPP moves (a few cycles each) instead of LDS
-// permutes.  row16_sum: every lane gets the sum over its 16-lane row (lanes
-// of one row may differ in the last bit: the association depends on the
-// quad).  wave_sum_u: the wave's sum from rows 0..3 in a fixed order,
-// identical in every lane.  seg_sum<TPC>: sum over aligned segments of TPC
-// lanes (32 or 64), valid in the segment's last lane.
-template <int CTRL, int RM>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, 0xf, false);
-  const int h2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, 0xf, false);
-  return __hiloint2double(h2, l2);
-}
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_d<0xB1, 0xf>(v);      // quad_perm [1,0,3,2]
-  v += dpp_d<0x4E, 0xf>(v);      // quad_perm [2,3,0,1]
-  v += dpp_d<0x124, 0xf>(v);     // row_ror:4
-  v += dpp_d<0x128, 0xf>(v);     // row_ror:8
-  return v;
-}
-__device__ __forceinline__ double lane_d(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-__device__ __forceinline__ double wave_sum_u(double v) {
-  v = row16_sum(v);
-  return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
-}
-template <int TPC>
-__device__ __forceinline__ double seg_sum(double v) {
-  static_assert(TPC == 32 || TPC == 64, "segments of 32 or 64 lanes");
-  if constexpr (TPC == 64) {
-    return wave_sum_u(v);
-  } else {
-    v = row16_sum(v);
-    return v + dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
-  }
-}
-
 __device__ void householder(double2 alpha, double xnorm2, double2& tau, double2& scale, double& beta) {
   if (xnorm2 == 0.0 && alpha.y == 0.0) {
     tau = make_double2(0.0, 0.0);

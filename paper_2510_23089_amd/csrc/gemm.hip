@@ -304,24 +304,104 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
 }
 
 // Sum of K-chunk partial results: out[i][j] = sum_c part[c][i][j], i, j < n
-// (j <= i only when `lower`).
-__global__ void ksplit_reduce_kernel(const double2* __restrict__ part, long long cstride, int nsplit,
+// (j <= i only when `lower`); partials have leading dimension ldp, out ld.
+__global__ void ksplit_reduce_kernel(const double2* __restrict__ part, long long cstride, int nsplit, int ldp,
                                      double2* __restrict__ out, int ld, DimExpr nrows, DimExpr ncols,
                                      long long bstride_part, long long bstride_out, int lower) {
   const int b = blockIdx.z;
   const int nr = min(dim_eval(nrows, b), (int)gridDim.y);
   const int i = blockIdx.y;
   if (i >= nr) return;
-  const int nc = min(min(dim_eval(ncols, b), ld), lower ? i + 1 : ld);
+  const int nc = min(min(dim_eval(ncols, b), min(ld, ldp)), lower ? i + 1 : ld);
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nc; j += gridDim.x * blockDim.x) {
     double2 s = make_double2(0.0, 0.0);
-    const double2* p = part + b * bstride_part + (long long)i * ld + j;
+    const double2* p = part + b * bstride_part + (long long)i * ldp + j;
     for (int c = 0; c < nsplit; ++c) {
       double2 v = p[c * cstride];
       s.x += v.x;
       s.y += v.y;
     }
     out[b * bstride_out + (long long)i * ld + j] = s;
+  }
+}
+
+// Gram matrices of very few rows: G = X X^H (lower triangle) for an n x K
+// operand X with n <= SK_N and K large (the first encode sites: 2, 4, 8
+// rows against up to 2^21 columns).  A tile-based MFMA product would waste
+// almost all of its work on padding here, and the data is read once, so
+// this is a streaming reduction: each thread takes columns k = kbeg + t,
+// kbeg + t + 256, ... of one K chunk, accumulates the n(n+1)/2 products
+// x_i conj(x_j) in FP64 registers, and the workgroup's sums (DPP within
+// waves, LDS across them) go to its own partial n x n block; the K-chunk
+// partials are summed by ksplit_reduce.  Grid: (K chunks, 1, fields).
+constexpr int SK_N = 8;
+constexpr int SK_NT = 256;
+constexpr int SK_P = SK_N * (SK_N + 1) / 2;
+
+
+template <typename TIn>
+__global__ __launch_bounds__(SK_NT) void gram_skinny_kernel(Operand A, DimExpr Mexp, DimExpr Kexp, FastDiv fm,
+                                                            FastDiv fk, int kmax, int nsplit, double2* part,
+                                                            int ldp) {
+  typedef typename Vec2<TIn>::t in2;
+  const int f = blockIdx.z, sp = blockIdx.x;
+  const int n = min(dim_eval(Mexp, f), SK_N);
+  const int K = min(dim_eval(Kexp, f), kmax);
+  int chunk = (K + nsplit - 1) / nsplit;
+  const int kbeg = sp * chunk, kend = min(K, kbeg + chunk);
+  const TIn* Ap = (const TIn*)A.ptr + 2 * ((long long)f * A.sb);
+  long long ro[SK_N];
+#pragma unroll
+  for (int i = 0; i < SK_N; ++i) ro[i] = i < n ? split_off(fm, i, A.sxh, A.sxl) : 0;
+  double ar[SK_P], ai[SK_P];
+#pragma unroll
+  for (int q = 0; q < SK_P; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
+  const double cs = A.conj ? -1.0 : 1.0;
+  for (int k = kbeg + (int)threadIdx.x; k < kend; k += SK_NT) {
+    const long long ko = split_off(fk, k, A.syh, A.syl);
+    double xr[SK_N], xi[SK_N];
+#pragma unroll
+    for (int i = 0; i < SK_N; ++i) {
+      in2 v;
+      v.x = 0; v.y = 0;
+      if (i < n) v = *(const in2*)(Ap + 2 * (ro[i] + ko));
+      xr[i] = (double)v.x;
+      xi[i] = cs * (double)v.y;
+    }
+    int q = 0;
+#pragma unroll
+    for (int i = 0; i < SK_N; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j, ++q) {
+        // x_i conj(x_j)
+        ar[q] = fma(xr[i], xr[j], fma(xi[i], xi[j], ar[q]));
+        ai[q] = fma(xi[i], xr[j], fma(-xr[i], xi[j], ai[q]));
+      }
+  }
+  __shared__ double red[SK_NT / 64][2 * SK_P];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int q = 0;
+#pragma unroll
+  for (int i = 0; i < SK_N; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j, ++q) {
+      if (i < n) {
+        const double sr = wave_sum_u(ar[q]), si = wave_sum_u(ai[q]);
+        if (lane == 0) { red[wv][2 * q] = sr; red[wv][2 * q + 1] = si; }
+      }
+    }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < SK_P) {
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    const int j = t - i * (i + 1) / 2;
+    if (i < n) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int w = 0; w < SK_NT / 64; ++w) { sr += red[w][2 * t]; si += red[w][2 * t + 1]; }
+      part[((long long)f * nsplit + sp) * ldp * ldp + (long long)i * ldp + j] = make_double2(sr, si);
+    }
   }
 }
 
@@ -442,6 +522,22 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
                         s);
 }
 
+hipError_t gram_skinny(const GemmSpec& sp, int nsplit, double* part, int ldp, hipStream_t s) {
+  if (sp.m_bound < 1 || sp.nfield < 1 || nsplit < 1) return hipSuccess;
+  if (sp.m_bound > SK_N || ldp < sp.m_bound) return hipErrorInvalidValue;
+  const dim3 grid(nsplit, 1, sp.nfield);
+  const FastDiv fm = make_fastdiv(sp.mlo), fk = make_fastdiv(sp.klo);
+  if (sp.types == GEMM_F32_GRAM64)
+    hipLaunchKernelGGL(gram_skinny_kernel<float>, grid, dim3(SK_NT), 0, s, sp.A, sp.M, sp.K, fm, fk, sp.k_bound,
+                       nsplit, (double2*)part, ldp);
+  else if (sp.types == GEMM_F64)
+    hipLaunchKernelGGL(gram_skinny_kernel<double>, grid, dim3(SK_NT), 0, s, sp.A, sp.M, sp.K, fm, fk, sp.k_bound,
+                       nsplit, (double2*)part, ldp);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 void autotune_record(bool on) {
   g_record = on;
   if (on) g_seen.clear();
@@ -551,14 +647,14 @@ void autotune_clear() {
   g_seen.clear();
 }
 
-hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,
+hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, int ldp, void* out, int ld,
                          DimExpr nrows, DimExpr ncols, int rows_bound, int cols_bound,
                          long long bstride_part, long long bstride_out, int batch_bound, int lower,
                          hipStream_t s) {
   int bx = (cols_bound + 255) / 256;
   if (bx < 1 || rows_bound < 1 || batch_bound < 1) return hipSuccess;
   hipLaunchKernelGGL(ksplit_reduce_kernel, dim3(bx, rows_bound, batch_bound), dim3(256), 0, s,
-                     (const double2*)part, cstride, nsplit, (double2*)out, ld, nrows, ncols,
+                     (const double2*)part, cstride, nsplit, ldp, (double2*)out, ld, nrows, ncols,
                      bstride_part, bstride_out, lower);
   return hipGetLastError();
 }

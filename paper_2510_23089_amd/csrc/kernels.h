@@ -37,11 +37,17 @@ hipError_t autotune_run(void* ws, size_t ws_bytes, hipStream_t s, int* n_tuned);
 int autotune_export(int* out, int max_entries);
 int autotune_import(const int* entries, int n);
 void autotune_clear();
-// Sum K-chunk partials into out (only j <= i when lower).
-hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, void* out, int ld,
+// Sum K-chunk partials (leading dimension ldp) into out (ld; only j <= i when lower).
+hipError_t ksplit_reduce(const void* part, long long cstride, int nsplit, int ldp, void* out, int ld,
                          DimExpr nrows, DimExpr ncols, int rows_bound, int cols_bound,
                          long long bstride_part, long long bstride_out, int batch_bound, int lower,
                          hipStream_t s);
+// Lower-triangle partial Gram matrices X X^H of an operand with at most
+// GRAM_SKINNY_N rows (sp.A = X, sp.M its rows, sp.K its columns; sp.B is
+// not read): nsplit K chunks per field, partial (f, c) at
+// part + (f * nsplit + c) * ldp * ldp.  FP64 accumulation.
+constexpr int GRAM_SKINNY_N = 8;
+hipError_t gram_skinny(const GemmSpec& sp, int nsplit, double* part, int ldp, hipStream_t s);
 
 // ---------------------------------------------------------------- eigensolver
 // Batched Hermitian eigen-decomposition of FP64 Gram matrices followed by the
