@@ -145,11 +145,12 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
 }
 
 int gemm(Ctx& c, DimExpr M, int mlo, int mb, DimExpr N, int nlo, int nb, DimExpr K, int klo, const Operand& A,
-         const Operand& B, const Operand& C, DimExpr batch = dx(1), int batch_bound = 1, int accumulate = 0) {
+         const Operand& B, const Operand& C, DimExpr batch = dx(1), int batch_bound = 1, int accumulate = 0,
+         int kb = 1 << 30) {
   GemmSpec g;
   g.M = M; g.N = N; g.K = K; g.batch = batch;
   g.mlo = mlo; g.nlo = nlo; g.klo = klo;
-  g.m_bound = mb; g.n_bound = nb; g.batch_bound = batch_bound; g.nfield = c.nf;
+  g.m_bound = mb; g.n_bound = nb; g.k_bound = kb; g.batch_bound = batch_bound; g.nfield = c.nf;
   g.A = A; g.B = B; g.C = C;
   g.accumulate = accumulate;
   g.types = c.gemm_t;
@@ -1148,7 +1149,7 @@ int encode_impl(const void* img, int img_dtype, int n, const qtt_opts& o, const 
       // R_{k+1}[i][c] = sum_p conj(U[p][i]) M[p][c]
       r = gemm(c, dv(c, 1, kout), 1, rb[k + 1], dx((int)q), 1, (int)q, dv(c, 2, rk), 2,
                opd(b.V1, 1, 0, 2 * chi, chi, 1, b.sV), opd(Rcur, 2 * q, q, 1, 0, 0, b.sq),
-               opd(Rn, q, 0, 1, 0, 0, b.sq));
+               opd(Rn, q, 0, 1, 0, 0, b.sq), dx(1), 1, 0, (int)pb);
       if (r) return r;
     } else {
       int r = gram(c, opd(Rcur, 1, 0, 2 * q, q, 1, b.sq), opd(Rcur, 2 * q, q, 1, 0, 0, b.sq), dx((int)q), 1, (int)q,

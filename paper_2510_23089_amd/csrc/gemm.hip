@@ -325,6 +325,75 @@ __global__ void ksplit_reduce_kernel(const double2* __restrict__ part, long long
   }
 }
 
+// Products with at most SM_M output rows and SM_K depth (the encode's
+// projections R_{k+1} = U^H M at the first sites: 2-16 rows, 2-16 deep, up to
+// 2^21 columns per field).  MFMA tiles would be almost all padding and the
+// work is a single pass over B and C, so each thread streams whole output
+// columns: op(A) (at most 16 x 16) sits in LDS, the thread loads its column
+// of op(B) and writes its column of C.  FP32 or FP64 arithmetic as the
+// inputs (no bfloat16 rounding: only the plain precision forms come here).
+constexpr int SM_M = 16, SM_K = 16, SM_NT = 256;
+
+template <typename T>
+__global__ __launch_bounds__(SM_NT) void gemm_smallmk_kernel(GemmArgs g) {
+  typedef typename Vec2<T>::t t2;
+  const int f = blockIdx.z;
+  const int M = min(min(dim_eval(g.M, f), g.Mmax), SM_M), N = min(dim_eval(g.N, f), g.Nmax);
+  const int K = min(min(dim_eval(g.K, f), g.Kmax), SM_K);
+  __shared__ t2 As[SM_M][SM_K];
+  const T* Ap = (const T*)g.A.ptr + 2 * ((long long)f * g.A.sb);
+  const T* Bp = (const T*)g.B.ptr + 2 * ((long long)f * g.B.sb);
+  T* Cp = (T*)g.C.ptr + 2 * ((long long)f * g.C.sb);
+  for (int e = threadIdx.x; e < SM_M * SM_K; e += SM_NT) {
+    const int i = e / SM_K, p = e - i * SM_K;
+    t2 v;
+    v.x = 0; v.y = 0;
+    if (i < M && p < K) {
+      v = *(const t2*)(Ap + 2 * (split_off(g.fm, i, g.A.sxh, g.A.sxl) + split_off(g.fk, p, g.A.syh, g.A.syl)));
+      if (g.A.conj) v.y = -v.y;
+    }
+    As[i][p] = v;
+  }
+  __syncthreads();
+  long long boff[SM_K];
+#pragma unroll
+  for (int p = 0; p < SM_K; ++p) boff[p] = p < K ? split_off(g.fk, p, g.B.sxh, g.B.sxl) : 0;
+  for (int j = blockIdx.x * SM_NT + threadIdx.x; j < N; j += gridDim.x * SM_NT) {
+    const long long bc = split_off(g.fn, j, g.B.syh, g.B.syl);
+    const long long cc = split_off(g.fn, j, g.C.syh, g.C.syl);
+    t2 b[SM_K];
+#pragma unroll
+    for (int p = 0; p < SM_K; ++p) {
+      b[p].x = 0; b[p].y = 0;
+      if (p < K) {
+        b[p] = *(const t2*)(Bp + 2 * (boff[p] + bc));
+        if (g.B.conj) b[p].y = -b[p].y;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < SM_M; ++i) {
+      if (i >= M) break;
+      T re = 0, im = 0;
+#pragma unroll
+      for (int p = 0; p < SM_K; ++p) {
+        const t2 a = As[i][p];
+        re = fma(a.x, b[p].x, fma(-a.y, b[p].y, re));
+        im = fma(a.x, b[p].y, fma(a.y, b[p].x, im));
+      }
+      t2* dst = (t2*)(Cp + 2 * (split_off(g.fm, i, g.C.sxh, g.C.sxl) + cc));
+      if (g.accumulate) {
+        const t2 o = *dst;
+        re += o.x;
+        im += o.y;
+      }
+      t2 w;
+      w.x = re;
+      w.y = im;
+      *dst = w;
+    }
+  }
+}
+
 // Gram matrices of very few rows: G = X X^H (lower triangle) for an n x K
 // operand X with n <= SK_N and K large (the first encode sites: 2, 4, 8
 // rows against up to 2^21 columns).  A tile-based MFMA product would waste
@@ -512,12 +581,23 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   if (sp.m_bound < 1 || sp.n_bound < 1 || sp.batch_bound < 1 || sp.nfield < 1) return hipSuccess;
   g.Mmax = sp.m_bound; g.Nmax = sp.n_bound; g.Kmax = sp.k_bound; g.Bmax = sp.batch_bound;
   // coalescing pattern: which index is unit-stride in memory
+  if (sp.m_bound <= SM_M && sp.k_bound <= SM_K && g.ksplit == 1 && sp.batch_bound == 1 &&
+      (sp.types == GEMM_F32 || sp.types == GEMM_F64)) {
+    g.Mmax = sp.m_bound; g.Nmax = sp.n_bound; g.Kmax = sp.k_bound; g.Bmax = 1;
+    const int gx = (int)std::min<long long>(((long long)sp.n_bound + SM_NT - 1) / SM_NT, 64);
+    const dim3 grid(gx, 1, sp.nfield);
+    if (sp.types == GEMM_F32) hipLaunchKernelGGL(gemm_smallmk_kernel<float>, grid, dim3(SM_NT), 0, s, g);
+    else hipLaunchKernelGGL(gemm_smallmk_kernel<double>, grid, dim3(SM_NT), 0, s, g);
+    return hipGetLastError();
+  }
   bool akm = (sp.A.syl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.A.syh == 1);
   bool bkm = (sp.B.sxl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.B.sxh == 1);
   TileKey key = make_key(sp, akm, bkm);
   if (g_record) g_seen.insert(key);
   auto it = g_tiles.find(key);
-  const int tile = it == g_tiles.end() ? 0 : it->second;
+  // untuned default: 32-row tiles when the rows (or both sides) are that small
+  const int tile = it != g_tiles.end() ? it->second
+                                       : (sp.m_bound <= 32 ? (sp.n_bound <= 32 ? 2 : 1) : 0);
   return launch_variant(g, sp.types, akm, bkm, tile, sp.m_bound, sp.n_bound, sp.batch_bound * sp.nfield, g.ksplit,
                         s);
 }
