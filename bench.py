@@ -56,8 +56,9 @@ CHI = 128
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # Memory traffic of the dominant kernel per launch, from two rocprofv3 counter
 # passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
-# copy); valid only while eig.hip is the source the counters were taken on.
-TRAFFIC = {"eig_sha256_prefix": "dcd29ed25c6c58e7", "bytes_per_launch": (25.54 + 6.58) * 1e6}
+# copy); valid only while eig.hip and common.h are the sources the counters
+# were taken on.
+TRAFFIC = {"src_sha256_prefix": "23cf682a38bc7c95", "bytes_per_launch": (44.69 + 21.61) * 1e6}
 
 
 def parse():
@@ -266,13 +267,14 @@ def grad_step_bench(steps, dev):
 
 def _traffic():
     import hashlib
-    path = os.path.join(ROOT, "paper_2510_23089_amd", "csrc", "eig.hip")
+    h = hashlib.sha256()
     try:
-        with open(path, "rb") as fh:
-            h = hashlib.sha256(fh.read()).hexdigest()[:16]
+        for name in ("eig.hip", "common.h"):
+            with open(os.path.join(ROOT, "paper_2510_23089_amd", "csrc", name), "rb") as fh:
+                h.update(fh.read())
     except OSError:
         return None
-    return TRAFFIC["bytes_per_launch"] if h == TRAFFIC["eig_sha256_prefix"] else None
+    return TRAFFIC["bytes_per_launch"] if h.hexdigest()[:16] == TRAFFIC["src_sha256_prefix"] else None
 
 
 def main():
