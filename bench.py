@@ -56,9 +56,9 @@ CHI = 128
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # Memory traffic of the dominant kernel per launch, from two rocprofv3 counter
 # passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
-# copy); valid only while eig.hip and common.h are the sources the counters
-# were taken on.
-TRAFFIC = {"src_sha256_prefix": "23cf682a38bc7c95", "bytes_per_launch": (44.69 + 21.61) * 1e6}
+# copy); valid only while the kernel's sources (see _kernel_source_hash) are
+# the ones the counters were taken on.
+TRAFFIC = {"src_sha256_prefix": "3c2c226f7e7ed4d2", "bytes_per_launch": (44.69 + 21.61) * 1e6}
 
 
 def parse():
@@ -265,16 +265,28 @@ def grad_step_bench(steps, dev):
     }
 
 
-def _traffic():
+def _kernel_source_hash():
+    """sha256 prefix of the sources the dominant kernel is built from: the
+    shared helpers (common.h), the eigensolver's helpers and workspace layout
+    (eig.hip up to the LDS reduction) and the multi-workgroup reduction."""
     import hashlib
-    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2510_23089_amd", "csrc")
+    with open(os.path.join(csrc, "common.h"), "rb") as fh:
+        common = fh.read()
+    with open(os.path.join(csrc, "eig.hip"), "rb") as fh:
+        eig = fh.read()
+    head = eig[:eig.index(b"// (a) n <= 128")]
+    a = eig.index(b"// (c) 128 < n <= 512 when the batch fits the chip")
+    b = eig.index(b"// ------------------------------------------------------------ 2. eigenvalues")
+    return hashlib.sha256(common + head + eig[a:b]).hexdigest()[:16]
+
+
+def _traffic():
     try:
-        for name in ("eig.hip", "common.h"):
-            with open(os.path.join(ROOT, "paper_2510_23089_amd", "csrc", name), "rb") as fh:
-                h.update(fh.read())
-    except OSError:
+        h = _kernel_source_hash()
+    except (OSError, ValueError):
         return None
-    return TRAFFIC["bytes_per_launch"] if h.hexdigest()[:16] == TRAFFIC["src_sha256_prefix"] else None
+    return TRAFFIC["bytes_per_launch"] if h == TRAFFIC["src_sha256_prefix"] else None
 
 
 def main():

@@ -1052,10 +1052,16 @@ struct EmitPack {
 };
 
 constexpr int BT_NT = 256;
-constexpr int BT_PER_LANE = EIG_NMAX / 64;
+// One wave per eigenvector (every wave on a SIMD of its own: the chain of
+// reflector applications is latency-bound).  Reflector rows come straight
+// from the matrix, each loaded DEPTH applications ahead of its use through a
+// ring of register buffers.
+template <int NM>
 __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int ld, long long gstride,
                                                        DimExpr nexp, int* kin, long long kstride, void* wsbase,
                                                        int nb, int kc, EmitPack ep) {
+  constexpr int PL = NM / 64;                 // entries per lane
+  constexpr int DEPTH = NM <= 256 ? 6 : 3;    // reflector rows in flight
   const int b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
   const int k = kin[b * kstride];
@@ -1063,23 +1069,21 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
   const int lane = threadIdx.x & 63;
   const double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
-  double2 v[BT_PER_LANE];
+  double2 v[PL];
 #pragma unroll
-  for (int q = 0; q < BT_PER_LANE; ++q) {
+  for (int q = 0; q < PL; ++q) {
     int i = lane + 64 * q;
     v[q] = make_double2(i < n && t < k ? W.z[(long long)t * nb + i] : 0.0, 0.0);
   }
-  __shared__ double2 stau[EIG_NMAX];
+  __shared__ double2 stau[NM];
   for (int i = threadIdx.x; i < n - 1; i += BT_NT) stau[i] = W.tau[i];
   __syncthreads();
   if (t >= k) return;
-  // reflector j lives in row j (columns > j+1) with an implicit 1 at j+1;
-  // three rows rotate through registers, each loaded two applications
-  // before its own
-  double2 u0[BT_PER_LANE], u1[BT_PER_LANE], u2[BT_PER_LANE];
+  // reflector j lives in row j (columns > j+1) with an implicit 1 at j+1
+  double2 ub[DEPTH][PL];
   auto load_u = [&](double2* u, int j) {
 #pragma unroll
-    for (int q = 0; q < BT_PER_LANE; ++q) {
+    for (int q = 0; q < PL; ++q) {
       int i = lane + 64 * q;
       u[q] = (j >= 0 && i > j + 1 && i < n) ? A[(long long)j * ld + i] : make_double2(0.0, 0.0);
     }
@@ -1090,7 +1094,7 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
     const int j1 = j + 1;
     double dre = 0.0, dim_ = 0.0;
 #pragma unroll
-    for (int q = 0; q < BT_PER_LANE; ++q) {
+    for (int q = 0; q < PL; ++q) {
       int i = lane + 64 * q;
       if (i == j1) u[q] = make_double2(1.0, 0.0);
       double2 p = cmulc(u[q], v[q]);
@@ -1101,20 +1105,17 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
     dim_ = wave_sum_u(dim_);
     const double2 f = cmul(tau, make_double2(dre, dim_));
 #pragma unroll
-    for (int q = 0; q < BT_PER_LANE; ++q) v[q] = csub(v[q], cmul(f, u[q]));
+    for (int q = 0; q < PL; ++q) v[q] = csub(v[q], cmul(f, u[q]));
   };
-  load_u(u0, n - 2);
-  load_u(u1, n - 3);
-  load_u(u2, n - 4);
-  for (int j = n - 2; j >= 0; j -= 3) {
-    apply_u(u0, j);
-    load_u(u0, j - 3);
-    if (j - 1 < 0) break;
-    apply_u(u1, j - 1);
-    load_u(u1, j - 4);
-    if (j - 2 < 0) break;
-    apply_u(u2, j - 2);
-    load_u(u2, j - 5);
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) load_u(ub[d], n - 2 - d);
+  for (int j = n - 2; j >= 0; j -= DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      if (j - d < 0) break;
+      apply_u(ub[d], j - d);
+      load_u(ub[d], j - d - DEPTH);
+    }
   }
   const double sg = W.sig[t];
   for (int e = 0; e < ep.ne; ++e) {
@@ -1124,7 +1125,7 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
     else if (em.pow == -1) sc = sg > 0.0 ? 1.0 / sg : 0.0;
     char* base = (char*)em.ptr;
 #pragma unroll
-    for (int q = 0; q < BT_PER_LANE; ++q) {
+    for (int q = 0; q < PL; ++q) {
       int i = lane + 64 * q;
       if (i >= n) continue;
       double2 x = make_double2(v[q].x * sc, (em.conj ? -v[q].y : v[q].y) * sc);
@@ -1262,8 +1263,12 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   EmitPack ep;
   ep.ne = sp.nemit;
   for (int i = 0; i < sp.nemit && i < 3; ++i) ep.e[i] = sp.emit[i];
-  hipLaunchKernelGGL(backtr_kernel, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s, (const double2*)sp.G, sp.ld,
-                     sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep);
+  if (nb <= 256)
+    hipLaunchKernelGGL(backtr_kernel<256>, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s, (const double2*)sp.G,
+                       sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep);
+  else
+    hipLaunchKernelGGL(backtr_kernel<EIG_NMAX>, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s,
+                       (const double2*)sp.G, sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep);
   return hipGetLastError();
 }
 
