@@ -471,12 +471,18 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
                                                             void* wsbase, int nb, int kc, int* status, int* nlog) {
   constexpr int TPC = MW_NT / CB;             // threads per owned column
   constexpr int NW = MW_NT / 64;
+  // CB = 32 (n <= 256): the rank-2 update of step k is deferred into step
+  // k + 1, where it runs while the waves holding the rows form the next
+  // reflector (w kept per row, two reflector buffers); the vectors are sized
+  // for n <= 256, which leaves LDS room for them.  CB = 16 updates in place.
+  constexpr bool DEFER = CB == 32;
+  constexpr int NM = DEFER ? 256 : EIG_NMAX;
   const int g = blockIdx.x, b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
   double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 Ac[MW_LDS];              // owned columns, Ac[cl * n + r]
-  __shared__ double2 sv[EIG_NMAX], sp[EIG_NMAX], sx[EIG_NMAX];
+  __shared__ double2 svb[DEFER ? 2 : 1][NM], sp[NM], sx[NM], sw[DEFER ? NM : 1];
   __shared__ double rnorm[NW];
   __shared__ double2 rdot[NW];
   __shared__ double2 s_alpha, s_tau;
@@ -514,6 +520,8 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
     const int buf = k & 1;
     u64* xc = (u64*)W.xv + (size_t)buf * nb * 4;
     u64* xp = (u64*)W.xp + (size_t)buf * nb * 4;
+    double2* sv = svb[DEFER ? (k & 1) : 0];
+    const double2* svp = svb[DEFER ? ((k & 1) ^ 1) : 0];   // reflector of step k - 1
     // ---- A: reflector of column k, formed (identically) by the waves that
     //         hold rows k + 1 .. n - 1; the others take tau after the barrier
     double2 scale = make_double2(0.0, 0.0);
@@ -538,6 +546,20 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
       const double2 v = tid == k1 ? make_double2(1.0, 0.0) : cmul(cr, scale);
       sv[tid] = v;
       if (g == 0 && tid > k1) A[(long long)k * ld + tid] = v;   // reflector kept for the back-transformation
+    }
+    if constexpr (DEFER) {
+      // deferred rank-2 update of step k - 1 on the owned columns c >= k,
+      // rows r >= k: A -= v w^H + w v^H with v = svp, w = sw
+      const int cu = c0 + mc;
+      if (k > 0 && mc < cn && cu >= k) {
+        const double2 wc = make_double2(sw[cu].x, -sw[cu].y), vc = make_double2(svp[cu].x, -svp[cu].y);
+        for (int r = k + ((lt - k) & (TPC - 1)); r < n; r += TPC) {
+          double2 a = Ac[mc * n + r];
+          a = csub(a, cmul(svp[r], wc));
+          a = csub(a, cmul(sw[r], vc));
+          Ac[mc * n + r] = a;
+        }
+      }
     }
     __syncthreads();
     const double2 tau = s_tau;
@@ -604,7 +626,7 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
     for (int i = 0; i < NW; ++i) dot = cadd(dot, rdot[i]);
     // w = p + alpha2 v,  alpha2 = -(tau/2)(p^H v)
     const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
-    if (act) {
+    if (!DEFER && act) {
       const double2 wcc = cadd(sp[c], cmul(alpha2, sv[c]));
       const double2 wc = make_double2(wcc.x, -wcc.y), vc = make_double2(sv[c].x, -sv[c].y);
       for (int r = rbeg; r < n; r += TPC) {
@@ -622,6 +644,7 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
       const double2 wk = make_double2(wkk.x, -wkk.y), vk = make_double2(sv[k1].x, -sv[k1].y);
       const double2 vr = sv[tid];
       const double2 wr = cadd(sp[tid], cmul(alpha2, vr));
+      if constexpr (DEFER) sw[tid] = wr;
       double2 a = sx[tid];
       a = csub(a, cmul(vr, wk));
       a = csub(a, cmul(wr, vk));
@@ -785,7 +808,8 @@ __global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, dou
 
 // One lane per eigenvector; its tridiagonal LU factors (with reciprocal
 // pivots) and iterate live in LDS: VPW vectors per workgroup, 5 doubles and
-// one pivot flag per matrix row and vector.  Only a few lanes of each wave
+// one pivot flag per matrix row and vector, packed so that a factorisation
+// step stores three words (two 16-byte pairs and the flag).  Only a few lanes of each wave
 // are busy, so every instruction costs a full wave slot: the recurrences are
 // branch-free (pivot choice by selects, one reciprocal per step from
 // v_rcp_f64 and two Newton steps), carry their running values in registers
@@ -832,12 +856,12 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
   }
   __syncthreads();
   if (t >= vpw || vi >= k) return;
-  // per-lane arrays, interleaved by lane (stride vpw) to spread LDS banks
-  double* D = ivs;
-  double* DL = D + (size_t)nb * vpw;
-  double* DU = DL + (size_t)nb * vpw;
-  double* DU2 = DU + (size_t)nb * vpw;
-  double* X = DU2 + (size_t)nb * vpw;
+  // per-lane arrays, interleaved by lane (stride vpw) to spread LDS banks:
+  // F = (reciprocal pivot, multiplier), U = (first, second superdiagonal of
+  // U), X the iterate, P the row-interchange flags
+  double2* F = (double2*)ivs;
+  double2* U = F + (size_t)nb * vpw;
+  double* X = (double*)(U + (size_t)nb * vpw);
   unsigned char* P = (unsigned char*)(X + (size_t)nb * vpw);
 #define IX(i) ((i) * vpw + t)
   if (n == 1) { W.z[(long long)vi * nb] = 1.0; return; }
@@ -866,16 +890,14 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
       const double di = fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur;
       const double r = recip(piv ? dl[u] : di);
       const double f = (piv ? di : dl[u]) * r;
-      D[IX(i)] = r;
-      DL[IX(i)] = f;
-      DU[IX(i)] = piv ? dn[u] : ducur;
-      DU2[IX(i)] = piv ? en[u] : 0.0;
+      F[IX(i)] = make_double2(r, f);
+      U[IX(i)] = make_double2(piv ? dn[u] : ducur, piv ? en[u] : 0.0);
       P[IX(i)] = piv ? 1 : 0;
       dcur = fma(-f, piv ? dn[u] : ducur, piv ? ducur : dn[u]);
       ducur = piv ? -f * en[u] : en[u];
     }
   }
-  D[IX(n - 1)] = recip(fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur);
+  F[IX(n - 1)] = make_double2(recip(fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur), 0.0);
   unsigned long long st = 0x9E3779B97F4A7C15ull ^ ((unsigned long long)(vi + 1) * 0xD1B54A32D192ED03ull) ^
                           ((unsigned long long)(b + 1) * 0x94D049BB133111EBull);
   double sc = 1.0;                            // scale of the stored iterate
@@ -896,7 +918,7 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
       for (int u = 0; u < IV_B; ++u) {
         const int i = min(i0 + u, n - 2);
         xn[u] = it == 0 ? 0.0 : X[IX(i + 1)] * sc;
-        dl[u] = DL[IX(i)];
+        dl[u] = F[IX(i)].y;
         pv[u] = P[IX(i)];
       }
 #pragma unroll
@@ -911,9 +933,9 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
     }
     X[IX(n - 1)] = xcur;
     // backward: U x = y
-    double x2 = xcur * D[IX(n - 1)];
+    double x2 = xcur * F[IX(n - 1)].x;
     X[IX(n - 1)] = x2;
-    double x1 = (X[IX(n - 2)] - DU[IX(n - 2)] * x2) * D[IX(n - 2)];
+    double x1 = (X[IX(n - 2)] - U[IX(n - 2)].x * x2) * F[IX(n - 2)].x;
     X[IX(n - 2)] = x1;
     double mx = fmax(fabs(x1), fabs(x2));
     ss = x1 * x1 + x2 * x2;
@@ -923,9 +945,10 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
       for (int u = 0; u < IV_B; ++u) {
         const int i = max(i0 - u, 0);
         xv[u] = X[IX(i)];
-        du[u] = DU[IX(i)];
-        du2[u] = DU2[IX(i)];
-        dd[u] = D[IX(i)];
+        const double2 uu = U[IX(i)];
+        du[u] = uu.x;
+        du2[u] = uu.y;
+        dd[u] = F[IX(i)].x;
       }
 #pragma unroll
       for (int u = 0; u < IV_B; ++u) {
