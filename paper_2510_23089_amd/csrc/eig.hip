@@ -147,10 +147,12 @@ __device__ void householder(double2 alpha, double xnorm2, double2& tau, double2&
 // (a) n <= 128: the packed lower triangle (n(n+1)/2 complex doubles, <= 132 KB)
 //     lives in LDS for the whole reduction; 1024 threads, 8 per row (row
 //     r = tid / 8) for the matrix-vector product and the rank-2 update.
-//     Lane 0 of row r updates the entry of the next column in that row and
-//     forms the partial sums of its norm, the (at most two) waves whose
-//     thread indices cover rows j + 1 .. n - 1 form the reflector
-//     redundantly, and the cross-lane sums use DPP: three barriers per step.
+//     Thread r updates the entry of the next column in row r and forms the
+//     partial sums of its norm; the rest of the rank-2 update is deferred
+//     into the next step, where it runs while the (at most two) waves whose
+//     thread indices cover rows j + 1 .. n - 1 form the reflector (two
+//     reflector buffers, w kept per row).  Cross-lane sums use DPP; three
+//     barriers per step.
 __device__ __forceinline__ double seg8_sum(double v) {   // valid in lanes 4..7 of each 8
   v += dpp_d<0xB1, 0xf>(v);      // quad_perm [1,0,3,2]
   v += dpp_d<0x4E, 0xf>(v);      // quad_perm [2,3,0,1]
@@ -166,7 +168,7 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
   double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 L[TL_TRI];
-  __shared__ double2 V[TL_NMAX], P[TL_NMAX];
+  __shared__ double2 Vb[2][TL_NMAX], P[TL_NMAX], Wv[TL_NMAX];
   __shared__ double rnorm[NW];
   __shared__ double2 rdot[NW];
   __shared__ double2 s_tau;
@@ -194,6 +196,8 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
   __syncthreads();
   for (int j = 0; j < n - 1; ++j) {
     const int j1 = j + 1;
+    double2* V = Vb[j & 1];
+    const double2* Vp = Vb[(j & 1) ^ 1];      // reflector of step j - 1
     // ---- reflector of column j: threads tid in [j1, n) form and write it
     //      (two waves at most compute the Householder scalars)
     if (wv * 64 + 63 >= j1 && wv * 64 < n) {
@@ -214,6 +218,20 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
         const double2 v = tid == j1 ? make_double2(1.0, 0.0) : cmul(L[tri(tid, j)], scale);
         V[tid] = v;
         if (tid > j1) A[(long long)j * ld + tid] = v;   // reflector kept for the back-transformation
+      }
+    }
+    // deferred rank-2 update of step j - 1 on columns c > j (column j was
+    // updated at the end of step j - 1), rows r >= c: A -= v w^H + w v^H
+    // with v = Vp, w = Wv; runs while the reflector above is formed
+    if (j > 0 && r >= j1 && r < n) {
+      const double2 vr = Vp[r], wr = Wv[r];
+#pragma unroll 2
+      for (int c = j1 + sl; c <= r; c += 8) {
+        const double2 vc = Vp[c], wc = Wv[c];
+        double2 a = L[tri(r, c)];
+        a = csub(a, cmul(vr, make_double2(wc.x, -wc.y)));
+        a = csub(a, cmul(wr, make_double2(vc.x, -vc.y)));
+        L[tri(r, c)] = a;
       }
     }
     __syncthreads();
@@ -247,24 +265,23 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
       if (lane == 0) rdot[wv] = dl;
     }
     __syncthreads();
-    // ---- rank-2 update of the lower trailing triangle: A -= v w^H + w v^H,
-    //      w = p + alpha2 v, alpha2 = -(tau/2)(p^H v)
+    // ---- w = p + alpha2 v, alpha2 = -(tau/2)(p^H v), kept per row for the
+    //      deferred update; column j1 is updated now (the next reflector
+    //      needs it), with the partial sums of its norm below row j1 + 1
     double2 dot = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i < NW; ++i) dot = cadd(dot, rdot[i]);
     const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
     double loc = 0.0;
-    if (r >= j1 && r < n) {
-      const double2 vr = V[r], wr = cadd(P[r], cmul(alpha2, vr));
-#pragma unroll 2
-      for (int c = j1 + sl; c <= r; c += 8) {
-        const double2 vc = V[c], wc = cadd(P[c], cmul(alpha2, vc));
-        double2 a = L[tri(r, c)];
-        a = csub(a, cmul(vr, make_double2(wc.x, -wc.y)));
-        a = csub(a, cmul(wr, make_double2(vc.x, -vc.y)));
-        L[tri(r, c)] = a;
-        if (c == j1 && r >= j1 + 2) loc = a.x * a.x + a.y * a.y;
-      }
+    if (tid >= j1 && tid < n) {
+      const double2 vr = V[tid], wr = cadd(P[tid], cmul(alpha2, vr));
+      Wv[tid] = wr;
+      const double2 wk = cadd(P[j1], cmul(alpha2, V[j1])), vk = V[j1];
+      double2 a = L[tri(tid, j1)];
+      a = csub(a, cmul(vr, make_double2(wk.x, -wk.y)));
+      a = csub(a, cmul(wr, make_double2(vk.x, -vk.y)));
+      L[tri(tid, j1)] = a;
+      if (tid >= j1 + 2) loc = a.x * a.x + a.y * a.y;
     }
     loc = wave_sum_u(loc);
     if (lane == 0) rnorm[wv] = loc;
