@@ -74,11 +74,11 @@ constexpr size_t PART_BYTES = 96ull << 20;   // Gram K-split partials (all field
 
 int ksplit_for(int nb, ll kb, int nf) {
   // lower-triangle tiles only; aim at about eight workgroups per compute
-  // unit, each K chunk at least 256 deep; partials are nb x nb per chunk
+  // unit, each K chunk at least 64 deep; partials are nb x nb per chunk
   const int t = (nb + 63) / 64;
   int tiles = t * (t + 1) / 2 * std::max(nf, 1);
   ll want = std::max<ll>(1, 2048 / std::max(tiles, 1));
-  ll bykb = std::max<ll>(1, kb / 256);
+  ll bykb = std::max<ll>(1, kb / 64);
   ll bymem = std::max<ll>(1, (ll)(PART_BYTES / (16ull * (size_t)nb * nb * std::max(nf, 1))));
   return (int)std::min<ll>({want, bykb, bymem, 256});
 }
