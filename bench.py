@@ -58,7 +58,7 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
 # copy); valid only while the kernel's sources (see _kernel_source_hash) are
 # the ones the counters were taken on.
-TRAFFIC = {"src_sha256_prefix": "3c2c226f7e7ed4d2", "bytes_per_launch": (44.69 + 21.61) * 1e6}
+TRAFFIC = {"src_sha256_prefix": "feaed273cebd8fb7", "bytes_per_launch": (44.68 + 21.61) * 1e6}
 
 
 def parse():
