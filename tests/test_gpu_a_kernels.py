@@ -75,7 +75,7 @@ def _rand_herm(rng, n, spectrum=None):
     return (q * spectrum) @ q.conj().T
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 33, 64, 100, 128, 200, 256])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 33, 64, 100, 128, 129, 200, 256, 300, 512])
 def test_heev_random(n):
     torch = need_gpu()
     L, lib = _lib()
@@ -104,6 +104,41 @@ def test_heev_random(n):
         # eigen-equation residual
         res = mats[b] @ u - u * ev[b, :k]
         assert np.max(np.abs(res)) < 1e-10 * abs(w[0])
+
+
+def _check_heev(mats, kept, ev, vec, kcap):
+    for b in range(mats.shape[0]):
+        w, v = np.linalg.eigh(mats[b])
+        w = w[::-1]
+        k = int(kept[b])
+        assert k == min(mats.shape[1], kcap)
+        assert np.max(np.abs(ev[b, :k] - w[:k])) < 1e-12 * abs(w[0])
+        u = vec[b, :, :k]
+        e = np.abs(u.conj().T @ u - np.eye(k))
+        wgt = np.sqrt(np.outer(ev[b, :k], ev[b, :k])) / abs(w[0])
+        assert np.max(e * wgt) < 1e-12
+        assert np.max(np.abs(mats[b] @ u - u * ev[b, :k])) < 1e-10 * abs(w[0])
+
+
+@pytest.mark.parametrize("n,batch", [(64, 2), (200, 2), (300, 2), (200, 40)])
+def test_heev_reads_lower_triangle_only(n, batch):
+    """Every reduction form (LDS n <= 128, multi-workgroup, and the streaming
+    one that 40 matrices of n = 200 force: 40 x 7 workgroups exceed the
+    chip) must reference only the lower triangle: garbage above the diagonal
+    changes nothing."""
+    torch = need_gpu()
+    L, lib = _lib()
+    say("heev lower", n, batch)
+    rng = np.random.default_rng(1000 + n + batch)
+    mats = np.stack([_rand_herm(rng, n, np.sort(10.0 ** rng.uniform(-6, 1, n))[::-1]) for _ in range(batch)])
+    dirty = mats.copy()
+    iu = np.triu_indices(n, 1)
+    for b in range(batch):
+        dirty[b][iu] = rng.standard_normal(len(iu[0])) * 1e3 + 1j * rng.standard_normal(len(iu[0]))
+    kcap = min(n, 64)
+    kept, ev, vec, st = _heev(torch, L, lib, dirty, kcap)
+    assert st == 0
+    _check_heev(mats, kept, ev, vec, kcap)
 
 
 def test_heev_keep_rule_and_degenerate():
