@@ -99,8 +99,12 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
     kend = min(K, kbeg + chunk);
   }
 
-  __shared__ TC As[2 * BKC][BM + PADA];
-  __shared__ TC Bs[BKC][2 * BN + PADB];
+  // FP32 operands: two LDS buffers (one barrier per stage, the next stage
+  // stored while this one's products run); FP64 keeps one (occupancy)
+  constexpr int NBUF = sizeof(TC) == 4 ? 2 : 1;
+  __shared__ TC Asb[NBUF][2 * BKC][BM + PADA];
+  __shared__ TC Bsb[NBUF][BKC][2 * BN + PADB];
+  int cur = 0;
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -154,7 +158,9 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
       rb[r] = v;
     }
   };
-  auto store_stage = [&]() {
+  auto store_stage = [&](int bi) {
+    TC (*As)[BM + PADA] = Asb[bi];
+    TC (*Bs)[2 * BN + PADB] = Bsb[bi];
 #pragma unroll
     for (int r = 0; r < A_PER_T; ++r) {
       TC re = (TC)ra[r].x, im = (TC)ra[r].y;
@@ -187,11 +193,20 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
 
   if (kbeg < kend) {
     load_stage(kbeg);
+    if constexpr (NBUF == 2) {
+      store_stage(0);
+      __syncthreads();
+    }
     for (int k0 = kbeg; k0 < kend; k0 += BKC) {
-      __syncthreads();
-      store_stage();
-      __syncthreads();
-      if (k0 + BKC < kend) load_stage(k0 + BKC);
+      if constexpr (NBUF == 1) {
+        __syncthreads();
+        store_stage(0);
+        __syncthreads();
+      }
+      const bool more = k0 + BKC < kend;
+      if (more) load_stage(k0 + BKC);
+      TC (*As)[BM + PADA] = Asb[cur];
+      TC (*Bs)[2 * BN + PADB] = Bsb[cur];
       if constexpr (BF != 0) {
         // 16 real k per MFMA: lane group lq supplies real k = 16 ks + 4 lq + v
 #pragma unroll
@@ -245,8 +260,7 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
             for (int j = 0; j < NJ; ++j)
               acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
-        continue;
-      }
+      } else {
 #pragma unroll
       for (int ks = 0; ks < BKC / 2; ++ks) {
         TC af[MI], bf[NJ];
@@ -263,6 +277,12 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<TC>::op(af[i], bf[j], acc[i][j]);
+      }
+      }
+      if constexpr (NBUF == 2) {
+        if (more) store_stage(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
       }
     }
   }
