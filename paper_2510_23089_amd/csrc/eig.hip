@@ -13,6 +13,10 @@
 //                the batch fits the chip; otherwise one workgroup per matrix
 //                streaming the trailing matrix from L2 once per step (the
 //                rank-2 update of step j fused with the product of step j+1).
+//                Both stop once the trailing matrix is 128 wide and hand its
+//                lower triangle to the LDS-resident kernel, which takes the
+//                last 128 steps (where the multi-workgroup exchange and the
+//                streaming passes cost several times more per step).
 //                Only the lower triangle of G is referenced (the streaming
 //                form first completes the matrix from it); reflectors are
 //                kept in the upper triangle.
@@ -163,10 +167,19 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
                                                             void* wsbase, int nb, int kc, int* nlog) {
   constexpr int NW = TL_NT / 64;
   const int b = blockIdx.x;
-  const int n = min(dim_eval(nexp, b), min(nb, TL_NMAX));
+  // the trailing block [k0, nf): the whole matrix when nf <= 128, otherwise
+  // the last 128 rows and columns, which the multi-workgroup reduction (c)
+  // leaves updated in the lower triangle after its first nf - 128 steps
+  const int nf = min(dim_eval(nexp, b), nb);
+  const int k0 = max(nf - TL_NMAX, 0);
+  const int n = nf - k0;
   if (nlog && threadIdx.x == 0) nlog[b] = n;
-  double2* A = Gall + (long long)b * gstride;
+  double2* A = Gall + (long long)b * gstride + (long long)k0 * ld + k0;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
+  W.d += k0;
+  W.e += k0;
+  W.e2 += k0;
+  W.tau += k0;
   __shared__ double2 L[TL_TRI];
   __shared__ double2 Vb[2][TL_NMAX], P[TL_NMAX], Wv[TL_NMAX];
   __shared__ double rnorm[NW];
@@ -302,6 +315,9 @@ __global__ __launch_bounds__(TS_NT) void tridiag_kernel(double2* Gall, int ld, l
   const int b = blockIdx.x;
   const int n = min(dim_eval(nexp, b), nb);
   if (nlog && threadIdx.x == 0) nlog[b] = n;
+  // steps 0 .. kstop - 1 here; the last 128 columns go to the LDS kernel
+  const int kstop = n - min(n, TL_NMAX);
+  if (kstop == 0) return;
   double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 vp[EIG_NMAX], wp[EIG_NMAX], vn[EIG_NMAX], pn[EIG_NMAX];
@@ -311,7 +327,7 @@ __global__ __launch_bounds__(TS_NT) void tridiag_kernel(double2* Gall, int ld, l
   const int tid = threadIdx.x;
   const int cl = tid % TS_COLS, q = tid / TS_COLS;
   bool pending = false;
-  for (int j = 0; j < n - 1; ++j) {
+  for (int j = 0; j < kstop; ++j) {
     const int j1 = j + 1;
     const int np = n - j1;
     // (a) finish row j with the pending rank-2 update of step j-1
@@ -399,15 +415,19 @@ __global__ __launch_bounds__(TS_NT) void tridiag_kernel(double2* Gall, int ld, l
     pending = (tau.x != 0.0 || tau.y != 0.0);
     __syncthreads();
   }
-  if (tid == 0 && n >= 1) {
-    double2 a = A[(long long)(n - 1) * ld + (n - 1)];
-    if (pending && n >= 2) {
-      double2 t1 = cmul(vp[n - 1], make_double2(wp[n - 1].x, -wp[n - 1].y));
-      double2 t2 = cmul(wp[n - 1], make_double2(vp[n - 1].x, -vp[n - 1].y));
-      a = csub(csub(a, t1), t2);
+  // hand-off: the lower triangle of the trailing block (rows and columns
+  // >= kstop), with the update still pending from the last step
+  const int m = n - kstop;
+  if (pending)
+    for (int e = tid; e < m * m; e += TS_NT) {
+      const int r = kstop + e / m, c = kstop + e % m;
+      if (c <= r) {
+        double2 a = A[(long long)r * ld + c];
+        a = csub(a, cmul(vp[r], make_double2(wp[c].x, -wp[c].y)));
+        a = csub(a, cmul(wp[r], make_double2(vp[c].x, -vp[c].y)));
+        A[(long long)r * ld + c] = a;
+      }
     }
-    W.d[n - 1] = a.x;
-  }
 }
 
 // (c) 128 < n <= 512 when the batch fits the chip: the matrix is split by
@@ -496,6 +516,10 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
   constexpr int NM = DEFER ? 256 : EIG_NMAX;
   const int g = blockIdx.x, b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
+  // steps 0 .. kstop - 1 here; the last 128 columns go to the LDS kernel
+  const int kstop = n - min(n, TL_NMAX);
+  if (nlog && g == 0 && threadIdx.x == 0) nlog[b] = n;
+  if (kstop == 0) return;                     // whole matrix fits the LDS kernel
   double2* A = Gall + (long long)b * gstride;
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double2 Ac[MW_LDS];              // owned columns, Ac[cl * n + r]
@@ -508,7 +532,6 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
   const int c0 = g * CB;
   const int cn = max(0, min(CB, n - c0));
   const int mc = tid / TPC, lt = tid - (tid / TPC) * TPC;
-  if (nlog && g == 0 && tid == 0) nlog[b] = n;
   if (tid == 0) s_bad = 0;
   // owned columns from the lower triangle only: workgroup 0 writes the
   // reflectors into the upper triangle while others may still be loading
@@ -532,7 +555,7 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
     if (tid == 1) s_alpha = cr;
   }
   __syncthreads();
-  for (int k = 0; k < n - 1; ++k) {
+  for (int k = 0; k < kstop; ++k) {
     const int k1 = k + 1;
     const int buf = k & 1;
     u64* xc = (u64*)W.xv + (size_t)buf * nb * 4;
@@ -673,7 +696,26 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
     if (lane == 0) rnorm[wv] = loc;
     __syncthreads();
   }
-  if (n >= 1 && g == 0 && tid == n - 1) W.d[n - 1] = cr.x;
+  // hand-off: the trailing block (rows and columns >= kstop) goes back to
+  // the lower triangle of A, after the update still deferred from the last step
+  if constexpr (DEFER) {
+    const int cu = c0 + mc;
+    if (mc < cn && cu >= kstop) {
+      const double2* svp = svb[(kstop & 1) ^ 1];
+      const double2 wc = make_double2(sw[cu].x, -sw[cu].y), vc = make_double2(svp[cu].x, -svp[cu].y);
+      for (int r = kstop + ((lt - kstop) & (TPC - 1)); r < n; r += TPC) {
+        double2 a = Ac[mc * n + r];
+        a = csub(a, cmul(svp[r], wc));
+        a = csub(a, cmul(sw[r], vc));
+        Ac[mc * n + r] = a;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * CB; e += MW_NT) {
+    const int r = e / CB, cl = e - r * CB, c = c0 + cl;
+    if (cl < cn && c >= kstop && r >= c) A[(long long)r * ld + c] = Ac[cl * n + r];
+  }
 }
 
 // ------------------------------------------------------------ 2. eigenvalues
@@ -1286,6 +1328,10 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
     g_prof.launches++;
     g_prof.slot += sp.batch;
   }
+  // the last 128 steps of the reductions (c) and (b), on one workgroup
+  if (nb > TL_NMAX)
+    hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
+                       sp.n, sp.ws, nb, kc, (int*)nullptr);
   hipLaunchKernelGGL(eigvals_kernel, dim3((kc + 3) / 4, sp.batch), dim3(EV_NT), 0, s, sp.n, kc, sp.ws, nb, kc,
                      sp.kcap_dev);
   hipLaunchKernelGGL(keep_kernel, dim3(sp.batch), dim3(KP_NT), 0, s, sp.n, kc, sp.cutoff, tau, sp.kout,
