@@ -7,8 +7,11 @@ pixel 1 um) propagates it to z = 0.5, 2 and 8 mm -- each propagation is a
 zip-up + truncation sweep for the x axis then the y axis at chi 128, the three
 distances advancing as one batch -- and each result is decompressed to the
 1024 x 1024 grid.  value = propagations / s over the whole step (encode and
-decompression included).  Inputs are resident in HBM before the timed region;
-the host float64 MPO construction is setup.
+decompression included).  Steps are software-pipelined over two streams: the
+encode of step k + 1 (a sequential chain of 19 single-field truncations)
+runs beside the propagation of step k, which leaves most compute units idle;
+serial_ms_per_step times the same steps on one stream.  Inputs are resident
+in HBM before the timed region; the host float64 MPO construction is setup.
 
 The dominant kernel (qtt::tridiag_mwg_kernel<32>, the Householder
 tridiagonalisation of the FP64 Gram matrices larger than 128, split over
@@ -309,23 +312,58 @@ def main():
     m = 2 * N_LOG2
     chi = a.chi
     nz = len(ZS)
-    psi = api.MPS(m, chi, device=dev)
+    psis = [api.MPS(m, chi, device=dev), api.MPS(m, chi, device=dev)]
     batch_in = api.MPSBatch(nz, m, chi, device=dev)
     mid = api.MPSBatch(nz, m, chi, device=dev)
     out = api.MPSBatch(nz, m, chi, device=dev)
     dens = torch.empty((nz, 1 << N_LOG2, 1 << N_LOG2), dtype=torch.complex64, device=dev)
+    main_s = torch.cuda.current_stream(dev)
+    side = torch.cuda.Stream(device=dev)          # default priority
 
-    def step():
-        # encode once, propagate the three distances as one batch, decompress all
-        api.tt_encode(d_field, chi, out=psi)
-        batch_in.fill_from(psi)
-        prop(batch_in, chi, tmp=mid, out=out)
-        api.tt_to_dense_batched(out, out=dens)
+    def run(steps, pipelined):
+        """`steps` steps, each: encode the field, propagate the three distances
+        as one batch, decompress all three.  Pipelined: the encode of step
+        k + 1 runs on a second stream while step k propagates (its input MPS
+        double-buffered); every step still performs all of its work."""
+        if not pipelined:
+            for _ in range(steps):
+                api.tt_encode(d_field, chi, out=psis[0])
+                batch_in.fill_from(psis[0])
+                prop(batch_in, chi, tmp=mid, out=out)
+                api.tt_to_dense_batched(out, out=dens)
+            return
+        ev_enc = [torch.cuda.Event(), torch.cuda.Event()]
+        ev_fill = torch.cuda.Event()
+        side.wait_stream(main_s)
+        with torch.cuda.stream(side):
+            api.tt_encode(d_field, chi, out=psis[0], ws_key="side")
+            ev_enc[0].record(side)
+        for k in range(steps):
+            main_s.wait_event(ev_enc[k & 1])
+            batch_in.fill_from(psis[k & 1])
+            ev_fill.record(main_s)
+            if k + 1 < steps:
+                side.wait_event(ev_fill)
+                with torch.cuda.stream(side):
+                    api.tt_encode(d_field, chi, out=psis[(k + 1) & 1], ws_key="side")
+                    ev_enc[(k + 1) & 1].record(side)
+            prop(batch_in, chi, tmp=mid, out=out)
+            api.tt_to_dense_batched(out, out=dens)
+        main_s.wait_stream(side)
 
-    for _ in range(a.warmup):
-        step()
+    run(1, False)
+    run(max(a.warmup, 1), True)
     api.check_status()
+    api.check_status("side")
     torch.cuda.synchronize()
+    # serial reference (same work, one stream), outside the profiled region
+    ev_s0 = torch.cuda.Event(enable_timing=True)
+    ev_s1 = torch.cuda.Event(enable_timing=True)
+    ev_s0.record()
+    run(a.steps, False)
+    ev_s1.record()
+    torch.cuda.synchronize()
+    serial_ms = ev_s0.elapsed_time(ev_s1) / a.steps
 
     lib = L.load()
     max_launch = 400 * a.steps
@@ -335,8 +373,7 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    for _ in range(a.steps):
-        step()
+    run(a.steps, True)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -344,6 +381,7 @@ def main():
     launches, entries, kms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     L.check(lib.tt_prof_end(ctypes.byref(launches), ctypes.byref(entries), ctypes.byref(kms)), "tt_prof_end")
     api.check_status()
+    api.check_status("side")
     ns = nlog[:entries.value].cpu().numpy().astype(np.float64)
     # the kernel takes the steps while the trailing matrix is wider than 128
     # (n - 128 of them); the LDS-resident kernel finishes the last 128
@@ -369,7 +407,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "single 1024x1024 complex64 field, z in {0.5, 2, 8} mm, chi 128; "
                                "encode + 3 propagations + 3 decompressions per step",
-                   "global_batch": 1, "chi": chi, "sites": m},
+                   "global_batch": 1, "chi": chi, "sites": m,
+                   "schedule": "encode of step k+1 on a second stream during the propagation of step k"},
+        "serial_ms_per_step": serial_ms,
         "roofline": {
             "kernel": "qtt::tridiag_mwg_kernel<32> (Householder reduction over 8 LDS-resident workgroups, "
                       "steps while the trailing matrix is wider than 128, "

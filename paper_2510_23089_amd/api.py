@@ -163,8 +163,10 @@ def check_status(key="default"):
 
 
 # ------------------------------------------------------------------ entry points
-def tt_encode(img, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None):
-    """Encode a square 2^n x 2^n device tensor (float32/64, complex64/128)."""
+def tt_encode(img, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None, ws_key="default"):
+    """Encode a square 2^n x 2^n device tensor (float32/64, complex64/128).
+    ws_key names the cached workspace (and its status word): calls that may
+    run concurrently on different streams need different keys."""
     lib = L.load()
     assert img.is_cuda and img.dim() == 2 and img.shape[0] == img.shape[1]
     n = int(img.shape[0]).bit_length() - 1
@@ -178,7 +180,7 @@ def tt_encode(img, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None
         out = MPS(m, chi_cap or chi, dtype=_ctype(prec), device=img.device)
     o = _opts(chi, 0, cutoff, tau, prec)
     nb = lib.tt_workspace_size(L.OP_ENCODE, m, int(chi), 1, o.prec)
-    ws = workspace(nb, img.device)
+    ws = workspace(nb, img.device, key=ws_key)
     s = out.cstruct()
     L.check(lib.tt_encode(_ptr(img), dt, n, ctypes.byref(o), ctypes.byref(s), _ptr(ws), nb, _stream()), "tt_encode")
     return out
