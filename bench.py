@@ -13,12 +13,12 @@ runs beside the propagation of step k, which leaves most compute units idle;
 serial_ms_per_step times the same steps on one stream.  Inputs are resident
 in HBM before the timed region; the host float64 MPO construction is setup.
 
-The dominant kernel (qtt::tridiag_mwg_kernel<32>, the Householder
-tridiagonalisation of the FP64 Gram matrices larger than 128, split over
-eight LDS-resident workgroups per matrix) is timed live with HIP events
-around each of its launches during the timed steps, and reports the
-algorithmic FP64 work (16/3) n^3 of each launch from the matrix sizes the
-kernel logs on the device.
+The dominant kernel (qtt::tridiag_lds_kernel, the Householder
+tridiagonalisation of the FP64 Gram matrices up to 128 and of the trailing
+128 x 128 block of wider ones, one workgroup per matrix with the packed
+triangle in LDS) is timed live with HIP events around each of its launches
+during the timed steps, and reports the algorithmic FP64 work (16/3) n^3 of
+each launch from the matrix or block sizes the kernel logs on the device.
 
 cpu_baseline: the float64 oracle (numpy/LAPACK) on the host, on a bounded
 sample of the same workload: encode + one propagation (x then y) at z = 2 mm.
@@ -61,7 +61,7 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
 # copy); valid only while the kernel's sources (see _kernel_source_hash) are
 # the ones the counters were taken on.
-TRAFFIC = {"src_sha256_prefix": "feaed273cebd8fb7", "bytes_per_launch": (44.68 + 21.61) * 1e6}
+TRAFFIC = {"src_sha256_prefix": "556fa2fe61ca4089", "bytes_per_launch": (99.95 * 2.0 + 151.66) * 1024.0}
 
 
 def parse():
@@ -271,17 +271,15 @@ def grad_step_bench(steps, dev):
 def _kernel_source_hash():
     """sha256 prefix of the sources the dominant kernel is built from: the
     shared helpers (common.h), the eigensolver's helpers and workspace layout
-    (eig.hip up to the LDS reduction) and the multi-workgroup reduction."""
+    (eig.hip up to the LDS reduction) and the LDS reduction itself."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_2510_23089_amd", "csrc")
     with open(os.path.join(csrc, "common.h"), "rb") as fh:
         common = fh.read()
     with open(os.path.join(csrc, "eig.hip"), "rb") as fh:
         eig = fh.read()
-    head = eig[:eig.index(b"// (a) n <= 128")]
-    a = eig.index(b"// (c) 128 < n <= 512 when the batch fits the chip")
-    b = eig.index(b"// ------------------------------------------------------------ 2. eigenvalues")
-    return hashlib.sha256(common + head + eig[a:b]).hexdigest()[:16]
+    b = eig.index(b"// (b) 128 < n <= 512: the full matrix is streamed")
+    return hashlib.sha256(common + eig[:b]).hexdigest()[:16]
 
 
 def _traffic():
@@ -368,7 +366,7 @@ def main():
     lib = L.load()
     max_launch = 400 * a.steps
     nlog = torch.zeros(max_launch * 8, dtype=torch.int32, device=dev)
-    L.check(lib.tt_prof_begin(1, ctypes.c_void_p(nlog.data_ptr()), nlog.numel(), max_launch), "tt_prof_begin")
+    L.check(lib.tt_prof_begin(2, ctypes.c_void_p(nlog.data_ptr()), nlog.numel(), max_launch), "tt_prof_begin")
     t0 = time.perf_counter()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -383,10 +381,9 @@ def main():
     api.check_status()
     api.check_status("side")
     ns = nlog[:entries.value].cpu().numpy().astype(np.float64)
-    # the kernel takes the steps while the trailing matrix is wider than 128
-    # (n - 128 of them); the LDS-resident kernel finishes the last 128
-    tail = np.minimum(ns, 128.0)
-    flops = float(np.sum(16.0 / 3.0 * (ns ** 3 - tail ** 3)))
+    # n = the matrix (n <= 128) or trailing block (the last 128 steps of a
+    # wider matrix) each launch reduces, logged by the kernel
+    flops = float(np.sum(16.0 / 3.0 * ns ** 3))
     nl = max(launches.value, 1)
     avg_launch_s = kms.value / 1e3 / nl
     achieved = flops / nl / avg_launch_s / 1e12 if launches.value else 0.0
@@ -411,9 +408,9 @@ def main():
                    "schedule": "encode of step k+1 on a second stream during the propagation of step k"},
         "serial_ms_per_step": serial_ms,
         "roofline": {
-            "kernel": "qtt::tridiag_mwg_kernel<32> (Householder reduction over 8 LDS-resident workgroups, "
-                      "steps while the trailing matrix is wider than 128, "
-                      "FP64 Gram eigensolver, 128 < n <= 256)",
+            "kernel": "qtt::tridiag_lds_kernel (Householder reduction to tridiagonal form, FP64 Gram "
+                      "eigensolver, one workgroup per matrix with its packed lower triangle in LDS: "
+                      "matrices up to 128 and the last 128 steps of wider ones)",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
@@ -424,7 +421,8 @@ def main():
             "launches": launches.value,
             "avg_launch_ms": avg_launch_s * 1e3,
             "kernel_share_of_step": kms.value / (ms * a.steps),
-            "work_per_launch": "(16/3) (n^3 - 128^3) FP64 flops per Gram matrix, n logged by the kernel",
+            "work_per_launch": "(16/3) n^3 FP64 flops per matrix or trailing block of size n <= 128, "
+                               "n logged by the kernel",
         },
         "wall_s": wall,
     }

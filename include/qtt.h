@@ -301,10 +301,13 @@ int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int*
 
 /* ---- diagnostics: per-launch timing of one kernel class ----
  * tt_prof_begin(what, nlog, max_entries, max_launches): from now on, every
- * launch of kernel class `what` (1 = the streaming Householder
- * tridiagonalisation used for Gram matrices larger than 128, 2 = the
- * LDS-resident one used up to 128) is bracketed by HIP events on its stream and writes its
- * actual matrix size n to the device int array nlog (one entry per matrix).
+ * launch of kernel class `what` (1 = the multi-workgroup or streaming
+ * Householder tridiagonalisation of Gram matrices larger than 128, which
+ * takes their first n - 128 steps; 2 = the LDS-resident one, which reduces
+ * matrices up to 128 and the trailing 128 x 128 block of larger ones) is
+ * bracketed by HIP events on its stream and writes the size n of the matrix
+ * (class 1) or of the block it reduces (class 2) to the device int array
+ * nlog (one entry per matrix).
  * tt_prof_end(launches, entries, total_ms): synchronise, return the number of
  * launches, of nlog entries written, and the summed event time in ms; stops
  * recording.  Not thread-safe; intended for benchmarks. */

@@ -1292,11 +1292,22 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   // tau == 0 selects the default; a negative tau keeps every computed pair
   // (full decompositions for the adjoint)
   const double tau = sp.tau == 0.0 ? 1e-13 : sp.tau;
-  // profiled class: PROF_TRIDIAG = the streaming reduction (n > 128), the
-  // dominant kernel; PROF_TRIDIAG_LDS = the LDS-resident one (n <= 128)
-  const int cls = nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG;
-  const bool prof = g_prof.what == cls && g_prof.launches < g_prof.max_launches &&
-                    g_prof.slot + sp.batch <= g_prof.max;
+  // profiled classes: PROF_TRIDIAG = the reductions of matrices wider than
+  // 128 (multi-workgroup or streaming, their first n - 128 steps);
+  // PROF_TRIDIAG_LDS = every launch of the LDS-resident kernel (whole
+  // matrices up to 128 and the last 128 steps of wider ones)
+  auto prof_on = [&](int cls) {
+    return g_prof.what == cls && g_prof.launches < g_prof.max_launches && g_prof.slot + sp.batch <= g_prof.max;
+  };
+  auto prof_begin = [&]() -> int* {
+    hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
+    return g_prof.nlog + g_prof.slot;
+  };
+  auto prof_end = [&]() {
+    hipEventRecord(g_prof.ev[2 * g_prof.launches + 1], s);
+    g_prof.launches++;
+    g_prof.slot += sp.batch;
+  };
   const int cb = nb <= 256 ? 32 : 16;
   const int groups = (nb + cb - 1) / cb;
   const bool mwg = nb > TL_NMAX && (long long)groups * sp.batch <= compute_units();
@@ -1307,8 +1318,8 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
     hipError_t fe = hermitian_fill(sp.G, sp.ld, sp.gstride, sp.n, nb, sp.batch, s);
     if (fe != hipSuccess) return fe;
   }
-  if (prof) hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
-  int* nl = prof ? g_prof.nlog + g_prof.slot : (int*)nullptr;
+  const bool prof = prof_on(nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG);
+  int* nl = prof ? prof_begin() : (int*)nullptr;
   if (nb <= TL_NMAX) {
     hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
                        sp.n, sp.ws, nb, kc, nl);
@@ -1323,15 +1334,15 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
     hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TS_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
                        sp.n, sp.ws, nb, kc, nl);
   }
-  if (prof) {
-    hipEventRecord(g_prof.ev[2 * g_prof.launches + 1], s);
-    g_prof.launches++;
-    g_prof.slot += sp.batch;
-  }
+  if (prof) prof_end();
   // the last 128 steps of the reductions (c) and (b), on one workgroup
-  if (nb > TL_NMAX)
+  if (nb > TL_NMAX) {
+    const bool pt = prof_on(PROF_TRIDIAG_LDS);
+    int* nt = pt ? prof_begin() : (int*)nullptr;
     hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, sp.ws, nb, kc, (int*)nullptr);
+                       sp.n, sp.ws, nb, kc, nt);
+    if (pt) prof_end();
+  }
   hipLaunchKernelGGL(eigvals_kernel, dim3((kc + 3) / 4, sp.batch), dim3(EV_NT), 0, s, sp.n, kc, sp.ws, nb, kc,
                      sp.kcap_dev);
   hipLaunchKernelGGL(keep_kernel, dim3(sp.batch), dim3(KP_NT), 0, s, sp.n, kc, sp.cutoff, tau, sp.kout,
