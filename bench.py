@@ -290,6 +290,51 @@ def _traffic():
     return TRAFFIC["bytes_per_launch"] if h == TRAFFIC["src_sha256_prefix"] else None
 
 
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 (matrix = vector)
+
+
+def contraction_pass(lib, L, run, dev, steps=2):
+    """Throughput of the contractions (MFMA) in a separate, untimed pass of
+    `steps` serial steps: every product and Gram matrix the library enqueues
+    is bracketed by HIP events and its algorithmic flops (8 M N K per complex
+    product, 4 n^2 K per Hermitian Gram, from the device-side sizes) logged
+    by the library; FP32-MFMA products are priced against the FP32 peak, the
+    FP64-accumulating Gram matrices against the FP64 peak."""
+    import ctypes
+    import torch
+    max_l = 600 * steps
+    flog = torch.zeros(2 * max_l, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    L.check(lib.tt_prof_begin_flops(ctypes.c_void_p(flog.data_ptr()), max_l), "tt_prof_begin_flops")
+    run(steps, False)
+    torch.cuda.synchronize()
+    nl, ne, tot = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    L.check(lib.tt_prof_end(ctypes.byref(nl), ctypes.byref(ne), ctypes.byref(tot)), "tt_prof_end")
+    n = nl.value
+    ms = (ctypes.c_float * max(n, 1))()
+    got = lib.tt_prof_times(ms, n)
+    if got < 0:
+        L.check(got, "tt_prof_times")
+    t = np.array(ms[:n], dtype=np.float64) / 1e3
+    fl = flog[:2 * n].view(n, 2).cpu().numpy()
+    is64 = fl[:, 1] > 0
+
+    def part(mask, col, peak, what):
+        f = float(fl[mask, col].sum())
+        sec = float(t[mask].sum())
+        ach = f / sec / 1e12 if sec > 0 else 0.0
+        return {"what": what, "launches_per_step": int(mask.sum()) // steps, "gflop_per_step": f / steps / 1e9,
+                "ms_per_step": sec * 1e3 / steps, "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                "frac": ach / peak}
+
+    return {"pass": "%d serial steps after the timed region, every contraction bracketed by HIP events" % steps,
+            "fp32_products": part(~is64, 0, FP32_PEAK_TFLOPS,
+                                  "complex64 products on v_mfma_f32 (zip-up, sweep, encode projections, decompression)"),
+            "fp64_gram": part(is64, 1, FP64_PEAK_TFLOPS,
+                              "Gram matrices of complex64 operands accumulated on v_mfma_f64 (K-split reductions "
+                              "included)")}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -388,6 +433,8 @@ def main():
     avg_launch_s = kms.value / 1e3 / nl
     achieved = flops / nl / avg_launch_s / 1e12 if launches.value else 0.0
 
+    mfma = contraction_pass(lib, L, run, dev)
+
     value = nz / (ms / 1e3)
     res = {
         "metric": "MPO x MPS Fresnel propagations/s at 2^20 px, chi=128",
@@ -424,6 +471,7 @@ def main():
             "work_per_launch": "(16/3) n^3 FP64 flops per matrix or trailing block of size n <= 128, "
                                "n logged by the kernel",
         },
+        "mfma": mfma,
         "wall_s": wall,
     }
     if a.copy_probe > 0:

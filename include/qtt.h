@@ -313,6 +313,20 @@ int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int*
  * recording.  Not thread-safe; intended for benchmarks. */
 int tt_prof_begin(int what, int* nlog, int max_entries, int max_launches);
 int tt_prof_end(int* launches, int* entries, double* total_ms);
+/* tt_prof_begin_flops(flog, max_launches): from now on every contraction the
+ * library enqueues (products and Gram matrices, with their K-split reductions)
+ * is bracketed by HIP events on its stream, and after the closing event a
+ * one-thread kernel adds the product's algorithmic flops -- 8 M N K per
+ * complex product, 4 n^2 K per Hermitian Gram (its lower half), from the
+ * device-side sizes summed over fields -- to flog[2 i] (FP32-MFMA products)
+ * or flog[2 i + 1] (FP64-accumulating ones) for launch i.  flog: device
+ * doubles, 2 * max_launches, zeroed by the caller.  Ends with tt_prof_end
+ * (entries is then 0).  tt_prof_times(ms, max): after tt_prof_end, the event
+ * time of each recorded launch (host floats, ms); returns how many were
+ * written or a negative qtt_status.  Diagnostics only: not thread-safe, and
+ * the extra kernels make a profiled run slower. */
+int tt_prof_begin_flops(double* flog, int max_launches);
+int tt_prof_times(float* ms, int max);
 
 /* ---- tile autotuner of the contraction kernel ----
  * The contraction kernel has several output-tile variants (64x64, 32x64,

@@ -26,6 +26,7 @@ EXPORTS = [
     "tt_saved_size", "mpo_apply_backward", "tt_to_dense_backward",
     "tt_check_status", "tt_last_error", "tt_version",
     "tt_cgemm", "tt_heev_workspace_size", "tt_heev", "tt_prof_begin", "tt_prof_end",
+    "tt_prof_begin_flops", "tt_prof_times",
     "tt_workspace_size_batched", "tt_encode_batched", "mpo_apply_batched", "tt_to_dense_batched",
     "tt_saved_size_batched", "mpo_apply_backward_batched", "tt_to_dense_backward_batched", "tt_intensity_loss",
     "tt_autotune_record", "tt_autotune_workspace_size", "tt_autotune_run", "tt_autotune_export",
@@ -108,6 +109,10 @@ def load(path=LIB_PATH):
     lib.tt_prof_begin.restype = i32
     lib.tt_prof_end.argtypes = [P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double)]
     lib.tt_prof_end.restype = i32
+    lib.tt_prof_begin_flops.argtypes = [vp, i32]
+    lib.tt_prof_begin_flops.restype = i32
+    lib.tt_prof_times.argtypes = [P(ctypes.c_float), i32]
+    lib.tt_prof_times.restype = i32
     lib.tt_workspace_size_batched.argtypes = [i32, i32, i32, i32, i32, i32]
     lib.tt_workspace_size_batched.restype = sz
     lib.tt_encode_batched.argtypes = [vp, i32, i32, P(QttOpts), vp, P(QttMpsBatch), vp, sz, vp]

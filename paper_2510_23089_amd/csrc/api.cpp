@@ -102,6 +102,24 @@ struct Ctx {
 
 DimExpr dv(const Ctx& c, int k, const int* p0 = nullptr, const int* p1 = nullptr) { return dx(k, p0, p1, c.bs); }
 
+// Diagnostics pass (tt_prof_begin_flops): every contraction below is
+// bracketed by HIP events on its stream; after the closing event a one-thread
+// kernel adds its algorithmic flops to the launch's two log entries.
+struct GemmProf {
+  bool on;
+  hipStream_t s;
+  explicit GemmProf(hipStream_t st) : s(st) {
+    on = g_prof.what == PROF_GEMM && g_prof.launches < g_prof.max_launches;
+    if (on) hipEventRecord(g_prof.ev[2 * g_prof.launches], s);
+  }
+  void done(const GemmSpec& g, double scale) {
+    if (!on) return;
+    hipEventRecord(g_prof.ev[2 * g_prof.launches + 1], s);
+    gemm_flops(g, scale, g_prof.flog + 2 * g_prof.launches, s);
+    g_prof.launches++;
+  }
+};
+
 // Hermitian Gram matrices (one per field) into ctx.G: G = op(A) . op(B).
 // Only the tiles touching the lower triangle are computed: the eigensolver
 // references the lower triangle alone.  K-split partials are nb x nb.
@@ -119,6 +137,8 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
   // the dedicated kernel instead of mostly-padding MFMA tiles
   const bool herm = B.ptr == A.ptr && B.conj != A.conj && B.sxh == A.syh && B.sxl == A.syl && B.syh == A.sxh &&
                     B.syl == A.sxl && B.sb == A.sb && B.sb2 == A.sb2;
+  // algorithmic work of a Hermitian Gram: the lower half, 4 n^2 K flops
+  GemmProf prof(c.s);
   if (herm && nb <= GRAM_SKINNY_N) {
     ll want = std::max<ll>(1, 2048 / std::max(c.nf, 1));
     ll byk = std::max<ll>(1, kb / 1024);
@@ -126,6 +146,8 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
     const int ns = (int)std::min<ll>({want, byk, bymem, 4096});
     HIPCHK(gram_skinny(g, ns, c.part, nb, c.s));
     HIPCHK(ksplit_reduce(c.part, gsp, ns, nb, c.G, c.gld, n, n, nb, nb, (ll)ns * gsp, gs, c.nf, 1, c.s));
+    g.k_bound = (int)std::min<ll>(kb, 1 << 30);
+    prof.done(g, 4.0);
     return QTT_OK;
   }
   int ks = ksplit_for(nb, kb, c.nf);
@@ -141,6 +163,8 @@ int gram(Ctx& c, const Operand& A, const Operand& B, DimExpr n, int nlo, int nb,
     g.C = opd(c.G, nlo * ld, ld, nlo, 1, 0, gs);
     HIPCHK(gemm_launch(g, c.s));
   }
+  g.k_bound = (int)std::min<ll>(kb, 1 << 30);
+  prof.done(g, 4.0);
   return QTT_OK;
 }
 
@@ -154,7 +178,9 @@ int gemm(Ctx& c, DimExpr M, int mlo, int mb, DimExpr N, int nlo, int nb, DimExpr
   g.A = A; g.B = B; g.C = C;
   g.accumulate = accumulate;
   g.types = c.gemm_t;
+  GemmProf prof(c.s);
   HIPCHK(gemm_launch(g, c.s));
+  prof.done(g, 8.0);
   return QTT_OK;
 }
 
@@ -1873,10 +1899,7 @@ int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int*
   return QTT_OK;
 }
 
-int tt_prof_begin(int what, int* nlog, int max_entries, int max_launches) {
-  g_err.clear();
-  if ((what != PROF_TRIDIAG && what != PROF_TRIDIAG_LDS) || !nlog || max_entries < 1 || max_launches < 1)
-    return fail(QTT_ERR_ARG, "tt_prof_begin: bad arguments");
+static int prof_events(int max_launches) {
   if (g_prof.ev) {
     for (int i = 0; i < 2 * g_prof.max_launches; ++i) hipEventDestroy(g_prof.ev[i]);
     delete[] g_prof.ev;
@@ -1884,13 +1907,46 @@ int tt_prof_begin(int what, int* nlog, int max_entries, int max_launches) {
   }
   g_prof.ev = new hipEvent_t[2 * (size_t)max_launches];
   for (int i = 0; i < 2 * max_launches; ++i) HIPCHK(hipEventCreate(&g_prof.ev[i]));
-  g_prof.what = what;
-  g_prof.nlog = nlog;
-  g_prof.max = max_entries;
   g_prof.slot = 0;
   g_prof.launches = 0;
   g_prof.max_launches = max_launches;
   return QTT_OK;
+}
+
+int tt_prof_begin(int what, int* nlog, int max_entries, int max_launches) {
+  g_err.clear();
+  if ((what != PROF_TRIDIAG && what != PROF_TRIDIAG_LDS) || !nlog || max_entries < 1 || max_launches < 1)
+    return fail(QTT_ERR_ARG, "tt_prof_begin: bad arguments");
+  const int rc = prof_events(max_launches);
+  if (rc != QTT_OK) return rc;
+  g_prof.what = what;
+  g_prof.nlog = nlog;
+  g_prof.flog = nullptr;
+  g_prof.max = max_entries;
+  return QTT_OK;
+}
+
+int tt_prof_begin_flops(double* flog, int max_launches) {
+  g_err.clear();
+  if (!flog || max_launches < 1) return fail(QTT_ERR_ARG, "tt_prof_begin_flops: bad arguments");
+  const int rc = prof_events(max_launches);
+  if (rc != QTT_OK) return rc;
+  g_prof.what = PROF_GEMM;
+  g_prof.nlog = nullptr;
+  g_prof.flog = flog;
+  g_prof.max = 0;
+  return QTT_OK;
+}
+
+int tt_prof_times(float* ms, int max) {
+  g_err.clear();
+  if (!ms || max < 0) return fail(QTT_ERR_ARG, "tt_prof_times: bad arguments");
+  const int n = std::min(max, g_prof.launches);
+  for (int i = 0; i < n; ++i) {
+    HIPCHK(hipEventSynchronize(g_prof.ev[2 * i + 1]));
+    HIPCHK(hipEventElapsedTime(&ms[i], g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
+  }
+  return n;
 }
 
 int tt_prof_end(int* launches, int* entries, double* total_ms) {

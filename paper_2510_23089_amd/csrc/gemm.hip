@@ -588,6 +588,24 @@ static hipError_t launch_variant(const GemmArgs& g0, int types, bool akm, bool b
   return hipErrorInvalidValue;
 }
 
+__global__ void gemm_flops_kernel(DimExpr M, DimExpr N, DimExpr K, DimExpr batch, int mb, int nb, int kb, int bb,
+                                  int nf, double scale, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int f = 0; f < nf; ++f) {
+    const double m = min(dim_eval(M, f), mb), n = min(dim_eval(N, f), nb), k = min(dim_eval(K, f), kb);
+    s += m * n * k * (double)min(dim_eval(batch, f), bb);
+  }
+  out[0] += scale * s;
+}
+
+hipError_t gemm_flops(const GemmSpec& sp, double scale, double* out, hipStream_t s) {
+  const int slot = sp.types == GEMM_F32_GRAM64 || sp.types == GEMM_F64 ? 1 : 0;
+  hipLaunchKernelGGL(gemm_flops_kernel, dim3(1), dim3(64), 0, s, sp.M, sp.N, sp.K, sp.batch, sp.m_bound,
+                     sp.n_bound, sp.k_bound, sp.batch_bound, sp.nfield, scale, out + slot);
+  return hipGetLastError();
+}
+
 hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   GemmArgs g;
   g.M = sp.M; g.N = sp.N; g.K = sp.K; g.batch = sp.batch;

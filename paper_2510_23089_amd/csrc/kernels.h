@@ -28,6 +28,11 @@ struct GemmSpec {
 
 FastDiv make_fastdiv(uint32_t d);
 hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s);
+// Algorithmic flops of the product sp describes, from its device-side sizes
+// (clamped to the host bounds, summed over fields and inner batch): scale *
+// M * N * K, added to out[0] for FP32-MFMA types and to out[1] for the
+// FP64-accumulating ones.  One thread; for the diagnostics pass only.
+hipError_t gemm_flops(const GemmSpec& sp, double scale, double* out, hipStream_t s);
 // Tile autotuner (host state, not thread-safe): record the call shapes of a
 // run, time every tile variant on synthetic operands of each shape, use the
 // fastest from then on; export / import the table as 6-int entries.
@@ -93,10 +98,11 @@ size_t eig_ws_bytes(int n_bound, int kcap, int batch);
 // roofline report): HIP events are recorded around every launch of the
 // selected class on its stream, and the kernel writes its actual problem size
 // to nlog[slot] so algorithmic work can be computed from real sizes.
-enum ProfWhat { PROF_NONE = 0, PROF_TRIDIAG = 1, PROF_TRIDIAG_LDS = 2 };
+enum ProfWhat { PROF_NONE = 0, PROF_TRIDIAG = 1, PROF_TRIDIAG_LDS = 2, PROF_GEMM = 3 };
 struct ProfHook {
   int what = PROF_NONE;
   int* nlog = nullptr;       // device ints: per launch, per batch entry
+  double* flog = nullptr;    // PROF_GEMM: device doubles, two per launch (FP32-MFMA and FP64-MFMA flops)
   int max = 0;               // capacity of nlog (entries)
   int slot = 0;              // next free entry
   int launches = 0;
