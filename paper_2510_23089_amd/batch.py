@@ -9,6 +9,11 @@ state |0> with bond 1, and its propagator is the Fresnel MPO of its own
 as it would be alone, while all members advance site by site together.  Per
 field bond caps go to the device as one int per field.
 
+Members are encoded on their own grids, one batched encode per distinct
+side (the padded image would only feed zeros to the leading Gram products),
+and placed behind 2(K - k) leading cores |0> of bond 1 -- the state the
+encode of the padded image produces there, up to a phase per core.
+
 The whole pipeline (encode, x then y application, optional refinement, and
 decompression) is a fixed sequence of stream-ordered library calls with no
 host synchronisation, so it can be captured once in a HIP graph and replayed.
@@ -51,24 +56,47 @@ class UnevenBatch:
         self.wy = api.MPOBatch([per_k[k][1] for k in self.ks], device=device)
         self.chi_dev = torch.tensor(self.chis, dtype=torch.int32, device=device)
         side = 1 << self.K
-        self.images = torch.zeros((self.count, side, side), dtype=torch.complex64, device=device)
         self.psi = api.MPSBatch(self.count, self.m, self.chi, device=device)
+        # one group per distinct side: member indices, native images, its encode
+        self.groups = []
+        for k in sorted(set(self.ks)):
+            idx = [i for i, kk in enumerate(self.ks) if kk == k]
+            n = 1 << k
+            imgs = torch.zeros((len(idx), n, n), dtype=torch.complex64, device=device)
+            enc = api.MPSBatch(len(idx), 2 * k, self.chi, device=device)
+            chis = torch.tensor([self.chis[i] for i in idx], dtype=torch.int32, device=device)
+            self.groups.append((k, idx, torch.tensor(idx, dtype=torch.long, device=device), imgs, enc, chis))
+            p = 2 * (self.K - k)
+            if p:
+                lead = torch.zeros((p, self.chi, 2, self.chi), dtype=torch.complex64, device=device)
+                lead[:, 0, 0, 0] = 1.0          # |0>, bond 1 (never rewritten by run())
+                self.psi.cores[idx, :p] = lead
         self.mid = api.MPSBatch(self.count, self.m, self.chi, device=device)
         self.out = api.MPSBatch(self.count, self.m, self.chi, device=device)
-        self.dense = torch.empty_like(self.images)
+        self.dense = torch.empty((self.count, side, side), dtype=torch.complex64, device=device)
         self.graph = None
 
     def load(self, fields):
-        """Copy host fields (list of 2^k x 2^k arrays) into the padded device batch."""
-        self.images.zero_()
-        for i, f in enumerate(fields):
-            n = f.shape[0]
-            assert n == 1 << self.ks[i]
-            self.images[i, :n, :n].copy_(torch.from_numpy(np.asarray(f)).to(torch.complex64))
+        """Copy host fields (list of 2^k x 2^k arrays) into the device batch."""
+        for k, idx, _, imgs, _, _ in self.groups:
+            for j, i in enumerate(idx):
+                f = np.asarray(fields[i])
+                assert f.shape[0] == 1 << k
+                imgs[j].copy_(torch.from_numpy(f).to(torch.complex64))
+
+    def encode(self):
+        """Encode every group on its own grid and place it behind its leading sites."""
+        for k, _, idx_dev, imgs, enc, chis in self.groups:
+            api.tt_encode_batched(imgs, self.chi, out=enc, chi_dev=chis)
+            p = 2 * (self.K - k)
+            self.psi.cores[:, p:].index_copy_(0, idx_dev, enc.cores)
+            self.psi.bonds[:, p:].index_copy_(0, idx_dev, enc.bonds)
+            self.psi.norms.index_copy_(0, idx_dev, enc.norms)
+        return self.psi
 
     def run(self):
         """The pipeline on the current stream (capturable)."""
-        api.tt_encode_batched(self.images, self.chi, out=self.psi, chi_dev=self.chi_dev)
+        self.encode()
         api.mpo_apply_batched(self.psi, self.wx, self.chi, out=self.mid, chi_dev=self.chi_dev, prec=self.prec,
                               refine=self.refine)
         api.mpo_apply_batched(self.mid, self.wy, self.chi, out=self.out, chi_dev=self.chi_dev, prec=self.prec,

@@ -160,3 +160,42 @@ def test_autotune_keeps_results_bit_identical():
     b.capture()
     assert torch.equal(b.replay().clone(), before)
     api.check_status()
+
+
+def test_native_group_encode_matches_padded_encode():
+    """UnevenBatch encodes each side on its own grid and puts 2(K - k) leading
+    |0> sites in front; the result must be the encode of the zero-padded
+    image (same bonds everywhere, same fields after propagation), and the
+    padding of the decompressed members must stay exactly zero."""
+    torch = need_gpu()
+    from paper_2510_23089_amd import api
+    from paper_2510_23089_amd import batch as BT
+    ks = [3, 5, 4, 5, 3, 4, 2]
+    chis = [4, 16, 8, 6, 8, 16, 4]
+    z = 20e-6
+    fields = [synth.aperture_field(70 + i, n=1 << k) for i, k in enumerate(ks)]
+    b = BT.UnevenBatch(ks, chis, LAM, DX, z)
+    b.load(fields)
+    got = b.run().clone()
+    api.check_status()
+    # the padded-image pipeline through the same MPOs
+    K = max(ks)
+    side = 1 << K
+    img = torch.zeros((len(ks), side, side), dtype=torch.complex64, device="cuda")
+    for i, f in enumerate(fields):
+        n = f.shape[0]
+        img[i, :n, :n] = torch.from_numpy(f).to(torch.complex64)
+    chi_dev = torch.tensor(chis, dtype=torch.int32, device="cuda")
+    psi = api.tt_encode_batched(img, max(chis), chi_dev=chi_dev)
+    assert torch.equal(psi.bonds, b.psi.bonds)
+    mid = api.mpo_apply_batched(psi, b.wx, max(chis), chi_dev=chi_dev)
+    out = api.mpo_apply_batched(mid, b.wy, max(chis), chi_dev=chi_dev)
+    ref = api.tt_to_dense_batched(out)
+    api.check_status()
+    assert torch.equal(out.bonds, b.out.bonds)
+    for i, k in enumerate(ks):
+        n = 1 << k
+        say("member", i, k)
+        assert rel(got[i, :n, :n].cpu().numpy(), ref[i, :n, :n].cpu().numpy()) < 1e-5
+        if n < side:
+            assert got[i, n:, :].abs().max().item() == 0 and got[i, :, n:].abs().max().item() == 0
