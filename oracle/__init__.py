@@ -23,7 +23,10 @@ refine    two-site variational fitting sweep (one FP32 refinement pass reading)
 grad      torch-CPU complex128 twin of zipup/sweep/decompress for autograd
 
 Parity status: every function above is pinned by at least one test in
-``tests/test_oracle_*.py``; see the docstrings for which.  The zip-up with a
-bond cap equal to the final cap (heavily truncated regime) is pinned only as
-"the identical algorithm" plus bounds (parity unpinned beyond that).
+``tests/test_oracle_*.py``; see the docstrings for which.  The truncating
+zip-up is pinned in closed form for operators of bond 1 (single-site
+unitaries on a left-canonical input: the right-to-left sequential truncated
+SVD of the exact result, i.e. the TT-SVD of the site-reversed vector); with
+operator bonds above 1 the truncating regime is pinned only as "the identical
+algorithm" plus bounds (parity unpinned beyond that).
 """

@@ -137,3 +137,43 @@ def test_truncated_zipup_bounded_by_opt():
     e_opt = _rel(Z.to_dense(opt, n), ref)
     assert e_got >= e_opt * (1 - 1e-9)
     assert e_got < 5.0 * e_opt          # two sequential capped applications
+
+
+def _site_unitaries(rng, m):
+    out = []
+    for _ in range(m):
+        z = rng.standard_normal((2, 2)) + 1j * rng.standard_normal((2, 2))
+        q, r = np.linalg.qr(z)
+        out.append(q * (np.diag(r) / np.abs(np.diag(r))))
+    return out
+
+
+@pytest.mark.parametrize("chi_zip,seed", [(2, 0), (3, 1), (5, 2), (9, 3)])
+def test_truncating_zipup_of_site_unitaries_is_right_to_left_ttsvd(chi_zip, seed):
+    """Truncating regime, closed form: for an MPO of single-site unitaries
+    (bond 1) and a left-canonical input, every left block stays orthonormal,
+    so the singular values the zip-up cuts at bond k are those of the exact
+    state W psi across that bond and the zip-up is the sequential truncated
+    SVD from the right -- the TT-SVD of the site-reversed vector.  Pins the
+    keep rule, the carry and the site order of the truncating zip-up against
+    the (separately pinned) TT-SVD and a dense application of the unitaries."""
+    rng = np.random.default_rng(400 + seed)
+    m = 8
+    v = rng.standard_normal(1 << m) + 1j * rng.standard_normal(1 << m)
+    psi = T.tt_svd(v, m, chi=BIG)                       # exact, left-canonical
+    us = _site_unitaries(rng, m)
+    mpo = [u.reshape(1, 2, 2, 1) for u in us]          # [D, t, s, D']
+    out = Z.zip_up(psi, mpo, chi_zip)
+    got = T.tt_dense(out)
+    # dense W v: unitary k acts on bit k (site k, most significant first)
+    y = v.reshape([2] * m)
+    for k, u in enumerate(us):
+        y = np.moveaxis(np.tensordot(u, y, axes=([1], [k])), 0, k)
+    # sequential truncated SVD from the right = TT-SVD of the reversed sites
+    rev = y.transpose(list(range(m - 1, -1, -1))).reshape(-1)
+    cr = T.tt_svd(rev, m, chi=chi_zip)
+    want = T.tt_dense(cr).reshape([2] * m).transpose(list(range(m - 1, -1, -1))).reshape(-1)
+    assert _rel(got, want) < 1e-12
+    assert Z.bonds(out) == T.bonds(cr)[::-1]
+    # and the cut really truncates
+    assert max(Z.bonds(out)) == chi_zip
