@@ -221,3 +221,57 @@ def test_batched_encode_matches_single():
     for f, chi in enumerate((16, 64)):
         ref = Z.to_dense(T.tt_svd(Q.to_quantics(imgs[f]), 12, chi, tau=1e-13), 6)
         assert rel(dense[f], ref) < (1e-4 if chi < 64 else 1e-5)
+
+
+def test_bench_configuration_full_size_vs_oracle():
+    """The benchmark's workload at its full size and in the launch
+    configuration it times: the 1024^2 aperture field (seed 0) encoded at
+    chi 128, the three distances 0.5 / 2 / 8 mm propagated as one batch (one
+    batched zip-up + sweep per axis, chi 128) and decompressed, against the
+    oracle's float64 TT-SVD, zip-up and sweep, distance by distance (the FP32
+    bar against the identically truncated result, 1e-4), with the same bond
+    profile.  The batch carries the oracle's MPO cores: the truncating zip-up
+    depends on the operator's gauge (its cuts see a non-orthonormal left
+    environment), so an identically truncated comparison needs the same cores."""
+    torch = need_gpu()
+    api = _api()
+    n, chi = 10, 128
+    zs = (0.5e-3, 2e-3, 8e-3)
+    e0 = synth.aperture_field(0, n=1 << n)
+    d = torch.from_numpy(e0).to(torch.complex64).cuda()
+    say("bench configuration: encode + batch of", len(zs))
+    psi = api.tt_encode(d, chi)
+    mpos = [_oracle_mpos(n, z) for z in zs]
+    wxb = api.MPOBatch([w[0] for w in mpos])
+    wyb = api.MPOBatch([w[1] for w in mpos])
+    m = 2 * n
+    bi = api.MPSBatch(len(zs), m, chi)
+    mid = api.MPSBatch(len(zs), m, chi)
+    out = api.MPSBatch(len(zs), m, chi)
+    bi.fill_from(psi)
+    api.mpo_apply_batched(bi, wxb, chi, out=mid)
+    api.mpo_apply_batched(mid, wyb, chi, out=out)
+    dens = api.tt_to_dense_batched(out).cpu().numpy()
+    api.check_status()
+    cores = T.tt_svd(Q.to_quantics(e0), m, chi, tau=1e-13)
+    assert [int(x) for x in psi.bonds.cpu()] == T.bonds(cores)
+    for i, z in enumerate(zs):
+        wx, wy, _ = mpos[i]
+        r1, _ = Z.mpo_apply(cores, wx, chi, tau=1e-13)
+        r2, _ = Z.mpo_apply(r1, wy, chi, tau=1e-13)
+        err = rel(dens[i], Z.to_dense(r2, n))
+        say("z = %g mm: rel err %.3e" % (z * 1e3, err))
+        assert err < 1e-4
+        assert [int(x) for x in out.bonds[i].cpu()] == T.bonds(r2)
+    # the library's own MPOs (as the benchmark runs them): a different gauge
+    # of the same operators, so a different truncation; both stay within the
+    # truncation error of the exact propagation
+    prop = api.FresnelBatch(n, LAM, DX, zs, device="cuda")
+    prop(bi, chi, tmp=mid, out=out)
+    own = api.tt_to_dense_batched(out).cpu().numpy()
+    api.check_status()
+    for i, z in enumerate(zs):
+        exact = F.fresnel_dense(e0, LAM, DX, z)
+        e_own, e_orc = rel(own[i], exact), rel(dens[i], exact)
+        say("z = %g mm: vs exact, library MPO %.3e, oracle MPO %.3e" % (z * 1e3, e_own, e_orc))
+        assert e_own < 1.5 * e_orc + 1e-3
