@@ -61,7 +61,7 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
 # copy); valid only while the kernel's sources (see _kernel_source_hash) are
 # the ones the counters were taken on.
-TRAFFIC = {"src_sha256_prefix": "556fa2fe61ca4089", "bytes_per_launch": (99.95 * 2.0 + 151.66) * 1024.0}
+TRAFFIC = {"src_sha256_prefix": "a22018cd5bfd9fae", "bytes_per_launch": (99.95 * 2.0 + 151.65) * 1024.0}
 
 
 def parse():

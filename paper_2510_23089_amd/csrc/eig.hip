@@ -72,8 +72,7 @@ __device__ double block_sum(double v, double* red) {
 struct EigWs {
   double *d, *e, *e2, *lam, *sig;
   double2* tau;
-  double *lu_dl, *lu_d, *lu_du, *lu_du2, *z;
-  int* piv;
+  double* z;                  // eigenvectors of T, vector-major (kc x nb)
   int* clus;
   // exchange area of the multi-workgroup reduction: the next column and the
   // partial products of two consecutive steps, as tagged 64-bit words
@@ -85,8 +84,7 @@ __host__ __device__ inline size_t eig_ws_per_matrix(int nb, int kc) {
   size_t s = 0;
   s += 5 * (size_t)nb * sizeof(double);          // d, e, e2, lam, sig
   s += (size_t)nb * sizeof(double2);             // tau
-  s += 5 * (size_t)nb * kc * sizeof(double);     // LU (4) + z
-  s += (size_t)nb * kc * sizeof(int);            // pivots
+  s += (size_t)nb * kc * sizeof(double);         // z
   s += ((size_t)kc * sizeof(int) + 15) / 16 * 16;  // cluster starts
   s += 8 * (size_t)nb * sizeof(double2);        // exchange area
   return (s + 255) / 256 * 256;
@@ -101,12 +99,7 @@ __host__ __device__ inline EigWs eig_ws_carve(void* base, int b, int nb, int kc)
   w.lam = (double*)p; p += nb * sizeof(double);
   w.sig = (double*)p; p += nb * sizeof(double);
   w.tau = (double2*)p; p += nb * sizeof(double2);
-  w.lu_dl = (double*)p; p += (size_t)nb * kc * sizeof(double);
-  w.lu_d = (double*)p; p += (size_t)nb * kc * sizeof(double);
-  w.lu_du = (double*)p; p += (size_t)nb * kc * sizeof(double);
-  w.lu_du2 = (double*)p; p += (size_t)nb * kc * sizeof(double);
   w.z = (double*)p; p += (size_t)nb * kc * sizeof(double);
-  w.piv = (int*)p; p += (size_t)nb * kc * sizeof(int);
   w.clus = (int*)p; p += ((size_t)kc * sizeof(int) + 15) / 16 * 16;
   w.xv = (double2*)p; p += 4 * (size_t)nb * sizeof(double2);
   w.xp = (double2*)p; p += 4 * (size_t)nb * sizeof(double2);
