@@ -245,6 +245,8 @@ def grad_step_bench(steps, dev):
     pr = AG.PhaseRetrieval(wx, wy, chi)
     loss, g = pr.loss_and_grad(mask.cores, mask.bonds, target)     # warm-up
     api.check_status()
+    # contraction tiles tuned on the gradient step's shapes (setup)
+    n_tuned = api.autotune(lambda: pr.loss_and_grad(mask.cores, mask.bonds, target), device=dev)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -263,6 +265,7 @@ def grad_step_bench(steps, dev):
                     "decompression, summed squared intensity error; forward with saved state + full adjoint",
         "dtype": "c64 (fp32 MFMA) + f64 eig and eig adjoint",
         "mpo_max_bond": int(max(prop.wx.d_bonds)),
+        "autotuned_contraction_shapes": n_tuned,
         "loss": float(loss),
         "grad_norm": float(g.abs().pow(2).sum().sqrt()),
     }
