@@ -631,10 +631,9 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   bool akm = (sp.A.syl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.A.syh == 1);
   bool bkm = (sp.B.sxl == 1 && sp.klo > 1) || (sp.klo == 1 && sp.B.sxh == 1);
   TileKey key = make_key(sp, akm, bkm);
-  // FP64-accumulating products (Gram matrices, the FP64 path) run long K
-  // loops that the short synthetic K of the tuner does not represent: they
-  // keep the default tiles
-  if (g_record && sp.types != GEMM_F32_GRAM64 && sp.types != GEMM_F64) g_seen.insert(key);
+  // every product is recorded, the FP64-accumulating Gram matrices included:
+  // their K-split chunks are short enough for the tuner's synthetic K
+  if (g_record) g_seen.insert(key);
   auto it = g_tiles.find(key);
   // untuned default: 32-row tiles when the rows (or both sides) are that small
   const int tile = it != g_tiles.end() ? it->second
