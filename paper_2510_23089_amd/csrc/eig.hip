@@ -142,8 +142,9 @@ __device__ void householder(double2 alpha, double xnorm2, double2& tau, double2&
 }
 
 // (a) n <= 128: the packed lower triangle (n(n+1)/2 complex doubles, <= 132 KB)
-//     lives in LDS for the whole reduction; 1024 threads, 8 per row (row
-//     r = tid / 8) for the matrix-vector product and the rank-2 update.
+//     lives in LDS for the whole reduction; 8 threads per row (row
+//     r = tid / 8) for the matrix-vector product and the rank-2 update, so
+//     128 to 1024 threads by the size bound.
 //     Thread r updates the entry of the next column in row r and forms the
 //     partial sums of its norm; the rest of the rank-2 update is deferred
 //     into the next step, where it runs while the (at most two) waves whose
@@ -156,9 +157,12 @@ __device__ __forceinline__ double seg8_sum(double v) {   // valid in lanes 4..7 
   return v + dpp_d<0x114, 0xf>(v);   // row_shr:4
 }
 
-__global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
-                                                            void* wsbase, int nb, int kc, int* nlog) {
-  constexpr int NW = TL_NT / 64;
+// NT = 8 threads per row for at most NT / 8 rows (the launch picks it from the
+// size bound: fewer waves per barrier for small matrices)
+template <int NT>
+__global__ __launch_bounds__(NT) void tridiag_lds_kernel(double2* Gall, int ld, long long gstride, DimExpr nexp,
+                                                         void* wsbase, int nb, int kc, int* nlog) {
+  constexpr int NW = NT / 64;
   const int b = blockIdx.x;
   // the trailing block [k0, nf): the whole matrix when nf <= 128, otherwise
   // the last 128 rows and columns, which the multi-workgroup reduction (c)
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(TL_NT) void tridiag_lds_kernel(double2* Gall, int l
   {
     // packed lower triangle, all loads independent: element e -> (r, c)
     const int T = n * (n + 1) / 2;
-    for (int e = tid; e < T; e += TL_NT) {
+    for (int e = tid; e < T; e += NT) {
       int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
       while (tri(r + 1, 0) <= e) ++r;
       while (tri(r, 0) > e) --r;
@@ -1314,8 +1318,18 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   const bool prof = prof_on(nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG);
   int* nl = prof ? prof_begin() : (int*)nullptr;
   if (nb <= TL_NMAX) {
-    hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, sp.ws, nb, kc, nl);
+    if (nb <= 16)
+      hipLaunchKernelGGL(tridiag_lds_kernel<128>, dim3(sp.batch), dim3(128), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
+    else if (nb <= 32)
+      hipLaunchKernelGGL(tridiag_lds_kernel<256>, dim3(sp.batch), dim3(256), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
+    else if (nb <= 64)
+      hipLaunchKernelGGL(tridiag_lds_kernel<512>, dim3(sp.batch), dim3(512), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
+    else
+      hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
   } else if (mwg) {
     if (cb == 32)
       hipLaunchKernelGGL(tridiag_mwg_kernel<32>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
@@ -1332,8 +1346,8 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   if (nb > TL_NMAX) {
     const bool pt = prof_on(PROF_TRIDIAG_LDS);
     int* nt = pt ? prof_begin() : (int*)nullptr;
-    hipLaunchKernelGGL(tridiag_lds_kernel, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, sp.ws, nb, kc, nt);
+    hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
+                       sp.gstride, sp.n, sp.ws, nb, kc, nt);
     if (pt) prof_end();
   }
   hipLaunchKernelGGL(eigvals_kernel, dim3((kc + 3) / 4, sp.batch), dim3(EV_NT), 0, s, sp.n, kc, sp.ws, nb, kc,
