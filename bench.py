@@ -7,11 +7,13 @@ pixel 1 um) propagates it to z = 0.5, 2 and 8 mm -- each propagation is a
 zip-up + truncation sweep for the x axis then the y axis at chi 128, the three
 distances advancing as one batch -- and each result is decompressed to the
 1024 x 1024 grid.  value = propagations / s over the whole step (encode and
-decompression included).  Steps are software-pipelined over two streams: the
-encode of step k + 1 (a sequential chain of 19 single-field truncations)
-runs beside the propagation of step k, which leaves most compute units idle;
-serial_ms_per_step times the same steps on one stream.  Inputs are resident
-in HBM before the timed region; the host float64 MPO construction is setup.
+decompression included).  A step is a chain of ~95 dependent truncations,
+each an FP64 eigensolve of one to three small matrices, so one step alone
+leaves most compute units idle: independent steps run concurrently, step k
+on stream k mod S (S = --inflight, default 3), each stream with its own
+buffers and library workspaces.  serial_ms_per_step times the same steps one
+at a time on one stream (the latency of a step).  Inputs are resident in HBM
+before the timed region; the host float64 MPO construction is setup.
 
 The dominant kernel (qtt::tridiag_lds_kernel, the Householder
 tridiagonalisation of the FP64 Gram matrices up to 128 and of the trailing
@@ -61,15 +63,18 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
 # copy); valid only while the kernel's sources (see _kernel_source_hash) are
 # the ones the counters were taken on.
-TRAFFIC = {"src_sha256_prefix": "a22018cd5bfd9fae", "bytes_per_launch": (99.95 * 2.0 + 151.65) * 1024.0}
+TRAFFIC = {"src_sha256_prefix": "0ca3fae355e4f795", "bytes_per_launch": (98.90 * 2.0 + 151.65) * 1024.0}
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--steps", type=int, default=30)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--chi", type=int, default=CHI)
+    p.add_argument("--inflight", type=int, default=3,
+                   help="independent steps executing concurrently, one stream each (3 fits the HIP runtime's "
+                        "default of four hardware queues beside the main stream)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-batched", action="store_true")
@@ -309,7 +314,7 @@ def contraction_pass(lib, L, run, dev, steps=2):
     flog = torch.zeros(2 * max_l, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     L.check(lib.tt_prof_begin_flops(ctypes.c_void_p(flog.data_ptr()), max_l), "tt_prof_begin_flops")
-    run(steps, False)
+    run(steps, 1)
     torch.cuda.synchronize()
     nl, ne, tot = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     L.check(lib.tt_prof_end(ctypes.byref(nl), ctypes.byref(ne), ctypes.byref(tot)), "tt_prof_end")
@@ -358,58 +363,61 @@ def main():
     m = 2 * N_LOG2
     chi = a.chi
     nz = len(ZS)
-    psis = [api.MPS(m, chi, device=dev), api.MPS(m, chi, device=dev)]
-    batch_in = api.MPSBatch(nz, m, chi, device=dev)
-    mid = api.MPSBatch(nz, m, chi, device=dev)
-    out = api.MPSBatch(nz, m, chi, device=dev)
-    dens = torch.empty((nz, 1 << N_LOG2, 1 << N_LOG2), dtype=torch.complex64, device=dev)
     main_s = torch.cuda.current_stream(dev)
-    side = torch.cuda.Stream(device=dev)          # default priority
 
-    def run(steps, pipelined):
+    class Lane:
+        """One step in flight: its own stream (default priority), state
+        buffers and library workspaces (keyed per lane)."""
+
+        def __init__(self, i):
+            self.s = torch.cuda.Stream(device=dev)
+            self.psi = api.MPS(m, chi, device=dev)
+            self.inp = api.MPSBatch(nz, m, chi, device=dev)
+            self.mid = api.MPSBatch(nz, m, chi, device=dev)
+            self.out = api.MPSBatch(nz, m, chi, device=dev)
+            self.dens = torch.empty((nz, 1 << N_LOG2, 1 << N_LOG2), dtype=torch.complex64, device=dev)
+            self.key = "lane%d" % i
+
+        def step(self):
+            api.tt_encode(d_field, chi, out=self.psi, ws_key=self.key)
+            self.inp.fill_from(self.psi)
+            prop(self.inp, chi, tmp=self.mid, out=self.out, ws_key=self.key)
+            api.tt_to_dense_batched(self.out, out=self.dens, ws_key=self.key + ".dense")
+
+        def check(self):
+            api.check_status(self.key)
+            api.check_status(self.key + ".dense")
+
+    lanes = [Lane(i) for i in range(max(a.inflight, 1))]
+
+    def run(steps, inflight):
         """`steps` steps, each: encode the field, propagate the three distances
-        as one batch, decompress all three.  Pipelined: the encode of step
-        k + 1 runs on a second stream while step k propagates (its input MPS
-        double-buffered); every step still performs all of its work."""
-        if not pipelined:
-            for _ in range(steps):
-                api.tt_encode(d_field, chi, out=psis[0])
-                batch_in.fill_from(psis[0])
-                prop(batch_in, chi, tmp=mid, out=out)
-                api.tt_to_dense_batched(out, out=dens)
-            return
-        ev_enc = [torch.cuda.Event(), torch.cuda.Event()]
-        ev_fill = torch.cuda.Event()
-        side.wait_stream(main_s)
-        with torch.cuda.stream(side):
-            api.tt_encode(d_field, chi, out=psis[0], ws_key="side")
-            ev_enc[0].record(side)
+        as one batch, decompress all three.  Step k runs on lane k mod
+        `inflight`: up to `inflight` independent steps execute concurrently
+        (every step performs all of its work; a lane's steps are ordered by
+        its stream).  inflight = 1: one stream, one step at a time."""
+        for ln in lanes[:inflight]:
+            ln.s.wait_stream(main_s)
         for k in range(steps):
-            main_s.wait_event(ev_enc[k & 1])
-            batch_in.fill_from(psis[k & 1])
-            ev_fill.record(main_s)
-            if k + 1 < steps:
-                side.wait_event(ev_fill)
-                with torch.cuda.stream(side):
-                    api.tt_encode(d_field, chi, out=psis[(k + 1) & 1], ws_key="side")
-                    ev_enc[(k + 1) & 1].record(side)
-            prop(batch_in, chi, tmp=mid, out=out)
-            api.tt_to_dense_batched(out, out=dens)
-        main_s.wait_stream(side)
+            ln = lanes[k % inflight]
+            with torch.cuda.stream(ln.s):
+                ln.step()
+        for ln in lanes[:inflight]:
+            main_s.wait_stream(ln.s)
 
-    run(1, False)
+    run(len(lanes), len(lanes))
     # contraction tiles tuned on this step's shapes (setup, before any timing;
     # variants differ only in output partitioning, so results are unchanged)
-    n_tuned = api.autotune(lambda: run(1, False), device=dev)
-    run(max(a.warmup, 1), True)
-    api.check_status()
-    api.check_status("side")
+    n_tuned = api.autotune(lambda: run(1, 1), device=dev)
+    run(a.warmup, len(lanes))
+    for ln in lanes:
+        ln.check()
     torch.cuda.synchronize()
     # serial reference (same work, one stream), outside the profiled region
     ev_s0 = torch.cuda.Event(enable_timing=True)
     ev_s1 = torch.cuda.Event(enable_timing=True)
     ev_s0.record()
-    run(a.steps, False)
+    run(a.steps, 1)
     ev_s1.record()
     torch.cuda.synchronize()
     serial_ms = ev_s0.elapsed_time(ev_s1) / a.steps
@@ -422,15 +430,15 @@ def main():
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    run(a.steps, True)
+    run(a.steps, len(lanes))
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1) / a.steps
     launches, entries, kms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     L.check(lib.tt_prof_end(ctypes.byref(launches), ctypes.byref(entries), ctypes.byref(kms)), "tt_prof_end")
-    api.check_status()
-    api.check_status("side")
+    for ln in lanes:
+        ln.check()
     ns = nlog[:entries.value].cpu().numpy().astype(np.float64)
     # n = the matrix (n <= 128) or trailing block (the last 128 steps of a
     # wider matrix) each launch reduces, logged by the kernel
@@ -458,7 +466,10 @@ def main():
         "config": {"workload": "single 1024x1024 complex64 field, z in {0.5, 2, 8} mm, chi 128; "
                                "encode + 3 propagations + 3 decompressions per step",
                    "global_batch": 1, "chi": chi, "sites": m,
-                   "schedule": "encode of step k+1 on a second stream during the propagation of step k",
+                   "steps_in_flight": len(lanes),
+                   "schedule": "step k on stream k mod %d (independent steps run concurrently, each with its "
+                               "own buffers and workspaces); serial_ms_per_step: the same steps one at a time "
+                               "on one stream" % len(lanes),
                    "autotuned_contraction_shapes": n_tuned},
         "serial_ms_per_step": serial_ms,
         "roofline": {
@@ -474,7 +485,7 @@ def main():
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "launches": launches.value,
             "avg_launch_ms": avg_launch_s * 1e3,
-            "kernel_share_of_step": kms.value / (ms * a.steps),
+            "kernel_ms_per_step": kms.value / a.steps,
             "work_per_launch": "(16/3) n^3 FP64 flops per matrix or trailing block of size n <= 128, "
                                "n logged by the kernel",
         },

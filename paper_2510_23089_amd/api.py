@@ -450,7 +450,9 @@ class MPOBatch:
 
 
 def mpo_apply_batched(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_dev=None, chi_cap=None,
-                      saved=None, prec=None, refine=False):
+                      saved=None, prec=None, refine=False, ws_key="default"):
+    """ws_key names the cached workspace (and its status word), as in tt_encode:
+    calls that may run concurrently on different streams need different keys."""
     lib = L.load()
     prec = _apply_prec(psi, prec)
     if out is None:
@@ -458,7 +460,7 @@ def mpo_apply_batched(psi, mpo, chi, chi_zip=0, cutoff=0.0, tau=0.0, out=None, c
     o = _opts(chi, chi_zip, cutoff, tau, prec, refine)
     nb = lib.tt_workspace_size_batched(L.OP_APPLY, psi.count, psi.n_sites, _cap(psi, out, chi, chi_zip), mpo.d_cap,
                                        o.prec)
-    ws = workspace(nb, psi.cores.device)
+    ws = workspace(nb, psi.cores.device, key=ws_key)
     si, so, w = psi.cstruct(), out.cstruct(), mpo.cstruct()
     sp, sn = (_ptr(saved), saved.numel()) if saved is not None else (None, 0)
     L.check(lib.mpo_apply_batched(ctypes.byref(si), ctypes.byref(w), ctypes.byref(o), _ptr(chi_dev),
@@ -536,7 +538,8 @@ def tt_encode_batched(imgs, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None,
     return out
 
 
-def tt_to_dense_batched(psi, out=None):
+def tt_to_dense_batched(psi, out=None, ws_key="dense"):
+    """ws_key: the cached workspace, as in tt_encode."""
     lib = L.load()
     n = psi.n_sites // 2
     if out is None:
@@ -544,7 +547,7 @@ def tt_to_dense_batched(psi, out=None):
     dt = L.QTT_C128 if out.dtype == torch.complex128 else L.QTT_C64
     nb = lib.tt_workspace_size_batched(L.OP_TO_DENSE, psi.count, psi.n_sites, psi.chi_cap, 1,
                                        L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32)
-    ws = workspace(nb, psi.cores.device, key="dense")
+    ws = workspace(nb, psi.cores.device, key=ws_key)
     s = psi.cstruct()
     L.check(lib.tt_to_dense_batched(ctypes.byref(s), _ptr(out), dt, _ptr(ws), nb, _stream()), "tt_to_dense_batched")
     return out
@@ -560,11 +563,11 @@ class FresnelBatch:
         self.count = len(zs)
 
     def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None, chi_dev=None, prec=None,
-                 refine=False):
+                 refine=False, ws_key="default"):
         mid = mpo_apply_batched(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp, chi_dev=chi_dev, prec=prec,
-                                refine=refine)
+                                refine=refine, ws_key=ws_key)
         return mpo_apply_batched(mid, self.wy, chi, chi_zip, cutoff, tau, out=out, chi_dev=chi_dev, prec=prec,
-                                 refine=refine)
+                                 refine=refine, ws_key=ws_key)
 
 
 class FresnelPropagator:

@@ -314,3 +314,60 @@ def test_concurrent_streams_with_separate_workspaces_match_serial():
     api.check_status("side")
     assert torch.equal(da, ref_a)
     assert torch.equal(pb.cores, rb.cores) and torch.equal(pb.bonds, rb.bonds)
+
+
+@pytest.mark.gpu
+def test_steps_in_flight_on_three_streams_match_serial():
+    """Whole steps (encode, batched propagation, decompression) of different
+    fields issued on three streams at once, each with its own buffers and
+    workspace keys, as the benchmark's concurrent schedule issues them: every
+    result is bit-identical to the same step run alone, and every
+    workspace's status word stays clean."""
+    torch = need_gpu()
+    api = _api()
+    say("steps in flight on three streams")
+    n, chi = 7, 24
+    zs = (20e-6, 50e-6, 80e-6)
+    m = 2 * n
+    prop = api.FresnelBatch(n, LAM, DX, zs, device="cuda")
+    fields = [torch.from_numpy(synth.aperture_field(20 + i, n=1 << n)).to(torch.complex64).cuda()
+              for i in range(6)]
+
+    class Lane:
+        def __init__(self, i):
+            self.s = torch.cuda.Stream()
+            self.psi = api.MPS(m, chi)
+            self.inp, self.mid, self.out = (api.MPSBatch(len(zs), m, chi) for _ in range(3))
+            self.key = "inflight%d" % i
+            self.res = []
+
+        def step(self, f):
+            api.tt_encode(f, chi, out=self.psi, ws_key=self.key)
+            self.inp.fill_from(self.psi)
+            prop(self.inp, chi, tmp=self.mid, out=self.out, ws_key=self.key)
+            self.res.append(api.tt_to_dense_batched(self.out, ws_key=self.key + ".dense"))
+
+    refs = []
+    for f in fields:
+        bi, mid, out = (api.MPSBatch(len(zs), m, chi) for _ in range(3))
+        bi.fill_from(api.tt_encode(f, chi))
+        prop(bi, chi, tmp=mid, out=out)
+        refs.append(api.tt_to_dense_batched(out).clone())
+    torch.cuda.synchronize()
+    lanes = [Lane(i) for i in range(3)]
+    main = torch.cuda.current_stream()
+    for ln in lanes:
+        ln.s.wait_stream(main)
+    for k, f in enumerate(fields):
+        ln = lanes[k % 3]
+        with torch.cuda.stream(ln.s):
+            ln.step(f)
+    for ln in lanes:
+        main.wait_stream(ln.s)
+    torch.cuda.synchronize()
+    api.check_status()
+    for ln in lanes:
+        api.check_status(ln.key)
+        api.check_status(ln.key + ".dense")
+    for k in range(len(fields)):
+        assert torch.equal(lanes[k % 3].res[k // 3], refs[k]), k
