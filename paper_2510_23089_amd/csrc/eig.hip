@@ -927,35 +927,40 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
   // LU with partial pivoting (tridiagonal); pivots stored as reciprocals,
   // pivots smaller than pivmin raised to it.  Step i sees the running
   // diagonal entry dcur = U[i][i] and superdiagonal ducur = U[i][i+1]; rows
-  // i + 1 and beyond are still untouched.
+  // i + 1 and beyond are still untouched.  Every loop below runs whole
+  // blocks of IV_B steps (inputs loaded ahead, no bounds test inside) and
+  // then the remaining steps one by one: a single wave carries the chain,
+  // so every branch inside it is paid in full.
   double dcur = sd[0] - mu, ducur = se[0];
-  for (int i0 = 0; i0 < n - 1; i0 += IV_B) {
+  auto lu_step = [&](int i, double dl, double dn, double en) {
+    const bool piv = fabs(dcur) < fabs(dl);
+    const double di = fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur;
+    const double r = recip(piv ? dl : di);
+    const double f = (piv ? di : dl) * r;
+    F[IX(i)] = make_double2(r, f);
+    U[IX(i)] = make_double2(piv ? dn : ducur, piv ? en : 0.0);
+    P[IX(i)] = piv ? 1 : 0;
+    dcur = fma(-f, piv ? dn : ducur, piv ? ducur : dn);
+    ducur = piv ? -f * en : en;
+  };
+  int i0 = 0;
+  for (; i0 + IV_B <= n - 1; i0 += IV_B) {
     double dl[IV_B], dn[IV_B], en[IV_B];
 #pragma unroll
     for (int u = 0; u < IV_B; ++u) {
-      const int i = min(i0 + u, n - 2);
-      dl[u] = se[i];
-      dn[u] = sd[i + 1] - mu;
-      en[u] = i < n - 2 ? se[i + 1] : 0.0;
+      dl[u] = se[i0 + u];
+      dn[u] = sd[i0 + u + 1] - mu;
+      en[u] = se[i0 + u + 1];                 // se[n - 1] = 0
     }
 #pragma unroll
-    for (int u = 0; u < IV_B; ++u) {
-      const int i = i0 + u;
-      if (i >= n - 1) break;
-      const bool piv = fabs(dcur) < fabs(dl[u]);
-      const double di = fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur;
-      const double r = recip(piv ? dl[u] : di);
-      const double f = (piv ? di : dl[u]) * r;
-      F[IX(i)] = make_double2(r, f);
-      U[IX(i)] = make_double2(piv ? dn[u] : ducur, piv ? en[u] : 0.0);
-      P[IX(i)] = piv ? 1 : 0;
-      dcur = fma(-f, piv ? dn[u] : ducur, piv ? ducur : dn[u]);
-      ducur = piv ? -f * en[u] : en[u];
-    }
+    for (int u = 0; u < IV_B; ++u) lu_step(i0 + u, dl[u], dn[u], en[u]);
   }
+  for (; i0 < n - 1; ++i0) lu_step(i0, se[i0], sd[i0 + 1] - mu, se[i0 + 1]);
   F[IX(n - 1)] = make_double2(recip(fabs(dcur) < pivmin ? copysign(pivmin, dcur) : dcur), 0.0);
+  // start vector: entry i is the i-th draw of the lane's stream
   unsigned long long st = 0x9E3779B97F4A7C15ull ^ ((unsigned long long)(vi + 1) * 0xD1B54A32D192ED03ull) ^
                           ((unsigned long long)(b + 1) * 0x94D049BB133111EBull);
+  for (int i = 0; i < n; ++i) X[IX(i)] = xs_next(st);
   double sc = 1.0;                            // scale of the stored iterate
   double ss = 0.0;                            // sum of squares of the last solution
   // three solves: with the shift accurate to ~eps ||T||, components along
@@ -965,29 +970,25 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
   // floor, and three solves take such components below the FP32 range
   for (int it = 0; it < IV_ITERS; ++it) {
     // forward: L y = P x (row interchanges); the stored x is scaled on load
-    // (the first pass draws x from the start stream instead)
-    double xcur = it == 0 ? xs_next(st) : X[IX(0)] * sc;
-    for (int i0 = 0; i0 < n - 1; i0 += IV_B) {
+    double xcur = X[IX(0)] * sc;
+    auto fw_step = [&](int i, double x1, double dl, bool p) {
+      X[IX(i)] = p ? x1 : xcur;
+      xcur = fma(-dl, p ? x1 : xcur, p ? xcur : x1);
+    };
+    i0 = 0;
+    for (; i0 + IV_B <= n - 1; i0 += IV_B) {
       double xn[IV_B], dl[IV_B];
       unsigned char pv[IV_B];
 #pragma unroll
       for (int u = 0; u < IV_B; ++u) {
-        const int i = min(i0 + u, n - 2);
-        xn[u] = it == 0 ? 0.0 : X[IX(i + 1)] * sc;
-        dl[u] = F[IX(i)].y;
-        pv[u] = P[IX(i)];
+        xn[u] = X[IX(i0 + u + 1)] * sc;
+        dl[u] = F[IX(i0 + u)].y;
+        pv[u] = P[IX(i0 + u)];
       }
 #pragma unroll
-      for (int u = 0; u < IV_B; ++u) {
-        const int i = i0 + u;
-        if (i >= n - 1) break;
-        const double x1 = it == 0 ? xs_next(st) : xn[u];
-        const bool p = pv[u] != 0;
-        X[IX(i)] = p ? x1 : xcur;
-        xcur = fma(-dl[u], p ? x1 : xcur, p ? xcur : x1);
-      }
+      for (int u = 0; u < IV_B; ++u) fw_step(i0 + u, xn[u], dl[u], pv[u] != 0);
     }
-    X[IX(n - 1)] = xcur;
+    for (; i0 < n - 1; ++i0) fw_step(i0, X[IX(i0 + 1)] * sc, F[IX(i0)].y, P[IX(i0)] != 0);
     // backward: U x = y
     double x2 = xcur * F[IX(n - 1)].x;
     X[IX(n - 1)] = x2;
@@ -995,28 +996,31 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
     X[IX(n - 2)] = x1;
     double mx = fmax(fabs(x1), fabs(x2));
     ss = x1 * x1 + x2 * x2;
-    for (int i0 = n - 3; i0 >= 0; i0 -= IV_B) {
+    auto bw_step = [&](int i, double xv, double du, double du2, double dd) {
+      const double x0 = (xv - du * x1 - du2 * x2) * dd;
+      X[IX(i)] = x0;
+      x2 = x1;
+      x1 = x0;
+      mx = fmax(mx, fabs(x0));
+      ss = fma(x0, x0, ss);
+    };
+    i0 = n - 3;
+    for (; i0 >= IV_B - 1; i0 -= IV_B) {
       double xv[IV_B], du[IV_B], du2[IV_B], dd[IV_B];
 #pragma unroll
       for (int u = 0; u < IV_B; ++u) {
-        const int i = max(i0 - u, 0);
-        xv[u] = X[IX(i)];
-        const double2 uu = U[IX(i)];
+        xv[u] = X[IX(i0 - u)];
+        const double2 uu = U[IX(i0 - u)];
         du[u] = uu.x;
         du2[u] = uu.y;
-        dd[u] = F[IX(i)].x;
+        dd[u] = F[IX(i0 - u)].x;
       }
 #pragma unroll
-      for (int u = 0; u < IV_B; ++u) {
-        const int i = i0 - u;
-        if (i < 0) break;
-        const double x0 = (xv[u] - du[u] * x1 - du2[u] * x2) * dd[u];
-        X[IX(i)] = x0;
-        x2 = x1;
-        x1 = x0;
-        mx = fmax(mx, fabs(x0));
-        ss = fma(x0, x0, ss);
-      }
+      for (int u = 0; u < IV_B; ++u) bw_step(i0 - u, xv[u], du[u], du2[u], dd[u]);
+    }
+    for (; i0 >= 0; --i0) {
+      const double2 uu = U[IX(i0)];
+      bw_step(i0, X[IX(i0)], uu.x, uu.y, F[IX(i0)].x);
     }
     sc = mx > 0.0 && isfinite(mx) ? 1.0 / mx : 1.0;
   }
