@@ -317,25 +317,26 @@ def test_concurrent_streams_with_separate_workspaces_match_serial():
 
 
 @pytest.mark.gpu
-def test_steps_in_flight_on_three_streams_match_serial():
+def test_steps_in_flight_on_four_streams_match_serial():
     """Whole steps (encode, batched propagation, decompression) of different
-    fields issued on three streams at once, each with its own buffers and
-    workspace keys, as the benchmark's concurrent schedule issues them: every
-    result is bit-identical to the same step run alone, and every
-    workspace's status word stays clean."""
+    fields issued on four streams at once (the current stream and three
+    more), each with its own buffers and workspace keys, as the benchmark's
+    concurrent schedule issues them: every result is bit-identical to the
+    same step run alone, and every workspace's status word stays clean."""
     torch = need_gpu()
     api = _api()
-    say("steps in flight on three streams")
+    say("steps in flight on four streams")
     n, chi = 7, 24
     zs = (20e-6, 50e-6, 80e-6)
     m = 2 * n
     prop = api.FresnelBatch(n, LAM, DX, zs, device="cuda")
     fields = [torch.from_numpy(synth.aperture_field(20 + i, n=1 << n)).to(torch.complex64).cuda()
-              for i in range(6)]
+              for i in range(8)]
+    main = torch.cuda.current_stream()
 
     class Lane:
         def __init__(self, i):
-            self.s = torch.cuda.Stream()
+            self.s = main if i == 0 else torch.cuda.Stream()
             self.psi = api.MPS(m, chi)
             self.inp, self.mid, self.out = (api.MPSBatch(len(zs), m, chi) for _ in range(3))
             self.key = "inflight%d" % i
@@ -354,12 +355,11 @@ def test_steps_in_flight_on_three_streams_match_serial():
         prop(bi, chi, tmp=mid, out=out)
         refs.append(api.tt_to_dense_batched(out).clone())
     torch.cuda.synchronize()
-    lanes = [Lane(i) for i in range(3)]
-    main = torch.cuda.current_stream()
+    lanes = [Lane(i) for i in range(4)]
     for ln in lanes:
         ln.s.wait_stream(main)
     for k, f in enumerate(fields):
-        ln = lanes[k % 3]
+        ln = lanes[k % 4]
         with torch.cuda.stream(ln.s):
             ln.step(f)
     for ln in lanes:
@@ -370,4 +370,4 @@ def test_steps_in_flight_on_three_streams_match_serial():
         api.check_status(ln.key)
         api.check_status(ln.key + ".dense")
     for k in range(len(fields)):
-        assert torch.equal(lanes[k % 3].res[k // 3], refs[k]), k
+        assert torch.equal(lanes[k % 4].res[k // 4], refs[k]), k
