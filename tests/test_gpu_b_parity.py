@@ -279,9 +279,8 @@ def test_bench_configuration_full_size_vs_oracle():
 
 def test_concurrent_streams_with_separate_workspaces_match_serial():
     """Library calls on two streams at once (an encode with its own workspace
-    on a second stream while a batched propagation runs on the current one,
-    as the benchmark's pipelined schedule issues them) give bit-identical
-    results to the same calls issued serially."""
+    on a second stream while a batched propagation runs on the current one)
+    give bit-identical results to the same calls issued serially."""
     torch = need_gpu()
     api = _api()
     n, chi = 7, 24
