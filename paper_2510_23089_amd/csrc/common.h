@@ -96,6 +96,25 @@ __device__ __forceinline__ double wave_sum_u(double v) {
   v = row16_sum(v);
   return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
+// Uniform wave sums of two values for about the price of one: a v_permlane32_swap
+// gives lanes 0..31 a[l] + a[l + 32] and lanes 32..63 b[l - 32] + b[l], a
+// v_permlane16_swap folds each half onto its two rows, and one row16_sum
+// finishes both; a is then read from lane 0 and b from lane 32.
+__device__ __forceinline__ void wave_sum2_u(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  double v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  const auto l16 = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false,
+                                                    false);
+  const auto h16 = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false,
+                                                    false);
+  v = __hiloint2double((int)h16[0], (int)l16[0]) + __hiloint2double((int)h16[1], (int)l16[1]);
+  v = row16_sum(v);
+  a = lane_d(v, 0);
+  b = lane_d(v, 32);
+}
 template <int TPC>
 __device__ __forceinline__ double seg_sum(double v) {
   static_assert(TPC == 32 || TPC == 64, "segments of 32 or 64 lanes");

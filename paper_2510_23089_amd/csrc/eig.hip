@@ -115,7 +115,8 @@ __device__ __forceinline__ int tri(int r, int c) { return (r * (r + 1) >> 1) + c
 
 template <int NT>
 __device__ double2 block_sum2(double2 v, double* red) {
-  double a = wave_sum(v.x), b = wave_sum(v.y);
+  double a = v.x, b = v.y;
+  wave_sum2_u(a, b);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   __syncthreads();
   if (l == 0) { red[2 * w] = a; red[2 * w + 1] = b; }
@@ -270,8 +271,7 @@ __global__ __launch_bounds__(NT) void tridiag_lds_kernel(double2* Gall, int ld, 
         P[r] = p;
         dl = cmulc(p, V[r]);
       }
-      dl.x = wave_sum_u(dl.x);
-      dl.y = wave_sum_u(dl.y);
+      wave_sum2_u(dl.x, dl.y);
       if (lane == 0) rdot[wv] = dl;
     }
     __syncthreads();
@@ -652,8 +652,7 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
           sx[tid - EIG_NMAX] = x;
         }
       }
-      dl.x = wave_sum_u(dl.x);
-      dl.y = wave_sum_u(dl.y);
+      wave_sum2_u(dl.x, dl.y);
       if (lane == 0) rdot[wv] = dl;
     }
     __syncthreads();
@@ -1184,8 +1183,7 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
       dre += p.x;
       dim_ += p.y;
     }
-    dre = wave_sum_u(dre);
-    dim_ = wave_sum_u(dim_);
+    wave_sum2_u(dre, dim_);
     const double2 f = cmul(tau, make_double2(dre, dim_));
 #pragma unroll
     for (int q = 0; q < PL; ++q) v[q] = csub(v[q], cmul(f, u[q]));

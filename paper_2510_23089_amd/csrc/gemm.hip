@@ -475,7 +475,8 @@ __global__ __launch_bounds__(SK_NT) void gram_skinny_kernel(Operand A, DimExpr M
 #pragma unroll
     for (int j = 0; j <= i; ++j, ++q) {
       if (i < n) {
-        const double sr = wave_sum_u(ar[q]), si = wave_sum_u(ai[q]);
+        double sr = ar[q], si = ai[q];
+        wave_sum2_u(sr, si);
         if (lane == 0) { red[wv][2 * q] = sr; red[wv][2 * q + 1] = si; }
       }
     }
