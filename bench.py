@@ -22,6 +22,11 @@ triangle in LDS) is timed live with HIP events around each of its launches
 during the timed steps, and reports the algorithmic FP64 work (16/3) n^3 of
 each launch from the matrix or block sizes the kernel logs on the device.
 
+parts: the step's parts timed on their own after the timed region: the
+propagations alone (from inputs already encoded, same concurrent lanes: the
+propagations/s of a propagation defined as the x and y applications), and
+the encode and the decompression of one step, one at a time.
+
 cpu_baseline: the float64 oracle (numpy/LAPACK) on the host, on a bounded
 sample of the same workload: encode + one propagation (x then y) at z = 2 mm.
 
@@ -301,6 +306,50 @@ def _traffic():
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 (matrix = vector)
 
 
+def parts_pass(lanes, steps, nz, dev):
+    """The step's parts timed on their own after the timed region: the
+    propagations alone (x then y for the three distances, from inputs already
+    encoded, on the same concurrent lanes), and the encode and the
+    decompression of one step, one at a time on one stream."""
+    import torch
+    main_s = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    def props():
+        for ln in lanes:
+            ln.s.wait_stream(main_s)
+        for k in range(steps):
+            ln = lanes[k % len(lanes)]
+            with torch.cuda.stream(ln.s):
+                ln.propagate()
+        for ln in lanes:
+            main_s.wait_stream(ln.s)
+
+    ln0 = lanes[0]
+    ms_prop = timed(props)
+    ms_enc = timed(lambda: [ln0.encode() for _ in range(steps)])
+    ms_dense = timed(lambda: [ln0.decompress() for _ in range(steps)])
+    for ln in lanes:
+        ln.check()
+    return {"propagation_only": {"propagations_per_s": nz * steps / (ms_prop / 1e3),
+                                 "ms_per_step": ms_prop / steps,
+                                 "what": "x then y for %d distances per step, inputs already encoded, %d steps on "
+                                         "the same %d concurrent lanes" % (nz, steps, len(lanes))},
+            "encode_ms": ms_enc / steps,
+            "decompression_ms": ms_dense / steps,
+            "serial": "encode (one 1024^2 field, chi 128) and decompression (three 1024^2 fields) of one step, "
+                      "one at a time on one stream"}
+
+
 def contraction_pass(lib, L, run, dev, steps=2):
     """Throughput of the contractions (MFMA) in a separate, untimed pass of
     `steps` serial steps: every product and Gram matrix the library enqueues
@@ -380,11 +429,20 @@ def main():
             self.dens = torch.empty((nz, 1 << N_LOG2, 1 << N_LOG2), dtype=torch.complex64, device=dev)
             self.key = "lane%d" % i
 
-        def step(self):
+        def encode(self):
             api.tt_encode(d_field, chi, out=self.psi, ws_key=self.key)
             self.inp.fill_from(self.psi)
+
+        def propagate(self):
             prop(self.inp, chi, tmp=self.mid, out=self.out, ws_key=self.key)
+
+        def decompress(self):
             api.tt_to_dense_batched(self.out, out=self.dens, ws_key=self.key + ".dense")
+
+        def step(self):
+            self.encode()
+            self.propagate()
+            self.decompress()
 
         def check(self):
             api.check_status(self.key)
@@ -450,6 +508,7 @@ def main():
     achieved = flops / nl / avg_launch_s / 1e12 if launches.value else 0.0
 
     mfma = contraction_pass(lib, L, run, dev)
+    parts = parts_pass(lanes, a.steps, nz, dev)
 
     value = nz / (ms / 1e3)
     res = {
@@ -474,6 +533,7 @@ def main():
                                "same steps one at a time on one stream" % (len(lanes), len(lanes) - 1),
                    "autotuned_contraction_shapes": n_tuned},
         "serial_ms_per_step": serial_ms,
+        "parts": parts,
         "roofline": {
             "kernel": "qtt::tridiag_lds_kernel (Householder reduction to tridiagonal form, FP64 Gram "
                       "eigensolver, one workgroup per matrix with its packed lower triangle in LDS: "
