@@ -1041,32 +1041,42 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
 // Runs of kept eigenvalues closer than reltol * |lambda_1| form clusters;
 // each cluster's vectors get classical Gram-Schmidt twice, member by member
 // (the first member stays).  A cluster whose vectors fit in LDS is
-// orthogonalised there and written back once; a larger one works on the
-// eigenvector scratch in place.  Dots: one wave per earlier member, lanes
-// over rows, DPP sums.
+// orthogonalised there (rows at a stride of 8 mod 32 doubles, so that the
+// segment reads below hit distinct banks) and written back once; a larger
+// one works on the eigenvector scratch in place.  The workgroup is split
+// into 128 segments of 8 lanes: the dots <z_s, z_j> take one segment each
+// (all earlier members in one round, 8-lane DPP sums), and the update of
+// z_j takes one segment per row, its 8 lanes over the earlier members.
 constexpr int CL_NT = 1024;
 constexpr int CL_LDS = 12 * 1024;             // doubles of cluster vectors held in LDS (96 KB)
+constexpr int CL_SEG = 8;                     // lanes per segment
+constexpr int CL_NSEG = CL_NT / CL_SEG;
 
-template <bool IN_LDS>
+__host__ __device__ inline int cl_ld(int n) { return (n + 23) / 32 * 32 + 8; }   // >= n, = 8 mod 32
+
 __device__ void cluster_gs(double* Z, int ldz, int m, int n, double* coef, double* red) {
   constexpr int NW = CL_NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int sg = tid / CL_SEG, sl = tid - sg * CL_SEG;
   for (int j = 1; j < m; ++j) {
     double* zj = Z + (long long)j * ldz;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int s0 = 0; s0 < j; s0 += NW) {
-        const int s = s0 + wv;
+      for (int s0 = 0; s0 < j; s0 += CL_NSEG) {
+        const int s = s0 + sg;
         double d = 0.0;
         if (s < j)
-          for (int i = lane; i < n; i += 64) d = fma(Z[(long long)s * ldz + i], zj[i], d);
-        d = wave_sum_u(d);
-        if (s < j && lane == 0) coef[s] = d;
+          for (int i = sl; i < n; i += CL_SEG) d = fma(Z[(long long)s * ldz + i], zj[i], d);
+        d = seg8_sum(d);
+        if (s < j && sl == CL_SEG - 1) coef[s] = d;
       }
       __syncthreads();
-      for (int i = tid; i < n; i += CL_NT) {
-        double v = zj[i];
-        for (int s = 0; s < j; ++s) v = fma(-coef[s], Z[(long long)s * ldz + i], v);
-        zj[i] = v;
+      for (int i0 = 0; i0 < n; i0 += CL_NSEG) {
+        const int i = i0 + sg;
+        double v = 0.0;
+        if (i < n)
+          for (int s = sl; s < j; s += CL_SEG) v = fma(coef[s], Z[(long long)s * ldz + i], v);
+        v = seg8_sum(v);
+        if (i < n && sl == CL_SEG - 1) zj[i] -= v;
       }
       __syncthreads();
     }
@@ -1107,20 +1117,21 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
     const int m = t - cs;                     // cluster [cs, t)
     if (m > 1) {
       double* zg = W.z + (long long)cs * nb;
-      if ((long long)m * n <= CL_LDS) {
+      const int ldz = cl_ld(n);
+      if ((long long)m * ldz <= CL_LDS) {
         for (int e = threadIdx.x; e < m * n; e += CL_NT) {
           const int j = e / n, i = e - j * n;
-          zs[e] = zg[(long long)j * nb + i];
+          zs[j * ldz + i] = zg[(long long)j * nb + i];
         }
         __syncthreads();
-        cluster_gs<true>(zs, n, m, n, coef, red);
+        cluster_gs(zs, ldz, m, n, coef, red);
         for (int e = threadIdx.x; e < m * n; e += CL_NT) {
           const int j = e / n, i = e - j * n;
-          if (j > 0) zg[(long long)j * nb + i] = zs[e];
+          if (j > 0) zg[(long long)j * nb + i] = zs[j * ldz + i];
         }
         __syncthreads();
       } else {
-        cluster_gs<false>(zg, nb, m, n, coef, red);
+        cluster_gs(zg, nb, m, n, coef, red);
       }
     }
     cs = t;
