@@ -823,24 +823,27 @@ __global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, dou
   const int n = min(dim_eval(nexp, b), nb);
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double red[KP_NT / 64];
+  __shared__ double slam[EIG_NMAX];
   __shared__ int s_k;
   const int kmax = min(min(n, kcap), kcap_dev ? max(kcap_dev[b], 1) : kcap);
+  // the eigenvalues the scan below reads, staged with independent loads
+  for (int t = threadIdx.x; t < kmax; t += KP_NT) slam[t] = W.lam[t];
   double loc = 0.0;
   for (int i = threadIdx.x; i < n; i += KP_NT) loc += W.d[i];
   const double total = block_sum<KP_NT>(loc, red);     // trace = sum of all eigenvalues
   if (threadIdx.x == 0) {
-    const double l0 = W.lam[0];
+    const double l0 = slam[0];
     int k = 0;
     bool bad = !isfinite(l0) || !isfinite(total);
     if (!bad && l0 > 0.0) {
       for (int t = 0; t < kmax; ++t) {
-        if (W.lam[t] > tau * l0) k = t + 1;
+        if (slam[t] > tau * l0) k = t + 1;
         else break;
       }
       if (cutoff > 0.0) {
         double kept = 0.0;
         for (int t = 0; t < k; ++t) {
-          kept += fmax(W.lam[t], 0.0);
+          kept += fmax(slam[t], 0.0);
           if (total - kept <= cutoff * total) { k = t + 1; break; }
         }
       }
@@ -853,7 +856,7 @@ __global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, dou
   __syncthreads();
   const int k = s_k;
   for (int t = threadIdx.x; t < kmax; t += KP_NT) {
-    double sg = W.lam[t] > 0.0 ? sqrt(W.lam[t]) : 0.0;
+    double sg = slam[t] > 0.0 ? sqrt(slam[t]) : 0.0;
     W.sig[t] = sg;
     if (sigma_out) sigma_out[(long long)b * kcap + t] = t < k ? sg : 0.0;
   }
