@@ -115,6 +115,33 @@ __device__ __forceinline__ void wave_sum2_u(double& a, double& b) {
   a = lane_d(v, 0);
   b = lane_d(v, 32);
 }
+// Uniform wave sums of three complex values (six reals) in one pass: the
+// permlane32 swaps fold the pairs (a.x, a.y), (b.x, b.y), (c.x, c.y) onto the
+// wave halves; a permlane16 swap then folds the first two results onto rows
+// (a.x, b.x, a.y, b.y) and the third onto (c.x, c.x, c.y, c.y); two row16_sums
+// finish them and readlane picks each row's total.
+__device__ __forceinline__ double2 pl32_fold(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  return make_double2(__hiloint2double((int)hi[0], (int)lo[0]), __hiloint2double((int)hi[1], (int)lo[1]));
+}
+__device__ __forceinline__ double2 pl16_fold(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  return make_double2(__hiloint2double((int)hi[0], (int)lo[0]), __hiloint2double((int)hi[1], (int)lo[1]));
+}
+__device__ __forceinline__ void wave_sum3c_u(double2& a, double2& b, double2& c) {
+  const double2 p = pl32_fold(a.x, a.y), q = pl32_fold(b.x, b.y), r = pl32_fold(c.x, c.y);
+  const double2 s2 = pl16_fold(p.x + p.y, q.x + q.y), t2 = pl16_fold(r.x + r.y, r.x + r.y);
+  const double s = row16_sum(s2.x + s2.y), t = row16_sum(t2.x + t2.y);
+  a = make_double2(lane_d(s, 0), lane_d(s, 32));
+  b = make_double2(lane_d(s, 16), lane_d(s, 48));
+  c = make_double2(lane_d(t, 0), lane_d(t, 32));
+}
 template <int TPC>
 __device__ __forceinline__ double seg_sum(double v) {
   static_assert(TPC == 32 || TPC == 64, "segments of 32 or 64 lanes");

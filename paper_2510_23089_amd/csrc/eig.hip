@@ -1202,14 +1202,51 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
 #pragma unroll
     for (int q = 0; q < PL; ++q) v[q] = csub(v[q], cmul(f, u[q]));
   };
+  // reflectors j (first) and j - 1 together: with a = u1^H x, b = u2^H x and
+  // c = u2^H u1 from one reduction, x -= f1 u1 + f2 u2 with f1 = tau_j a and
+  // f2 = tau_{j-1} (b - f1 c)
+  auto apply_pair = [&](double2* u1, int j, double2* u2) {
+    const double2 t1 = stau[j], t2 = stau[j - 1];
+    double2 a = make_double2(0.0, 0.0), bb = a, c = a;
+#pragma unroll
+    for (int q = 0; q < PL; ++q) {
+      int i = lane + 64 * q;
+      if (i == j + 1) u1[q] = make_double2(1.0, 0.0);
+      if (i == j) u2[q] = make_double2(1.0, 0.0);
+      a = cadd(a, cmulc(u1[q], v[q]));
+      bb = cadd(bb, cmulc(u2[q], v[q]));
+      c = cadd(c, cmulc(u2[q], u1[q]));
+    }
+    wave_sum3c_u(a, bb, c);
+    const double2 f1 = cmul(t1, a);
+    const double2 f2 = cmul(t2, csub(bb, cmul(f1, c)));
+#pragma unroll
+    for (int q = 0; q < PL; ++q) v[q] = csub(v[q], cadd(cmul(f1, u1[q]), cmul(f2, u2[q])));
+  };
 #pragma unroll
   for (int d = 0; d < DEPTH; ++d) load_u(ub[d], n - 2 - d);
-  for (int j = n - 2; j >= 0; j -= DEPTH) {
+  if constexpr (DEPTH % 2 == 0) {
+    for (int j = n - 2; j >= 0; j -= DEPTH) {
 #pragma unroll
-    for (int d = 0; d < DEPTH; ++d) {
-      if (j - d < 0) break;
-      apply_u(ub[d], j - d);
-      load_u(ub[d], j - d - DEPTH);
+      for (int d = 0; d < DEPTH; d += 2) {
+        const int jj = j - d;
+        if (jj >= 1) {
+          apply_pair(ub[d], jj, ub[d + 1]);
+          load_u(ub[d], jj - DEPTH);
+          load_u(ub[d + 1], jj - 1 - DEPTH);
+        } else if (jj == 0) {                 // an odd count ends on one reflector
+          apply_u(ub[d], 0);
+        }
+      }
+    }
+  } else {
+    for (int j = n - 2; j >= 0; j -= DEPTH) {
+#pragma unroll
+      for (int d = 0; d < DEPTH; ++d) {
+        if (j - d < 0) break;
+        apply_u(ub[d], j - d);
+        load_u(ub[d], j - d - DEPTH);
+      }
     }
   }
   const double sg = W.sig[t];
