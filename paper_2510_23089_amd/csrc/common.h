@@ -142,6 +142,16 @@ __device__ __forceinline__ void wave_sum3c_u(double2& a, double2& b, double2& c)
   b = make_double2(lane_d(s, 16), lane_d(s, 48));
   c = make_double2(lane_d(t, 0), lane_d(t, 32));
 }
+// Sums of two values over each 32-lane half of the wave, valid in lanes 31 and
+// 63: a permlane16 fold leaves x's 16-lane partials on rows 0 and 2 and y's on
+// rows 1 and 3, one row16_sum finishes both, and row_bcast:15 brings each
+// half's x total to the row that holds its y total.
+__device__ __forceinline__ void seg32_sum2(double& x, double& y) {
+  const double2 f = pl16_fold(x, y);
+  const double v = row16_sum(f.x + f.y);
+  y = v;
+  x = dpp_d<0x142, 0xA>(v);
+}
 template <int TPC>
 __device__ __forceinline__ double seg_sum(double v) {
   static_assert(TPC == 32 || TPC == 64, "segments of 32 or 64 lanes");

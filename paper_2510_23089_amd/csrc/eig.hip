@@ -127,6 +127,25 @@ __device__ double2 block_sum2(double2 v, double* red) {
   return s;
 }
 
+// Pairwise sums of the per-wave partials (a dependency chain of log2 N adds
+// instead of N); N is a power of two, every lane gets the same bits.
+template <int N>
+__device__ __forceinline__ double tree_sum(const double* a) {
+  if constexpr (N == 1) {
+    return a[0];
+  } else {
+    return tree_sum<N / 2>(a) + tree_sum<N / 2>(a + N / 2);
+  }
+}
+template <int N>
+__device__ __forceinline__ double2 tree_sum2(const double2* a) {
+  if constexpr (N == 1) {
+    return a[0];
+  } else {
+    return cadd(tree_sum2<N / 2>(a), tree_sum2<N / 2>(a + N / 2));
+  }
+}
+
 __device__ void householder(double2 alpha, double xnorm2, double2& tau, double2& scale, double& beta) {
   if (xnorm2 == 0.0 && alpha.y == 0.0) {
     tau = make_double2(0.0, 0.0);
@@ -212,9 +231,7 @@ __global__ __launch_bounds__(NT) void tridiag_lds_kernel(double2* Gall, int ld, 
     // ---- reflector of column j: threads tid in [j1, n) form and write it
     //      (two waves at most compute the Householder scalars)
     if (wv * 64 + 63 >= j1 && wv * 64 < n) {
-      double xnorm2 = 0.0;
-#pragma unroll
-      for (int i = 0; i < NW; ++i) xnorm2 += rnorm[i];
+      const double xnorm2 = tree_sum<NW>(rnorm);
       double2 tau, scale;
       double beta;
       householder(L[tri(j1, j)], xnorm2, tau, scale, beta);
@@ -278,9 +295,7 @@ __global__ __launch_bounds__(NT) void tridiag_lds_kernel(double2* Gall, int ld, 
     // ---- w = p + alpha2 v, alpha2 = -(tau/2)(p^H v), kept per row for the
     //      deferred update; column j1 is updated now (the next reflector
     //      needs it), with the partial sums of its norm below row j1 + 1
-    double2 dot = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < NW; ++i) dot = cadd(dot, rdot[i]);
+    const double2 dot = tree_sum2<NW>(rdot);
     const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
     double loc = 0.0;
     if (tid >= j1 && tid < n) {
@@ -563,9 +578,7 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
     //         hold rows k + 1 .. n - 1; the others take tau after the barrier
     double2 scale = make_double2(0.0, 0.0);
     if (wv * 64 + 63 >= k1 && wv * 64 < n) {
-      double xnorm2 = 0.0;
-#pragma unroll
-      for (int i = 0; i < NW; ++i) xnorm2 += rnorm[i];
+      const double xnorm2 = tree_sum<NW>(rnorm);
       double2 tau;
       double beta;
       householder(s_alpha, xnorm2, tau, scale, beta);
@@ -610,8 +623,12 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
       double2 acc = make_double2(0.0, 0.0);
       if (act)
         for (int r = rbeg; r < n; r += TPC) acc = cadd(acc, cmulc(Ac[mc * n + r], sv[r]));
-      acc.x = seg_sum<TPC>(acc.x);
-      acc.y = seg_sum<TPC>(acc.y);
+      if constexpr (TPC == 64) {
+        wave_sum2_u(acc.x, acc.y);
+      } else {
+        static_assert(TPC == 32, "columns owned by 32 or 64 threads");
+        seg32_sum2(acc.x, acc.y);
+      }
       if (act && lt == TPC - 1) tag_store(xp + (size_t)c * 4, cmul(tau, acc), (unsigned)k1);
     }
     if (k1 >= c0 && k1 < c0 + cn) {
@@ -657,9 +674,7 @@ __global__ __launch_bounds__(MW_NT) void tridiag_mwg_kernel(double2* Gall, int l
     }
     __syncthreads();
     if (s_bad) return;
-    double2 dot = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int i = 0; i < NW; ++i) dot = cadd(dot, rdot[i]);
+    const double2 dot = tree_sum2<NW>(rdot);
     // w = p + alpha2 v,  alpha2 = -(tau/2)(p^H v)
     const double2 alpha2 = cmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), dot);
     if (!DEFER && act) {
