@@ -49,7 +49,13 @@
  *   caller-owned device workspace `ws` of at least tt_workspace_size(...)
  *   bytes; its first 256 bytes hold the device status word.
  * Streams.  Every call is enqueued on `stream` (a hipStream_t; NULL = the
- *   default stream) and returns without synchronising.
+ *   default stream) and returns without synchronising.  Calls on one stream
+ *   may share a workspace (they run in stream order); calls that may run at
+ *   the same time on different streams need disjoint workspaces and disjoint
+ *   outputs, since the workspace holds the call's scratch and status word.
+ *   The library keeps no device state of its own between calls (the
+ *   autotuned tile table and the profiling hooks are host-side), so calls on
+ *   different streams with their own workspaces do not interact.
  * Errors.  Argument errors are detected on the host before anything is
  *   enqueued and returned as negative codes.  Numerical failures (non-finite
  *   values reaching an eigensolver) are recorded in the device status word
