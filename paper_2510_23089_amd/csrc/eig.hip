@@ -839,22 +839,26 @@ __global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, dou
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double red[KP_NT / 64];
   __shared__ double slam[EIG_NMAX];
-  __shared__ int s_k;
+  __shared__ int s_k, s_first;
   const int kmax = min(min(n, kcap), kcap_dev ? max(kcap_dev[b], 1) : kcap);
-  // the eigenvalues the scan below reads, staged with independent loads
+  // the eigenvalues the rule reads, staged with independent loads
   for (int t = threadIdx.x; t < kmax; t += KP_NT) slam[t] = W.lam[t];
+  if (threadIdx.x == 0) s_first = kmax;
   double loc = 0.0;
   for (int i = threadIdx.x; i < n; i += KP_NT) loc += W.d[i];
   const double total = block_sum<KP_NT>(loc, red);     // trace = sum of all eigenvalues
+  const double l0 = slam[0];
+  const bool bad = !isfinite(l0) || !isfinite(total);
+  const bool pos = !bad && l0 > 0.0;
+  // the first eigenvalue not above tau * lambda_1 (NaN included), in parallel
+  if (pos)
+    for (int t = threadIdx.x; t < kmax; t += KP_NT)
+      if (!(slam[t] > tau * l0)) atomicMin(&s_first, t);
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double l0 = slam[0];
     int k = 0;
-    bool bad = !isfinite(l0) || !isfinite(total);
-    if (!bad && l0 > 0.0) {
-      for (int t = 0; t < kmax; ++t) {
-        if (slam[t] > tau * l0) k = t + 1;
-        else break;
-      }
+    if (pos) {
+      k = s_first;
       if (cutoff > 0.0) {
         double kept = 0.0;
         for (int t = 0; t < k; ++t) {
