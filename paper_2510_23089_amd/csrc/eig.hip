@@ -1126,6 +1126,7 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
   __shared__ double coef[EIG_NMAX];
   __shared__ double slam[EIG_NMAX];
   __shared__ double zs[CL_LDS];
+  __shared__ unsigned long long jmask[EIG_NMAX / 64];
   const double tn = fabs(W.lam[0]);
   int joins = 0;
   for (int t = threadIdx.x; t < k; t += CL_NT) {
@@ -1133,11 +1134,33 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
     if (t > 0 && !(W.lam[t - 1] - W.lam[t] > reltol * tn)) joins = 1;
   }
   if (!__syncthreads_or(joins)) return;       // no clusters: nothing to do
-  int cs = 0;
-  for (int t = 1; t <= k; ++t) {
-    if (t < k && !(slam[t - 1] - slam[t] > reltol * tn)) continue;
-    const int m = t - cs;                     // cluster [cs, t)
-    if (m > 1) {
+  // bit t of the mask: eigenvalue t (1 <= t < k) joins t - 1; one ballot per
+  // 64 indices, then the runs of set bits are visited without touching the
+  // singletons between them
+  const int nwords = (k + 63) >> 6;
+  {
+    const int w = threadIdx.x >> 6, t = threadIdx.x;
+    if (w < nwords) {
+      const bool j = t >= 1 && t < k && !(slam[t - 1] - slam[t] > reltol * tn);
+      const unsigned long long word = __ballot(j);
+      if ((threadIdx.x & 63) == 0) jmask[w] = word;
+    }
+  }
+  __syncthreads();
+  int tnext = 1;
+  while (tnext < k) {
+    // first joined index s >= tnext, then the first index e > s that does not join
+    int w = tnext >> 6;
+    unsigned long long word = jmask[w] & (~0ull << (tnext & 63));
+    while (word == 0 && ++w < nwords) word = jmask[w];
+    if (word == 0) break;
+    const int s = w * 64 + __ffsll((long long)word) - 1;
+    unsigned long long gap = ~jmask[w] & (~0ull << (s & 63));
+    while (gap == 0 && ++w < nwords) gap = ~jmask[w];
+    const int te = gap == 0 ? k : min(w * 64 + __ffsll((long long)gap) - 1, k);
+    const int cs = s - 1, m = te - cs;        // cluster [cs, te), m >= 2
+    tnext = te + 1;
+    {
       double* zg = W.z + (long long)cs * nb;
       const int ldz = cl_ld(n);
       if ((long long)m * ldz <= CL_LDS) {
@@ -1156,7 +1179,6 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
         cluster_gs(zg, nb, m, n, coef, red);
       }
     }
-    cs = t;
   }
 }
 
