@@ -34,6 +34,40 @@ def _keep(s, rel):
     return max(1, int(np.argmax(tail <= rel * rel * tot)) + 1)
 
 
+def round_left(cores, rel=1e-12):
+    """Left-canonical rounding of an operator MPO: an LQ sweep right to left
+    (every core right of the cut an isometry), then an SVD sweep left to
+    right keeping at each bond the singular values whose discarded squared
+    weight is at most rel^2 / (n-1) of the total, minus numerical zeros
+    (sigma_i <= 1e-13 sigma_1).  The left singular vectors stay as the cores
+    and S V^H moves right, so the result is the form the sequential SVD of
+    the dense operator produces (Sec. 6.1, brute-force MPO construction): every
+    core but the last left-orthonormal as a (D_l * 4) x D_r matrix, the
+    operator's weight in the last core, bonds equal to the Schmidt ranks at
+    that cutoff.  The truncating zip-up sees the operator's left bond through
+    its Gram matrices, which are invariant only under unitary changes of the
+    bond basis, so this canonical form fixes what the zip-up computes."""
+    c = [np.asarray(x, dtype=np.complex128) for x in cores]
+    n = len(c)
+    if n == 1:
+        return c
+    for k in range(n - 1, 0, -1):
+        dl, _, _, dr = c[k].shape
+        q, r = np.linalg.qr(c[k].reshape(dl, 4 * dr).conj().T)
+        c[k] = q.conj().T.reshape(-1, 2, 2, dr)
+        c[k - 1] = np.tensordot(c[k - 1], r.conj().T, axes=(3, 0))
+    per = rel / np.sqrt(n - 1)
+    for k in range(n - 1):
+        dl, _, _, dr = c[k].shape
+        u, s, vh = np.linalg.svd(c[k].reshape(dl * 4, dr), full_matrices=False)
+        d = _keep(s, per)
+        if s[0] > 0.0:
+            d = min(d, max(1, int(np.count_nonzero(s > 1e-13 * s[0]))))
+        c[k] = u[:, :d].reshape(dl, 2, 2, d)
+        c[k + 1] = np.tensordot(s[:d, None] * vh[:d], c[k + 1], axes=(1, 0))
+    return c
+
+
 def compress(cores, rel=1e-13):
     """Recompress an MPO: QR sweep left to right, then SVD sweep right to left
     keeping per bond a relative discarded weight <= rel^2 / (n-1)."""
@@ -162,11 +196,13 @@ def diag_br(n, lam, dx, z, rel=1e-14):
 
 # ------------------------------------------------------------------ propagator
 def fresnel_axis(n, lam, dx, z, rel=1e-12):
-    """Per-axis real-space Fresnel propagator QFT_br^H diag_br(T) QFT_br."""
+    """Per-axis real-space Fresnel propagator QFT_br^H diag_br(T) QFT_br, in
+    the left-canonical form of `round_left` (discarded weight rel^2 / (n-1)
+    per bond)."""
     q = qft_br(n)
     d = diag_br(n, lam, dx, z)
     dq = compress(mul(d, q), rel * 1e-2)
-    return compress(mul(dagger(q), dq), rel)
+    return round_left(compress(mul(dagger(q), dq), rel * 1e-2), rel)
 
 
 def identity_core(d):
