@@ -356,6 +356,26 @@ int tt_autotune_export(int32_t* entries, int max_entries);
 int tt_autotune_import(const int32_t* entries, int n);
 int tt_autotune_clear(void);
 
+/* ---- allocation-free application ----
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same computation, kernels and results as mpo_apply (no saved
+ * buffer), with the workspace taken from a static device array of
+ * QTT_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (address looked up once per device; the stream's
+ * device must be the current device).  Nothing is allocated by the call.
+ * Problems whose workspace (tt_workspace_size for these exact sizes) exceeds
+ * the array are rejected with QTT_ERR_WORKSPACE before anything is enqueued.
+ * The array's status word is cleared at the start of every call and, if
+ * status_out (device int) is non-NULL, copied there at the end (QTT_OK or a
+ * negative qtt_status), in stream order.  Every call on one GPU shares the
+ * array and it keeps the last call's contents: calls that may overlap on one
+ * GPU (different streams, or several host threads) race and must be
+ * serialised by the caller. */
+#define QTT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mpo_apply_noalloc(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts, qtt_mps* out,
+                      int32_t* status_out, void* stream);
+
 /* Synchronise `stream`, read the device status word in ws, reset it to 0 and
  * return it (QTT_OK or a negative qtt_status). */
 int tt_check_status(void* ws, void* stream);

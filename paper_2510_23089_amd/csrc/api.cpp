@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2001,6 +2002,67 @@ int tt_autotune_import(const int32_t* entries, int n) {
 int tt_autotune_clear(void) {
   g_err.clear();
   autotune_clear();
+  return QTT_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free application --------------------------------------------
+// The workspace of mpo_apply_noalloc is this file-scope device array: every
+// GPU the library runs on holds its own copy (QTT_NOALLOC_SCRATCH_BYTES) until
+// the process ends, and every call on that GPU reuses it.  In host code the
+// array's name is only a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+namespace {
+__device__ __align__(256) unsigned char scratch[QTT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+int scratch_ptr(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(QTT_ERR_ARG, "device %d outside [0, %d)", dev, kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail(QTT_ERR_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    if (!p) return fail(QTT_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QTT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mpo_apply_noalloc(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts, qtt_mps* out,
+                      int32_t* status_out, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if ((r = check_mps(out, "out"))) return r;
+  if (in->cores == out->cores) return fail(QTT_ERR_ARG, "in and out must not alias");
+  if (!W) return fail(QTT_ERR_ARG, "MPO is NULL");
+  ApplySetup su;
+  if ((r = apply_setup(view(in), W, nullptr, opts, view(out), false, su))) return r;
+  const size_t need = apply_bytes(su.p, su.csz, 1);
+  if (need > QTT_NOALLOC_SCRATCH_BYTES)
+    return fail(QTT_ERR_WORKSPACE, "mpo_apply_noalloc: this problem needs %zu bytes of scratch, the static "
+                "scratch holds %zu (use mpo_apply with a caller workspace)", need, (size_t)QTT_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((r = scratch_ptr(&ws))) return r;
+  hipStream_t s = (hipStream_t)stream;
+  // the status word starts at zero on every call (a fill kernel, not a
+  // memset node, so the call can be captured into a graph)
+  HIPCHK(zero_fill(ws, 256, s));
+  if ((r = apply_common(view(in), W, nullptr, opts, view(out), nullptr, ws, QTT_NOALLOC_SCRATCH_BYTES, stream,
+                        false)))
+    return r;
+  if (status_out) HIPCHK(copy_ints((const int*)ws, status_out, 1, s));
   return QTT_OK;
 }
 
