@@ -1,34 +1,40 @@
 """Benchmark: MPO x MPS Fresnel propagations per second at 2^20 px, chi = 128.
 
-Workload (one step): one seeded 1024 x 1024 complex64 field (disk aperture of
-radius 300 px, 1/f^2-power amplitude modulation, smoothed random phase) is
-encoded into a 20-site quantics MPS (chi 128); the Fresnel MPO (lambda 500 nm,
-pixel 1 um) propagates it to z = 0.5, 2 and 8 mm -- each propagation is a
-zip-up + truncation sweep for the x axis then the y axis at chi 128, the three
-distances advancing as one batch -- and each result is decompressed to the
-1024 x 1024 grid.  value = propagations / s over the whole step (encode and
-decompression included).  A step is a chain of ~95 dependent truncations,
-each an FP64 eigensolve of one to three small matrices, so one step alone
-leaves most compute units idle: independent steps run concurrently, step k
-on stream k mod S (S = --inflight, default 4: the main stream and three
-more), each stream with its own buffers and library workspaces.  serial_ms_per_step times the same steps one
-at a time on one stream (the latency of a step).  Inputs are resident in HBM
-before the timed region; the host float64 MPO construction is setup.
+Workload (one step): B (--fields-per-step, default 4) seeded 1024 x 1024
+complex64 fields (disk aperture of radius 300 px, 1/f^2-power amplitude
+modulation, smoothed random phase; seeds 0..B-1) are encoded into 20-site
+quantics MPS (chi 128) by one batched encode; the Fresnel MPO (lambda 500 nm,
+pixel 1 um) propagates each to z = 0.5, 2 and 8 mm -- each propagation is a
+zip-up + truncation sweep for the x axis then the y axis at chi 128, the 3B
+(field, distance) members advancing as one batch -- and every result is
+decompressed to the 1024 x 1024 grid.  value = propagations / s over whole
+steps (encode and decompression included).  A step is a chain of ~95
+dependent truncations, each an FP64 eigensolve of one small matrix per
+member, so independent steps also run concurrently: step k on stream k mod
+S (S = --inflight, default 2: the main stream and one more), each stream
+with its own buffers and library workspaces.  Nothing else runs inside the
+timed region.  serial_ms_per_step: one field's step (its three distances as
+one batch) timed alone on one stream, i.e. the latency of a single field.
+Inputs are resident in HBM before the timed region; the host float64 MPO
+construction is setup.
 
 The dominant kernel (qtt::tridiag_lds_kernel, the Householder
 tridiagonalisation of the FP64 Gram matrices up to 128 and of the trailing
 128 x 128 block of wider ones, one workgroup per matrix with the packed
-triangle in LDS) is timed live with HIP events around each of its launches
-during the timed steps, and reports the algorithmic FP64 work (16/3) n^3 of
-each launch from the matrix or block sizes the kernel logs on the device.
+triangle in LDS) is timed in a pass of its own right after the timed region
+(same steps, same lanes), with HIP events around each of its launches on
+their streams, and reports the algorithmic FP64 work (16/3) n^3 of each
+launch from the matrix or block sizes the kernel logs on the device; its
+time per step and share of a step come from a serial pass.
 
-parts: the step's parts timed on their own after the timed region: the
-propagations alone (from inputs already encoded, same concurrent lanes: the
-propagations/s of a propagation defined as the x and y applications), and
-the encode and the decompression of one step, one at a time.
+parts: a single field's step split into its parts, timed on their own after
+the timed region on one stream: the propagations alone (its three distances
+from inputs already encoded: a propagation is the x and y applications), the
+encode and the decompression.
 
 cpu_baseline: the float64 oracle (numpy/LAPACK) on the host, on a bounded
-sample of the same workload: encode + one propagation (x then y) at z = 2 mm.
+sample of the same workload: one propagation (x then y) of the first field
+at z = 2 mm, median of three runs (its encode reported beside it).
 
 batched (the uneven-batch precision form): 256 fields with side 2^k, k
 uniform in {8..11}, and bond caps uniform in {16, 32, 64, 128} (seeded draws),
@@ -74,12 +80,16 @@ TRAFFIC = {"src_sha256_prefix": "ac66566e2bff046f", "bytes_per_launch": (98.11 *
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=32)
-    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--steps", type=int, default=24)
+    p.add_argument("--warmup", type=int, default=2, help="warm-up steps per lane")
+    p.add_argument("--fields-per-step", type=int, default=4,
+                   help="independent 1024^2 fields per step, each propagated to the three distances as one batch")
+    p.add_argument("--serial-steps", type=int, default=8)
+    p.add_argument("--no-parts", action="store_true")
     p.add_argument("--chi", type=int, default=CHI)
-    p.add_argument("--inflight", type=int, default=4,
+    p.add_argument("--inflight", type=int, default=2,
                    help="independent steps executing concurrently, one stream each: the main stream and "
-                        "inflight - 1 more (4 fills the HIP runtime's default of four hardware queues)")
+                        "inflight - 1 more (at most 4: the HIP runtime's default of four hardware queues)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-grad", action="store_true")
     p.add_argument("--no-batched", action="store_true")
@@ -115,20 +125,26 @@ def cpu_baseline(field, chi):
         pass
     c = OM.mpo_from_matrix(F.fresnel_matrix_1d(1 << N_LOG2, LAM, DX, 2e-3), N_LOG2)
     wx, wy = OM.embed_axis(c, "x"), OM.embed_axis(c, "y")
-    t0 = time.perf_counter()
-    cores = T.tt_svd(Q.to_quantics(field), 2 * N_LOG2, chi)
-    t1 = time.perf_counter()
-    c1, _ = Z.mpo_apply(cores, wx, chi)
-    Z.mpo_apply(c1, wy, chi)
-    t2 = time.perf_counter()
-    t_prop = t2 - t1
+    t_enc, t_props = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        cores = T.tt_svd(Q.to_quantics(field), 2 * N_LOG2, chi)
+        t1 = time.perf_counter()
+        c1, _ = Z.mpo_apply(cores, wx, chi)
+        Z.mpo_apply(c1, wy, chi)
+        t2 = time.perf_counter()
+        t_enc.append(t1 - t0)
+        t_props.append(t2 - t1)
+    t_prop = float(np.median(t_props))
+    t_e = float(np.median(t_enc))
     return {
         "value": 1.0 / t_prop,
         "unit": "propagations/s",
         "cores": threads or os.cpu_count(),
         "kind": "oracle",
         "sample": "float64 numpy/LAPACK oracle on the host: one propagation (x then y, z=2 mm, chi %d) of "
-                  "the same 1024^2 field (%.2f s); its encode (%.2f s) is not in value" % (chi, t_prop, t1 - t0),
+                  "the first 1024^2 field, median of 3 runs (%.2f s); its encode (median %.2f s) is not in value"
+                  % (chi, t_prop, t_e),
         "cpu": _cpu_model(),
     }
 
@@ -342,11 +358,11 @@ def parts_pass(lanes, steps, nz, dev):
         ln.check()
     return {"propagation_only": {"propagations_per_s": nz * steps / (ms_prop / 1e3),
                                  "ms_per_step": ms_prop / steps,
-                                 "what": "x then y for %d distances per step, inputs already encoded, %d steps on "
-                                         "the same %d concurrent lanes" % (nz, steps, len(lanes))},
+                                 "what": "x then y for the %d distances of one field (one batch), inputs already "
+                                         "encoded, %d steps on one stream" % (nz, steps)},
             "encode_ms": ms_enc / steps,
             "decompression_ms": ms_dense / steps,
-            "serial": "encode (one 1024^2 field, chi 128) and decompression (three 1024^2 fields) of one step, "
+            "serial": "encode (one 1024^2 field, chi 128) and decompression (three 1024^2 fields) of one field, "
                       "one at a time on one stream"}
 
 
@@ -395,8 +411,8 @@ def contraction_pass(lib, L, run, dev, steps=2):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py: this build measures one GPU only (the workload is a single field; "
-              "DESIGN.md describes how the path would shard). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py: this build measures one GPU only (DESIGN.md describes how the path would shard). "
+              "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import ctypes
     import torch
@@ -406,35 +422,42 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
-    field = synth.aperture_field(0, n=1 << N_LOG2)
-    d_field = torch.from_numpy(field).to(torch.complex64).to(dev)
-    prop = api.FresnelBatch(N_LOG2, LAM, DX, ZS, device=dev)
+    nb = max(a.fields_per_step, 1)
+    fields = [synth.aperture_field(seed, n=1 << N_LOG2) for seed in range(nb)]
+    d_fields = torch.from_numpy(np.stack(fields)).to(torch.complex64).to(dev)
+    nz = len(ZS)
+    prop = api.FresnelBatch(N_LOG2, LAM, DX, ZS * nb, device=dev)       # member f * nz + j: field f, ZS[j]
+    prop1 = api.FresnelBatch(N_LOG2, LAM, DX, ZS, device=dev)           # one field (serial latency)
     m = 2 * N_LOG2
     chi = a.chi
-    nz = len(ZS)
     main_s = torch.cuda.current_stream(dev)
 
     class Lane:
         """One step in flight: its own stream (default priority), state
-        buffers and library workspaces (keyed per lane)."""
+        buffers and library workspaces (keyed per lane).  A step: encode nf
+        fields (one batched encode), propagate each to the nz distances (one
+        batched zip-up + sweep per axis over nf * nz members), decompress all."""
 
-        def __init__(self, i):
-            # lane 0 runs on the main stream: with three more streams that
-            # fills the HIP runtime's default of four hardware queues
+        def __init__(self, i, nf, pr):
             self.s = main_s if i == 0 else torch.cuda.Stream(device=dev)
-            self.psi = api.MPS(m, chi, device=dev)
-            self.inp = api.MPSBatch(nz, m, chi, device=dev)
-            self.mid = api.MPSBatch(nz, m, chi, device=dev)
-            self.out = api.MPSBatch(nz, m, chi, device=dev)
-            self.dens = torch.empty((nz, 1 << N_LOG2, 1 << N_LOG2), dtype=torch.complex64, device=dev)
-            self.key = "lane%d" % i
+            self.nf, self.prop = nf, pr
+            self.img = d_fields[:nf]
+            self.enc = api.MPSBatch(nf, m, chi, device=dev)
+            self.inp = api.MPSBatch(nf * nz, m, chi, device=dev)
+            self.mid = api.MPSBatch(nf * nz, m, chi, device=dev)
+            self.out = api.MPSBatch(nf * nz, m, chi, device=dev)
+            self.dens = torch.empty((nf * nz, 1 << N_LOG2, 1 << N_LOG2), dtype=torch.complex64, device=dev)
+            self.key = "lane%d.%d" % (i, nf)
 
         def encode(self):
-            api.tt_encode(d_field, chi, out=self.psi, ws_key=self.key)
-            self.inp.fill_from(self.psi)
+            api.tt_encode_batched(self.img, chi, out=self.enc, ws_key=self.key + ".enc")
+            # every field's MPS is the input of its nz propagations (device copies)
+            sh = self.enc.cores.shape
+            self.inp.cores.view(self.nf, nz, *sh[1:]).copy_(self.enc.cores.unsqueeze(1).expand(-1, nz, *sh[1:]))
+            self.inp.bonds.view(self.nf, nz, m + 1).copy_(self.enc.bonds.unsqueeze(1).expand(-1, nz, m + 1))
 
         def propagate(self):
-            prop(self.inp, chi, tmp=self.mid, out=self.out, ws_key=self.key)
+            self.prop(self.inp, chi, tmp=self.mid, out=self.out, ws_key=self.key)
 
         def decompress(self):
             api.tt_to_dense_batched(self.out, out=self.dens, ws_key=self.key + ".dense")
@@ -445,72 +468,82 @@ def main():
             self.decompress()
 
         def check(self):
-            api.check_status(self.key)
-            api.check_status(self.key + ".dense")
+            for k in (self.key, self.key + ".enc", self.key + ".dense"):
+                api.check_status(k)
 
-    lanes = [Lane(i) for i in range(max(a.inflight, 1))]
+    lanes = [Lane(i, nb, prop) for i in range(max(a.inflight, 1))]
+    single = Lane(0, 1, prop1)
 
-    def run(steps, inflight):
-        """`steps` steps, each: encode the field, propagate the three distances
-        as one batch, decompress all three.  Step k runs on lane k mod
-        `inflight`: up to `inflight` independent steps execute concurrently
-        (every step performs all of its work; a lane's steps are ordered by
-        its stream).  inflight = 1: one stream, one step at a time."""
-        for ln in lanes[:inflight]:
+    def run(steps, inflight, lane_set=None):
+        """`steps` steps; step k on lane k mod `inflight` (each lane's steps are
+        ordered by its stream, different lanes run concurrently)."""
+        ls = (lane_set or lanes)[:inflight]
+        for ln in ls:
             ln.s.wait_stream(main_s)
         for k in range(steps):
-            ln = lanes[k % inflight]
+            ln = ls[k % len(ls)]
             with torch.cuda.stream(ln.s):
                 ln.step()
-        for ln in lanes[:inflight]:
+        for ln in ls:
             main_s.wait_stream(ln.s)
 
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
     run(len(lanes), len(lanes))
-    # contraction tiles tuned on this step's shapes (setup, before any timing;
+    run(1, 1, [single])
+    # contraction tiles tuned on the steps' shapes (setup, before any timing;
     # variants differ only in output partitioning, so results are unchanged)
-    n_tuned = api.autotune(lambda: run(1, 1), device=dev)
-    run(a.warmup, len(lanes))
+    n_tuned = api.autotune(lambda: (run(1, 1), run(1, 1, [single])), device=dev)
+    run(a.warmup * len(lanes), len(lanes))
     for ln in lanes:
         ln.check()
-    torch.cuda.synchronize()
-    # serial reference (same work, one stream), outside the profiled region
-    ev_s0 = torch.cuda.Event(enable_timing=True)
-    ev_s1 = torch.cuda.Event(enable_timing=True)
-    ev_s0.record()
-    run(a.steps, 1)
-    ev_s1.record()
-    torch.cuda.synchronize()
-    serial_ms = ev_s0.elapsed_time(ev_s1) / a.steps
-
-    lib = L.load()
-    max_launch = 400 * a.steps
-    nlog = torch.zeros(max_launch * 8, dtype=torch.int32, device=dev)
-    L.check(lib.tt_prof_begin(2, ctypes.c_void_p(nlog.data_ptr()), nlog.numel(), max_launch), "tt_prof_begin")
+    # ---- headline: nothing but the steps inside the timed region
     t0 = time.perf_counter()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    run(a.steps, len(lanes))
-    ev1.record()
-    torch.cuda.synchronize()
+    ms = timed(lambda: run(a.steps, len(lanes))) / a.steps
     wall = time.perf_counter() - t0
-    ms = ev0.elapsed_time(ev1) / a.steps
+    for ln in lanes:
+        ln.check()
+    # ---- latency of one field's step (one field, its nz distances, one stream)
+    run(2, 1, [single])
+    serial_ms = timed(lambda: run(a.serial_steps, 1, [single])) / a.serial_steps
+    # ---- dominant kernel, its launches bracketed by HIP events on their
+    # streams, in a pass of its own: the same steps on the same lanes
+    lib = L.load()
+    psteps = len(lanes) * 2
+    max_launch = 200 * psteps * nb
+    nlog = torch.zeros(max_launch * nz * 4, dtype=torch.int32, device=dev)
+    L.check(lib.tt_prof_begin(2, ctypes.c_void_p(nlog.data_ptr()), nlog.numel(), max_launch), "tt_prof_begin")
+    ms_prof = timed(lambda: run(psteps, len(lanes))) / psteps
     launches, entries, kms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     L.check(lib.tt_prof_end(ctypes.byref(launches), ctypes.byref(entries), ctypes.byref(kms)), "tt_prof_end")
-    for ln in lanes:
-        ln.check()
     ns = nlog[:entries.value].cpu().numpy().astype(np.float64)
-    # n = the matrix (n <= 128) or trailing block (the last 128 steps of a
-    # wider matrix) each launch reduces, logged by the kernel
     flops = float(np.sum(16.0 / 3.0 * ns ** 3))
     nl = max(launches.value, 1)
     avg_launch_s = kms.value / 1e3 / nl
     achieved = flops / nl / avg_launch_s / 1e12 if launches.value else 0.0
+    # the same kernel's time per step in a serial pass (one stream, no overlap)
+    L.check(lib.tt_prof_begin(2, ctypes.c_void_p(nlog.data_ptr()), nlog.numel(), max_launch), "tt_prof_begin")
+    run(2, 1)
+    torch.cuda.synchronize()
+    l2, e2, k2 = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    L.check(lib.tt_prof_end(ctypes.byref(l2), ctypes.byref(e2), ctypes.byref(k2)), "tt_prof_end")
+    ms_serial_batch = timed(lambda: run(2, 1)) / 2
 
     mfma = contraction_pass(lib, L, run, dev)
-    parts = parts_pass(lanes, a.steps, nz, dev)
+    gflop = mfma["fp32_products"]["gflop_per_step"] + mfma["fp64_gram"]["gflop_per_step"]
+    for ln in lanes:
+        ln.check()
 
-    value = nz / (ms / 1e3)
+    props_per_step = nz * nb
+    value = props_per_step / (ms / 1e3)
     res = {
         "metric": "MPO x MPS Fresnel propagations/s at 2^20 px, chi=128",
         "value": value,
@@ -524,16 +557,18 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 (fp32 MFMA) + f64 eig",
         "data": "synthetic",
-        "config": {"workload": "single 1024x1024 complex64 field, z in {0.5, 2, 8} mm, chi 128; "
-                               "encode + 3 propagations + 3 decompressions per step",
-                   "global_batch": 1, "chi": chi, "sites": m,
+        "config": {"workload": "%d independent 1024x1024 complex64 aperture fields (seeds 0..%d) per step, each "
+                               "propagated to z in {0.5, 2, 8} mm at chi %d: one batched encode, one batched "
+                               "zip-up + sweep per axis over the %d (field, z) members, %d decompressions"
+                               % (nb, nb - 1, chi, props_per_step, props_per_step),
+                   "global_batch": nb, "chi": chi, "sites": m,
                    "steps_in_flight": len(lanes),
-                   "schedule": "step k on stream k mod %d (the main stream and %d more; independent steps run "
-                               "concurrently, each with its own buffers and workspaces); serial_ms_per_step: the "
-                               "same steps one at a time on one stream" % (len(lanes), len(lanes) - 1),
+                   "schedule": "step k on stream k mod %d (the main stream and %d more, default priority, each "
+                               "lane with its own buffers and workspaces)" % (len(lanes), len(lanes) - 1),
                    "autotuned_contraction_shapes": n_tuned},
         "serial_ms_per_step": serial_ms,
-        "parts": parts,
+        "serial": "one field, its three distances as one batch (encode, x and y application, decompression), "
+                  "steps one at a time on one stream: the latency of a single field",
         "roofline": {
             "kernel": "qtt::tridiag_lds_kernel (Householder reduction to tridiagonal form, FP64 Gram "
                       "eigensolver, one workgroup per matrix with its packed lower triangle in LDS: "
@@ -547,9 +582,20 @@ def main():
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "launches": launches.value,
             "avg_launch_ms": avg_launch_s * 1e3,
-            "kernel_ms_per_step": kms.value / a.steps,
+            "pass": "%d steps on the timed region's lanes right after it, every launch of the kernel bracketed "
+                    "by HIP events on its stream (%.2f ms per step with the events)" % (psteps, ms_prof),
+            "kernel_ms_per_step_serial": k2.value / 2,
+            "serial_ms_per_step": ms_serial_batch,
+            "kernel_share_serial": (k2.value / 2) / ms_serial_batch if ms_serial_batch > 0 else None,
             "work_per_launch": "(16/3) n^3 FP64 flops per matrix or trailing block of size n <= 128, "
                                "n logged by the kernel",
+            "end_to_end": {
+                "gflop_per_step": gflop,
+                "what": "algorithmic contraction flops of a step (FP32-MFMA products + FP64-accumulated Gram "
+                        "matrices, from the contraction pass) over the headline ms_per_step",
+                "achieved_tflops": gflop / ms if ms > 0 else 0.0,
+                "frac_of_fp32_peak": gflop / ms / FP32_PEAK_TFLOPS if ms > 0 else 0.0,
+            },
         },
         "mfma": mfma,
         "wall_s": wall,
@@ -562,12 +608,14 @@ def main():
         torch.cuda.synchronize()
         res["copy_probe_mib"] = a.copy_probe
         del src, dst
+    if not a.no_parts:
+        res["parts"] = parts_pass([single], a.serial_steps, nz, dev)
     if not a.no_batched:
         res["batched"] = batched_bench(dev)
     if not a.no_grad:
         res["grad_step"] = grad_step_bench(a.grad_steps, dev)
     if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(field, chi)
+        res["cpu_baseline"] = cpu_baseline(fields[0], chi)
     print(json.dumps(res), flush=True)
 
 

@@ -519,8 +519,9 @@ def intensity_loss(field, target, with_grad=True):
     return loss, grad
 
 
-def tt_encode_batched(imgs, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None, chi_dev=None):
-    """imgs: device tensor (count, N, N)."""
+def tt_encode_batched(imgs, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None, out=None, chi_dev=None,
+                      ws_key="encode"):
+    """imgs: device tensor (count, N, N).  ws_key: the cached workspace, as in tt_encode."""
     lib = L.load()
     count = int(imgs.shape[0])
     n = int(imgs.shape[1]).bit_length() - 1
@@ -531,7 +532,7 @@ def tt_encode_batched(imgs, chi, cutoff=0.0, tau=0.0, prec="fp32", chi_cap=None,
         out = MPSBatch(count, 2 * n, chi_cap or chi, dtype=_ctype(prec), device=imgs.device)
     o = _opts(chi, 0, cutoff, tau, prec)
     nb = lib.tt_workspace_size_batched(L.OP_ENCODE, count, 2 * n, int(chi), 1, o.prec)
-    ws = workspace(nb, imgs.device, key="encode")
+    ws = workspace(nb, imgs.device, key=ws_key)
     s = out.cstruct()
     L.check(lib.tt_encode_batched(_ptr(imgs), dt, n, ctypes.byref(o), _ptr(chi_dev), ctypes.byref(s), _ptr(ws), nb,
                                   _stream()), "tt_encode_batched")
@@ -557,7 +558,11 @@ class FresnelBatch:
     """x- and y-axis Fresnel MPOs for several distances z, batched (one field per z)."""
 
     def __init__(self, n, lam, dx, zs, dtype=torch.complex64, device="cuda", rel=1e-12):
-        props = [FresnelPropagator(n, lam, dx, z, dtype=dtype, device=device, rel=rel) for z in zs]
+        uniq = {}
+        for z in zs:
+            if z not in uniq:
+                uniq[z] = FresnelPropagator(n, lam, dx, z, dtype=dtype, device=device, rel=rel)
+        props = [uniq[z] for z in zs]
         self.wx = MPOBatch([p.wx for p in props], dtype=dtype, device=device)
         self.wy = MPOBatch([p.wy for p in props], dtype=dtype, device=device)
         self.count = len(zs)
