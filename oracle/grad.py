@@ -30,6 +30,16 @@ from .ttsvd import keep_count, TAU_F64
 
 CT = torch.complex128
 
+# Pairs (kept i, discarded j) with lam_i - lam_j <= GAP_AD * lam_1 contribute
+# nothing to the derivative.  Reading: an eigensolver working on the Gram
+# matrix separates eigenvectors by inverse iteration only where the gap is
+# well above its shift accuracy (~eps lam_1): three solves shrink a foreign
+# component by (eps lam_1 / gap)^3, so below ~1e-12 lam_1 the split of a pair
+# into two vectors is decided by the start vectors, and a cut between them
+# has no derivative at that resolution; its term, divided by that gap, would
+# amplify an arbitrary rotation.  The twin drops the same terms.
+GAP_AD = 1e-12
+
 
 def as_tensors(cores, requires_grad=False):
     return [torch.tensor(np.asarray(c), dtype=CT, requires_grad=requires_grad) for c in cores]
@@ -42,7 +52,8 @@ class _KeepRight(torch.autograd.Function):
     Backward: with G = M^H M = V diag(lam) V^H (all n eigenpairs), incoming
     gradients gV (n x k) and gC (rows x k),
         Vbar = gV + M^H gC,           Mbar = gC V_k^H,
-        Z_ij = (V_perp^H Vbar)_ij / (lam_j - lam_i)   (i discarded, j kept),
+        Z_ij = (V_perp^H Vbar)_ij / (lam_j - lam_i)   (i discarded, j kept;
+               0 where lam_j - lam_i <= GAP_AD lam_1),
         Gbar = V_perp Z V_k^H,        Mbar += M (Gbar + Gbar^H).
     The kept-kept block of the eigenvector derivative is left out: every use
     of the pair (V_k, M V_k) in the zip-up and the sweep is invariant under
@@ -74,7 +85,10 @@ class _KeepRight(torch.autograd.Function):
             mbar = mbar + g_c @ vk.conj().T
         if vp.shape[1] > 0:
             den = lam[None, :k] - lam[k:, None]
-            z = (vp.conj().T @ vbar) / den
+            # pairs closer than the eigenvector resolution carry no derivative
+            keep = den > GAP_AD * lam[0]
+            z = torch.where(keep, (vp.conj().T @ vbar) / torch.where(keep, den, torch.ones_like(den)),
+                            torch.zeros((), dtype=CT))
             gbar = vp @ z @ vk.conj().T
             mbar = mbar + mat @ (gbar + gbar.conj().T)
         return mbar, None

@@ -25,16 +25,16 @@ def _wrap(cores, bonds):
 
 class _Apply(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, cores, bonds, mpo, chi, chi_zip):
+    def forward(ctx, cores, bonds, mpo, chi, chi_zip, tau):
         psi = _wrap(cores, bonds)
         batched = cores.dim() == 5
         saved = api.saved_buffer(psi, mpo, chi, chi_zip)
         if batched:
-            out = api.mpo_apply_batched(psi, mpo, chi, chi_zip, saved=saved)
+            out = api.mpo_apply_batched(psi, mpo, chi, chi_zip, tau=tau, saved=saved)
         else:
-            out = api.mpo_apply(psi, mpo, chi, chi_zip, saved=saved)
+            out = api.mpo_apply(psi, mpo, chi, chi_zip, tau=tau, saved=saved)
         ctx.save_for_backward(cores, bonds, out.cores, out.bonds, saved)
-        ctx.mpo, ctx.chi, ctx.chi_zip, ctx.batched = mpo, chi, chi_zip, batched
+        ctx.mpo, ctx.chi, ctx.chi_zip, ctx.batched, ctx.tau = mpo, chi, chi_zip, batched, tau
         ctx.mark_non_differentiable(out.bonds)
         return out.cores, out.bonds
 
@@ -44,10 +44,10 @@ class _Apply(torch.autograd.Function):
         psi, out = _wrap(cores, bonds), _wrap(ocores, obonds)
         gout = _wrap(g_cores.contiguous(), obonds)
         if ctx.batched:
-            g = api.mpo_apply_backward_batched(psi, ctx.mpo, ctx.chi, saved, out, gout, ctx.chi_zip)
+            g = api.mpo_apply_backward_batched(psi, ctx.mpo, ctx.chi, saved, out, gout, ctx.chi_zip, tau=ctx.tau)
         else:
-            g = api.mpo_apply_backward(psi, ctx.mpo, ctx.chi, saved, out, gout, ctx.chi_zip)
-        return g.cores, None, None, None, None
+            g = api.mpo_apply_backward(psi, ctx.mpo, ctx.chi, saved, out, gout, ctx.chi_zip, tau=ctx.tau)
+        return g.cores, None, None, None, None, None
 
 
 class _Dense(torch.autograd.Function):
@@ -82,9 +82,11 @@ class _Loss(torch.autograd.Function):
         return grad * g.to(grad.real.dtype), None
 
 
-def mpo_apply(cores, bonds, mpo, chi, chi_zip=0):
-    """Differentiable MPO x MPS (zip-up + sweep to chi); returns (cores, bonds)."""
-    return _Apply.apply(cores, bonds, mpo, int(chi), int(chi_zip or 0))
+def mpo_apply(cores, bonds, mpo, chi, chi_zip=0, tau=0.0):
+    """Differentiable MPO x MPS (zip-up + sweep to chi); returns (cores, bonds).
+    tau: the keep rule's numerical-zero threshold on lam_i / lam_1 (0: the
+    library default)."""
+    return _Apply.apply(cores, bonds, mpo, int(chi), int(chi_zip or 0), float(tau or 0.0))
 
 
 def to_dense(cores, bonds):
@@ -100,14 +102,16 @@ def intensity_loss(field, target):
 class PhaseRetrieval:
     """Loss and gradient of a mask MPS (or a batch of them) under Fresnel
     propagation: L = sum (|dense(W^y W^x mask)|^2 - I_target)^2, with both
-    applications truncated to chi.  wx, wy: MPO (single) or MPOBatch."""
+    applications truncated to chi.  wx, wy: MPO (single) or MPOBatch.
+    tau: keep threshold of both applications (0: the library default)."""
 
-    def __init__(self, wx, wy, chi, chi_zip=0):
+    def __init__(self, wx, wy, chi, chi_zip=0, tau=0.0):
         self.wx, self.wy, self.chi, self.chi_zip = wx, wy, int(chi), int(chi_zip or 0)
+        self.tau = float(tau or 0.0)
 
     def field(self, cores, bonds):
-        c1, b1 = mpo_apply(cores, bonds, self.wx, self.chi, self.chi_zip)
-        c2, b2 = mpo_apply(c1, b1, self.wy, self.chi, self.chi_zip)
+        c1, b1 = mpo_apply(cores, bonds, self.wx, self.chi, self.chi_zip, self.tau)
+        c2, b2 = mpo_apply(c1, b1, self.wy, self.chi, self.chi_zip, self.tau)
         return to_dense(c2, b2)
 
     def loss(self, cores, bonds, target):

@@ -230,8 +230,11 @@ struct ApplyPlan {
   int rmax, dmax;
 };
 
+// diff: the application keeps state for its adjoint and factors every bond
+// on the side the adjoint differentiates (zip-up M^H M, sweep M M^H), so the
+// Gram bound covers those sides.
 ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_zip, const int* dbonds,
-                          const int* kind, int dcap, int refine = 0) {
+                          const int* kind, int dcap, int refine = 0, int diff = 0) {
   ApplyPlan p;
   p.refine = refine;
   p.m = m; p.chi_in = chi_in; p.chi_out = chi_out; p.chi_max = chi_max;
@@ -258,6 +261,10 @@ ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_z
     g = (int)std::max<ll>(g, std::min(pb, qb));
   }
   for (int k = 0; k < m - 1; ++k) g = std::max(g, std::min(2 * p.rout[k], p.beta[k + 1]));
+  if (diff) {
+    for (int k = 1; k < m; ++k) g = std::max(g, 2 * p.beta[k + 1]);
+    for (int k = 0; k < m - 1; ++k) g = std::max(g, 2 * p.rout[k]);
+  }
   if (refine) {
     // fitting sweep: the pair (k, k+1) matrix is (2 r_k) x (2 beta_(k+2)), so
     // the output bonds may exceed the zip-up bonds; buffers use zc >= chi_max
@@ -510,7 +517,12 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     }
     const ll pb = (ll)p.rin[k] * Da, qb = 2ll * p.beta[k + 1];
     int* kout = b.zbonds + k;
-    if (qb <= pb) {
+    // a forward that keeps state for its adjoint factors on the side the
+    // adjoint differentiates (M^H M here), so that both see the same Gram
+    // matrix and the same kept eigenvectors bit for bit; the other side would
+    // rebuild V_k as U^H M / sigma, whose small-sigma directions carry the
+    // FP32 error of M divided by sigma
+    if (qb <= pb || sv) {
       // column side: G = M^H M (q x q)
       Operand A = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
       Operand B = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
@@ -667,8 +679,9 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     const ll pb = 2ll * p.rout[k], qb = p.beta[k + 1];
     void* next = center_at(k + 1);
     const char* znext = core_z(k + 1);
-    // M = center [(r,t), b]: strides (2 zc, zc) rows, 1 cols
-    if (qb < pb) {
+    // M = center [(r,t), b]: strides (2 zc, zc) rows, 1 cols.  With saved
+    // state the row side (M M^H), the factorisation the adjoint differentiates
+    if (qb < pb && !sv) {
       Operand A = opd(center, 1, 0, 2 * zc, zc, 1, sCenter);
       Operand B = opd(center, 2 * zc, zc, 1, 0, 0, sCenter);
       int r = gram(c, A, B, dv(c, 1, bk), 1, (int)qb, dv(c, 2, rk), 2, pb);
@@ -737,7 +750,7 @@ struct ApplySetup {
 // Validate the arguments of an application.  identity: W ignored, every site
 // an identity pass-through of bond 1 (used by tt_truncate).
 int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opts* opts, const MpsB& out,
-                bool identity, ApplySetup& su) {
+                bool identity, ApplySetup& su, bool diff = false) {
   if (in.m != out.m) return fail(QTT_ERR_SHAPE, "in/out n_sites differ");
   if (in.nf != out.nf) return fail(QTT_ERR_SHAPE, "in/out batch counts differ");
   if (in.dtype != out.dtype) return fail(QTT_ERR_DTYPE, "in/out dtypes differ");
@@ -787,7 +800,7 @@ int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opt
   W.dbonds = su.dbonds.data();
   W.kind = su.kind.data();
   su.p = make_apply_plan(m, in.cap, out.cap, o.chi_max, o.chi_zip, su.dbonds.data(), su.kind.data(), W.dcap,
-                         identity ? 0 : o.refine);
+                         identity ? 0 : o.refine, diff ? 1 : 0);
   su.csz = in.dtype == QTT_C128 ? 16 : 8;
   return QTT_OK;
 }
@@ -797,7 +810,7 @@ int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_op
                  size_t saved_sz = 0) {
   if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
   ApplySetup su;
-  int r = apply_setup(in, W1, Wb, opts, out, identity, su);
+  int r = apply_setup(in, W1, Wb, opts, out, identity, su, saved != nullptr);
   if (r) return r;
   size_t need = apply_bytes(su.p, su.csz, in.nf);
   if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
@@ -1079,7 +1092,7 @@ int backward_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt
     return fail(QTT_ERR_SHAPE, "grad_in must match in (sites, count, chi_cap, dtype)");
   if (gin.cores == in.cores || gout.cores == out.cores) return fail(QTT_ERR_ARG, "gradients must not alias the states");
   ApplySetup su;
-  int r = apply_setup(in, W1, Wb, opts, out, false, su);
+  int r = apply_setup(in, W1, Wb, opts, out, false, su, true);
   if (r) return r;
   if (su.p.refine) return fail(QTT_ERR_ARG, "the adjoint covers the plain sweep only (refine = 0)");
   if (bwd_nmax(su.p) > 512) return fail(QTT_ERR_CAPACITY, "adjoint eigenproblem larger than 512");
@@ -1098,8 +1111,10 @@ ApplyPlan capacity_plan(int m, int chi_cap, int d_cap, bool identity, int refine
   std::vector<int> db(m + 1, identity ? 1 : d_cap);
   db[0] = db[m] = 1;
   std::vector<int> kind(m, identity ? 1 : 0);
+  // upper bound for every use: any precision, the refinement sweep and the
+  // Gram sides of an application that keeps state for its adjoint
   return make_apply_plan(m, chi_cap, chi_cap, chi_cap, chi_cap, db.data(), kind.data(), identity ? 1 : d_cap,
-                         refine);
+                         refine, identity ? 0 : 1);
 }
 
 size_t apply_ws(int m, int chi_cap, int d_cap, int prec, bool identity, int nf) {

@@ -1333,12 +1333,15 @@ __global__ void adj_scale_kernel(DimExpr nexp, int* kin, long long kstride, void
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   if (j >= n) return;
   const double lj = W.lam[j < kc ? j : 0];
-  const double eps = 1e-15 * fabs(W.lam[0]) + 1e-300;
+  // pairs closer than the inverse iteration's resolution (three solves at a
+  // shift accurate to ~eps lam_1 split eigenvectors only where the gap is
+  // well above 1e-12 lam_1) have no resolvable derivative: their term is 0
+  const double gmin = 1e-12 * fabs(W.lam[0]);
   for (int i = threadIdx.x; i < kkb; i += blockDim.x) {
     double f = 0.0;
     if (j >= kkb && j < kfull) {
       const double d = W.lam[i] - lj;
-      f = d / (d * d + eps * eps);
+      f = d > gmin ? 1.0 / d : 0.0;
     }
     long long o = (long long)b * s_batch + (long long)j * ldy + i;
     // rows outside [kk, kept) are stored as exact zeros (never read, so

@@ -114,8 +114,9 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s);
 hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s);
 // Eigenvector-adjoint scaling after a full decomposition (sp.kcap = n, every
 // pair kept): Y[j][i] (row j = eigenvector index, column i < kk[f]) becomes
-//   Y[j][i] / (lam_i - lam_j)  for kk[f] <= j < kept, and 0 otherwise,
-// with lam from the decomposition just run (regularised denominator).
+//   Y[j][i] / (lam_i - lam_j)  for kk[f] <= j < kept where lam_i - lam_j >
+//   1e-12 lam_1, and 0 otherwise (pairs the eigensolver does not resolve),
+// with lam from the decomposition just run.
 hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long long s_batch, const int* kk,
                              long long kk_stride, int kk_bound, int dtype, hipStream_t s);
 

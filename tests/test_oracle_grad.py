@@ -137,3 +137,48 @@ def test_truncated_loss_gradient_vs_finite_differences(chi, seed):
             ad = g.real if part == "re" else g.imag
             errs.append(abs(fd - ad) / max(1e-3, max(abs(g) for g in np.concatenate([q.ravel() for q in grads]))))
     assert max(errs) < 1e-6
+
+
+def test_loss_gradient_where_the_keep_threshold_binds_vs_finite_differences():
+    """A keep threshold that binds (tau = 1e-10 on lam_i / lam_1: the ranks of
+    a smooth mask's propagation drop below those kept at the float64 floor)
+    leaves the twin's gradient equal to central finite differences of its own
+    loss: the threshold selects the kept pairs, the derivative stays exact
+    (no pair of this problem is closer than GAP_AD lam_1)."""
+    n, z, chi = 5, 40e-6, 32
+    rng = np.random.default_rng(11)
+    mask = T.tt_svd(Q.to_quantics(np.exp(1j * synth.smoothed_phase(21, 1 << n, 6.0, np.pi / 8))), 2 * n, chi)
+    tgt = np.exp(1j * synth.smoothed_phase(22, 1 << n, 3.0, np.pi / 2))
+    wx, wy = _axis_mpos(n, z)
+    tc = T.tt_svd(Q.to_quantics(tgt), 2 * n, chi)
+    t1, _ = Z.mpo_apply(tc, wx, chi)
+    t2, _ = Z.mpo_apply(t1, wy, chi)
+    target = np.abs(Z.to_dense(t2, n)) ** 2
+    with torch.no_grad():
+        floor = OG.propagate(OG.as_tensors(mask), wx, wy, chi)
+        ad_map = OG.propagate(OG.as_tensors(mask), wx, wy, chi, tau=1e-10)
+    b_floor = [1] + [int(c.shape[2]) for c in floor]
+    b_ad = [1] + [int(c.shape[2]) for c in ad_map]
+    assert any(x < y for x, y in zip(b_ad, b_floor)), (b_ad, b_floor)
+    loss, grads = OG.loss_and_grad(mask, wx, wy, target, chi, n, tau=1e-10)
+
+    def loss_at(cores):
+        with torch.no_grad():
+            out = OG.propagate(OG.as_tensors(cores), wx, wy, chi, tau=1e-10)
+            return float(OG.intensity_loss(OG.to_dense(out, n), torch.as_tensor(target)))
+
+    gmax = max(np.abs(g).max() for g in grads)
+    h = 1e-6
+    worst = 0.0
+    for _ in range(20):
+        k = int(rng.integers(0, 2 * n))
+        idx = tuple(int(rng.integers(0, d)) for d in mask[k].shape)
+        for unit in (1.0, 1j):
+            cp = [c.copy() for c in mask]
+            cm = [c.copy() for c in mask]
+            cp[k][idx] += h * unit
+            cm[k][idx] -= h * unit
+            fd = (loss_at(cp) - loss_at(cm)) / (2 * h)
+            ad = grads[k][idx].real if unit == 1.0 else grads[k][idx].imag
+            worst = max(worst, abs(fd - ad) / gmax)
+    assert worst < 1e-6
