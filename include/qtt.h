@@ -195,8 +195,13 @@ int mpo_apply_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt
                       qtt_mps_batch* out, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream);
 int tt_to_dense_batched(const qtt_mps_batch* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream);
 
-/* Recompress an MPS in place: QR sweep right to left, then SVD sweep left to
- * right with cap opts->chi_max (TT-rounding).  Output left-canonical. */
+/* Recompress an MPS in place (the truncation of Sec. 4 and App. A applied to
+ * an existing MPS: every bond is a Schmidt cut whose singular values decide
+ * what is kept): orthogonalisation right to left, then an SVD truncation
+ * sweep left to right with cap opts->chi_max and the keep rule above
+ * (TT-rounding).  Output left-canonical, *inout->norm = ||result||.  The
+ * bonds are rewritten on the device; cores outside them are left as they
+ * were.  Workspace: tt_workspace_size(QTT_OP_TRUNCATE, ...). */
 int tt_truncate(qtt_mps* inout, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream);
 
 /* Decompress: out[a][b] (row-major N x N, out_dtype C64 or C128) = the field
@@ -280,6 +285,21 @@ int tt_eval_points(const qtt_mps* in, const int32_t* rows, const int32_t* cols, 
 size_t tt_to_dense_block_workspace_size(int n_sites, int chi_cap, int log2_block, int prec);
 int tt_to_dense_block(const qtt_mps* in, int log2_block, int block_row, int block_col, void* out, int out_dtype,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* Decompression of a window (Sec. 3, decompression in Fig. 6): out[i][j]
+ * (row-major rows x cols, out_dtype C64/C128, device) = the field at pixel
+ * (row0 + i, col0 + j), for any window inside the N x N field.  It is
+ * assembled from the aligned 2^log2_block blocks that cover it (log2_block
+ * <= 0: half the window's longer side rounded up to a power of two, so at
+ * most 3 x 3 blocks), each decompressed by tt_to_dense_block into a scratch
+ * block in ws and its part of the window copied out; nothing else of the
+ * field is formed.  Errors: QTT_ERR_SHAPE for a window outside the field or a
+ * block size outside [1, n].  Workspace:
+ * tt_to_dense_window_workspace_size(n_sites, chi_cap, rows, cols, log2_block,
+ * prec). */
+size_t tt_to_dense_window_workspace_size(int n_sites, int chi_cap, int rows, int cols, int log2_block, int prec);
+int tt_to_dense_window(const qtt_mps* in, int row0, int col0, int rows, int cols, int log2_block, void* out,
+                       int out_dtype, void* ws, size_t ws_bytes, void* stream);
 
 /* ---- auxiliary entry points (the building blocks of the calls above) ---- */
 

@@ -330,21 +330,20 @@ def tt_to_dense_block(psi, log2_block, block_row, block_col, out=None):
     return out
 
 
-def tt_to_dense_window(psi, row0, col0, rows, cols, log2_block=None):
-    """An arbitrary rows x cols window at (row0, col0), assembled from the
-    aligned blocks that cover it (nothing outside those blocks is formed)."""
-    n = psi.n_sites // 2
-    if log2_block is None:
-        log2_block = max(1, min(n, max(rows, cols).bit_length() - 1))
-    side = 1 << log2_block
-    out = torch.empty((rows, cols), dtype=psi.dtype, device=psi.cores.device)
-    for br in range(row0 // side, (row0 + rows - 1) // side + 1):
-        for bc in range(col0 // side, (col0 + cols - 1) // side + 1):
-            blk = tt_to_dense_block(psi, log2_block, br, bc)
-            r0, c0 = br * side, bc * side
-            ra, rb = max(row0, r0), min(row0 + rows, r0 + side)
-            ca, cb = max(col0, c0), min(col0 + cols, c0 + side)
-            out[ra - row0:rb - row0, ca - col0:cb - col0] = blk[ra - r0:rb - r0, ca - c0:cb - c0]
+def tt_to_dense_window(psi, row0, col0, rows, cols, log2_block=0, out=None):
+    """An arbitrary rows x cols window at (row0, col0) of the field, assembled
+    by the library from the aligned blocks that cover it (nothing outside
+    those blocks is formed); log2_block 0 lets the library pick the block."""
+    lib = L.load()
+    if out is None:
+        out = torch.empty((rows, cols), dtype=psi.dtype, device=psi.cores.device)
+    dt = L.QTT_C128 if out.dtype == torch.complex128 else L.QTT_C64
+    prec = L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32
+    nb = lib.tt_to_dense_window_workspace_size(psi.n_sites, psi.chi_cap, rows, cols, int(log2_block or 0), prec)
+    ws = workspace(max(nb, 256), psi.cores.device, key="window")
+    s = psi.cstruct()
+    L.check(lib.tt_to_dense_window(ctypes.byref(s), row0, col0, rows, cols, int(log2_block or 0), _ptr(out), dt,
+                                   _ptr(ws), max(nb, 256), _stream()), "tt_to_dense_window")
     return out
 
 

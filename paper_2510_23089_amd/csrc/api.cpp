@@ -1864,6 +1864,64 @@ int tt_to_dense_block(const qtt_mps* in, int log2_block, int block_row, int bloc
   return dense_impl(v, out, out_dtype, db, s, off, bnd, 0);
 }
 
+// log2 of the block side a window is assembled from: half the window's
+// longer side rounded up to a power of two (at most 3 x 3 blocks, so at most
+// 2.25 times the window's pixels are decompressed), within [1, n]
+static int window_log2_block(int n, int rows, int cols, int log2_block) {
+  if (log2_block > 0) return log2_block;
+  const int w = std::max(rows, cols);
+  int lb = 1;
+  while (lb < n && (1 << (lb + 1)) < w) ++lb;
+  return lb;
+}
+
+size_t tt_to_dense_window_workspace_size(int n_sites, int chi_cap, int rows, int cols, int log2_block, int prec) {
+  if (n_sites < 2 || (n_sites & 1) || rows < 1 || cols < 1) return 0;
+  const int n = n_sites / 2;
+  const int lb = window_log2_block(n, rows, cols, log2_block);
+  if (lb < 1 || lb > n) return 0;
+  const size_t wb = tt_to_dense_block_workspace_size(n_sites, chi_cap, lb, prec);
+  if (!wb) return 0;
+  const size_t csz = prec == QTT_PREC_FP64 ? 16 : 8;
+  return (wb + 255) / 256 * 256 + ((size_t)1 << (2 * lb)) * csz;
+}
+
+int tt_to_dense_window(const qtt_mps* in, int row0, int col0, int rows, int cols, int log2_block, void* out,
+                       int out_dtype, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if (!out || !ws) return fail(QTT_ERR_ARG, "NULL argument");
+  if (out_dtype != QTT_C64 && out_dtype != QTT_C128) return fail(QTT_ERR_DTYPE, "out dtype must be C64 or C128");
+  const int n = in->n_sites / 2;
+  const long long N = 1ll << n;
+  if (rows < 1 || cols < 1 || row0 < 0 || col0 < 0 || row0 + (long long)rows > N || col0 + (long long)cols > N)
+    return fail(QTT_ERR_SHAPE, "window (%d, %d) + (%d, %d) outside the %lld x %lld field", row0, col0, rows, cols, N, N);
+  const int lb = window_log2_block(n, rows, cols, log2_block);
+  if (lb < 1 || lb > n) return fail(QTT_ERR_SHAPE, "log2_block %d outside [1, %d]", lb, n);
+  const int prec = in->dtype == QTT_C128 ? QTT_PREC_FP64 : QTT_PREC_FP32;
+  const size_t need = tt_to_dense_window_workspace_size(in->n_sites, in->chi_cap, rows, cols, log2_block, prec);
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  const size_t wb = (tt_to_dense_block_workspace_size(in->n_sites, in->chi_cap, lb, prec) + 255) / 256 * 256;
+  char* blk = (char*)ws + wb;
+  const size_t osz = out_dtype == QTT_C128 ? 16 : 8;
+  const long long side = 1ll << lb;
+  hipStream_t s = (hipStream_t)stream;
+  for (long long br = row0 / side; br <= (row0 + rows - 1) / side; ++br) {
+    for (long long bc = col0 / side; bc <= (col0 + cols - 1) / side; ++bc) {
+      if ((r = tt_to_dense_block(in, lb, (int)br, (int)bc, blk, out_dtype, ws, wb, stream))) return r;
+      const long long r0 = br * side, c0 = bc * side;
+      const long long ra = std::max<long long>(row0, r0), rb = std::min<long long>(row0 + rows, r0 + side);
+      const long long ca = std::max<long long>(col0, c0), cb = std::min<long long>(col0 + cols, c0 + side);
+      const int nr = (int)(rb - ra), nc = (int)(cb - ca);
+      HIPCHK(block_copy(blk + ((ra - r0) * side + (ca - c0)) * osz, side, 1,
+                        (char*)out + ((ra - row0) * cols + (ca - col0)) * osz, cols, 1, dx(nr), dx(nc), nr, nc,
+                        out_dtype == QTT_C128 ? 1 : 0, s));
+    }
+  }
+  return QTT_OK;
+}
+
 int tt_cgemm(int M, int N, int K, const void* A, int lda, int conj_a, const void* B, int ldb, int conj_b, void* C,
              int ldc, int prec, void* stream) {
   g_err.clear();

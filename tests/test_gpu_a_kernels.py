@@ -175,3 +175,46 @@ def test_heev_nonfinite_flags_status():
     m[3, 3] = np.nan
     kept, ev, vec, st = _heev(torch, L, lib, m[None], 4)
     assert st == -7
+
+
+@pytest.mark.parametrize("n,kcap", [(200, 160), (256, 200)])
+def test_heev_degenerate_runs_across_bitmask_words(n, kcap):
+    """Clusters of exactly equal eigenvalues found from the joined-neighbour
+    bitmask (one 64-bit word per 64 eigenvalues): a run straddling indices
+    63/64, a run starting inside the second word, a run after index 128 and
+    one straddling 127/128, with singletons between them.  Every kept vector
+    is orthonormal to 1e-12 and satisfies the eigen-equation to 1e-10 ||G||,
+    and each run's vectors span that eigenvalue's eigenspace."""
+    torch = need_gpu()
+    L, lib = _lib()
+    say("heev degenerate runs", n, kcap)
+    rng = np.random.default_rng(31 + n)
+    spec = list(np.linspace(10.0, 6.0, 60))            # singletons 0..59
+    spec += [5.0] * 8                                  # run 60..67 across the 63/64 boundary
+    spec += list(np.linspace(4.9, 4.0, 10))            # singletons 68..77
+    spec += [3.5] * 5                                  # run 78..82 inside word 1
+    spec += list(np.linspace(3.4, 2.5, 43))            # singletons 83..125
+    spec += [2.0] * 4                                  # run 126..129 across 127/128
+    spec += list(np.linspace(1.9, 1.5, 6))             # singletons 130..135
+    spec += [1.0] * 7                                  # run 136..142 after 128
+    spec += list(np.linspace(0.9, 0.1, n - len(spec)))
+    spec = np.array(spec[:n])
+    assert np.all(np.diff(spec) <= 0)
+    mats = _rand_herm(rng, n, spec)[None]
+    kept, ev, vec, st = _heev(torch, L, lib, mats, kcap)
+    assert st == 0
+    k = int(kept[0])
+    assert k == kcap
+    assert np.max(np.abs(ev[0, :k] - spec[:k])) < 1e-12 * spec[0]
+    u = vec[0, :, :k]
+    assert np.max(np.abs(u.conj().T @ u - np.eye(k))) < 1e-12
+    assert np.max(np.abs(mats[0] @ u - u * ev[0, :k])) < 1e-10 * spec[0]
+    w, v = np.linalg.eigh(mats[0])
+    w, v = w[::-1], v[:, ::-1]
+    for a, b in ((60, 68), (78, 83), (126, 130), (136, 143)):
+        if b > k:
+            continue
+        # projector onto the exact eigenspace equals the projector onto the kept run
+        pe = v[:, a:b] @ v[:, a:b].conj().T
+        pk = u[:, a:b] @ u[:, a:b].conj().T
+        assert np.max(np.abs(pe - pk)) < 1e-10, (a, b)

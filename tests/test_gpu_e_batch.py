@@ -199,3 +199,35 @@ def test_native_group_encode_matches_padded_encode():
         assert rel(got[i, :n, :n].cpu().numpy(), ref[i, :n, :n].cpu().numpy()) < 1e-5
         if n < side:
             assert got[i, n:, :].abs().max().item() == 0 and got[i, :, n:].abs().max().item() == 0
+
+
+def test_uneven_batch_full_size_members_vs_oracle():
+    """Members at the sizes of the 256-field batch's extremes, through the
+    padded pipeline with the oracle's MPOs (z = 2 mm): a 2048^2 field at chi
+    128 (22 sites) and a 256^2 field at chi 16 padded into it, each against the
+    oracle's TT-SVD, zip-up and sweep on its own grid (FP32 bar 1e-4 against
+    the identically truncated result, equal bonds, zero padding outside)."""
+    torch = need_gpu()
+    from paper_2510_23089_amd import api
+    ks = [11, 8]
+    chis = [128, 16]
+    z = 2e-3
+    fields = [synth.aperture_field(40 + i, n=1 << k) for i, k in enumerate(ks)]
+    say("full-size uneven members", ks, chis)
+    psi, out, dense = _run_batch(api, torch, fields, ks, chis, z)
+    K = max(ks)
+    for i, (k, chi, f) in enumerate(zip(ks, chis, fields)):
+        cores = T.tt_svd(Q.to_quantics(f), 2 * k, chi, tau=1e-13)
+        _, _, c = _oracle_padded(k, K, z)
+        wx, wy = OM.embed_axis(c, "x"), OM.embed_axis(c, "y")
+        r1, _ = Z.mpo_apply(cores, wx, chi, tau=1e-13)
+        r2, _ = Z.mpo_apply(r1, wy, chi, tau=1e-13)
+        ref = Z.to_dense(r2, k)
+        n = 1 << k
+        got = dense[i].cpu().numpy()
+        err = rel(got[:n, :n], ref)
+        say("  member %d (2^%d, chi %d): rel err %.3e" % (i, k, chi, err))
+        assert err < 1e-4
+        assert [int(x) for x in out.bonds[i].cpu()][2 * (K - k):] == Z.bonds(r2)
+        if n < got.shape[0]:
+            assert np.abs(got[n:, :]).max() == 0 and np.abs(got[:, n:]).max() == 0
