@@ -29,7 +29,13 @@
  *   actual bonds (host array d_bonds[0..m]) -- operator bonds are static --
  *   core k at element offset k * d_cap * 4 * d_cap; t is the output bit and s
  *   the input bit.  site_kind[k] = 1 marks an identity site whose bond is
- *   passed through (D_k == D_(k+1), core not read); NULL means all general.
+ *   passed through (D_k == D_(k+1), core not read); site_kind[k] = 2 a
+ *   diagonal site (W[.][t][s][.] = 0 for t != s: an operator diagonal in the
+ *   computational basis there, such as the transfer function between the two
+ *   Fourier transforms of Sec. 6.1 or an element-wise product, Sec. 5), whose
+ *   forward contraction reads only the t = s blocks (the zero blocks must
+ *   still be stored: the adjoint and the fitting sweep read the full core);
+ *   NULL means all general.
  * Truncation (qtt_opts).  At every bond, with lam_i the squared singular
  *   values in descending order, keep
  *       k = min(cap, k_eps, #{lam_i > tau * lam_1}), at least 1,
@@ -109,7 +115,7 @@ typedef struct {
   int32_t dtype;              /* QTT_C64 or QTT_C128 (matching the MPS)    */
   const void* cores;          /* device, n_sites * d_cap * 4 * d_cap       */
   const int32_t* d_bonds;     /* HOST, n_sites + 1 ints, d_bonds[0] = d_bonds[m] = 1 */
-  const int32_t* site_kind;   /* HOST, n_sites ints or NULL (0 general, 1 identity) */
+  const int32_t* site_kind;   /* HOST, n_sites ints or NULL (0 general, 1 identity, 2 diagonal) */
 } qtt_mpo;
 
 /* A batch of `count` MPS of identical shape in one allocation: field f's
@@ -194,6 +200,22 @@ int tt_encode_batched(const void* img, int img_dtype, int log2_side, const qtt_o
 int mpo_apply_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt_opts* opts, const int32_t* chi_dev,
                       qtt_mps_batch* out, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, void* stream);
 int tt_to_dense_batched(const qtt_mps_batch* in, void* out, int out_dtype, void* ws, size_t ws_bytes, void* stream);
+
+/* Element-wise (Hadamard) product of two fields in MPS form, out = a (.) b,
+ * or conj(a) (.) b if conj_a (Sec. 5: the local contraction of physical
+ * indices that maps the focal-plane field to the PSF, |phi> (.) |phi>^dag,
+ * and the product of the two spectra in the image-formation equation).  It is
+ * computed as the application of the diagonal operator of a (cores
+ * delta_ts A_k, built on the device from a's cores and device bonds; bonds
+ * bounded by a->chi_cap) to b: zip-up with the diagonal-site contraction,
+ * cap opts->chi_zip, then the truncation sweep to opts->chi_max, exactly as
+ * mpo_apply.  a and b: same n_sites and dtype; out must not alias either.
+ * out is left-canonical, *out->norm = ||out||.  Workspace:
+ * tt_hadamard_workspace_size(n_sites, a->chi_cap, max capacity of b / out /
+ * chi_zip, prec). */
+size_t tt_hadamard_workspace_size(int n_sites, int chi_cap_a, int chi_cap, int prec);
+int tt_hadamard(const qtt_mps* a, int conj_a, const qtt_mps* b, const qtt_opts* opts, qtt_mps* out, void* ws,
+                size_t ws_bytes, void* stream);
 
 /* Recompress an MPS in place (the truncation of Sec. 4 and App. A applied to
  * an existing MPS: every bond is a Schmidt cut whose singular values decide

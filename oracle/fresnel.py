@@ -70,3 +70,41 @@ def gaussian_beam_exact_1d(n_side, w0, lam, dx, z, c):
     q = 1.0 + 1j * z / zr
     u = (np.arange(n_side) - c) * dx
     return np.exp(-u * u / (w * w * q)) / np.sqrt(q)
+
+
+def transfer_lattice_1d(n_side, lam, dx, z):
+    """Transfer function of the tight-binding (discrete Laplacian) model of
+    Sec. 6.2: energies -2J cos(2 pi k / N) with hopping J = lam / (4 pi dx^2)
+    (the constant shift, a global phase, chosen so that k = 0 has phase 0):
+    T(k) = exp(-i 2 J z (1 - cos(2 pi k / N))).  Its small-k limit is the
+    parabolic transfer function exp(-i pi lam z f^2)."""
+    k = np.arange(n_side)
+    two_jz = lam * z / (2.0 * np.pi * dx * dx)
+    return np.exp(-1j * two_jz * (1.0 - np.cos(2.0 * np.pi * k / n_side)))
+
+
+def lattice_matrix_1d(n_side, lam, dx, z):
+    """Dense N x N lattice propagator F^-1 diag(T) F (periodic)."""
+    eye = np.eye(n_side, dtype=np.complex128)
+    t = transfer_lattice_1d(n_side, lam, dx, z)
+    return np.fft.ifft(np.fft.fft(eye, axis=0) * t[:, None], axis=0)
+
+
+def angular_spectrum_transfer(n_side, lam, dx, z):
+    """Angular-spectrum transfer function of Sec. 6.1 on the FFT frequency
+    grid, T(f_a, f_b) = exp(2 pi i z (sqrt(1/lam^2 - f_a^2 - f_b^2) - 1/lam)):
+    the constant phase e^{ikz} is dropped as for the Fresnel form; where
+    f_a^2 + f_b^2 > 1/lam^2 the square root is i sqrt(f^2 - 1/lam^2), so the
+    evanescent components decay."""
+    f = np.fft.fftfreq(n_side, d=dx)
+    arg = 1.0 / lam ** 2 - (f[:, None] ** 2 + f[None, :] ** 2)
+    kz = np.sqrt(arg.astype(np.complex128))          # principal root: i sqrt(|arg|) for arg < 0
+    return np.exp(2j * np.pi * z * (kz - 1.0 / lam))
+
+
+def angular_spectrum_dense(e0, lam, dx, z):
+    """Propagate an N x N field by the angular-spectrum transfer function
+    (periodic grid, no padding): IFFT2(FFT2(E0) T)."""
+    e0 = np.asarray(e0, dtype=np.complex128)
+    t = angular_spectrum_transfer(e0.shape[0], lam, dx, z)
+    return np.fft.ifft2(np.fft.fft2(e0) * t)

@@ -96,3 +96,22 @@ def hadamard_mpo(n):
     """Hadamard transform H_1^(x)n as a bond-1 MPO (Sec. 5)."""
     h1 = np.array([[1.0, 1.0], [1.0, -1.0]]) / np.sqrt(2.0)
     return [h1.reshape(1, 2, 2, 1).astype(np.complex128) for _ in range(n)]
+
+
+def diag_mpo_from_vector(v, n_sites, rel_err=1e-12):
+    """diag(v) for a length-2^n_sites vector as an MPO by the brute-force
+    construction of Sec. 6.1: the interleaved unfoldings of a diagonal matrix
+    are those of v with zero rows and columns added, so the sequential SVD of
+    v itself (same per-bond rule as mpo_from_matrix) gives its cores, each
+    placed on the t = s diagonal."""
+    from .ttsvd import tt_svd
+    eps = rel_err * rel_err / max(n_sites - 1, 1)
+    cores = tt_svd(np.asarray(v, dtype=np.complex128), n_sites, chi=1 << n_sites, eps=eps)
+    out = []
+    for c in cores:
+        r0, _, r1 = c.shape
+        w = np.zeros((r0, 2, 2, r1), dtype=np.complex128)
+        w[:, 0, 0, :] = c[:, 0, :]
+        w[:, 1, 1, :] = c[:, 1, :]
+        out.append(w)
+    return out

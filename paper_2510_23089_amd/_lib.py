@@ -33,7 +33,7 @@ EXPORTS = [
     "tt_autotune_import", "tt_autotune_clear",
     "tt_encode_separable_workspace_size", "tt_encode_separable", "tt_eval_points_workspace_size", "tt_eval_points",
     "tt_to_dense_block_workspace_size", "tt_to_dense_block", "mpo_apply_noalloc",
-    "tt_to_dense_window_workspace_size", "tt_to_dense_window",
+    "tt_to_dense_window_workspace_size", "tt_to_dense_window", "tt_hadamard_workspace_size", "tt_hadamard",
 ]
 
 
@@ -160,6 +160,10 @@ def load(path=LIB_PATH):
     lib.tt_to_dense_window_workspace_size.restype = sz
     lib.tt_to_dense_window.argtypes = [P(QttMps), i32, i32, i32, i32, i32, vp, i32, vp, sz, vp]
     lib.tt_to_dense_window.restype = i32
+    lib.tt_hadamard_workspace_size.argtypes = [i32, i32, i32, i32]
+    lib.tt_hadamard_workspace_size.restype = sz
+    lib.tt_hadamard.argtypes = [P(QttMps), i32, P(QttMps), P(QttOpts), P(QttMps), vp, sz, vp]
+    lib.tt_hadamard.restype = i32
     lib.mpo_apply_noalloc.argtypes = [P(QttMps), P(QttMpo), P(QttOpts), P(QttMps), vp, vp]
     lib.mpo_apply_noalloc.restype = i32
     lib.tt_check_status.argtypes = [vp, vp]

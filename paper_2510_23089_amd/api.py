@@ -347,6 +347,22 @@ def tt_to_dense_window(psi, row0, col0, rows, cols, log2_block=0, out=None):
     return out
 
 
+def tt_hadamard(a, b, chi, conj_a=False, chi_zip=0, cutoff=0.0, tau=0.0, out=None, chi_cap=None):
+    """Element-wise product out = a (.) b (conj(a) (.) b if conj_a) of two
+    MPS of the same site count, truncated to chi (zip-up cap chi_zip)."""
+    lib = L.load()
+    if out is None:
+        out = MPS(b.n_sites, chi_cap or chi, dtype=b.dtype, device=b.cores.device)
+    o = _opts(chi, chi_zip, cutoff, tau, b.prec)
+    cap = max(b.chi_cap, out.chi_cap, int(chi_zip or 0), int(chi))
+    nb = lib.tt_hadamard_workspace_size(b.n_sites, a.chi_cap, cap, o.prec)
+    ws = workspace(nb, b.cores.device, key="hadamard")
+    sa, sb, so = a.cstruct(), b.cstruct(), out.cstruct()
+    L.check(lib.tt_hadamard(ctypes.byref(sa), 1 if conj_a else 0, ctypes.byref(sb), ctypes.byref(o), ctypes.byref(so),
+                            _ptr(ws), nb, _stream()), "tt_hadamard")
+    return out
+
+
 class MPSBatch:
     """count MPS of one shape in one allocation: cores (count, m, chi_cap, 2, chi_cap)."""
 
@@ -422,7 +438,12 @@ class MPOBatch:
         # a site is a pass-through (kind 1) for the batch when it is one for
         # every member (its padded bond profile then stays equal across it)
         if all(k is not None for k in kinds):
-            kind = np.array([int(all(int(k[j]) == 1 for k in kinds)) for j in range(m)], dtype=np.int32)
+            # identity for the batch when an identity for every member,
+            # diagonal when diagonal for every member, else general
+            kind = np.zeros(m, dtype=np.int32)
+            for j in range(m):
+                kj = {int(k[j]) for k in kinds}
+                kind[j] = kj.pop() if len(kj) == 1 and kj <= {1, 2} else 0
             ok = all(prof[j] == prof[j + 1] for j in range(m) if kind[j] == 1)
             self.site_kind = kind if ok and kind.any() else None
         else:
@@ -590,6 +611,112 @@ class FresnelPropagator:
     def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0, tmp=None, out=None, prec=None, refine=False):
         mid = mpo_apply(psi, self.wx, chi, chi_zip, cutoff, tau, out=tmp, prec=prec, refine=refine)
         return mpo_apply(mid, self.wy, chi, chi_zip, cutoff, tau, out=out, prec=prec, refine=refine)
+
+
+_QFT_CACHE = {}
+
+
+def _qft_pair(n, rel=1e-12):
+    """(QFT_br, QFT_br^H) per-axis MPOs, left-canonical, cached per n."""
+    from . import mpo_build as B
+    if n not in _QFT_CACHE:
+        q = B.round_left(B.qft_br(n), rel)
+        _QFT_CACHE[n] = (q, B.round_left(B.dagger(q), rel))
+    return _QFT_CACHE[n]
+
+
+class FresnelThreeStage:
+    """The per-axis propagator applied as its three factors (Sec. 6.1, Fig. of
+    the MPO product): QFT_br, the diagonal transfer function, QFT_br^H, each
+    an MPO application (zip-up + sweep to chi) of its own, x axis then y axis.
+    route: the diagonal's construction ("svd", "pauli" or, for the lattice
+    dispersion, "bessel"); its sites run the diagonal contraction."""
+
+    def __init__(self, n, lam, dx, z, route="svd", dispersion="parabolic", dtype=torch.complex64, device="cuda",
+                 rel=1e-12):
+        from . import mpo_build as B
+        q, iq = _qft_pair(n, rel)
+        d = B.diag_fresnel(n, lam, dx, z, route, dispersion, rel=rel)
+        self.axis = {"qft": q, "diag": d, "iqft": iq}
+        self.stages = {}
+        for ax in ("x", "y"):
+            seq = []
+            for name, cores, diag in (("qft", q, False), ("diag", d, True), ("iqft", iq, False)):
+                c, kind = B.embed(cores, ax, diag=diag)
+                seq.append(MPO(c, kind, dtype=dtype, device=device, d_cap=max(B.bonds(cores))))
+            self.stages[ax] = seq
+
+    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0):
+        out = psi
+        for ax in ("x", "y"):
+            for w in self.stages[ax]:
+                out = mpo_apply(out, w, chi, chi_zip, cutoff, tau)
+        return out
+
+
+def qft2(psi, chi, inverse=False, chi_zip=0, cutoff=0.0, tau=0.0):
+    """2-D unitary DFT of the field (x then y; with bit-reversed frequency
+    registers, as the QFT MPO of Sec. 5 produces them), or its inverse
+    (bit-reversed registers in, natural order out)."""
+    from . import mpo_build as B
+    n = psi.n_sites // 2
+    q, iq = _qft_pair(n)
+    w1 = iq if inverse else q
+    key = (n, inverse, str(psi.cores.device), psi.dtype)
+    mp = _QFT_MPO.get(key)
+    if mp is None:
+        mp = [MPO(*B.embed(w1, ax), dtype=psi.dtype, device=psi.cores.device, d_cap=max(B.bonds(w1)))
+              for ax in ("x", "y")]
+        _QFT_MPO[key] = mp
+    out = mpo_apply(psi, mp[0], chi, chi_zip, cutoff, tau)
+    return mpo_apply(out, mp[1], chi, chi_zip, cutoff, tau)
+
+
+_QFT_MPO = {}
+
+
+def psf(pupil, chi, chi_field=None, chi_zip=0):
+    """Point spread function of a pupil field (Sec. 5): the focal-plane field
+    phi = QFT(pupil) (x then y, bit-reversed frequency registers, truncated
+    to chi_field), then PSF = conj(phi) (.) phi, truncated to chi.  Returns
+    (phi, psf) as MPS."""
+    phi = qft2(pupil, chi_field or chi, chi_zip=chi_zip)
+    return phi, tt_hadamard(phi, phi, chi, conj_a=True, chi_zip=chi_zip)
+
+
+def image_formation(obj, psf_mps, chi, chi_zip=0):
+    """Image of a scene through an optical system of point spread function
+    psf (both on the natural N x N grid, Sec. 5, equation of the convolution):
+    IQFT(QFT(psf) (.) QFT(obj)), every step truncated to chi; with unitary
+    transforms this is the circular convolution psf * obj divided by N."""
+    a = qft2(psf_mps, chi, chi_zip=chi_zip)
+    b = qft2(obj, chi, chi_zip=chi_zip)
+    return qft2(tt_hadamard(a, b, chi, chi_zip=chi_zip), chi, inverse=True, chi_zip=chi_zip)
+
+
+class AngularSpectrum:
+    """The non-paraxial angular-spectrum propagator (Sec. 6.1): QFT on both
+    axes, the 2-D transfer function as one diagonal MPO over all 2n sites
+    (it does not separate), inverse QFT on both axes; five MPO applications
+    (zip-up + sweep to chi each)."""
+
+    def __init__(self, n, lam, dx, z, dtype=torch.complex64, device="cuda", rel=1e-12):
+        from . import mpo_build as B
+        q, iq = _qft_pair(n, rel)
+        d2 = B.angular_spectrum_diag(n, lam, dx, z, rel)
+        self.diag_cores = d2
+        dq = max(B.bonds(q))
+        self.qx = MPO(*B.embed(q, "x"), dtype=dtype, device=device, d_cap=dq)
+        self.qy = MPO(*B.embed(q, "y"), dtype=dtype, device=device, d_cap=dq)
+        self.iqx = MPO(*B.embed(iq, "x"), dtype=dtype, device=device, d_cap=dq)
+        self.iqy = MPO(*B.embed(iq, "y"), dtype=dtype, device=device, d_cap=dq)
+        self.d = MPO(d2, [2] * len(d2), dtype=dtype, device=device)
+
+    def __call__(self, psi, chi, chi_zip=0, cutoff=0.0, tau=0.0):
+        out = psi
+        for w in (self.qx, self.qy, self.d, self.iqy, self.iqx):
+            out = mpo_apply(out, w, chi, chi_zip, cutoff, tau)
+        return out
 
 
 # ------------------------------------------------------------------ autotuner

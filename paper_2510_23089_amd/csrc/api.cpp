@@ -500,7 +500,19 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       int r = gemm(c, dv(c, 2, ra), 2, 2 * p.rin[k], dv(c, Db, bet), Db, Db * p.beta[k + 1], dv(c, 1, rb), 1, A, B, C);
       if (r) return r;
     }
-    if (!ident) {
+    if (p.kind[k] == 2) {
+      // diagonal site (W[w'][t][s][w] = 0 for t != s): per output bit t,
+      // M[a][w'][b][t] = sum_w X[a][b][t][w] W[w'][t][t][w] -- half the depth
+      // of the general product, no reads of the zero blocks
+      const char* Wk = Wc + (size_t)k * dcap * 4 * dcap * csz;
+      for (int t = 0; t < 2; ++t) {
+        Operand A = opd((const char*)b.X + (size_t)t * Db * csz, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db);
+        Operand B = opd(Wk + (size_t)3 * t * Db * csz, 1, 0, 4 * Db, 0, 0, sW);
+        Operand C = opd((char*)b.Mb + (size_t)t * csz, 2, 0, 2 * zc, 0, 0, b.sX, (ll)Da * zc * 2);
+        int r = gemm(c, dv(c, 1, bet), 1, p.beta[k + 1], dx(Da), 1, Da, dx(Db), 1, A, B, C, dv(c, 1, ra), p.rin[k]);
+        if (r) return r;
+      }
+    } else if (!ident) {
       // GEMM2 (inner batch over a): M[a][w'][b][t] = sum_{s,w} X[a][b][s][w] W[w'][t][s][w]
       Operand A = opd(b.X, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db);
       Operand B = opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 1, 0, 4 * Db, 2 * Db, 0, sW);
@@ -792,6 +804,7 @@ int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opt
     }
     for (int k = 0; k < m; ++k) {
       su.kind[k] = kd ? kd[k] : 0;
+      if (su.kind[k] < 0 || su.kind[k] > 2) return fail(QTT_ERR_ARG, "site_kind[%d] = %d not in {0, 1, 2}", k, su.kind[k]);
       if (su.kind[k] == 1 && su.dbonds[k] != su.dbonds[k + 1])
         return fail(QTT_ERR_SHAPE, "identity site %d changes the bond", k);
     }
@@ -1629,6 +1642,47 @@ int mpo_apply_batched(const qtt_mps_batch* in, const qtt_mpo_batch* W, const qtt
   MpoB wb = mpob_view(W);
   return apply_common(view(in), nullptr, &wb, opts, view(out), chi_dev, ws, ws_bytes, stream, false, saved,
                       saved_bytes);
+}
+
+static size_t hadamard_mpo_bytes(int m, int cap_a, size_t csz) {
+  return ((size_t)m * cap_a * 4 * cap_a * csz + 255) / 256 * 256;
+}
+
+size_t tt_hadamard_workspace_size(int n_sites, int chi_cap_a, int chi_cap, int prec) {
+  const size_t ap = tt_workspace_size(QTT_OP_APPLY, n_sites, chi_cap, chi_cap_a, prec);
+  if (!ap || chi_cap_a < 1 || chi_cap_a > 256) return 0;
+  return hadamard_mpo_bytes(n_sites, chi_cap_a, prec == QTT_PREC_FP64 ? 16 : 8) + ap;
+}
+
+int tt_hadamard(const qtt_mps* a, int conj_a, const qtt_mps* b, const qtt_opts* opts, qtt_mps* out, void* ws,
+                size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mps(a, "a"))) return r;
+  if ((r = check_mps(b, "b"))) return r;
+  if ((r = check_mps(out, "out"))) return r;
+  if (a->n_sites != b->n_sites) return fail(QTT_ERR_SHAPE, "a has %d sites, b %d", a->n_sites, b->n_sites);
+  if (a->dtype != b->dtype) return fail(QTT_ERR_DTYPE, "a and b dtypes differ");
+  if (out->cores == b->cores || out->cores == a->cores) return fail(QTT_ERR_ARG, "out must not alias a or b");
+  if (!ws) return fail(QTT_ERR_ARG, "workspace is NULL");
+  const int m = a->n_sites, dcap = a->chi_cap;
+  const size_t csz = a->dtype == QTT_C128 ? 16 : 8;
+  const size_t wsz = hadamard_mpo_bytes(m, dcap, csz);
+  if (ws_bytes < wsz) return fail(QTT_ERR_WORKSPACE, "workspace %zu < %zu bytes for the operator", ws_bytes, wsz);
+  // the element-wise product a (.) b is the diagonal operator of a applied to
+  // b: its cores are delta_ts A_k, bonds those of any MPS of a's capacity
+  std::vector<int> db = mps_bounds(m, dcap);
+  std::vector<int> kind(m, 2);
+  qtt_mpo W;
+  W.n_sites = m;
+  W.d_cap = dcap;
+  W.dtype = a->dtype;
+  W.cores = ws;
+  W.d_bonds = db.data();
+  W.site_kind = kind.data();
+  HIPCHK(mps_to_diag_mpo(a->cores, a->bonds, a->chi_cap, conj_a ? 1 : 0, ws, dcap, m, a->dtype == QTT_C128 ? 1 : 0,
+                         (hipStream_t)stream));
+  return apply_common(view(b), &W, nullptr, opts, view(out), nullptr, (char*)ws + wsz, ws_bytes - wsz, stream, false);
 }
 
 int tt_truncate(qtt_mps* inout, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream) {

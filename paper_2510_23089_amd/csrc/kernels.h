@@ -172,6 +172,12 @@ hipError_t select_bit(const void* C, long long ldc, void* Lnext, long long ldl, 
 hipError_t gather_col0(const void* Lf, long long ldl, void* out, int count, int dtype, hipStream_t s);
 hipError_t unit_rows(void* L, long long ldl, int count, int cap, int dtype, hipStream_t s);
 hipError_t fill_point(int* rows, int* cols, int row, int col, hipStream_t s);
+// Diagonal MPO of an MPS for the element-wise product: core k dense
+// [D_k][t][s][D_(k+1)] at element offset k * dcap * 4 * dcap with D_k =
+// min(cap, 2^k, 2^(m-k)), W = delta_ts A_k (conj if conj), zero outside the
+// MPS's device bonds.  dtype 0 complex64, 1 complex128.
+hipError_t mps_to_diag_mpo(const void* A, const int* bonds, int cap, int conj, void* W, int dcap, int m, int dtype,
+                           hipStream_t s);
 // Scan a complex buffer for non-finite values and flag the status word.
 hipError_t check_finite(const void* p, int dtype, long long count, int* status, hipStream_t s);
 

@@ -373,6 +373,53 @@ hipError_t set_one_b(void* p, long long s_f, int dtype, int nf, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Diagonal MPO of an MPS (the element-wise product with that MPS as an
+// operator): W[k][w][t][s][w'] = delta_ts A_k[w][s][w'] (conjugated if conj)
+// for w, w' inside the MPS's device bonds, 0 elsewhere up to the operator's
+// bond bounds D_k = min(cap, 2^k, 2^(m-k)) (the bounds of any m-site MPS of
+// capacity cap; zero padding leaves the operator unchanged).  One thread per
+// (site, w, t, s, w') of the d_cap-strided operator.
+__device__ __forceinline__ int mps_bound(int k, int m, int cap) {
+  const int a = k >= 30 ? cap : min(cap, 1 << k);
+  const int b = m - k >= 30 ? cap : min(cap, 1 << (m - k));
+  return min(a, b);
+}
+
+template <typename C>
+__global__ void mps_to_diag_mpo_kernel(const C* A, const int* bonds, int cap, int conj, C* W, int dcap, int m) {
+  const long long per = (long long)dcap * 4 * dcap;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= per * m) return;
+  const int k = (int)(e / per);
+  const long long r = e - (long long)k * per;
+  const int w = (int)(r / (4 * dcap)), ts = (int)((r / dcap) & 3), w2 = (int)(r % dcap);
+  const int t = ts >> 1, sb = ts & 1;
+  const int dl = mps_bound(k, m, cap), dr = mps_bound(k + 1, m, cap);
+  if (w >= dl || w2 >= dr) return;                       // outside this site's operator bonds
+  const int bl = min(bonds[k], cap), br = min(bonds[k + 1], cap);
+  C v;
+  v.x = 0;
+  v.y = 0;
+  if (t == sb && w < bl && w2 < br) {
+    v = A[(long long)k * cap * 2 * cap + (long long)w * 2 * cap + (long long)sb * cap + w2];
+    if (conj) v.y = -v.y;
+  }
+  W[(long long)k * per + ((long long)w * 4 + ts) * dr + w2] = v;
+}
+
+hipError_t mps_to_diag_mpo(const void* A, const int* bonds, int cap, int conj, void* W, int dcap, int m, int dtype,
+                           hipStream_t s) {
+  const long long tot = (long long)dcap * 4 * dcap * m;
+  const int blocks = (int)((tot + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(mps_to_diag_mpo_kernel<float2>, dim3(blocks), dim3(256), 0, s, (const float2*)A, bonds, cap,
+                       conj, (float2*)W, dcap, m);
+  else
+    hipLaunchKernelGGL(mps_to_diag_mpo_kernel<double2>, dim3(blocks), dim3(256), 0, s, (const double2*)A, bonds, cap,
+                       conj, (double2*)W, dcap, m);
+  return hipGetLastError();
+}
+
 // Write one complex element (used to seed the zip-up carry with 1).
 __global__ void set_one_kernel(void* p, int dtype) {
   if (dtype == 0) ((float2*)p)[0] = make_float2(1.f, 0.f);

@@ -209,19 +209,206 @@ def identity_core(d):
     return np.einsum("ab,ts->atsb", np.eye(d), np.eye(2)).astype(np.complex128)
 
 
-def embed(cores_1d, axis):
+def embed(cores_1d, axis, diag=False):
     """2n-site quantics MPO for one axis; returns (cores, site_kind) with
-    site_kind 1 on the identity (pass-through) sites."""
+    site_kind 1 on the identity (pass-through) sites and, for an operator
+    diagonal in the computational basis (diag=True), 2 on its own sites."""
     cores, kind = [], []
+    own = 2 if diag else 0
     for c in cores_1d:
         if axis == "x":
             cores += [c, identity_core(c.shape[3])]
-            kind += [0, 1]
+            kind += [own, 1]
         else:
             cores += [identity_core(c.shape[0]), c]
-            kind += [1, 0]
+            kind += [1, own]
     return cores, kind
 
 
 def bonds(cores):
     return [1] + [int(c.shape[3]) for c in cores]
+
+
+# ------------------------------------------------------------------ diagonal operators, other routes
+# Sec. 6.2: a diagonal operator U = diag(exp(-i phi(s))) on an n-bit register
+# (bits s_1..s_n, most significant first) has three constructions as an MPO:
+#   * the sequential SVD of its diagonal (diag_br above);
+#   * the Pauli-Z expansion phi = sum_S c_S prod_{j in S} Z_j, whose
+#     coefficients are the Walsh-Hadamard transform of phi; since the strings
+#     commute, U = prod_S (cos c_S I - i sin c_S P_S), each factor a bond-2
+#     MPO, absorbed one after the other into the identity with recompression
+#     (the gate-product circuit of the paper);
+#   * for the lattice dispersion phi = t cos(2 pi x_s), x_s = sum_j s_j 2^-j,
+#     the Jacobi-Anger expansion exp(-i t cos a) = sum_p (-i)^p J_p(t) e^{ipa},
+#     a closed-form MPO of bond 2 p_max + 1 (phases e^{i p theta_j s_j} per
+#     site, theta_j = 2 pi / 2^j, Bessel weights on the left boundary).
+Z1 = np.array([1.0, -1.0])
+
+
+def walsh_hadamard(phi):
+    """c_S = 2^-n sum_s phi(s) (-1)^(sum_{j in S} s_j) for every subset S of
+    the n register bits, indexed like the register (bit j of the index is
+    bit j of the bitmask S); fast transform in n butterfly passes."""
+    c = np.array(phi, dtype=np.float64).copy()
+    n = int(round(np.log2(c.size)))
+    h = 1
+    for _ in range(n):
+        c = c.reshape(-1, 2, h)
+        a, b = c[:, 0, :].copy(), c[:, 1, :].copy()
+        c[:, 0, :] = a + b
+        c[:, 1, :] = a - b
+        c = c.reshape(-1)
+        h *= 2
+    return c / c.size
+
+
+def _string_factor(n, mask, omega):
+    """MPO of exp(-i omega P_S) = cos(omega) I - i sin(omega) P_S, P_S the
+    product of Z over the register bits in S (bitmask, MSB = site 0)."""
+    sites = [j for j in range(n) if (mask >> (n - 1 - j)) & 1]
+    eye = np.eye(2, dtype=np.complex128)
+    z = np.diag(Z1).astype(np.complex128)
+    cores = [eye.reshape(1, 2, 2, 1).copy() for _ in range(n)]
+    if not sites:
+        cores[0] = cores[0] * np.exp(-1j * omega)
+        return cores
+    j0, j1 = sites[0], sites[-1]
+    if j0 == j1:
+        cores[j0] = (np.cos(omega) * eye - 1j * np.sin(omega) * z).reshape(1, 2, 2, 1)
+        return cores
+    w = np.zeros((1, 2, 2, 2), dtype=np.complex128)
+    w[0, :, :, 0] = np.cos(omega) * eye
+    w[0, :, :, 1] = -1j * np.sin(omega) * z
+    cores[j0] = w
+    for j in range(j0 + 1, j1):
+        w = np.zeros((2, 2, 2, 2), dtype=np.complex128)
+        w[0, :, :, 0] = eye
+        w[1, :, :, 1] = z if j in sites else eye
+        cores[j] = w
+    w = np.zeros((2, 2, 2, 1), dtype=np.complex128)
+    w[0, :, :, 0] = eye
+    w[1, :, :, 0] = z
+    cores[j1] = w
+    return cores
+
+
+def diag_pauli(phi, gate_cutoff=0.0, rel=1e-12):
+    """MPO of diag(exp(-i phi)) from the gates of its Pauli-Z expansion:
+    strings with |c_S| > gate_cutoff (0 keeps every nonzero one), absorbed
+    one by one with recompression; left-canonical result."""
+    phi = np.asarray(phi, dtype=np.float64)
+    n = int(round(np.log2(phi.size)))
+    c = walsh_hadamard(phi)
+    scale = max(np.abs(c).max(), 1e-300)
+    acc = [np.eye(2, dtype=np.complex128).reshape(1, 2, 2, 1) for _ in range(n)]
+    for mask in np.flatnonzero(np.abs(c) > max(gate_cutoff, 1e-15 * scale)):
+        acc = compress(mul(_string_factor(n, int(mask), float(c[mask])), acc), rel * 1e-2)
+    return round_left(acc, rel)
+
+
+def diag_bessel(n, t, p_max, bitrev=False, rel=1e-12):
+    """MPO of diag(exp(-i t cos(2 pi x))) on n register bits by the
+    Jacobi-Anger expansion truncated at |p| <= p_max, x the register read
+    most significant bit first (x = sum_j s_j 2^-j), or with the register in
+    bit-reversed order (bitrev: site j carries the bit of weight 2^(j-1) / N,
+    as the output register of QFT_br).  Closed form, then left-canonical
+    rounding (the closed form's bond 2 p_max + 1 is far above the rank);
+    rel = 0 returns the closed form unrounded."""
+    from scipy.special import jv
+    ps = np.arange(-p_max, p_max + 1)
+    chi = ps.size
+    left = ((-1j) ** ps) * jv(ps, t)
+    theta = [2.0 * np.pi / 2.0 ** (j + 1) for j in range(n)]
+    if bitrev:
+        theta = theta[::-1]
+    cores = []
+    for j in range(n):
+        w = np.zeros((chi, 2, 2, chi), dtype=np.complex128)
+        for s in range(2):
+            w[np.arange(chi), s, s, np.arange(chi)] = np.exp(1j * ps * theta[j] * s)
+        cores.append(w)
+    cores[0] = np.tensordot(left, cores[0], axes=(0, 0))[None]
+    cores[-1] = cores[-1].sum(axis=3)[..., None]
+    if not rel:
+        return cores                                  # the closed form itself, bond 2 p_max + 1
+    return round_left(compress(cores, rel * 1e-2), rel)
+
+
+def transfer_lattice(n, lam, dx, z):
+    """Transfer function of the lattice (tight-binding) model of Sec. 6.2 on
+    the FFT frequency grid: exp(-i 2 J z (1 - cos(2 pi k / N))), hopping
+    J = lam / (4 pi dx^2); the parabolic form is its small-k limit."""
+    k = np.arange(1 << n)
+    t = lam * z / (2.0 * np.pi * dx * dx)
+    return np.exp(-1j * t * (1.0 - np.cos(2.0 * np.pi * k / (1 << n))))
+
+
+def fresnel_phase_br(n, lam, dx, z, dispersion="parabolic"):
+    """Phase phi with T = exp(-i phi) in the bit-reversed frequency register."""
+    if dispersion == "parabolic":
+        f = np.fft.fftfreq(1 << n, d=dx)
+        phi = np.pi * lam * z * f * f
+    else:
+        k = np.arange(1 << n)
+        phi = lam * z / (2.0 * np.pi * dx * dx) * (1.0 - np.cos(2.0 * np.pi * k / (1 << n)))
+    return phi[bit_reverse(n)]
+
+
+def diag_fresnel(n, lam, dx, z, route="svd", dispersion="parabolic", p_max=None, rel=1e-12):
+    """The transfer function between the two Fourier transforms (Sec. 6.1,
+    Fig. of the MPO product) as a diagonal MPO on the bit-reversed frequency
+    register, by one of the routes above; left-canonical."""
+    phi = fresnel_phase_br(n, lam, dx, z, dispersion)
+    if route == "svd":
+        return round_left(_diag_cores(_vec_tt(np.exp(-1j * phi), rel * 1e-2)), rel)
+    if route == "pauli":
+        return diag_pauli(phi, rel=rel)
+    if route == "bessel":
+        if dispersion != "lattice":
+            raise ValueError("the Bessel closed form is that of the lattice dispersion")
+        t = lam * z / (2.0 * np.pi * dx * dx)
+        pm = p_max if p_max is not None else int(np.ceil(abs(t) + 12.0 * max(abs(t), 1.0) ** (1.0 / 3.0) + 14))
+        # exp(-i t (1 - cos a)) = exp(-i t) exp(+i t cos a): the expansion at -t
+        cores = diag_bessel(n, -t, pm, bitrev=True, rel=rel)
+        cores[0] = cores[0] * np.exp(-1j * t)
+        return cores
+    raise ValueError(route)
+
+
+def _diag_cores(vec_cores):
+    out = []
+    for c in vec_cores:
+        r0, _, r1 = c.shape
+        w = np.zeros((r0, 2, 2, r1), dtype=np.complex128)
+        w[:, 0, 0, :] = c[:, 0, :]
+        w[:, 1, 1, :] = c[:, 1, :]
+        out.append(w)
+    return out
+
+
+def fresnel_three_stage(n, lam, dx, z, route="svd", dispersion="parabolic", rel=1e-12):
+    """Per-axis factors (QFT_br, diag_br(T), QFT_br^H) of the propagator,
+    each left-canonical, applied right to left: U = QFT^H . diag . QFT."""
+    q = round_left(qft_br(n), rel)
+    d = diag_fresnel(n, lam, dx, z, route, dispersion, rel=rel)
+    return q, d, round_left(dagger(q), rel)
+
+
+def angular_spectrum_diag(n, lam, dx, z, rel=1e-12):
+    """Angular-spectrum transfer function exp(2 pi i z (sqrt(1/lam^2 - f^2) -
+    1/lam)) (Sec. 6.1, global phase e^{ikz} dropped; evanescent components
+    decay as exp(-2 pi z sqrt(f^2 - 1/lam^2))) on the 2n interleaved sites of
+    the two bit-reversed frequency registers, as a diagonal MPO by the
+    sequential SVD of its diagonal: not separable, so one 2-D operator."""
+    fr = np.fft.fftfreq(1 << n, d=dx)[bit_reverse(n)]
+    f2 = fr[:, None] ** 2 + fr[None, :] ** 2
+    arg = 1.0 / lam ** 2 - f2
+    kz = np.where(arg >= 0.0, np.sqrt(np.abs(arg)) + 0j, 1j * np.sqrt(np.abs(arg)))
+    t = np.exp(2j * np.pi * z * (kz - 1.0 / lam))
+    # quantics order: bit p of the row register then bit p of the column one
+    v = t.reshape((2,) * (2 * n))
+    order = []
+    for p in range(n):
+        order += [p, n + p]
+    v = np.ascontiguousarray(v.transpose(order)).reshape(-1)
+    return round_left(_diag_cores(_vec_tt(v, rel * 1e-2)), rel)

@@ -168,3 +168,16 @@ def test_gaussian_beam_closed_form_1d(n_side, w0, z):
     if n_side <= 1024:
         two = F.gaussian_beam_exact(n_side, w0, LAM, DX, z, c, c)
         assert np.allclose(np.outer(ref, ref), two, rtol=0, atol=1e-13)
+
+
+def test_diag_mpo_from_vector_equals_the_brute_force_construction():
+    """The diagonal shortcut gives the same operator, bonds and Schmidt
+    values as the interleaved sequential SVD of the dense diagonal matrix."""
+    from oracle import mpo as OM
+    rng = np.random.default_rng(5)
+    n = 5
+    v = np.exp(1j * np.cumsum(rng.standard_normal(1 << n)) * 0.2)
+    a = OM.diag_mpo_from_vector(v, n)
+    b = OM.mpo_from_matrix(np.diag(v), n)
+    assert np.abs(OM.mpo_dense(a) - np.diag(v)).max() < 1e-12
+    assert [c.shape[3] for c in a] == [c.shape[3] for c in b]
