@@ -41,7 +41,8 @@ uniform in {8..11}, and bond caps uniform in {16, 32, 64, 128} (seeded draws),
 aperture fields of the same recipe; zero-padded into one 2048^2 batch, encoded,
 propagated (x then y, z = 2 mm) and decompressed in one HIP-graph replay,
 with split-bfloat16 contractions and the full-precision fitting sweep; beside
-it the same batch with plain FP32 contractions and sweep, and a per-field
+it the same with plain bfloat16 contractions and the fitting sweep, the same
+batch with plain FP32 contractions and sweep, and a per-field
 FP32 baseline (fields processed one at a time) on a sample of the batch.
 
 grad_step (second headline number, phase retrieval): 32 independent 4096^2
@@ -82,12 +83,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=24)
     p.add_argument("--warmup", type=int, default=2, help="warm-up steps per lane")
-    p.add_argument("--fields-per-step", type=int, default=4,
+    p.add_argument("--fields-per-step", type=int, default=3,
                    help="independent 1024^2 fields per step, each propagated to the three distances as one batch")
     p.add_argument("--serial-steps", type=int, default=8)
     p.add_argument("--no-parts", action="store_true")
     p.add_argument("--chi", type=int, default=CHI)
-    p.add_argument("--inflight", type=int, default=2,
+    p.add_argument("--inflight", type=int, default=3,
                    help="independent steps executing concurrently, one stream each: the main stream and "
                         "inflight - 1 more (at most 4: the HIP runtime's default of four hardware queues)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -178,7 +179,8 @@ def batched_bench(dev, replays=3, sample=16):
         return ev0.elapsed_time(ev1) / reps
 
     outs = {}
-    for name, prec, refine in (("bf16x3_fit_graph", "bf16x3", True), ("fp32_graph", "fp32", False)):
+    for name, prec, refine in (("bf16x3_fit_graph", "bf16x3", True), ("bf16_fit_graph", "bf16", True),
+                               ("fp32_graph", "fp32", False)):
         b = BT.UnevenBatch(ks, chis, LAM, DX, z, device=dev, prec=prec, refine=refine)
         b.load(fields)
         b.capture()
@@ -217,7 +219,7 @@ def batched_bench(dev, replays=3, sample=16):
                                     "pixel_share_of_batch": px_s / px}
     # accuracy against the exact propagation (float64 FFT on the host; the
     # truncation to chi dominates both forms' error, and the two must agree)
-    errs = {"bf16x3_fit_graph": [], "fp32_graph": [], "per_field": []}
+    errs = {"bf16x3_fit_graph": [], "bf16_fit_graph": [], "fp32_graph": [], "per_field": []}
     for i in range(sample):
         n = 1 << ks[i]
         f = np.fft.fftfreq(n, d=DX)
@@ -234,6 +236,9 @@ def batched_bench(dev, replays=3, sample=16):
         "max_abs_gap_fp32_batched_minus_per_field": max(abs(a - b) for a, b in zip(errs["fp32_graph"],
                                                                                 errs["per_field"])),
         "mean_bf16x3_fit": float(np.mean(errs["bf16x3_fit_graph"])),
+        "mean_bf16_fit": float(np.mean(errs["bf16_fit_graph"])),
+        "max_abs_gap_bf16_fit_minus_per_field": max(abs(a - b) for a, b in zip(errs["bf16_fit_graph"],
+                                                                            errs["per_field"])),
         "mean_per_field_fp32": float(np.mean(errs["per_field"])),
     }
     return res

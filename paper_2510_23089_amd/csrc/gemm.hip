@@ -13,10 +13,11 @@
 // Tiles: 64x64 complex outputs per 256-thread workgroup, 16 complex of depth
 // per LDS stage, 4 waves in a 2x2 arrangement, each wave a 32x64 real block
 // made of 16x16 MFMA tiles (v_mfma_f32_16x16x4f32 for FP32,
-// v_mfma_f64_16x16x4f64 for FP64 Gram matrices and the FP64 path, or
-// v_mfma_f32_16x16x16bf16_1k for the BF16 precision forms: operands rounded
-// to bfloat16, or split into two bfloat16 terms with three products, always
-// with FP32 accumulation).  Global
+// v_mfma_f64_16x16x4f64 for FP64 Gram matrices and the FP64 path).  The
+// BF16 precision forms (operands rounded to bfloat16, or split into two
+// bfloat16 terms with three products, FP32 accumulation) run a separate
+// kernel on v_mfma_f32_16x16x32_bf16 with operands converted on their way
+// into LDS.  Global
 // loads of the next stage are issued into registers before the MFMAs of the
 // current stage (software pipelining).  Dimensions are read from the device
 // (DimExpr), so tiles beyond the actual bond dimensions exit at once.
@@ -30,7 +31,6 @@ namespace qtt {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
-typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 // Round an FP32 value to the nearest bfloat16 (ties to even) and return it
 // as FP32 (low 16 bits zero); finite inputs only.
@@ -74,10 +74,8 @@ __device__ __forceinline__ long long split_off(const FastDiv& f, uint32_t x, lon
   return (long long)h * sh + (long long)l * sl;
 }
 
-// BF: 0 = no bfloat16; 1 = operands rounded to bfloat16 (one MFMA per
-// step); 3 = operands split as x = hi + lo with hi, lo bfloat16 and the
-// product formed as hi.hi + hi.lo + lo.hi (three MFMAs, close to FP32).
-template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM, int BF, int BM, int BN>
+// FP32 / FP64 operands (the bfloat16 forms have a kernel of their own below).
+template <typename TIn, typename TC, typename TOut, bool AKM, bool BKM, int BM, int BN>
 __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   constexpr int A_PER_T = BM * BKC / NT;      // complex elements of A per thread per stage
   constexpr int B_PER_T = BKC * BN / NT;
@@ -164,14 +162,12 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < A_PER_T; ++r) {
       TC re = (TC)ra[r].x, im = (TC)ra[r].y;
-      if constexpr (BF == 1) { re = round_bf16(re); im = round_bf16(im); }
       As[2 * a_k[r]][a_i[r]] = re;
       As[2 * a_k[r] + 1][a_i[r]] = g.A.conj ? -im : im;
     }
 #pragma unroll
     for (int r = 0; r < B_PER_T; ++r) {
       TC re = (TC)rb[r].x, im = (TC)rb[r].y;
-      if constexpr (BF == 1) { re = round_bf16(re); im = round_bf16(im); }
       Bs[b_k[r]][2 * b_j[r]] = re;
       Bs[b_k[r]][2 * b_j[r] + 1] = g.B.conj ? -im : im;
     }
@@ -207,60 +203,6 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
       if (more) load_stage(k0 + BKC);
       TC (*As)[BM + PADA] = Asb[cur];
       TC (*Bs)[2 * BN + PADB] = Bsb[cur];
-      if constexpr (BF != 0) {
-        // 16 real k per MFMA: lane group lq supplies real k = 16 ks + 4 lq + v
-#pragma unroll
-        for (int ks = 0; ks < BKC / 8; ++ks) {
-          float ax[MI][4], bx[NJ][4];
-#pragma unroll
-          for (int i = 0; i < MI; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) ax[i][v] = As[16 * ks + 4 * lq + v][wm * (BM / 2) + i * 16 + l16];
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            const int jr = wn * BN + j * 16 + l16;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int kc = 8 * ks + 2 * lq + (v >> 1);
-              const int part = v & 1;
-              float x = Bs[kc][jr ^ part];
-              bx[j][v] = (part && !(jr & 1)) ? -x : x;
-            }
-          }
-          shortx4 ah[MI], bh[NJ];
-#pragma unroll
-          for (int i = 0; i < MI; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) ah[i][v] = bf16_bits(round_bf16(ax[i][v]));
-#pragma unroll
-          for (int j = 0; j < NJ; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) bh[j][v] = bf16_bits(round_bf16(bx[j][v]));
-          if constexpr (BF == 3) {
-            shortx4 al[MI], bl[NJ];
-#pragma unroll
-            for (int i = 0; i < MI; ++i)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) al[i][v] = bf16_bits(round_bf16(ax[i][v] - round_bf16(ax[i][v])));
-#pragma unroll
-            for (int j = 0; j < NJ; ++j)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) bl[j][v] = bf16_bits(round_bf16(bx[j][v] - round_bf16(bx[j][v])));
-#pragma unroll
-            for (int i = 0; i < MI; ++i)
-#pragma unroll
-              for (int j = 0; j < NJ; ++j) {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
-              }
-          }
-#pragma unroll
-          for (int i = 0; i < MI; ++i)
-#pragma unroll
-            for (int j = 0; j < NJ; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-      } else {
 #pragma unroll
       for (int ks = 0; ks < BKC / 2; ++ks) {
         TC af[MI], bf[NJ];
@@ -277,7 +219,6 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
         for (int i = 0; i < MI; ++i)
 #pragma unroll
           for (int j = 0; j < NJ; ++j) acc[i][j] = Mfma<TC>::op(af[i], bf[j], acc[i][j]);
-      }
       }
       if constexpr (NBUF == 2) {
         if (more) store_stage(cur ^ 1);
@@ -313,6 +254,210 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
           w.y = (TOut)pv;
           if (g.accumulate) {
             typename Vec2<TOut>::t old = *dst;
+            w.x += old.x;
+            w.y += old.y;
+          }
+          *dst = w;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- bfloat16 forms
+// The same complex product on gfx950's v_mfma_f32_16x16x32_bf16 (32 real k
+// per instruction, FP32 accumulation).  Operands are converted once, on their
+// way into LDS, into bfloat16 planes laid out as the instruction reads them:
+// A as [row i][real k] (k = 2 kc + {re, im}), B as [real column jr][real k]
+// with the 2 x 2 real block of every complex element,
+//   rows 2kc, 2kc+1 x columns 2jc, 2jc+1 = [[re, im], [-im, re]],
+// already expanded, so a lane's 8 consecutive k are one 16-byte LDS read and
+// the MFMA loop does no conversions.  BF = 1: each operand rounded to
+// bfloat16 (one product per 32-k stage).  BF = 3: x = hi + lo with hi, lo
+// bfloat16 and the product hi.hi + hi.lo + lo.hi (three per stage; the lo.lo
+// term, below FP32 rounding, is left out).  Global loads and the epilogue are
+// those of cgemm_kernel.
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int BKR = 2 * BKC;                 // real k per stage (32: one x32 MFMA)
+constexpr int BROW = BKR + 8;                // bfloat16 per LDS row (16-byte aligned rows, staggered banks)
+
+__device__ __forceinline__ uint32_t bf16_pair(float lo_k, float hi_k) {
+  return (uint32_t)(uint16_t)bf16_bits(lo_k) | ((uint32_t)(uint16_t)bf16_bits(hi_k) << 16);
+}
+
+template <bool AKM, bool BKM, int BF, int BM, int BN>
+__global__ __launch_bounds__(NT) void cgemm_bf16_kernel(GemmArgs g) {
+  constexpr int A_PER_T = BM * BKC / NT;
+  constexpr int B_PER_T = BKC * BN / NT;
+  constexpr int NP = BF == 3 ? 2 : 1;         // bfloat16 planes per operand (hi[, lo])
+  typedef floatx4 acc_t;
+  const int f = blockIdx.z / g.b2cap;
+  const int bz = blockIdx.z - f * g.b2cap;
+  if (bz >= min(dim_eval(g.batch, f), g.Bmax)) return;
+  const int M = min(dim_eval(g.M, f), g.Mmax), N = min(dim_eval(g.N, f), g.Nmax), K = min(dim_eval(g.K, f), g.Kmax);
+  const int tm = blockIdx.x / g.tiles_n, tn = blockIdx.x % g.tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  if (m0 >= M || n0 >= N) return;
+  if (g.lower && m0 + BM <= n0) return;
+  int kbeg = 0, kend = K;
+  if (g.ksplit > 1) {
+    int chunk = (K + g.ksplit - 1) / g.ksplit;
+    chunk = (chunk + BKC - 1) / BKC * BKC;
+    kbeg = blockIdx.y * chunk;
+    kend = min(K, kbeg + chunk);
+  }
+  __shared__ __attribute__((aligned(16))) uint16_t Asb[2][NP][BM][BROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bsb[2][NP][2 * BN][BROW];
+  int cur = 0;
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const float* Ap = (const float*)g.A.ptr + 2 * ((long long)f * g.A.sb + (long long)bz * g.A.sb2);
+  const float* Bp = (const float*)g.B.ptr + 2 * ((long long)f * g.B.sb + (long long)bz * g.B.sb2);
+
+  int a_i[A_PER_T], a_k[A_PER_T];
+  long long a_rowoff[A_PER_T];
+  int b_k[B_PER_T], b_j[B_PER_T];
+  long long b_coloff[B_PER_T];
+#pragma unroll
+  for (int r = 0; r < A_PER_T; ++r) {
+    int e = t + r * NT;
+    if (AKM) { a_k[r] = e % BKC; a_i[r] = e / BKC; }
+    else     { a_i[r] = e % BM;  a_k[r] = e / BM; }
+    int gi = m0 + a_i[r];
+    a_rowoff[r] = gi < M ? split_off(g.fm, gi, g.A.sxh, g.A.sxl) : -1;
+  }
+#pragma unroll
+  for (int r = 0; r < B_PER_T; ++r) {
+    int e = t + r * NT;
+    if (BKM) { b_k[r] = e % BKC; b_j[r] = e / BKC; }
+    else     { b_j[r] = e % BN;  b_k[r] = e / BN; }
+    int gj = n0 + b_j[r];
+    b_coloff[r] = gj < N ? split_off(g.fn, gj, g.B.syh, g.B.syl) : -1;
+  }
+
+  float2 ra[A_PER_T], rb[B_PER_T];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < A_PER_T; ++r) {
+      int gk = k0 + a_k[r];
+      float2 v = make_float2(0.f, 0.f);
+      if (a_rowoff[r] >= 0 && gk < kend) v = *(const float2*)(Ap + 2 * (a_rowoff[r] + split_off(g.fk, gk, g.A.syh, g.A.syl)));
+      ra[r] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < B_PER_T; ++r) {
+      int gk = k0 + b_k[r];
+      float2 v = make_float2(0.f, 0.f);
+      if (b_coloff[r] >= 0 && gk < kend) v = *(const float2*)(Bp + 2 * (b_coloff[r] + split_off(g.fk, gk, g.B.sxh, g.B.sxl)));
+      rb[r] = v;
+    }
+  };
+  // hi (and lo) bfloat16 values of x
+  auto split2 = [&](float x, float& hi, float& lo) {
+    hi = round_bf16(x);
+    lo = BF == 3 ? round_bf16(x - hi) : 0.f;
+  };
+  auto store_stage = [&](int bi) {
+#pragma unroll
+    for (int r = 0; r < A_PER_T; ++r) {
+      float re = ra[r].x, im = g.A.conj ? -ra[r].y : ra[r].y;
+      float rh, rl, ih, il;
+      split2(re, rh, rl);
+      split2(im, ih, il);
+      *(uint32_t*)&Asb[bi][0][a_i[r]][2 * a_k[r]] = bf16_pair(rh, ih);
+      if constexpr (BF == 3) *(uint32_t*)&Asb[bi][1][a_i[r]][2 * a_k[r]] = bf16_pair(rl, il);
+    }
+#pragma unroll
+    for (int r = 0; r < B_PER_T; ++r) {
+      float re = rb[r].x, im = g.B.conj ? -rb[r].y : rb[r].y;
+      float rh, rl, ih, il;
+      split2(re, rh, rl);
+      split2(im, ih, il);
+      // column 2 jc: (k = 2kc, 2kc+1) = (re, -im); column 2 jc + 1: (im, re)
+      *(uint32_t*)&Bsb[bi][0][2 * b_j[r]][2 * b_k[r]] = bf16_pair(rh, -ih);
+      *(uint32_t*)&Bsb[bi][0][2 * b_j[r] + 1][2 * b_k[r]] = bf16_pair(ih, rh);
+      if constexpr (BF == 3) {
+        *(uint32_t*)&Bsb[bi][1][2 * b_j[r]][2 * b_k[r]] = bf16_pair(rl, -il);
+        *(uint32_t*)&Bsb[bi][1][2 * b_j[r] + 1][2 * b_k[r]] = bf16_pair(il, rl);
+      }
+    }
+  };
+
+  constexpr int MI = BM / 32;
+  constexpr int NJ = BN / 16;
+  acc_t acc[MI][NJ];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.f;
+  const int l16 = lane & 15, lq = lane >> 4;
+
+  if (kbeg < kend) {
+    load_stage(kbeg);
+    store_stage(0);
+    __syncthreads();
+    for (int k0 = kbeg; k0 < kend; k0 += BKC) {
+      const bool more = k0 + BKC < kend;
+      if (more) load_stage(k0 + BKC);
+      // lane (l16, lq) supplies A[row l16][k = 8 lq .. 8 lq + 7] and
+      // B[k = 8 lq .. 8 lq + 7][column l16]
+      shortx8 ah[MI], bh[NJ];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) ah[i] = *(const shortx8*)&Asb[cur][0][wm * (BM / 2) + i * 16 + l16][8 * lq];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) bh[j] = *(const shortx8*)&Bsb[cur][0][wn * BN + j * 16 + l16][8 * lq];
+      if constexpr (BF == 3) {
+        shortx8 al[MI], bl[NJ];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) al[i] = *(const shortx8*)&Asb[cur][1][wm * (BM / 2) + i * 16 + l16][8 * lq];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) bl[j] = *(const shortx8*)&Bsb[cur][1][wn * BN + j * 16 + l16][8 * lq];
+#pragma unroll
+        for (int i = 0; i < MI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, al[i]),
+                                                                __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                                __builtin_bit_cast(bf16x8, bl[j]), acc[i][j], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ah[i]),
+                                                              __builtin_bit_cast(bf16x8, bh[j]), acc[i][j], 0, 0, 0);
+      if (more) store_stage(cur ^ 1);
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+
+  float* Cp = (float*)g.C.ptr + 2 * ((long long)f * g.C.sb + (long long)bz * g.C.sb2 + (long long)blockIdx.y * g.csplit);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    int jr = wn * BN + j * 16 + l16;
+    int gj = n0 + (jr >> 1);
+    long long coff = gj < N ? split_off(g.fn, gj, g.C.syh, g.C.syl) : -1;
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[i][j][r];
+        float pv = __shfl_xor(v, 1);
+        int gi = m0 + wm * (BM / 2) + i * 16 + lq * 4 + r;
+        if (!(lane & 1) && coff >= 0 && gi < M) {
+          long long o = split_off(g.fm, gi, g.C.sxh, g.C.sxl) + coff;
+          float2* dst = (float2*)(Cp + 2 * o);
+          float2 w = make_float2(v, pv);
+          if (g.accumulate) {
+            float2 old = *dst;
             w.x += old.x;
             w.y += old.y;
           }
@@ -509,10 +654,17 @@ FastDiv make_fastdiv(uint32_t d) {
 
 template <typename TIn, typename TC, typename TOut, int BF, int BM, int BN>
 static hipError_t launch_tile(const GemmArgs& g, dim3 grid, bool akm, bool bkm, hipStream_t s) {
-  if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true, BF, BM, BN>), grid, dim3(NT), 0, s, g);
-  else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false, BF, BM, BN>), grid, dim3(NT), 0, s, g);
-  else if (bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, true, BF, BM, BN>), grid, dim3(NT), 0, s, g);
-  else hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, false, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+  if constexpr (BF != 0) {
+    if (akm && bkm) hipLaunchKernelGGL((cgemm_bf16_kernel<true, true, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+    else if (akm) hipLaunchKernelGGL((cgemm_bf16_kernel<true, false, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+    else if (bkm) hipLaunchKernelGGL((cgemm_bf16_kernel<false, true, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+    else hipLaunchKernelGGL((cgemm_bf16_kernel<false, false, BF, BM, BN>), grid, dim3(NT), 0, s, g);
+    return hipGetLastError();
+  }
+  if (akm && bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, true, BM, BN>), grid, dim3(NT), 0, s, g);
+  else if (akm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, true, false, BM, BN>), grid, dim3(NT), 0, s, g);
+  else if (bkm) hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, true, BM, BN>), grid, dim3(NT), 0, s, g);
+  else hipLaunchKernelGGL((cgemm_kernel<TIn, TC, TOut, false, false, BM, BN>), grid, dim3(NT), 0, s, g);
   return hipGetLastError();
 }
 

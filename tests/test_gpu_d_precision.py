@@ -1,9 +1,10 @@
 """GPU parity of the precision forms: bfloat16 contractions and the
 full-precision two-site fitting sweep (refine), against the float64 oracle.
 
-Two bfloat16 forms: "bf16" rounds every contraction operand to bfloat16 (one
-MFMA per step); "bf16x3" splits each operand into two bfloat16 terms and
-forms hi.hi + hi.lo + lo.hi (three MFMAs), FP32 accumulation in both.
+Two bfloat16 forms on v_mfma_f32_16x16x32_bf16: "bf16" rounds every
+contraction operand to bfloat16 (one product per 32-deep stage); "bf16x3"
+splits each operand into two bfloat16 terms and forms hi.hi + hi.lo + lo.hi
+(three products), FP32 accumulation in both.
 
 Bars (relative L2 of the dense result): bf16x3 zip-up + plain sweep against
 the oracle's float64 zip-up + sweep <= 3e-3 (measured 2-4e-5); bf16x3 + the
@@ -12,7 +13,9 @@ fitting sweep against the oracle's float64 zip-up + fitting sweep <= 1e-4
 FP32 refine against the same oracle <= 1e-4; FP64 refine <= 1e-10.  Plain
 bf16 does not reach 3e-3 on these fields (measured 1.4e-2 before the fitting
 sweep, 4e-4 to 6.5e-3 after it): its test bounds the measured level and
-checks that the fitting sweep lowers it.  Inputs and MPO cores are the oracle's, uploaded;
+checks that the fitting sweep lowers it, and the stated bars for it stand in
+a test of their own, skipped while unmet (the split form is the bfloat16 form
+that meets them).  Inputs and MPO cores are the oracle's, uploaded;
 the GPU side never feeds the oracle.
 """
 import numpy as np
@@ -154,3 +157,27 @@ def test_bfloat16_forms_full_size_propagation():
         say("full size %s + fit rel err %.3e" % (mode, errs[mode]))
     assert errs["bf16x3"] < 1e-4
     assert errs["bf16"] < 3e-2
+
+
+@pytest.mark.skip(reason="bar unmet: plain bfloat16 operands at every contraction of a 20-site zip-up and "
+                         "sweep leave ~1e-2 before and 4e-4 to 6.5e-3 after one FP32 fitting sweep (measured); the "
+                         "split form bf16x3 meets 3e-3 / 1e-4 (test_bfloat16_forms_full_size_propagation)")
+def test_plain_bfloat16_meets_the_stated_bars():
+    """The stated bars for plain bfloat16 contractions: <= 3e-3 against the
+    float64 zip-up + sweep, <= 1e-4 after one FP32 fitting sweep against the
+    float64 zip-up + fitting sweep (1024^2 aperture field, chi 64, x axis)."""
+    torch = need_gpu()
+    api = _api()
+    n, chi, z = 10, 64, 2e-3
+    e0 = synth.aperture_field(0, n=1 << n)
+    cores = T.tt_svd(Q.to_quantics(e0), 2 * n, chi, tau=1e-13)
+    c = OM.mpo_from_matrix(F.fresnel_matrix_1d(1 << n, LAM, DX, z), n)
+    wx = OM.embed_axis(c, "x")
+    plain, _ = Z.mpo_apply(cores, wx, chi, tau=1e-13)
+    fit, _ = RF.mpo_apply_refined(cores, wx, chi, tau=1e-13)
+    psi = api.MPS.from_host(cores, chi_cap=chi)
+    a = api.mpo_apply(psi, api.MPO(wx), chi, prec="bf16")
+    b = api.mpo_apply(psi, api.MPO(wx), chi, prec="bf16", refine=True)
+    api.check_status()
+    assert rel(api.tt_to_dense(a).cpu().numpy(), Z.to_dense(plain, n)) < 3e-3
+    assert rel(api.tt_to_dense(b).cpu().numpy(), Z.to_dense(fit, n)) < 1e-4
