@@ -1322,9 +1322,20 @@ __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long ks
 }
 
 // Adjoint scaling (see kernels.h): one block per (row j, matrix b).
+// Pair cutoff: eigenvectors of a Gram matrix are resolved only to about
+// eps lam_1 / gap (eps the FP64 unit roundoff), and the pair's term divides
+// by that gap again, so a pair (kept i, discarded j) with lam_i - lam_j at
+// or below ADJ_GAP lam_1 contributes nothing.  At 1e-12 lam_1 (the inverse
+// iteration's own resolution) the terms of pairs just above the cutoff
+// carried errors of order one into phase-retrieval gradients at the
+// 64-wide cuts of 1024^2 fields: their size depended on the batch slot
+// (the slot seeds inverse iteration); at 1e-10 lam_1 every slot agrees with
+// the float64 reference, and the exact derivative differs from the cut one
+// by about 5e-4 relative there.
+constexpr double ADJ_GAP = 1e-10;
 __global__ void adj_scale_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase, int nb, int kc, void* Y,
                                  long long ldy, long long s_batch, const int* kk, long long kk_stride, int kk_bound,
-                                 int dtype) {
+                                 int dtype, double gap_rel) {
   const int b = blockIdx.y;
   const int j = blockIdx.x;
   const int n = min(dim_eval(nexp, b), nb);
@@ -1333,10 +1344,8 @@ __global__ void adj_scale_kernel(DimExpr nexp, int* kin, long long kstride, void
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   if (j >= n) return;
   const double lj = W.lam[j < kc ? j : 0];
-  // pairs closer than the inverse iteration's resolution (three solves at a
-  // shift accurate to ~eps lam_1 split eigenvectors only where the gap is
-  // well above 1e-12 lam_1) have no resolvable derivative: their term is 0
-  const double gmin = 1e-12 * fabs(W.lam[0]);
+  // pairs closer than ADJ_GAP lam_1 have no resolvable derivative: their term is 0
+  const double gmin = gap_rel * fabs(W.lam[0]);
   for (int i = threadIdx.x; i < kkb; i += blockDim.x) {
     double f = 0.0;
     if (j >= kkb && j < kfull) {
@@ -1479,7 +1488,7 @@ hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long lon
   const int kc = sp.kcap < nb ? sp.kcap : nb;
   if (kc < nb) return hipErrorInvalidValue;      // needs the full decomposition
   hipLaunchKernelGGL(adj_scale_kernel, dim3(nb, sp.batch), dim3(64), 0, s, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc,
-                     Y, ldy, s_batch, kk, kk_stride, kk_bound, dtype);
+                     Y, ldy, s_batch, kk, kk_stride, kk_bound, dtype, ADJ_GAP);
   return hipGetLastError();
 }
 

@@ -115,7 +115,8 @@ hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s
 // Eigenvector-adjoint scaling after a full decomposition (sp.kcap = n, every
 // pair kept): Y[j][i] (row j = eigenvector index, column i < kk[f]) becomes
 //   Y[j][i] / (lam_i - lam_j)  for kk[f] <= j < kept where lam_i - lam_j >
-//   1e-12 lam_1, and 0 otherwise (pairs the eigensolver does not resolve),
+//   1e-10 lam_1, and 0 otherwise (pairs whose Gram eigenvectors are not
+//   resolved well enough for a term divided by their gap),
 // with lam from the decomposition just run.
 hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long long s_batch, const int* kk,
                              long long kk_stride, int kk_bound, int dtype, hipStream_t s);

@@ -240,19 +240,23 @@ def test_phase_retrieval_gradient_at_the_c5_bond_shape():
     """The phase-retrieval gradient at the bond and operator shapes of the
     4096^2 benchmark problem, on its 1024^2 stand-in (20 sites; mask and
     application caps chi = 64, so the same 128 x 128 Gram eigenproblems;
-    Fresnel MPO at z = 2 mm, operator bond 32), two problems as one batch:
+    Fresnel MPO at z = 2 mm, operator bond 32): two problems, each in four
+    of eight batch slots (every slot seeds inverse iteration differently):
     masks exp(i phi) with phi smoothed over 16 px at std pi/8, targets the
     oracle's propagated intensity of masks at std pi/2; keep rule with
-    tau = 1e-13 on both sides.  Bars: GPU FP32 gradient vs the FP64 oracle gradient 1e-3 relative L2
-    (per problem), GPU FP64 vs oracle 1e-5, GPU FP32 vs GPU FP64 1e-3; central
-    differences of the GPU FP64 loss on 50 seeded entries agree with the
-    adjoint to 2e-3 of the largest gradient entry at h = 1e-3 and to 1e-6 at
-    h = 1e-6, on the same problem with tau = 1e-10 (at tau = 1e-13 kept
-    eigenvalues near 1e-13 lam_1 cross the threshold under a step of 1e-6, so
-    the loss is not smooth at that scale): the cuts at chi = 64 separate
-    eigenvalues only 2-5 % apart, so a step of 1e-3 in a core entry leaves the
-    linear regime of the truncation (measured: 5.5e-4 at h = 1e-3, 1.8e-4 at
-    1e-4, 2.7e-8 at 1e-6)."""
+    tau = 1e-13 on both sides.  Bars, every slot: GPU FP32 gradient vs the
+    FP64 oracle gradient 1e-3 relative L2, GPU FP64 vs oracle 1e-5, GPU FP32
+    vs GPU FP64 1e-3 (measured: FP32 1.0-3.1e-4, FP64 4e-9 to 2.5e-7; with
+    the adjoint's pair cutoff at 1e-12 lam_1 instead of 1e-10 some slots
+    reached 4e-3 in FP32 and 6e-3 in FP64); central differences of the GPU
+    FP64 loss on 50 seeded entries agree with the adjoint to 2e-3 of the
+    largest gradient entry at h = 1e-3 and to 1e-6 at h = 1e-6, on the same
+    problem with tau = 1e-8 (at tau = 1e-13 kept eigenvalues near 1e-13 lam_1
+    cross the threshold under a step of 1e-6, so the loss is not smooth at
+    that scale, and at tau = 1e-10 pairs straddle the cut closer than the
+    pair cutoff): the cuts at chi = 64 separate eigenvalues only 2-5 % apart,
+    so a step of 1e-3 in a core entry leaves the linear regime of the
+    truncation (measured: 1.9e-4 at h = 1e-3, 3.5e-8 at 1e-6)."""
     torch = need_gpu()
     api = _api()
     from paper_2510_23089_amd import autograd as AG
@@ -271,33 +275,41 @@ def test_phase_retrieval_gradient_at_the_c5_bond_shape():
         targets.append(np.abs(Z.to_dense(t2, n)) ** 2)
     refs = [OG.loss_and_grad(masks[p], wx, wy, targets[p], chi, n, tau=tau) for p in range(2)]
 
+    slots = [0, 1, 1, 0, 0, 1, 1, 0]
+
     def run(prec, tau=tau):
         dt = torch.complex64 if prec == "fp32" else torch.complex128
         rt = torch.float32 if prec == "fp32" else torch.float64
-        psi = api.MPSBatch(2, 2 * n, chi, dtype=dt)
-        for p in range(2):
-            psi.fill_from(api.MPS.from_host(masks[p], chi_cap=chi, dtype=dt), p)
-        pr = AG.PhaseRetrieval(api.MPOBatch([wx] * 2, dtype=dt), api.MPOBatch([wy] * 2, dtype=dt), chi, tau=tau)
-        tg = torch.from_numpy(np.stack(targets)).to(rt).cuda()
+        ns = len(slots)
+        psi = api.MPSBatch(ns, 2 * n, chi, dtype=dt)
+        for i, p in enumerate(slots):
+            psi.fill_from(api.MPS.from_host(masks[p], chi_cap=chi, dtype=dt), i)
+        pr = AG.PhaseRetrieval(api.MPOBatch([wx] * ns, dtype=dt), api.MPOBatch([wy] * ns, dtype=dt), chi, tau=tau)
+        tg = torch.from_numpy(np.stack([targets[p] for p in slots])).to(rt).cuda()
         loss, g = pr.loss_and_grad(psi.cores, psi.bonds, tg)
         api.check_status()
         b = psi.bonds.cpu().numpy()
         gn = g.cpu().numpy()
-        grads = [[gn[p, k, :b[p, k], :, :b[p, k + 1]].astype(np.complex128) for k in range(2 * n)] for p in range(2)]
+        grads = [[gn[i, k, :b[i, k], :, :b[i, k + 1]].astype(np.complex128) for k in range(2 * n)]
+                 for i in range(ns)]
         return float(loss), grads, (pr, psi, tg, gn, b)
 
     l32, g32, _ = run("fp32")
     l64, g64, _ = run("fp64")
-    lref = sum(r[0] for r in refs)
+    lref = sum(refs[p][0] for p in slots)
     assert abs(l64 - lref) < 1e-10 * lref
     assert abs(l32 - lref) < 1e-5 * lref
-    for p in range(2):
-        e32, e64, e3264 = _rel_list(g32[p], refs[p][1]), _rel_list(g64[p], refs[p][1]), _rel_list(g32[p], g64[p])
-        say("  problem %d: fp32 vs oracle %.2e, fp64 vs oracle %.2e, fp32 vs fp64 %.2e" % (p, e32, e64, e3264))
+    errs = []
+    for i, p in enumerate(slots):
+        e32, e64, e3264 = _rel_list(g32[i], refs[p][1]), _rel_list(g64[i], refs[p][1]), _rel_list(g32[i], g64[i])
+        say("  slot %d (problem %d): fp32 vs oracle %.2e, fp64 vs oracle %.2e, fp32 vs fp64 %.2e"
+            % (i, p, e32, e64, e3264))
+        errs.append((e32, e64, e3264))
+    for e32, e64, e3264 in errs:
         assert e32 < 1e-3
         assert e64 < 1e-5
         assert e3264 < 1e-3
-    _, _, (pr, psi, tg, gn, b) = run("fp64", 1e-10)
+    _, _, (pr, psi, tg, gn, b) = run("fp64", 1e-8)
     rng = np.random.default_rng(5)
     gmax = np.abs(gn).max()
     h = 1e-3
@@ -311,7 +323,7 @@ def test_phase_retrieval_gradient_at_the_c5_bond_shape():
 
     worst, worst_small = 0.0, 0.0
     for _ in range(50):
-        p = int(rng.integers(0, 2))
+        p = int(rng.integers(0, len(slots)))
         k = int(rng.integers(0, 2 * n))
         idx = (p, k, int(rng.integers(0, b[p, k])), int(rng.integers(0, 2)), int(rng.integers(0, b[p, k + 1])))
         unit = 1.0 if rng.integers(0, 2) == 0 else 1j
@@ -333,10 +345,10 @@ def test_phase_retrieval_gradient_4096_batch_of_32_every_position():
     directions) fill all 32 slots, 16 copies each, with the oracle's FP64
     mask cores; every slot's FP32 gradient matches the FP64 oracle gradient of
     its problem to 1e-3 relative L2, and the copies agree with each other to
-    the same bar (measured 1-3e-4: the slots' eigensolvers start inverse
-    iteration from different vectors, so FP32 rounding lands differently;
-    the position-dependent failure it guards against was 1e4 to 1e9 times
-    the gradient's norm)."""
+    the same bar (measured 4e-5 against the oracle and 7e-6 between copies:
+    the slots' eigensolvers start inverse iteration from different vectors,
+    so FP32 rounding lands differently; the position-dependent failure it
+    guards against was 1e4 to 1e9 times the gradient's norm)."""
     torch = need_gpu()
     api = _api()
     from paper_2510_23089_amd import autograd as AG
@@ -368,15 +380,17 @@ def test_phase_retrieval_gradient_4096_batch_of_32_every_position():
     b = psi.bonds.cpu().numpy()
     gn = g.cpu().numpy()
     worst = {p: 0.0 for p in probs}
+    spread = {p: 0.0 for p in probs}
     first = {}
     for i, p in enumerate(slot):
         got = [gn[i, k, :b[i, k], :, :b[i, k + 1]].astype(np.complex128) for k in range(2 * n)]
-        e = _rel_list(got, refs[p][1])
-        worst[p] = max(worst[p], e)
+        worst[p] = max(worst[p], _rel_list(got, refs[p][1]))
         if p in first:
-            assert _rel_list(got, first[p]) < 1e-3, (i, p)
+            spread[p] = max(spread[p], _rel_list(got, first[p]))
         else:
             first[p] = got
     say("  worst FP32 vs oracle over the slots: %s" % {p: "%.2e" % worst[p] for p in probs})
+    say("  largest disagreement between copies: %s" % {p: "%.2e" % spread[p] for p in probs})
     for p in probs:
         assert worst[p] < 1e-3
+        assert spread[p] < 1e-3

@@ -140,11 +140,13 @@ def test_truncated_loss_gradient_vs_finite_differences(chi, seed):
 
 
 def test_loss_gradient_where_the_keep_threshold_binds_vs_finite_differences():
-    """A keep threshold that binds (tau = 1e-10 on lam_i / lam_1: the ranks of
+    """A keep threshold that binds (tau = 1e-8 on lam_i / lam_1: the ranks of
     a smooth mask's propagation drop below those kept at the float64 floor)
     leaves the twin's gradient equal to central finite differences of its own
     loss: the threshold selects the kept pairs, the derivative stays exact
-    (no pair of this problem is closer than GAP_AD lam_1)."""
+    (no pair of this problem straddles the cut closer than GAP_AD lam_1; at
+    tau = 1e-10 some do, and dropping them moves the gradient by 8e-4 of its
+    largest entry)."""
     n, z, chi = 5, 40e-6, 32
     rng = np.random.default_rng(11)
     mask = T.tt_svd(Q.to_quantics(np.exp(1j * synth.smoothed_phase(21, 1 << n, 6.0, np.pi / 8))), 2 * n, chi)
@@ -156,15 +158,15 @@ def test_loss_gradient_where_the_keep_threshold_binds_vs_finite_differences():
     target = np.abs(Z.to_dense(t2, n)) ** 2
     with torch.no_grad():
         floor = OG.propagate(OG.as_tensors(mask), wx, wy, chi)
-        ad_map = OG.propagate(OG.as_tensors(mask), wx, wy, chi, tau=1e-10)
+        ad_map = OG.propagate(OG.as_tensors(mask), wx, wy, chi, tau=1e-8)
     b_floor = [1] + [int(c.shape[2]) for c in floor]
     b_ad = [1] + [int(c.shape[2]) for c in ad_map]
     assert any(x < y for x, y in zip(b_ad, b_floor)), (b_ad, b_floor)
-    loss, grads = OG.loss_and_grad(mask, wx, wy, target, chi, n, tau=1e-10)
+    loss, grads = OG.loss_and_grad(mask, wx, wy, target, chi, n, tau=1e-8)
 
     def loss_at(cores):
         with torch.no_grad():
-            out = OG.propagate(OG.as_tensors(cores), wx, wy, chi, tau=1e-10)
+            out = OG.propagate(OG.as_tensors(cores), wx, wy, chi, tau=1e-8)
             return float(OG.intensity_loss(OG.to_dense(out, n), torch.as_tensor(target)))
 
     gmax = max(np.abs(g).max() for g in grads)
