@@ -74,8 +74,10 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # Memory traffic of the dominant kernel per launch, from two rocprofv3 counter
 # passes (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000 after calibration on a plain
 # copy); valid only while the kernel's sources (see _kernel_source_hash) are
-# the ones the counters were taken on.
-TRAFFIC = {"src_sha256_prefix": "ac66566e2bff046f", "bytes_per_launch": (98.11 * 2.0 + 151.64) * 1024.0}
+# the ones the counters were taken on, and for the schedule they were taken in
+# (a launch holds one matrix per (field, z) member of a step).
+TRAFFIC = {"src_sha256_prefix": "ac66566e2bff046f", "fields_per_step": 3,
+           "bytes_per_launch": (252.888 * 2.0 + 397.649) * 1024.0}
 
 
 def parse():
@@ -316,7 +318,9 @@ def _kernel_source_hash():
     return hashlib.sha256(common + eig[:b]).hexdigest()[:16]
 
 
-def _traffic():
+def _traffic(fields_per_step):
+    if fields_per_step != TRAFFIC["fields_per_step"]:
+        return None
     try:
         h = _kernel_source_hash()
     except (OSError, ValueError):
@@ -583,7 +587,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": _traffic(),
+            "traffic": _traffic(a.fields_per_step),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "launches": launches.value,
             "avg_launch_ms": avg_launch_s * 1e3,

@@ -30,13 +30,26 @@ def test_default_steps_fill_every_lane_equally():
     assert a.steps % a.inflight == 0
 
 
-def test_traffic_reported_only_for_the_counted_sources(monkeypatch):
+def test_traffic_reported_only_for_the_counted_sources_and_schedule(monkeypatch):
     h = bench._kernel_source_hash()
     assert len(h) == 16
+    b = bench.TRAFFIC["fields_per_step"]
     monkeypatch.setitem(bench.TRAFFIC, "src_sha256_prefix", h)
-    assert bench._traffic() == bench.TRAFFIC["bytes_per_launch"]
+    assert bench._traffic(b) == bench.TRAFFIC["bytes_per_launch"]
+    # another schedule puts another number of matrices into each launch
+    assert bench._traffic(b + 1) is None
     monkeypatch.setitem(bench.TRAFFIC, "src_sha256_prefix", "0" * 16 if h != "0" * 16 else "1" * 16)
-    assert bench._traffic() is None
+    assert bench._traffic(b) is None
+
+
+def test_counted_schedule_is_the_default():
+    old = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        a = bench.parse()
+    finally:
+        sys.argv = old
+    assert a.fields_per_step == bench.TRAFFIC["fields_per_step"]
 
 
 def test_committed_traffic_matches_the_current_sources():
