@@ -1,6 +1,6 @@
 """Benchmark: MPO x MPS Fresnel propagations per second at 2^20 px, chi = 128.
 
-Workload (one step): B (--fields-per-step, default 4) seeded 1024 x 1024
+Workload (one step): B (--fields-per-step, default 5) seeded 1024 x 1024
 complex64 fields (disk aperture of radius 300 px, 1/f^2-power amplitude
 modulation, smoothed random phase; seeds 0..B-1) are encoded into 20-site
 quantics MPS (chi 128) by one batched encode; the Fresnel MPO (lambda 500 nm,
@@ -12,8 +12,11 @@ steps (encode and decompression included).  A step is a chain of ~95
 dependent truncations, each an FP64 eigensolve of one small matrix per
 member, so independent steps also run concurrently: step k on stream k mod
 S (S = --inflight, default 2: the main stream and one more), each stream
-with its own buffers and library workspaces.  Nothing else runs inside the
-timed region.  serial_ms_per_step: one field's step (its three distances as
+with its own buffers and library workspaces.  The multi-workgroup reduction
+of the 256-wide zip-up Gram matrices needs its 8 workgroups per matrix
+resident together, so 3 B x 8 x S must stay within the 256 compute units
+(B S <= 10; its waits are bounded, so an oversubscribed schedule reports an
+error instead of hanging).  Nothing else runs inside the timed region.  serial_ms_per_step: one field's step (its three distances as
 one batch) timed alone on one stream, i.e. the latency of a single field.
 Inputs are resident in HBM before the timed region; the host float64 MPO
 construction is setup.
@@ -76,8 +79,8 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 (vector = matrix)
 # copy); valid only while the kernel's sources (see _kernel_source_hash) are
 # the ones the counters were taken on, and for the schedule they were taken in
 # (a launch holds one matrix per (field, z) member of a step).
-TRAFFIC = {"src_sha256_prefix": "ac66566e2bff046f", "fields_per_step": 3,
-           "bytes_per_launch": (252.888 * 2.0 + 397.649) * 1024.0}
+TRAFFIC = {"src_sha256_prefix": "ac66566e2bff046f", "fields_per_step": 5,
+           "bytes_per_launch": (369.345 * 2.0 + 618.611) * 1024.0}
 
 
 def parse():
@@ -85,12 +88,12 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=24)
     p.add_argument("--warmup", type=int, default=2, help="warm-up steps per lane")
-    p.add_argument("--fields-per-step", type=int, default=3,
+    p.add_argument("--fields-per-step", type=int, default=5,
                    help="independent 1024^2 fields per step, each propagated to the three distances as one batch")
     p.add_argument("--serial-steps", type=int, default=8)
     p.add_argument("--no-parts", action="store_true")
     p.add_argument("--chi", type=int, default=CHI)
-    p.add_argument("--inflight", type=int, default=3,
+    p.add_argument("--inflight", type=int, default=2,
                    help="independent steps executing concurrently, one stream each: the main stream and "
                         "inflight - 1 more (at most 4: the HIP runtime's default of four hardware queues)")
     p.add_argument("--no-cpu-baseline", action="store_true")
