@@ -45,8 +45,10 @@ aperture fields of the same recipe; zero-padded into one 2048^2 batch, encoded,
 propagated (x then y, z = 2 mm) and decompressed in one HIP-graph replay,
 with split-bfloat16 contractions and the full-precision fitting sweep; beside
 it the same with plain bfloat16 contractions and the fitting sweep, the same
-batch with plain FP32 contractions and sweep, and a per-field
-FP32 baseline (fields processed one at a time) on a sample of the batch.
+batch with plain FP32 contractions and sweep, the same FP32 work without
+padding (one lockstep batch per side on its own stream, the four chains as
+parallel branches of one graph), and a per-field FP32 baseline (fields
+processed one at a time) on a sample of the batch.
 
 grad_step (second headline number, phase retrieval): 32 independent 4096^2
 problems (24 sites), a learnable phase mask exp(i phi) (phi: iid N(0,1)
@@ -185,15 +187,19 @@ def batched_bench(dev, replays=3, sample=16):
 
     outs = {}
     for name, prec, refine in (("bf16x3_fit_graph", "bf16x3", True), ("bf16_fit_graph", "bf16", True),
-                               ("fp32_graph", "fp32", False)):
-        b = BT.UnevenBatch(ks, chis, LAM, DX, z, device=dev, prec=prec, refine=refine)
+                               ("fp32_graph", "fp32", False), ("fp32_grouped_graph", "fp32", False)):
+        cls = BT.GroupedBatch if "grouped" in name else BT.UnevenBatch
+        b = cls(ks, chis, LAM, DX, z, device=dev, prec=prec, refine=refine)
         b.load(fields)
         b.capture()
         ms_untuned = timed(b.replay, replays)
         n_tuned = b.tune()
         b.capture()
         ms = timed(b.replay, replays)
-        api.check_status()
+        if "grouped" in name:
+            b.check_status()
+        else:
+            api.check_status()
         outs[name] = [b.field(i).clone() for i in range(sample)]
         res[name] = {"ms_per_batch": ms, "fields_per_s": len(ks) / (ms / 1e3),
                      "propagations_per_s": len(ks) / (ms / 1e3), "ms_per_batch_untuned": ms_untuned,
@@ -224,7 +230,8 @@ def batched_bench(dev, replays=3, sample=16):
                                     "pixel_share_of_batch": px_s / px}
     # accuracy against the exact propagation (float64 FFT on the host; the
     # truncation to chi dominates both forms' error, and the two must agree)
-    errs = {"bf16x3_fit_graph": [], "bf16_fit_graph": [], "fp32_graph": [], "per_field": []}
+    errs = {"bf16x3_fit_graph": [], "bf16_fit_graph": [], "fp32_graph": [], "fp32_grouped_graph": [],
+            "per_field": []}
     for i in range(sample):
         n = 1 << ks[i]
         f = np.fft.fftfreq(n, d=DX)
@@ -239,6 +246,8 @@ def batched_bench(dev, replays=3, sample=16):
         "max_abs_gap_bf16x3_fit_minus_per_field": max(abs(a - b) for a, b in zip(errs["bf16x3_fit_graph"],
                                                                               errs["per_field"])),
         "max_abs_gap_fp32_batched_minus_per_field": max(abs(a - b) for a, b in zip(errs["fp32_graph"],
+                                                                                errs["per_field"])),
+        "max_abs_gap_fp32_grouped_minus_per_field": max(abs(a - b) for a, b in zip(errs["fp32_grouped_graph"],
                                                                                 errs["per_field"])),
         "mean_bf16x3_fit": float(np.mean(errs["bf16x3_fit_graph"])),
         "mean_bf16_fit": float(np.mean(errs["bf16_fit_graph"])),

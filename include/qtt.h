@@ -221,7 +221,9 @@ int tt_hadamard(const qtt_mps* a, int conj_a, const qtt_mps* b, const qtt_opts* 
  * an existing MPS: every bond is a Schmidt cut whose singular values decide
  * what is kept): orthogonalisation right to left, then an SVD truncation
  * sweep left to right with cap opts->chi_max and the keep rule above
- * (TT-rounding).  Output left-canonical, *inout->norm = ||result||.  The
+ * (TT-rounding).  The input may be any MPS whose inner bonds fit its
+ * capacity (not necessarily canonical, bonds not limited to 2^k: a sum of
+ * MPS is one).  Output left-canonical, *inout->norm = ||result||.  The
  * bonds are rewritten on the device; cores outside them are left as they
  * were.  Workspace: tt_workspace_size(QTT_OP_TRUNCATE, ...). */
 int tt_truncate(qtt_mps* inout, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream);
@@ -301,6 +303,24 @@ int tt_intensity_loss(const void* field, const void* target, int dtype, int log2
 size_t tt_encode_separable_workspace_size(int log2_side, int chi_cap, int prec);
 int tt_encode_separable(const void* vec_a, const void* vec_b, int vec_dtype, int log2_side, qtt_mps* out,
                         void* ws, size_t ws_bytes, void* stream);
+/* tt_encode_low_rank: E0[a][b] = sum_r vecs_a[r][a] * vecs_b[r][b], r < rank,
+ * on a 2^n x 2^n grid (n = log2_side, even) without forming the 2-D array.
+ * The sequential SVD of a dense field costs exponentially in the number of
+ * sites (Sec. 4); a field of low separation rank is built instead from its
+ * factors: every term is encoded as by tt_encode_separable with bond cap
+ * term_cap, the rank terms are summed as MPS (bonds add: first core side by
+ * side, last core stacked, the rest block-diagonal), and the sum is
+ * recompressed by TT-rounding (as tt_truncate, keep rule of opts: Sec. 4).
+ * vecs_a, vecs_b: device, rank x 2^n elements each, row r = term r, dtype
+ * vec_dtype (F32/F64/C64/C128; the MPS dtype decides the precision).
+ * rank in [1, 16]; rank * term_cap <= out->chi_cap <= 256 (the sum's bonds
+ * must fit before rounding).  out: left-canonical, bonds <= opts->chi_max,
+ * *out->norm written when not NULL.  Workspace:
+ * tt_encode_low_rank_workspace_size(log2_side, rank, term_cap, out->chi_cap,
+ * prec), its first bytes the status word of every step. */
+size_t tt_encode_low_rank_workspace_size(int log2_side, int rank, int term_cap, int chi_cap, int prec);
+int tt_encode_low_rank(const void* vecs_a, const void* vecs_b, int vec_dtype, int log2_side, int rank, int term_cap,
+                       qtt_mps* out, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream);
 size_t tt_eval_points_workspace_size(int n_sites, int chi_cap, int count, int prec);
 int tt_eval_points(const qtt_mps* in, const int32_t* rows, const int32_t* cols, int count, void* out,
                    void* ws, size_t ws_bytes, void* stream);

@@ -22,10 +22,19 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _device(device):
+    """torch.device with its index filled in ("cuda" and "cuda:0" name one
+    cache slot, so a status check finds the workspace its call used)."""
+    d = torch.device(device) if device is not None else torch.device("cuda")
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
 def workspace(nbytes, device=None, key="default"):
     """Cached device workspace (zero-initialised on first use: the status word
     must start at 0)."""
-    device = device or torch.device("cuda")
+    device = _device(device)
     k = (key, str(device))
     buf = _WS_CACHE.get(k)
     if buf is None or buf.numel() < nbytes:
@@ -295,6 +304,35 @@ def tt_encode_separable(vec_a, vec_b, chi_cap, prec="fp32", out=None):
     s = out.cstruct()
     L.check(lib.tt_encode_separable(_ptr(va), _ptr(vb), dt, n, ctypes.byref(s), _ptr(ws), nb, _stream()),
             "tt_encode_separable")
+    return out
+
+
+def tt_encode_low_rank(vecs_a, vecs_b, chi, term_cap=None, chi_cap=None, tau=0.0, prec="fp32", out=None,
+                       ws_key="low_rank"):
+    """Field sum_r vecs_a[r][a] * vecs_b[r][b] (two device tensors of shape
+    (rank, 2^n), n even) as a 2n-site MPS of bonds <= chi, without forming
+    the 2-D array: the terms encoded as separable fields (bond cap term_cap,
+    default chi_cap // rank), summed as MPS and TT-rounded."""
+    lib = L.load()
+    assert vecs_a.dim() == 2 and vecs_a.shape == vecs_b.shape
+    rank, N = int(vecs_a.shape[0]), int(vecs_a.shape[1])
+    n = N.bit_length() - 1
+    assert (1 << n) == N
+    dt = {torch.float32: L.QTT_F32, torch.float64: L.QTT_F64,
+          torch.complex64: L.QTT_C64, torch.complex128: L.QTT_C128}[vecs_a.dtype]
+    va = vecs_a.contiguous()
+    vb = vecs_b.to(vecs_a.dtype).contiguous()
+    if out is None:
+        out = MPS(2 * n, chi_cap or 256, dtype=_ctype(prec), device=vecs_a.device)
+    tc = int(term_cap or out.chi_cap // rank)
+    o = _opts(chi, 0, 0.0, tau, prec)
+    nb = lib.tt_encode_low_rank_workspace_size(n, rank, tc, out.chi_cap, o.prec)
+    if nb == 0:
+        raise ValueError("rank %d / term_cap %d / chi_cap %d outside the supported range" % (rank, tc, out.chi_cap))
+    ws = workspace(nb, vecs_a.device, key=ws_key)
+    s = out.cstruct()
+    L.check(lib.tt_encode_low_rank(_ptr(va), _ptr(vb), dt, n, rank, tc, ctypes.byref(s), ctypes.byref(o), _ptr(ws), nb,
+                                   _stream()), "tt_encode_low_rank")
     return out
 
 

@@ -133,3 +133,112 @@ class UnevenBatch:
         """Dense result of member i on its own 2^k grid (device view)."""
         n = 1 << self.ks[i]
         return self.dense[i, :n, :n]
+
+
+class GroupedBatch:
+    """The same uneven batch without padding: one lockstep batch per distinct
+    side 2^k, on its own 2k sites with the Fresnel MPO of its own grid, each
+    group on a stream of its own (forked from the calling stream and joined
+    back to it), so the groups' chains run concurrently and a captured graph
+    holds them as parallel branches of one launch.  Each group has its own
+    workspaces and status words (keys "grp<k>-enc", "grp<k>-apply",
+    "grp<k>-dense")."""
+
+    def __init__(self, ks, chis, lam, dx, z, device="cuda", prec="fp32", refine=False, rel=1e-12):
+        self.ks = [int(k) for k in ks]
+        self.chis = [int(c) for c in chis]
+        self.count = len(self.ks)
+        self.prec, self.refine = prec, refine
+        self.device = torch.device(device)
+        self.where = [None] * self.count          # member -> (group, position)
+        self.groups = []
+        for k in sorted(set(self.ks)):
+            idx = [i for i, kk in enumerate(self.ks) if kk == k]
+            for j, i in enumerate(idx):
+                self.where[i] = (len(self.groups), j)
+            n, cnt = 1 << k, len(idx)
+            chi = max(self.chis[i] for i in idx)
+            w1 = B.fresnel_axis(k, lam, dx, z, rel)
+            cx, kx = B.embed(w1, "x")
+            cy, ky = B.embed(w1, "y")
+            wx = api.MPO(cx, kx, dtype=torch.complex64, device="cpu")
+            wy = api.MPO(cy, ky, dtype=torch.complex64, device="cpu")
+            g = {
+                "k": k, "idx": idx, "chi": chi,
+                "chi_dev": torch.tensor([self.chis[i] for i in idx], dtype=torch.int32, device=device),
+                "imgs": torch.zeros((cnt, n, n), dtype=torch.complex64, device=device),
+                "wx": api.MPOBatch([wx] * cnt, device=device),
+                "wy": api.MPOBatch([wy] * cnt, device=device),
+                "psi": api.MPSBatch(cnt, 2 * k, chi, device=device),
+                "mid": api.MPSBatch(cnt, 2 * k, chi, device=device),
+                "out": api.MPSBatch(cnt, 2 * k, chi, device=device),
+                "dense": torch.empty((cnt, n, n), dtype=torch.complex64, device=device),
+                "stream": torch.cuda.Stream(device=self.device),
+                "key": "grp%d" % k,
+            }
+            self.groups.append(g)
+        self.graph = None
+
+    def load(self, fields):
+        """Copy host fields (list of 2^k x 2^k arrays) into the device groups."""
+        for g in self.groups:
+            for j, i in enumerate(g["idx"]):
+                f = np.asarray(fields[i])
+                assert f.shape[0] == 1 << g["k"]
+                g["imgs"][j].copy_(torch.from_numpy(f).to(torch.complex64))
+
+    def run(self):
+        """The pipeline, forked over the groups' streams and joined back to
+        the current stream (capturable)."""
+        cur = torch.cuda.current_stream(self.device)
+        for g in self.groups:
+            g["stream"].wait_stream(cur)
+        for g in self.groups:
+            with torch.cuda.stream(g["stream"]):
+                key = g["key"]
+                api.tt_encode_batched(g["imgs"], g["chi"], out=g["psi"], chi_dev=g["chi_dev"], ws_key=key + "-enc")
+                api.mpo_apply_batched(g["psi"], g["wx"], g["chi"], out=g["mid"], chi_dev=g["chi_dev"],
+                                      prec=self.prec, refine=self.refine, ws_key=key + "-apply")
+                api.mpo_apply_batched(g["mid"], g["wy"], g["chi"], out=g["out"], chi_dev=g["chi_dev"],
+                                      prec=self.prec, refine=self.refine, ws_key=key + "-apply")
+                api.tt_to_dense_batched(g["out"], out=g["dense"], ws_key=key + "-dense")
+        for g in self.groups:
+            cur.wait_stream(g["stream"])
+        return [g["dense"] for g in self.groups]
+
+    def check_status(self):
+        for g in self.groups:
+            for part in ("-enc", "-apply", "-dense"):
+                api.check_status(key=g["key"] + part)
+
+    def tune(self, path=None):
+        """Autotune the contraction tiles on this batch's call shapes (before capture)."""
+        return api.autotune(self.run, device=self.device, path=path)
+
+    def capture(self):
+        """Record run() in a HIP graph after one eager run that sizes every
+        workspace; replay() then re-issues every group's chain in one launch."""
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            self.run()
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        torch.cuda.synchronize(self.device)
+        self._held = list(api._WS_CACHE.values())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def field(self, i):
+        """Dense result of member i on its own 2^k grid (device view)."""
+        gi, j = self.where[i]
+        return self.groups[gi]["dense"][j]
+
+    def bonds(self, i):
+        gi, j = self.where[i]
+        return self.groups[gi]["out"].bonds[j]

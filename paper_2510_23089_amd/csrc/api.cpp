@@ -224,6 +224,7 @@ std::vector<int> mps_bounds(int m, int chi) {
 struct ApplyPlan {
   int m, chi_in, chi_out, chi_zip, chi_max, dcap, zc;   // zc: zip capacity stride
   int refine = 0;                                        // fitting sweep instead of the plain sweep
+  int free_in = 0;                                       // inner input bonds bounded by the capacity only
   std::vector<int> rin, beta, rout, D;
   std::vector<int> kind;
   int gram_nb;     // largest Gram size
@@ -233,13 +234,19 @@ struct ApplyPlan {
 // diff: the application keeps state for its adjoint and factors every bond
 // on the side the adjoint differentiates (zip-up M^H M, sweep M M^H), so the
 // Gram bound covers those sides.
+// free_in: the input's inner bonds are bounded by its capacity only, not by
+// the physical 2^k (TT-rounding of an arbitrary MPS, e.g. a sum of MPS whose
+// bonds add up beyond 2^k at the ends of the chain).
 ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_zip, const int* dbonds,
-                          const int* kind, int dcap, int refine = 0, int diff = 0) {
+                          const int* kind, int dcap, int refine = 0, int diff = 0, int free_in = 0) {
   ApplyPlan p;
   p.refine = refine;
   p.m = m; p.chi_in = chi_in; p.chi_out = chi_out; p.chi_max = chi_max;
   p.chi_zip = chi_zip; p.dcap = dcap;
   p.rin = mps_bounds(m, chi_in);
+  p.free_in = free_in;
+  if (free_in)
+    for (int k = 1; k < m; ++k) p.rin[k] = chi_in;
   p.D.assign(dbonds, dbonds + m + 1);
   p.kind.assign(m, 0);
   if (kind) for (int k = 0; k < m; ++k) p.kind[k] = kind[k];
@@ -479,7 +486,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     return sv ? (char*)sv->N + (size_t)k * nf * b.sCtr * csz : b.center[(k - 1) & 1];
   };
 
-  HIPCHK(sanitize_bonds(in.bonds, b.inb, m, (int)ci, b.status, nf, s));
+  HIPCHK(sanitize_bonds(in.bonds, b.inb, m, (int)ci, b.status, nf, s, p.free_in));
   HIPCHK(set_ints(b.zbonds, nf * bs, 1, s));
   c.kcap_dev = chi_dev;          // per-field caps lower both the zip-up and the sweep caps
   HIPCHK(set_one_b(carry_at(m - 1), b.sC, real, nf, s));
@@ -813,7 +820,7 @@ int apply_setup(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_opt
   W.dbonds = su.dbonds.data();
   W.kind = su.kind.data();
   su.p = make_apply_plan(m, in.cap, out.cap, o.chi_max, o.chi_zip, su.dbonds.data(), su.kind.data(), W.dcap,
-                         identity ? 0 : o.refine, diff ? 1 : 0);
+                         identity ? 0 : o.refine, diff ? 1 : 0, identity ? 1 : 0);
   su.csz = in.dtype == QTT_C128 ? 16 : 8;
   return QTT_OK;
 }
@@ -1127,7 +1134,7 @@ ApplyPlan capacity_plan(int m, int chi_cap, int d_cap, bool identity, int refine
   // upper bound for every use: any precision, the refinement sweep and the
   // Gram sides of an application that keeps state for its adjoint
   return make_apply_plan(m, chi_cap, chi_cap, chi_cap, chi_cap, db.data(), kind.data(), identity ? 1 : d_cap,
-                         refine, identity ? 0 : 1);
+                         refine, identity ? 0 : 1, identity ? 1 : 0);
 }
 
 size_t apply_ws(int m, int chi_cap, int d_cap, int prec, bool identity, int nf) {
@@ -1843,6 +1850,71 @@ int tt_encode_separable(const void* vec_a, const void* vec_b, int vec_dtype, int
                     real, status, s));
   (void)eb;
   return QTT_OK;
+}
+
+// ---- low-rank encode: a sum of separable terms, never densified
+static size_t vec_elem_bytes(int vec_dtype) {
+  return vec_dtype == QTT_C128 ? 16 : (vec_dtype == QTT_C64 || vec_dtype == QTT_F64) ? 8 : 4;
+}
+
+size_t tt_encode_low_rank_workspace_size(int log2_side, int rank, int term_cap, int chi_cap, int prec) {
+  if (rank < 1 || rank > QTT_MAX_RANK || term_cap < 1 || term_cap > 256 || chi_cap < 1 || chi_cap > 256) return 0;
+  const size_t sep = tt_encode_separable_workspace_size(log2_side, term_cap, prec);
+  if (!sep) return 0;
+  const size_t csz = prec == QTT_PREC_FP64 ? 16 : 8;
+  const int m = 2 * log2_side;
+  const size_t tru = tt_workspace_size(QTT_OP_TRUNCATE, m, chi_cap, 1, prec);
+  Carver cv(nullptr);
+  cv.take(std::max(sep, tru));
+  cv.take((size_t)rank * m * term_cap * 2 * term_cap * csz);
+  cv.take((size_t)rank * (m + 1) * sizeof(int));
+  return cv.off;
+}
+
+int tt_encode_low_rank(const void* vecs_a, const void* vecs_b, int vec_dtype, int log2_side, int rank, int term_cap,
+                       qtt_mps* out, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if (!vecs_a || !vecs_b || !ws) return fail(QTT_ERR_ARG, "NULL argument");
+  if ((r = check_mps(out, "out"))) return r;
+  if (rank < 1 || rank > QTT_MAX_RANK) return fail(QTT_ERR_ARG, "rank %d outside [1, %d]", rank, QTT_MAX_RANK);
+  if (log2_side < 2 || (log2_side & 1) || log2_side > 30)
+    return fail(QTT_ERR_SHAPE, "log2_side %d must be even and in [2, 30]", log2_side);
+  if (out->n_sites != 2 * log2_side) return fail(QTT_ERR_SHAPE, "out has %d sites, need %d", out->n_sites, 2 * log2_side);
+  if (vec_dtype < QTT_C64 || vec_dtype > QTT_F64) return fail(QTT_ERR_DTYPE, "bad vector dtype %d", vec_dtype);
+  if (term_cap < 1 || (long long)rank * term_cap > out->chi_cap)
+    return fail(QTT_ERR_CAPACITY, "rank %d x term_cap %d exceeds out->chi_cap %d", rank, term_cap, out->chi_cap);
+  const int real = out->dtype == QTT_C128 ? 1 : 0;
+  const int prec = real ? QTT_PREC_FP64 : QTT_PREC_FP32;
+  const size_t csz = real ? 16 : 8;
+  const size_t need = tt_encode_low_rank_workspace_size(log2_side, rank, term_cap, out->chi_cap, prec);
+  if (!need) return fail(QTT_ERR_CAPACITY, "term_cap %d outside [1, 256]", term_cap);
+  if (ws_bytes < need) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, need);
+  const int m = 2 * log2_side;
+  const size_t sub_bytes = std::max(tt_encode_separable_workspace_size(log2_side, term_cap, prec),
+                                    tt_workspace_size(QTT_OP_TRUNCATE, m, out->chi_cap, 1, prec));
+  // the sub-calls' workspace comes first, so their status word is this call's
+  Carver cw(ws);
+  void* sub = cw.take(sub_bytes);
+  char* terms = (char*)cw.take((size_t)rank * m * term_cap * 2 * term_cap * csz);
+  int* tbonds = (int*)cw.take((size_t)rank * (m + 1) * sizeof(int));
+  const size_t tstride = (size_t)m * term_cap * 2 * term_cap * csz;
+  const size_t vstride = ((size_t)1 << log2_side) * vec_elem_bytes(vec_dtype);
+  for (int t = 0; t < rank; ++t) {
+    qtt_mps term;
+    term.n_sites = m;
+    term.chi_cap = term_cap;
+    term.dtype = out->dtype;
+    term.cores = terms + t * tstride;
+    term.bonds = tbonds + t * (m + 1);
+    term.norm = nullptr;
+    r = tt_encode_separable((const char*)vecs_a + t * vstride, (const char*)vecs_b + t * vstride, vec_dtype,
+                            log2_side, &term, sub, sub_bytes, stream);
+    if (r) return r;
+  }
+  HIPCHK(direct_sum(terms, tbonds, rank, term_cap, m, out->cores, out->bonds, out->chi_cap, real, (int*)sub,
+                    (hipStream_t)stream));
+  return tt_truncate(out, opts, sub, sub_bytes, stream);
 }
 
 size_t tt_eval_points_workspace_size(int n_sites, int chi_cap, int count, int prec) {

@@ -141,7 +141,9 @@ hipError_t block_copy(const void* src, long long s_rs, long long s_cs, void* dst
 hipError_t set_ints(int* dev, int count, int val, hipStream_t s);
 hipError_t copy_ints(const int* src, int* dst, int count, hipStream_t s);
 // Clamped copy of caller bonds (see misc.hip); nf fields at stride m+1.
-hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, int nf, hipStream_t s);
+// free_inner: inner bonds bounded by cap only (not by 2^min(k, m - k)).
+hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, int nf, hipStream_t s,
+                          int free_inner = 0);
 // Batched (nf fields) versions of the small helpers: field f adds f * stride.
 hipError_t block_copy_b(const void* src, long long s_rs, long long s_cs, long long s_f, void* dst, long long d_rs,
                         long long d_cs, long long d_f, DimExpr rows, DimExpr cols, int rows_bound, int cols_bound,
@@ -179,6 +181,17 @@ hipError_t fill_point(int* rows, int* cols, int row, int col, hipStream_t s);
 // MPS's device bonds.  dtype 0 complex64, 1 complex128.
 hipError_t mps_to_diag_mpo(const void* A, const int* bonds, int cap, int conj, void* W, int dcap, int m, int dtype,
                            hipStream_t s);
+// Most terms a low-rank encode sums, and the status code of a sum whose
+// bonds exceed the output capacity (QTT_ERR_CAPACITY).
+constexpr int QTT_MAX_RANK = 16;
+constexpr int ST_CAPACITY = -5;
+// Direct sum of `rank` MPS of m sites (capacity tcap each, back to back with
+// their device bonds) into one MPS of capacity ocap whose bond at every inner
+// cut is the sum of the terms' bonds: first core side by side, last core
+// stacked, the others block-diagonal; every element of the output capacity is
+// written.  A sum that exceeds ocap flags QTT_ERR_CAPACITY in the status word.
+hipError_t direct_sum(const void* terms, const int* tbonds, int rank, int tcap, int m, void* out, int* ob, int ocap,
+                      int dtype, int* status, hipStream_t s);
 // Scan a complex buffer for non-finite values and flag the status word.
 hipError_t check_finite(const void* p, int dtype, long long count, int* status, hipStream_t s);
 

@@ -174,20 +174,22 @@ hipError_t check_finite(const void* p, int dtype, long long count, int* status, 
 // [1, min(cap, 2^k, 2^(m-k))]; out-of-range input flags the status word.  All
 // kernels read the clamped copy, so no device-side size can exceed the
 // storage the host sized its buffers and launch grids for.
-__global__ void sanitize_bonds_kernel(const int* src, int* dst, int m, int cap, int* status) {
+__global__ void sanitize_bonds_kernel(const int* src, int* dst, int m, int cap, int* status, int free_inner) {
   int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k > m) return;
   src += (long long)blockIdx.y * (m + 1);
   dst += (long long)blockIdx.y * (m + 1);
   int e = min(k, m - k);
-  int bound = e >= 30 ? cap : min(cap, 1 << e);
+  int bound = e >= 30 || (free_inner && e > 0) ? cap : min(cap, 1 << e);
   int v = src[k];
   int c = min(max(v, 1), bound);
   if (c != v) set_status(status, -5);
   dst[k] = c;
 }
-hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, int nf, hipStream_t s) {
-  hipLaunchKernelGGL(sanitize_bonds_kernel, dim3((m + 1 + 255) / 256, nf), dim3(256), 0, s, src, dst, m, cap, status);
+hipError_t sanitize_bonds(const int* src, int* dst, int m, int cap, int* status, int nf, hipStream_t s,
+                          int free_inner) {
+  hipLaunchKernelGGL(sanitize_bonds_kernel, dim3((m + 1 + 255) / 256, nf), dim3(256), 0, s, src, dst, m, cap, status,
+                     free_inner);
   return hipGetLastError();
 }
 
@@ -560,4 +562,71 @@ hipError_t fill_point(int* rows, int* cols, int row, int col, hipStream_t s) {
   return hipGetLastError();
 }
 
+}  // namespace qtt
+
+namespace qtt {
+// ---- direct sum of R MPS (rank terms of a low-rank field): the sum's bond at
+// cut k is the sum of the terms' bonds there; core 0 places the terms' row
+// vectors side by side, the last core stacks their columns, every other core
+// is block-diagonal.  Terms share one capacity tcap and sit back to back
+// (term r at element offset r * m * tcap * 2 * tcap, bonds at r * (m + 1)).
+template <typename T>
+__global__ void direct_sum_kernel(const T* terms, const int* tbonds, int rank, int tcap, int m, T* out, int* ob,
+                                  int ocap, int* status) {
+  const int k = blockIdx.y;
+  const int* b0 = tbonds;
+  // offsets of every term's block at cuts k and k + 1 and the sum's bonds
+  int lo_off[QTT_MAX_RANK], hi_off[QTT_MAX_RANK];
+  int lsum = 0, hsum = 0;
+  for (int r = 0; r < rank; ++r) {
+    const int* b = b0 + r * (m + 1);
+    const int bl = k == 0 ? 1 : min(b[k], tcap), bh = k == m - 1 ? 1 : min(b[k + 1], tcap);
+    lo_off[r] = k == 0 ? 0 : lsum;
+    hi_off[r] = k == m - 1 ? 0 : hsum;
+    lsum += bl;
+    hsum += bh;
+  }
+  const int L = k == 0 ? 1 : lsum, R = k == m - 1 ? 1 : hsum;
+  if (L > ocap || R > ocap) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) set_status(status, ST_CAPACITY);
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (k == 0) ob[0] = 1;
+    ob[k + 1] = R;
+  }
+  T* O = out + (long long)k * ocap * 2 * ocap;
+  const long long tot = (long long)ocap * 2 * ocap;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot; e += (long long)gridDim.x * blockDim.x) {
+    const int l = (int)(e / (2 * ocap)), rem = (int)(e - (long long)l * 2 * ocap), s = rem / ocap, c = rem - s * ocap;
+    T val;
+    val.x = 0;
+    val.y = 0;
+    if (l < L && c < R) {
+      for (int r = 0; r < rank; ++r) {
+        const int* b = b0 + r * (m + 1);
+        const int bl = k == 0 ? 1 : min(b[k], tcap), bh = k == m - 1 ? 1 : min(b[k + 1], tcap);
+        const int li = k == 0 ? l : l - lo_off[r], ci = k == m - 1 ? c : c - hi_off[r];
+        if (li >= 0 && li < bl && ci >= 0 && ci < bh) {
+          val = terms[(long long)r * m * tcap * 2 * tcap + (long long)k * tcap * 2 * tcap + (long long)li * 2 * tcap +
+                      s * tcap + ci];
+          break;
+        }
+      }
+    }
+    O[e] = val;
+  }
+}
+hipError_t direct_sum(const void* terms, const int* tbonds, int rank, int tcap, int m, void* out, int* ob, int ocap,
+                      int dtype, int* status, hipStream_t s) {
+  if (rank < 1 || rank > QTT_MAX_RANK) return hipErrorInvalidValue;
+  dim3 g(64, m);
+  if (dtype == 0)
+    hipLaunchKernelGGL(direct_sum_kernel<float2>, g, dim3(256), 0, s, (const float2*)terms, tbonds, rank, tcap, m,
+                       (float2*)out, ob, ocap, status);
+  else
+    hipLaunchKernelGGL(direct_sum_kernel<double2>, g, dim3(256), 0, s, (const double2*)terms, tbonds, rank, tcap, m,
+                       (double2*)out, ob, ocap, status);
+  return hipGetLastError();
+}
 }  // namespace qtt

@@ -11,5 +11,5 @@ workloads of Sec. 5-6 are apertures carrying a phase field.
 """
 from .fields import (  # noqa: F401
     blob_image, aperture_field, beam_grating_field, batch_specs,
-    grating_beam_1d, smoothed_phase, random_field, gaussian_beam,
+    grating_beam_1d, smoothed_phase, random_field, gaussian_beam, beam_sum_1d,
 )

@@ -131,3 +131,26 @@ def random_field(seed, n):
     """iid complex Gaussian n x n field (complex128), for brute-force tests."""
     rng = np.random.default_rng(seed)
     return rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+
+
+def beam_sum_1d(seed, n, rank, w_frac=(0.05, 0.2), tilt_max=0.05):
+    """Factors of a field of separation rank ``rank``: a sum of Gaussian beams
+    with tilts, E0[a, b] = sum_r u_r(a) v_r(b), each u_r, v_r a 1-D Gaussian
+    exp(-(x - c)^2 / w^2) times a tilt exp(2 pi i f x) (centre c ~ U(0.2, 0.8) n,
+    width w ~ U(w_frac) n, tilt f ~ U(-tilt_max, tilt_max) cycles/px, complex
+    amplitude of unit modulus on u_r).  Returns two complex128 arrays
+    (rank, n)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(n, dtype=np.float64)
+    us, vs = [], []
+    for _ in range(rank):
+        facs = []
+        for _axis in range(2):
+            c = rng.uniform(0.2, 0.8) * n
+            w = rng.uniform(*w_frac) * n
+            f = rng.uniform(-tilt_max, tilt_max)
+            facs.append(np.exp(-((x - c) ** 2) / (w * w)) * np.exp(2j * np.pi * f * x))
+        amp = np.exp(2j * np.pi * rng.uniform())
+        us.append(amp * facs[0])
+        vs.append(facs[1])
+    return np.stack(us), np.stack(vs)

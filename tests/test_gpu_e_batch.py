@@ -231,3 +231,54 @@ def test_uneven_batch_full_size_members_vs_oracle():
         assert [int(x) for x in out.bonds[i].cpu()][2 * (K - k):] == Z.bonds(r2)
         if n < got.shape[0]:
             assert np.abs(got[n:, :]).max() == 0 and np.abs(got[:, n:]).max() == 0
+
+
+def test_grouped_batch_vs_oracle_padded_batch_and_graph():
+    """The unpadded form (one lockstep batch per side, each on its own
+    stream): every member equals the oracle's zip-up + sweep on its own grid
+    (FP32 bar 1e-4, equal bonds), agrees with the padded batch to FP32
+    rounding (the K-split of the Gram products follows the batch width, so
+    the sums may associate differently), and graph replays equal eager runs
+    bit for bit, with eager work in between."""
+    torch = need_gpu()
+    from paper_2510_23089_amd import api
+    from paper_2510_23089_amd import batch as BT
+    ks = [3, 5, 4, 5, 3, 4, 5]
+    chis = [4, 16, 8, 6, 8, 16, 12]
+    z = 20e-6
+    fields = [synth.aperture_field(10 + i, n=1 << k) for i, k in enumerate(ks)]
+    gb = BT.GroupedBatch(ks, chis, LAM, DX, z)
+    gb.load(fields)
+    gb.run()
+    torch.cuda.synchronize()
+    gb.check_status()
+    pb = BT.UnevenBatch(ks, chis, LAM, DX, z)
+    pb.load(fields)
+    pb.run()
+    api.check_status()
+    from paper_2510_23089_amd import mpo_build as B
+    for i, (k, chi, f) in enumerate(zip(ks, chis, fields)):
+        cores = T.tt_svd(Q.to_quantics(f), 2 * k, chi, tau=1e-13)
+        c = OM.mpo_from_matrix(F.fresnel_matrix_1d(1 << k, LAM, DX, z), k)
+        r1, _ = Z.mpo_apply(cores, OM.embed_axis(c, "x"), chi, tau=1e-13)
+        r2, _ = Z.mpo_apply(r1, OM.embed_axis(c, "y"), chi, tau=1e-13)
+        got = gb.field(i).cpu().numpy()
+        e = rel(got, Z.to_dense(r2, k))
+        e_pad = rel(got, pb.field(i).cpu().numpy())
+        say("member %d (2^%d, chi %d): vs oracle %.2e, vs padded batch %.2e" % (i, k, chi, e, e_pad))
+        assert e < 1e-4
+        assert e_pad < 1e-5
+        assert [int(x) for x in gb.bonds(i).cpu()] == T.bonds(r2)
+    eager = [d.clone() for d in gb.run()]
+    torch.cuda.synchronize()
+    gb.capture()
+    for rep in range(3):
+        gb.replay()
+        torch.cuda.synchronize()
+        for g, d in zip(gb.groups, eager):
+            assert torch.equal(g["dense"], d), rep
+        junk = gb.run()
+        torch.cuda.synchronize()
+        for a, d in zip(junk, eager):
+            assert torch.equal(a, d)
+    gb.check_status()
