@@ -100,8 +100,21 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   // FP32 operands: two LDS buffers (one barrier per stage, the next stage
   // stored while this one's products run); FP64 keeps one (occupancy)
   constexpr int NBUF = sizeof(TC) == 4 ? 2 : 1;
-  __shared__ TC Asb[NBUF][2 * BKC][BM + PADA];
-  __shared__ TC Bsb[NBUF][BKC][2 * BN + PADB];
+  // FP32 A tile without padding, its columns XOR-swizzled per row: the MFMA
+  // reads (4 k-rows x 16 columns) and the k-major stores (16 even or odd
+  // k-rows x 4 columns) then touch every bank exactly twice, the minimum for
+  // 64 four-byte accesses (a 4-float pad gave 4-way conflicts on both).  The
+  // FP32 B tile, when not stored k-major, pads its rows by 16 floats so the
+  // two k-rows of a read fall on opposite bank halves.
+  constexpr bool SWZ = sizeof(TC) == 4;
+  constexpr int SA = SWZ ? BM : BM + PADA;
+  constexpr int SB = 2 * BN + (SWZ && !BKM ? 16 : PADB);
+  __shared__ TC Asb[NBUF][2 * BKC][SA];
+  __shared__ TC Bsb[NBUF][BKC][SB];
+  auto acol = [](int row, int col) -> int {
+    if constexpr (SWZ) return col ^ ((((row >> 1) & 3) << 2) | ((((row >> 3) ^ row) & 1) << 4));
+    else return col;
+  };
   int cur = 0;
 
   const int t = threadIdx.x;
@@ -157,13 +170,13 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
     }
   };
   auto store_stage = [&](int bi) {
-    TC (*As)[BM + PADA] = Asb[bi];
-    TC (*Bs)[2 * BN + PADB] = Bsb[bi];
+    TC (*As)[SA] = Asb[bi];
+    TC (*Bs)[SB] = Bsb[bi];
 #pragma unroll
     for (int r = 0; r < A_PER_T; ++r) {
       TC re = (TC)ra[r].x, im = (TC)ra[r].y;
-      As[2 * a_k[r]][a_i[r]] = re;
-      As[2 * a_k[r] + 1][a_i[r]] = g.A.conj ? -im : im;
+      As[2 * a_k[r]][acol(2 * a_k[r], a_i[r])] = re;
+      As[2 * a_k[r] + 1][acol(2 * a_k[r] + 1, a_i[r])] = g.A.conj ? -im : im;
     }
 #pragma unroll
     for (int r = 0; r < B_PER_T; ++r) {
@@ -201,13 +214,13 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
       }
       const bool more = k0 + BKC < kend;
       if (more) load_stage(k0 + BKC);
-      TC (*As)[BM + PADA] = Asb[cur];
-      TC (*Bs)[2 * BN + PADB] = Bsb[cur];
+      TC (*As)[SA] = Asb[cur];
+      TC (*Bs)[SB] = Bsb[cur];
 #pragma unroll
       for (int ks = 0; ks < BKC / 2; ++ks) {
         TC af[MI], bf[NJ];
 #pragma unroll
-        for (int i = 0; i < MI; ++i) af[i] = As[ks * 4 + lq][wm * (BM / 2) + i * 16 + l16];
+        for (int i = 0; i < MI; ++i) af[i] = As[ks * 4 + lq][acol(ks * 4 + lq, wm * (BM / 2) + i * 16 + l16)];
         const int kc = ks * 2 + (lane >> 5);
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
