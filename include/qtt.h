@@ -321,6 +321,22 @@ int tt_encode_separable(const void* vec_a, const void* vec_b, int vec_dtype, int
 size_t tt_encode_low_rank_workspace_size(int log2_side, int rank, int term_cap, int chi_cap, int prec);
 int tt_encode_low_rank(const void* vecs_a, const void* vecs_b, int vec_dtype, int log2_side, int rank, int term_cap,
                        qtt_mps* out, const qtt_opts* opts, void* ws, size_t ws_bytes, void* stream);
+/* tt_sample: perfect sampling of photon detection events (Sec. 5: samples
+ * drawn from |E(a, b)|^2 / ||E||^2 directly from an orthogonalised MPS, with
+ * O(chi^2) work per site and sample, the distribution never formed).  in must
+ * be left-canonical (the output of tt_encode, mpo_apply, tt_truncate; the
+ * norm may sit in the last core): sites are visited from the last to the
+ * first, and with the sites left of k an isometry the probability of bit s
+ * at site k given the bits drawn right of it is |A_k[s] R|^2 over the sum of
+ * both, R the boundary vector of the drawn bits (renormalised each site).
+ * uniforms: device, count x n_sites doubles in [0, 1): sample p takes bit 0
+ * at site k when uniforms[p * n_sites + k] * (p0 + p1) < p0.  rows, cols:
+ * device int32 outputs (pixel coordinates, most significant bit at the first
+ * site).  Products in the MPS precision, probabilities summed in FP64.
+ * Workspace: tt_sample_workspace_size(n_sites, chi_cap, count, prec). */
+size_t tt_sample_workspace_size(int n_sites, int chi_cap, int count, int prec);
+int tt_sample(const qtt_mps* in, const double* uniforms, int count, int32_t* rows, int32_t* cols, void* ws,
+              size_t ws_bytes, void* stream);
 size_t tt_eval_points_workspace_size(int n_sites, int chi_cap, int count, int prec);
 int tt_eval_points(const qtt_mps* in, const int32_t* rows, const int32_t* cols, int count, void* out,
                    void* ws, size_t ws_bytes, void* stream);

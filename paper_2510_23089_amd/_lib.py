@@ -32,7 +32,7 @@ EXPORTS = [
     "tt_autotune_record", "tt_autotune_workspace_size", "tt_autotune_run", "tt_autotune_export",
     "tt_autotune_import", "tt_autotune_clear",
     "tt_encode_separable_workspace_size", "tt_encode_separable", "tt_eval_points_workspace_size", "tt_eval_points",
-    "tt_encode_low_rank_workspace_size", "tt_encode_low_rank",
+    "tt_encode_low_rank_workspace_size", "tt_encode_low_rank", "tt_sample_workspace_size", "tt_sample",
     "tt_to_dense_block_workspace_size", "tt_to_dense_block", "mpo_apply_noalloc",
     "tt_to_dense_window_workspace_size", "tt_to_dense_window", "tt_hadamard_workspace_size", "tt_hadamard",
 ]
@@ -153,6 +153,10 @@ def load(path=LIB_PATH):
     lib.tt_encode_low_rank_workspace_size.restype = sz
     lib.tt_encode_low_rank.argtypes = [vp, vp, i32, i32, i32, i32, P(QttMps), P(QttOpts), vp, sz, vp]
     lib.tt_encode_low_rank.restype = i32
+    lib.tt_sample_workspace_size.argtypes = [i32, i32, i32, i32]
+    lib.tt_sample_workspace_size.restype = sz
+    lib.tt_sample.argtypes = [P(QttMps), vp, i32, vp, vp, vp, sz, vp]
+    lib.tt_sample.restype = i32
     lib.tt_eval_points_workspace_size.argtypes = [i32, i32, i32, i32]
     lib.tt_eval_points_workspace_size.restype = sz
     lib.tt_eval_points.argtypes = [P(QttMps), vp, vp, i32, vp, vp, sz, vp]

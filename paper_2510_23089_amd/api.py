@@ -336,6 +336,32 @@ def tt_encode_low_rank(vecs_a, vecs_b, chi, term_cap=None, chi_cap=None, tau=0.0
     return out
 
 
+def tt_sample(psi, count=None, uniforms=None, seed=0, ws_key="sample"):
+    """Perfect samples (rows, cols) of |E|^2 / ||E||^2 from a left-canonical
+    MPS (device int32 tensors).  uniforms: device float64 (count, n_sites) in
+    [0, 1), the random numbers the sampling draws; by default torch's
+    generator seeded with `seed` on the MPS's device."""
+    lib = L.load()
+    m = psi.n_sites
+    dev = psi.cores.device
+    if uniforms is None:
+        g = torch.Generator(device=dev)
+        g.manual_seed(int(seed))
+        uniforms = torch.rand((int(count), m), dtype=torch.float64, device=dev, generator=g)
+    uniforms = uniforms.to(torch.float64).contiguous()
+    count = int(uniforms.shape[0])
+    assert uniforms.shape[1] == m
+    rows = torch.empty(count, dtype=torch.int32, device=dev)
+    cols = torch.empty(count, dtype=torch.int32, device=dev)
+    prec = L.PREC_FP64 if psi.prec == "fp64" else L.PREC_FP32
+    nb = lib.tt_sample_workspace_size(m, psi.chi_cap, count, prec)
+    ws = workspace(nb, dev, key=ws_key)
+    s = psi.cstruct()
+    L.check(lib.tt_sample(ctypes.byref(s), _ptr(uniforms), count, _ptr(rows), _ptr(cols), _ptr(ws), nb, _stream()),
+            "tt_sample")
+    return rows, cols
+
+
 def tt_eval_points(psi, rows, cols):
     """Field values at pixels (rows[p], cols[p]) (device int32 tensors)."""
     lib = L.load()

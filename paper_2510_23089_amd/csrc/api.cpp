@@ -1917,6 +1917,46 @@ int tt_encode_low_rank(const void* vecs_a, const void* vecs_b, int vec_dtype, in
   return tt_truncate(out, opts, sub, sub_bytes, stream);
 }
 
+// ---- perfect sampling (right to left over a left-canonical MPS)
+size_t tt_sample_workspace_size(int n_sites, int chi_cap, int count, int prec) {
+  return tt_eval_points_workspace_size(n_sites, chi_cap, count, prec);
+}
+
+int tt_sample(const qtt_mps* in, const double* uniforms, int count, int32_t* rows, int32_t* cols, void* ws,
+              size_t ws_bytes, void* stream) {
+  g_err.clear();
+  int r;
+  if ((r = check_mps(in, "in"))) return r;
+  if (!uniforms || !rows || !cols || !ws) return fail(QTT_ERR_ARG, "NULL argument");
+  if (count < 1) return fail(QTT_ERR_ARG, "count %d < 1", count);
+  const int m = in->n_sites;
+  const int real = in->dtype == QTT_C128 ? 1 : 0;
+  const size_t csz = real ? 16 : 8;
+  Carver cv(nullptr);
+  carve_eval(cv, m, in->chi_cap, count, csz);
+  if (ws_bytes < cv.off) return fail(QTT_ERR_WORKSPACE, "workspace %zu < required %zu bytes", ws_bytes, cv.off);
+  Carver cw(ws);
+  EvalBufs b = carve_eval(cw, m, in->chi_cap, count, csz);
+  hipStream_t s = (hipStream_t)stream;
+  Ctx c = make_ctx(s, real, 1, m, b.status);
+  const ll ch = in->chi_cap;
+  std::vector<int> rb = mps_bounds(m, ch);
+  auto core = [&](int k) { return (char*)in->cores + (size_t)k * ch * 2 * ch * c.csz; };
+  HIPCHK(sanitize_bonds(in->bonds, b.bonds, m, (int)ch, b.status, 1, s));
+  HIPCHK(unit_rows(b.L[0], b.ldl, count, (int)ch, real, s));
+  int cur = 0;
+  for (int k = m - 1; k >= 0; --k) {
+    // C[p][(r, s)] = sum_r' A_k[r][s][r'] R_p[r']
+    r = gemm(c, dx(count), 1, count, dv(c, 2, b.bonds + k), 2, 2 * rb[k], dv(c, 1, b.bonds + k + 1), 1,
+             opd(b.L[cur], b.ldl, 0, 1, 0), opd(core(k), 1, 0, 2 * ch, ch), opd(b.C, b.ldc, 0, 2, 1));
+    if (r) return r;
+    HIPCHK(sample_select(b.C, b.ldc, b.L[cur ^ 1], b.ldl, uniforms, m, k, b.bonds + k, (int)ch, rows, cols, count,
+                         real, s));
+    cur ^= 1;
+  }
+  return QTT_OK;
+}
+
 size_t tt_eval_points_workspace_size(int n_sites, int chi_cap, int count, int prec) {
   if (n_sites < 2 || (n_sites & 1) || chi_cap < 1 || chi_cap > 256 || count < 1) return 0;
   Carver cv(nullptr);

@@ -192,6 +192,13 @@ constexpr int ST_CAPACITY = -5;
 // written.  A sum that exceeds ocap flags QTT_ERR_CAPACITY in the status word.
 hipError_t direct_sum(const void* terms, const int* tbonds, int rank, int tcap, int m, void* out, int* ob, int ocap,
                       int dtype, int* status, hipStream_t s);
+// Perfect sampling, one site for every sample: from C[p][2 r + s] (the core
+// of site k applied to sample p's boundary vector) draw bit s with
+// probability |C[p][2 . + s]|^2 / |C[p]|^2 against uni[p * m + site], write
+// the normalised C[p][2 . + s] to Rn[p] (zero beyond the bond) and the bit into
+// rows[p] (even site) or cols[p] (odd site), most significant bit first.
+hipError_t sample_select(const void* C, long long ldc, void* Rn, long long ldr, const double* uni, int m, int site,
+                         const int* bond, int cap, int* rows, int* cols, int count, int dtype, hipStream_t s);
 // Scan a complex buffer for non-finite values and flag the status word.
 hipError_t check_finite(const void* p, int dtype, long long count, int* status, hipStream_t s);
 

@@ -630,3 +630,64 @@ hipError_t direct_sum(const void* terms, const int* tbonds, int rank, int tcap, 
   return hipGetLastError();
 }
 }  // namespace qtt
+
+namespace qtt {
+// ---- perfect sampling: one bit per sample at site k.  C[p][2 r + s] holds
+// (A_k[s] R_p)[r] for this sample's boundary vector R_p (right of site k);
+// with the sites left of k an isometry, the probability of bit s given the
+// bits already drawn is |C[p][2 . + s]|^2 / (|C[p][2 . + 0]|^2 + |C[p][2 . + 1]|^2).
+// The bit is s = 0 when u * (p0 + p1) < p0 (u the sample's uniform for this
+// site), the new boundary vector C[p][2 . + s] / sqrt(p_s), and the bit is
+// written into the row (even site) or column (odd site) coordinate, most
+// significant bit first.  One wave per sample; sums in FP64.
+template <typename T>
+__global__ void sample_select_kernel(const T* C, long long ldc, T* Rn, long long ldr, const double* uni, int m,
+                                     int site, const int* bond, int cap, int* rows, int* cols, int count) {
+  const int p = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (p >= count) return;
+  const int lane = threadIdx.x & 63;
+  const int bk = min(max(bond[0], 1), cap);
+  const T* Cp = C + (long long)p * ldc;
+  double s0 = 0.0, s1 = 0.0;
+  for (int r = lane; r < bk; r += 64) {
+    const T a = Cp[2 * r], b = Cp[2 * r + 1];
+    s0 += (double)a.x * a.x + (double)a.y * a.y;
+    s1 += (double)b.x * b.x + (double)b.y * b.y;
+  }
+  s0 = wave_sum_u(s0);
+  s1 = wave_sum_u(s1);
+  const double u = uni[(long long)p * m + site];
+  const int bit = (s0 + s1 > 0.0 && !(u * (s0 + s1) < s0)) ? 1 : 0;
+  const double ps = bit ? s1 : s0;
+  const double sc = ps > 0.0 ? 1.0 / sqrt(ps) : 0.0;
+  for (int r = lane; r < cap; r += 64) {
+    T v;
+    v.x = 0;
+    v.y = 0;
+    if (r < bk) {
+      const T a = Cp[2 * r + bit];
+      v.x = (decltype(v.x))(a.x * sc);
+      v.y = (decltype(v.y))(a.y * sc);
+    }
+    Rn[(long long)p * ldr + r] = v;
+  }
+  if (lane == 0) {
+    const int n = m >> 1, q = site >> 1, sh = n - 1 - q;
+    int* dst = (site & 1) ? cols : rows;
+    const int prev = site == m - 1 || site == m - 2 ? 0 : dst[p];   // the first bit of each coordinate starts it
+    dst[p] = prev | (bit << sh);
+  }
+}
+hipError_t sample_select(const void* C, long long ldc, void* Rn, long long ldr, const double* uni, int m, int site,
+                         const int* bond, int cap, int* rows, int* cols, int count, int dtype, hipStream_t s) {
+  if (count < 1) return hipSuccess;
+  dim3 g((count + 3) / 4);
+  if (dtype == 0)
+    hipLaunchKernelGGL(sample_select_kernel<float2>, g, dim3(256), 0, s, (const float2*)C, ldc, (float2*)Rn, ldr, uni,
+                       m, site, bond, cap, rows, cols, count);
+  else
+    hipLaunchKernelGGL(sample_select_kernel<double2>, g, dim3(256), 0, s, (const double2*)C, ldc, (double2*)Rn, ldr,
+                       uni, m, site, bond, cap, rows, cols, count);
+  return hipGetLastError();
+}
+}  // namespace qtt
