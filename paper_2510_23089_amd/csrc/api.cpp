@@ -192,8 +192,17 @@ EigEmit emit(void* p, int lo, ll s_hi, ll s_lo, ll s_col, int conj, int pow, int
   return e;
 }
 
+// Kept reduction of an eig call: save receives the tridiagonal forms, load
+// starts from forms saved by an earlier call on the same Gram buffer (whose
+// reflectors must still be in place); ld: per-matrix stride in doubles.
+struct TriIO {
+  double* save = nullptr;
+  const double* load = nullptr;
+  ll ld = 0;
+};
+
 int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kout, std::initializer_list<EigEmit> em,
-        EigSpec* spec_out = nullptr) {
+        EigSpec* spec_out = nullptr, TriIO tio = TriIO()) {
   EigSpec e;
   e.G = c.G; e.ld = c.gld; e.gstride = (ll)c.gld * c.gld;
   e.n = n; e.n_bound = nb;
@@ -207,6 +216,9 @@ int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kou
   e.nemit = 0;
   for (const EigEmit& x : em) e.emit[e.nemit++] = x;
   e.sigma_out = nullptr;
+  e.tri_save = tio.save;
+  e.tri_load = tio.load;
+  e.tri_ld = tio.ld;
   if (nb > c.eig_nb) return fail(QTT_ERR_WORKSPACE, "eig size %d exceeds workspace bound %d", nb, c.eig_nb);
   HIPCHK(eig_launch(e, c.s));
   if (spec_out) *spec_out = e;
@@ -353,17 +365,34 @@ ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   return b;
 }
 
+// Largest eigenproblem of the adjoint: the Gram sides of every truncation.
+int bwd_nmax(const ApplyPlan& p) {
+  int g = 1;
+  for (int k = 1; k < p.m; ++k) g = std::max(g, 2 * p.beta[k + 1]);
+  for (int k = 0; k < p.m - 1; ++k) g = std::max(g, 2 * p.rout[k]);
+  return g;
+}
+
 // What a forward application keeps for its adjoint (caller-owned `saved`
 // buffer): the bonds it chose, the zip-up cores, the carry entering every
-// zip-up site and the centre entering every sweep step.  Slot k of the carries
-// and centres holds all fields (field stride as in the workspace).
+// zip-up site, the centre entering every sweep step, and every truncation's
+// Householder reduction (reflectors in an L x L FP64 complex matrix plus the
+// tridiagonal form), so that the adjoint's full decompositions start from the
+// very reduction the forward truncated with.  Slot k of the carries and
+// centres holds all fields (field stride as in the workspace); reduction slot
+// k is zip-up site k, slot m + k sweep step k.
 struct SavedBufs {
   int* inb;
   int* zbonds;
   void* Z;
   void* C;
   void* N;
+  double* G;
+  double* T;
   ll sZ, sC, sCtr;
+  int L, nf;
+  double* gslot(int j) const { return G + (size_t)j * nf * L * L * 2; }
+  double* tslot(int j) const { return T + (size_t)j * nf * 5 * L; }
 };
 
 SavedBufs carve_saved(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
@@ -371,11 +400,15 @@ SavedBufs carve_saved(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   ApplyBufs t = carve_apply(dry, p, csz, nf);
   SavedBufs v;
   v.sZ = t.sZ; v.sC = t.sC; v.sCtr = t.sCtr;
+  v.L = bwd_nmax(p);
+  v.nf = nf;
   v.inb = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
   v.zbonds = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
   v.Z = cv.take(nf * v.sZ * csz);
   v.C = cv.take((size_t)p.m * nf * v.sC * csz);
   v.N = cv.take((size_t)p.m * nf * v.sCtr * csz);
+  v.G = (double*)cv.take((size_t)2 * p.m * nf * v.L * v.L * 16);
+  v.T = (double*)cv.take((size_t)2 * p.m * nf * 5 * v.L * sizeof(double));
   return v;
 }
 
@@ -542,14 +575,22 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     // rebuild V_k as U^H M / sigma, whose small-sigma directions carry the
     // FP32 error of M divided by sigma
     if (qb <= pb || sv) {
-      // column side: G = M^H M (q x q)
+      // column side: G = M^H M (q x q); with saved state reduced in the
+      // saved slot of this site and its tridiagonal form kept beside it
+      Ctx cg = c;
+      TriIO tio;
+      if (sv) {
+        cg.G = sv->gslot(k); cg.gld = sv->L;
+        tio.save = sv->tslot(k); tio.ld = 5ll * sv->L;
+      }
       Operand A = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
       Operand B = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
-      int r = gram(c, A, B, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da, pb);
+      int r = gram(cg, A, B, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da, pb);
       if (r) return r;
-      r = eig(c, dv(c, 2, bet), (int)qb, p.beta[k], o.cutoff, o.tau, kout,
+      r = eig(cg, dv(c, 2, bet), (int)qb, p.beta[k], o.cutoff, o.tau, kout,
               {emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV),                      // V [q][i]
-               emit(core_z(k), 2, 1, zc, 2 * zc, 1, 0, real, b.sZ)});          // B_k[i][t][b] = conj V[(b,t)][i]
+               emit(core_z(k), 2, 1, zc, 2 * zc, 1, 0, real, b.sZ)},           // B_k[i][t][b] = conj V[(b,t)][i]
+              nullptr, tio);
       if (r) return r;
       // carry_next[a][i][w'] = sum_q M[(a,w')][q] V[q][i]
       Operand A2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
@@ -720,13 +761,20 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
                opd(next, 2 * zc, 0, 1, zc, 0, b.sCtr));
       if (r) return r;
     } else {
+      Ctx cg = c;
+      TriIO tio;
+      if (sv) {
+        cg.G = sv->gslot(m + k); cg.gld = sv->L;
+        tio.save = sv->tslot(m + k); tio.ld = 5ll * sv->L;
+      }
       Operand A = opd(center, 2 * zc, zc, 1, 0, 0, sCenter);
       Operand B = opd(center, 1, 0, 2 * zc, zc, 1, sCenter);
-      int r = gram(c, A, B, dv(c, 2, rk), 2, (int)pb, dv(c, 1, bk), 1, qb);
+      int r = gram(cg, A, B, dv(c, 2, rk), 2, (int)pb, dv(c, 1, bk), 1, qb);
       if (r) return r;
-      r = eig(c, dv(c, 2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout,
+      r = eig(cg, dv(c, 2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout,
               {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut),   // out core k = U
-               emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV)});            // U [p][i]
+               emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV)},             // U [p][i]
+              nullptr, tio);
       if (r) return r;
       // R[i][b] = sum_p conj(U[p][i]) M[p][b]
       r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 1, bk), 1, (int)qb, dv(c, 2, rk), 2,
@@ -851,7 +899,9 @@ int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_op
 // Reverse of the sweep (right to left), then of the zip-up (left to right).
 // Every truncation M -> (V_k, M V_k) (zip-up: B = V_k^H, carry = M V_k; sweep
 // on N^H: U = V_k, R = U^H N) is differentiated with the full FP64 eigen-
-// decomposition G = M^H M = V diag(lam) V^H recomputed from the saved inputs:
+// decomposition G = M^H M = V diag(lam) V^H, completed from the Householder
+// reduction the forward kept (the Gram product and the reduction are not
+// redone, and the adjoint sees the factorisation the forward truncated with):
 //   Vbar = gV + M^H gC,  Z = F o (V^H Vbar) with F_ji = 1/(lam_i - lam_j) for
 //   discarded j and kept i (0 elsewhere),  P = V Z,
 //   Mbar = (gC + M P) V_k^H + (M V_k) P^H.
@@ -867,19 +917,10 @@ struct BwdBufs {
   void* Nbar[2];
   void *R, *Rbar;
   void *Vall, *Vbar, *Y, *P;
-  double* G;
-  double* part;
   void* eigws;
   ll sX, sC, sZ, sCtr, sR, sE;
   int nmax;
 };
-
-int bwd_nmax(const ApplyPlan& p) {
-  int g = 1;
-  for (int k = 1; k < p.m; ++k) g = std::max(g, 2 * p.beta[k + 1]);
-  for (int k = 0; k < p.m - 1; ++k) g = std::max(g, 2 * p.rout[k]);
-  return g;
-}
 
 BwdBufs carve_bwd(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   Carver dry(nullptr);
@@ -905,8 +946,6 @@ BwdBufs carve_bwd(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   b.Vbar = cv.take(nf * b.sE * csz);
   b.Y = cv.take(nf * b.sE * csz);
   b.P = cv.take(nf * b.sE * csz);
-  b.G = (double*)cv.take((size_t)nf * b.nmax * b.nmax * 16);
-  b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256ull * b.nmax * b.nmax * 16 * nf));
   b.eigws = cv.take(eig_ws_bytes(b.nmax, b.nmax, nf));
   return b;
 }
@@ -922,7 +961,7 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
   const int m = p.m, nf = in.nf;
   const int real = in.dtype == QTT_C128 ? 1 : 0;
   Ctx c = make_ctx(s, real, nf, m, b.status);
-  c.G = b.G; c.gld = b.nmax; c.part = b.part; c.eigws = b.eigws;
+  c.G = nullptr; c.gld = 0; c.part = nullptr; c.eigws = b.eigws;
   c.eig_nb = b.nmax; c.eig_kc = b.nmax;
   c.kcap_dev = nullptr;
   const ll ci = in.cap, co = out.cap, zc = p.zc, L = b.nmax;
@@ -939,6 +978,19 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
   auto center_at = [&](int k) { return k == 0 ? core_z(0) : (char*)sv.N + (size_t)k * nf * b.sCtr * csz; };
   const char* Wc = (const char*)W.cores;
   const ll dcap = p.dcap;
+  // the forward's Gram reduction of truncation slot j (reflectors and form)
+  auto reduced = [&](int j) {
+    Ctx cg = c;
+    cg.G = sv.gslot(j);
+    cg.gld = sv.L;
+    return cg;
+  };
+  auto kept = [&](int j) {
+    TriIO t;
+    t.load = sv.tslot(j);
+    t.ld = 5ll * sv.L;
+    return t;
+  };
   int r;
 
   HIPCHK(zero_fill(gin.cores, (size_t)nf * sIn * csz, s));
@@ -975,11 +1027,11 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
     r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 1, bk), 1, opd(N, zc, 0, 1, 0, 0, sN),
              opd(b.Rbar, 1, 0, zc, 0, 1, b.sR), opd(b.Vbar, L, 0, 1, 0, 0, b.sE), dx(1), 1, 1);
     if (r) return r;
-    // full decomposition of N N^H
-    r = gram(c, opd(N, zc, 0, 1, 0, 0, sN), opd(N, 1, 0, zc, 0, 1, sN), dv(c, 2, rk), 1, nr, dv(c, 1, bk), 1, nbk);
-    if (r) return r;
+    // full decomposition of N N^H, from the forward's reduction
     EigSpec es;
-    r = eig(c, dv(c, 2, rk), nr, nr, 0.0, -1.0, b.kfull, {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)}, &es);
+    Ctx cr = reduced(m + k);
+    r = eig(cr, dv(c, 2, rk), nr, nr, 0.0, -1.0, b.kfull, {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)},
+            &es, kept(m + k));
     if (r) return r;
     // Y = Vall^H Vbar, scaled in place to Z; P = Vall Z
     r = gemm(c, dv(c, 1, b.kfull), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 2, rk), 1, opd(b.Vall, 1, 0, L, 0, 1, b.sE),
@@ -1050,13 +1102,11 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
                opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX), opd(gcur, zc * Da, 1, Da, 0, 0, b.sC),
                opd(b.Vbar, L, 0, 1, 0, 0, b.sE), dx(1), 1, 1);
       if (r) return r;
-      // full decomposition of M^H M
-      r = gram(c, opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX), Mrows, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da,
-               pb);
-      if (r) return r;
+      // full decomposition of M^H M, from the forward's reduction
       EigSpec es;
-      r = eig(c, dv(c, 2, bet), (int)qb, (int)qb, 0.0, -1.0, b.kfull, {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)},
-              &es);
+      Ctx cr = reduced(k);
+      r = eig(cr, dv(c, 2, bet), (int)qb, (int)qb, 0.0, -1.0, b.kfull,
+              {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)}, &es, kept(k));
       if (r) return r;
       r = gemm(c, dv(c, 1, b.kfull), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 2, bet), 1,
                opd(b.Vall, 1, 0, L, 0, 1, b.sE), opd(b.Vbar, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE));

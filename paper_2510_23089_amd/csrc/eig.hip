@@ -1312,6 +1312,23 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
 }
 
 // Kept eigenvalues to a caller array (zero beyond the kept count).
+// The tridiagonal form of one matrix between its workspace and a compact
+// buffer [d | e | e^2 | Householder scalars (re, im)] of 5 nb doubles at
+// batch stride tld.  load 0: workspace -> buffer; 1: buffer -> workspace.
+__global__ void tri_copy_kernel(void* wsbase, int nb, int kc, double* buf, long long tld, int load) {
+  EigWs W = eig_ws_carve(wsbase, blockIdx.x, nb, kc);
+  double* t = buf + (long long)blockIdx.x * tld;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    double* w[5] = {W.d + i, W.e + i, W.e2 + i, &W.tau[i].x, &W.tau[i].y};
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      double* c = t + (long long)j * nb + i;
+      if (load) *w[j] = *c;
+      else *c = *w[j];
+    }
+  }
+}
+
 __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long kstride, void* wsbase, int nb, int kc,
                                   double* out, int ldo) {
   (void)nexp;
@@ -1411,50 +1428,58 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
     g_prof.launches++;
     g_prof.slot += sp.batch;
   };
-  const int cb = nb <= 256 ? 32 : 16;
-  const int groups = (nb + cb - 1) / cb;
-  const bool mwg = nb > TL_NMAX && (long long)groups * sp.batch <= compute_units();
-  if (mwg) hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc);
-  if (nb > TL_NMAX && !mwg) {
-    // the streaming reduction updates the full matrix in place: complete it
-    // from the lower triangle first
-    hipError_t fe = hermitian_fill(sp.G, sp.ld, sp.gstride, sp.n, nb, sp.batch, s);
-    if (fe != hipSuccess) return fe;
-  }
-  const bool prof = prof_on(nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG);
-  int* nl = prof ? prof_begin() : (int*)nullptr;
-  if (nb <= TL_NMAX) {
-    if (nb <= 16)
-      hipLaunchKernelGGL(tridiag_lds_kernel<128>, dim3(sp.batch), dim3(128), 0, s, (double2*)sp.G, sp.ld,
-                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
-    else if (nb <= 32)
-      hipLaunchKernelGGL(tridiag_lds_kernel<256>, dim3(sp.batch), dim3(256), 0, s, (double2*)sp.G, sp.ld,
-                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
-    else if (nb <= 64)
-      hipLaunchKernelGGL(tridiag_lds_kernel<512>, dim3(sp.batch), dim3(512), 0, s, (double2*)sp.G, sp.ld,
-                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
-    else
-      hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
-                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
-  } else if (mwg) {
-    if (cb == 32)
-      hipLaunchKernelGGL(tridiag_mwg_kernel<32>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
-                         sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
-    else
-      hipLaunchKernelGGL(tridiag_mwg_kernel<16>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
-                         sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
+  if (sp.tri_load) {
+    // a reduction kept from an earlier call on the same matrices
+    hipLaunchKernelGGL(tri_copy_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc,
+                       const_cast<double*>(sp.tri_load), sp.tri_ld, 1);
   } else {
-    hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TS_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, sp.ws, nb, kc, nl);
-  }
-  if (prof) prof_end();
-  // the last 128 steps of the reductions (c) and (b), on one workgroup
-  if (nb > TL_NMAX) {
-    const bool pt = prof_on(PROF_TRIDIAG_LDS);
-    int* nt = pt ? prof_begin() : (int*)nullptr;
-    hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
-                       sp.gstride, sp.n, sp.ws, nb, kc, nt);
-    if (pt) prof_end();
+    const int cb = nb <= 256 ? 32 : 16;
+    const int groups = (nb + cb - 1) / cb;
+    const bool mwg = nb > TL_NMAX && (long long)groups * sp.batch <= compute_units();
+    if (mwg) hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc);
+    if (nb > TL_NMAX && !mwg) {
+      // the streaming reduction updates the full matrix in place: complete it
+      // from the lower triangle first
+      hipError_t fe = hermitian_fill(sp.G, sp.ld, sp.gstride, sp.n, nb, sp.batch, s);
+      if (fe != hipSuccess) return fe;
+    }
+    const bool prof = prof_on(nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG);
+    int* nl = prof ? prof_begin() : (int*)nullptr;
+    if (nb <= TL_NMAX) {
+      if (nb <= 16)
+        hipLaunchKernelGGL(tridiag_lds_kernel<128>, dim3(sp.batch), dim3(128), 0, s, (double2*)sp.G, sp.ld,
+                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
+      else if (nb <= 32)
+        hipLaunchKernelGGL(tridiag_lds_kernel<256>, dim3(sp.batch), dim3(256), 0, s, (double2*)sp.G, sp.ld,
+                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
+      else if (nb <= 64)
+        hipLaunchKernelGGL(tridiag_lds_kernel<512>, dim3(sp.batch), dim3(512), 0, s, (double2*)sp.G, sp.ld,
+                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
+      else
+        hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
+                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
+    } else if (mwg) {
+      if (cb == 32)
+        hipLaunchKernelGGL(tridiag_mwg_kernel<32>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
+                           sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
+      else
+        hipLaunchKernelGGL(tridiag_mwg_kernel<16>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
+                           sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
+    } else {
+      hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TS_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
+                         sp.n, sp.ws, nb, kc, nl);
+    }
+    if (prof) prof_end();
+    // the last 128 steps of the reductions (c) and (b), on one workgroup
+    if (nb > TL_NMAX) {
+      const bool pt = prof_on(PROF_TRIDIAG_LDS);
+      int* nt = pt ? prof_begin() : (int*)nullptr;
+      hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nt);
+      if (pt) prof_end();
+    }
+    if (sp.tri_save)
+      hipLaunchKernelGGL(tri_copy_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc, sp.tri_save, sp.tri_ld, 0);
   }
   hipLaunchKernelGGL(eigvals_kernel, dim3((kc + 3) / 4, sp.batch), dim3(EV_NT), 0, s, sp.n, kc, sp.ws, nb, kc,
                      sp.kcap_dev);

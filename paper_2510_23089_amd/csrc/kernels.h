@@ -90,6 +90,14 @@ struct EigSpec {
   EigEmit emit[3];
   int nemit;
   double* sigma_out;          // optional: device FP64 singular values [batch][kcap]
+  // Optional kept reduction.  tri_save: once the matrices are reduced, their
+  // tridiagonal forms (d, e, e^2 and the complex Householder scalars, 5
+  // n_bound doubles per matrix, batch stride tri_ld) are copied there; the
+  // reflectors stay in G.  tri_load: no reduction at all; the forms are read
+  // back from there and G must hold the reflectors the same reduction left.
+  double* tri_save = nullptr;
+  const double* tri_load = nullptr;
+  long long tri_ld = 0;
 };
 
 size_t eig_ws_bytes(int n_bound, int kcap, int batch);
