@@ -208,6 +208,48 @@ def test_batched_apply_uneven_chi_vs_oracle():
         assert abs(float(out.norms[f].cpu()) - np.linalg.norm(ref)) < 1e-4 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_sweep_full_rank_certificate_mixed_batch(prec):
+    """Sweep steps whose cap and cutoff cannot cut settle safely nonsingular
+    Gram matrices by a Cholesky factor instead of the eigen-decomposition.  In
+    one batch: a full-rank random field (settled steps), a smooth blob whose
+    spectrum reaches the keep threshold (near-singular steps left to the
+    eigensolver) and a field under a per-field cap of 8 (capped steps left to
+    it too).  Each field vs the oracle's identically truncated result with
+    equal bonds and norm, and every output core left-orthonormal."""
+    torch = need_gpu()
+    api = _api()
+    dt = torch.complex64 if prec == "fp32" else torch.complex128
+    n, z, cap = 5, 1e-3, 32
+    fields = [synth.random_field(3, 32), synth.blob_image(9, n=32), synth.aperture_field(2, n=32)]
+    chis = (32, 32, 8)
+    cores = [T.tt_svd(Q.to_quantics(e), 2 * n, cap, tau=1e-13) for e in fields]
+    wx, wy, _ = _oracle_mpos(n, z)
+    psi = api.MPSBatch(3, 2 * n, cap, dtype=dt)
+    for f in range(3):
+        psi.fill_from(api.MPS.from_host(cores[f], chi_cap=cap, dtype=dt), f)
+    mx = api.MPOBatch([wx] * 3, dtype=dt)
+    my = api.MPOBatch([wy] * 3, dtype=dt)
+    chi_dev = torch.tensor(chis, dtype=torch.int32, device="cuda")
+    say("certificate mixed batch", prec)
+    mid = api.mpo_apply_batched(psi, mx, cap, chi_dev=chi_dev)
+    out = api.mpo_apply_batched(mid, my, cap, chi_dev=chi_dev)
+    dense = api.tt_to_dense_batched(out).cpu().numpy()
+    api.check_status()
+    tol, otol = (1e-4, 1e-5) if prec == "fp32" else (1e-10, 1e-12)
+    for f in range(3):
+        c1, _ = Z.mpo_apply(cores[f], wx, chis[f], tau=1e-13)
+        ref_cores, _ = Z.mpo_apply(c1, wy, chis[f], tau=1e-13)
+        ref = Z.to_dense(ref_cores, n)
+        assert rel(dense[f], ref) < tol, (f, rel(dense[f], ref))
+        assert [int(x) for x in out.bonds[f].cpu()] == Z.bonds(ref_cores), f
+        assert abs(float(out.norms[f].cpu()) - np.linalg.norm(ref)) < tol * np.linalg.norm(ref)
+        for k, a in enumerate(out.field(f)[:-1]):
+            a2 = a.reshape(-1, a.shape[2]).astype(np.complex128)
+            err = np.abs(a2.conj().T @ a2 - np.eye(a2.shape[1])).max()
+            assert err < otol, (f, k, err)
+
+
 def test_batched_encode_matches_single():
     torch = need_gpu()
     api = _api()
