@@ -388,22 +388,6 @@ size_t tt_heev_workspace_size(int n, int kcap, int batch);
 int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int* kept, double* evals,
             void* evecs, void* ws, size_t ws_bytes, void* stream);
 
-/* Full-rank certificate of a batch of Hermitian matrices, as the truncation
- * sweep applies it where its cap and cutoff cannot cut (Sec. 4: a bond cut
- * that keeps every direction only changes the gauge, so any orthonormal basis
- * of the range carries the same state).  G: device, batch x n x n complex128
- * row-major, lower triangle referenced, not modified; n <= 128.  Per matrix b:
- * G = L L^H (Cholesky) and X = L^{-1}; the matrix is certified when
- * ||X||_F^2 trace(G) tau 4 < 1, which places every eigenvalue above 4 tau
- * lambda_1, so the keep rule would keep all n.  Writes settled[b] (device
- * int: 1 certified, 0 not), kept[b] = n for a certified matrix (untouched
- * otherwise), and, if non-NULL, factor[b*n*n + p*n + i] = L[p][i] and
- * inv_h[b*n*n + p*n + i] = conj(X[i][p]) (device complex128; written for
- * certified matrices only, zero above / below the triangle).  tau <= 0
- * selects 1e-13.  Asynchronous on `stream`; no workspace. */
-int tt_chol_certify(const void* G, int n, int batch, double tau, int* kept, int* settled, void* factor,
-                    void* inv_h, void* stream);
-
 /* ---- diagnostics: per-launch timing of one kernel class ----
  * tt_prof_begin(what, nlog, max_entries, max_launches): from now on, every
  * launch of kernel class `what` (1 = the multi-workgroup or streaming

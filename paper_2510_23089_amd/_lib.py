@@ -25,7 +25,7 @@ EXPORTS = [
     "tt_workspace_size", "tt_encode", "mpo_apply", "tt_truncate", "tt_to_dense",
     "tt_saved_size", "mpo_apply_backward", "tt_to_dense_backward",
     "tt_check_status", "tt_last_error", "tt_version",
-    "tt_cgemm", "tt_heev_workspace_size", "tt_heev", "tt_chol_certify", "tt_prof_begin", "tt_prof_end",
+    "tt_cgemm", "tt_heev_workspace_size", "tt_heev", "tt_prof_begin", "tt_prof_end",
     "tt_prof_begin_flops", "tt_prof_times",
     "tt_workspace_size_batched", "tt_encode_batched", "mpo_apply_batched", "tt_to_dense_batched",
     "tt_saved_size_batched", "mpo_apply_backward_batched", "tt_to_dense_backward_batched", "tt_intensity_loss",
@@ -107,8 +107,6 @@ def load(path=LIB_PATH):
     lib.tt_heev_workspace_size.restype = sz
     lib.tt_heev.argtypes = [vp, i32, i32, i32, dbl, dbl, vp, vp, vp, vp, sz, vp]
     lib.tt_heev.restype = i32
-    lib.tt_chol_certify.argtypes = [vp, i32, i32, dbl, vp, vp, vp, vp, vp]
-    lib.tt_chol_certify.restype = i32
     lib.tt_prof_begin.argtypes = [i32, vp, i32, i32]
     lib.tt_prof_begin.restype = i32
     lib.tt_prof_end.argtypes = [P(ctypes.c_int), P(ctypes.c_int), P(ctypes.c_double)]

@@ -225,28 +225,6 @@ int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kou
   return QTT_OK;
 }
 
-// Full-rank certificate ahead of an eig call on the same Gram buffer (see
-// chol_certify); returns the size expression the eig call must use.
-struct CholEmit {
-  EigEmit e;
-  int src;
-};
-int chol(Ctx& c, DimExpr n, int nb, double tau, int* kout, int* neff, std::initializer_list<CholEmit> em,
-         DimExpr& n_left) {
-  CholSpec h;
-  h.G = c.G; h.ld = c.gld; h.gstride = (ll)c.gld * c.gld;
-  h.n = n; h.n_bound = nb; h.tau = tau;
-  h.kcap_dev = c.kcap_dev;
-  h.kout = kout; h.kstride = c.bs;
-  h.neff = neff; h.nstride = c.bs;
-  h.batch = c.nf;
-  h.nemit = 0;
-  for (const CholEmit& x : em) { h.emit[h.nemit] = x.e; h.src[h.nemit] = x.src; h.nemit++; }
-  HIPCHK(chol_certify(h, c.s));
-  n_left = dv(c, 1, neff);
-  return QTT_OK;
-}
-
 // ------------------------------------------------------------ bond bounds
 std::vector<int> mps_bounds(int m, int chi) {
   std::vector<int> r(m + 1);
@@ -325,7 +303,6 @@ struct ApplyBufs {
   int* status;
   int* inb;        // sanitised copy of the input bonds, nf x (m+1)
   int* zbonds;     // zip bonds, nf x (m+1)
-  int* neff;       // per field: size left to the eigensolver after chol_certify (0 = settled)
   void* Z;         // zip cores [m][zc][2][zc] per field
   void* carry[2];  // [a][b][w]: rmax x zc x dmax per field
   void* X;         // [a][b][s][w]
@@ -373,7 +350,6 @@ ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   b.G = (double*)cv.take((size_t)nf * nmax * nmax * 16);
   b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256 * nmax * nmax * 16 * (size_t)nf));
   b.eigws = cv.take(eig_ws_bytes((int)nmax, std::max(p.chi_zip, p.chi_max), nf));
-  b.neff = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
   b.sY = (ll)zc * p.dmax * p.rmax * 2;
   b.sTh = (ll)2 * zc * 2 * zc;
   b.sL = (ll)zc * p.dmax * p.rmax;
@@ -765,26 +741,14 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     const char* znext = core_z(k + 1);
     // M = center [(r,t), b]: strides (2 zc, zc) rows, 1 cols.  With saved
     // state the row side (M M^H), the factorisation the adjoint differentiates
-    // A step whose cap and cutoff cannot cut keeps every direction unless the
-    // Gram matrix is near singular: a certified Cholesky factor G = L L^H then
-    // replaces the eigenvectors (column side: L^{-H} for V / sigma and L for
-    // V sigma, so the output core is M L^{-H} and the next centre L^H Z_(k+1);
-    // row side: the identity for U)
-    const bool certify = o.cutoff == 0.0 && !sv && (qb < pb ? p.rout[k + 1] >= qb && qb <= 128
-                                                            : p.rout[k + 1] >= pb && pb <= 128);
     if (qb < pb && !sv) {
       Operand A = opd(center, 1, 0, 2 * zc, zc, 1, sCenter);
       Operand B = opd(center, 2 * zc, zc, 1, 0, 0, sCenter);
       int r = gram(c, A, B, dv(c, 1, bk), 1, (int)qb, dv(c, 2, rk), 2, pb);
       if (r) return r;
-      const EigEmit eV1 = emit(b.V1, 1, zc, 0, 1, 0, -1, real, b.sV);     // V / sigma
-      const EigEmit eV2 = emit(b.V2, 1, zc, 0, 1, 0, 1, real, b.sV);      // V * sigma
-      DimExpr ne = dv(c, 1, bk);
-      if (certify) {
-        r = chol(c, dv(c, 1, bk), (int)qb, o.tau, kout, b.neff, {{eV1, CH_XH}, {eV2, CH_L}}, ne);
-        if (r) return r;
-      }
-      r = eig(c, ne, (int)qb, p.rout[k + 1], o.cutoff, o.tau, kout, {eV1, eV2});
+      r = eig(c, dv(c, 1, bk), (int)qb, p.rout[k + 1], o.cutoff, o.tau, kout,
+              {emit(b.V1, 1, zc, 0, 1, 0, -1, real, b.sV),     // V / sigma
+               emit(b.V2, 1, zc, 0, 1, 0, 1, real, b.sV)});    // V * sigma
       if (r) return r;
       // out core k [(r,t)][i] = M V/sigma
       r = gemm(c, dv(c, 2, rk), 2, (int)pb, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 1, bk), 1,
@@ -807,14 +771,10 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       Operand B = opd(center, 1, 0, 2 * zc, zc, 1, sCenter);
       int r = gram(cg, A, B, dv(c, 2, rk), 2, (int)pb, dv(c, 1, bk), 1, qb);
       if (r) return r;
-      const EigEmit eU = emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut);   // out core k = U
-      const EigEmit eV1 = emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV);             // U [p][i]
-      DimExpr ne = dv(c, 2, rk);
-      if (certify) {
-        r = chol(cg, dv(c, 2, rk), (int)pb, o.tau, kout, b.neff, {{eU, CH_EYE}, {eV1, CH_EYE}}, ne);
-        if (r) return r;
-      }
-      r = eig(cg, ne, (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout, {eU, eV1}, nullptr, tio);
+      r = eig(cg, dv(c, 2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout,
+              {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut),   // out core k = U
+               emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV)},             // U [p][i]
+              nullptr, tio);
       if (r) return r;
       // R[i][b] = sum_p conj(U[p][i]) M[p][b]
       r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 1, bk), 1, (int)qb, dv(c, 2, rk), 2,
@@ -2226,41 +2186,6 @@ int tt_heev(void* G, int n, int batch, int kcap, double cutoff, double tau, int*
   hipStream_t s = (hipStream_t)stream;
   HIPCHK(eig_launch(e, s));
   if (evals) HIPCHK(eig_copy_evals(e, evals, kcap, s));
-  return QTT_OK;
-}
-
-// neff = 0 marks a settled matrix; settled[b] = 1 - min(neff[b], 1)
-__global__ void settled_flags_kernel(const int* neff, int* settled, int batch) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < batch) settled[b] = neff[b] == 0 ? 1 : 0;
-}
-
-int tt_chol_certify(const void* G, int n, int batch, double tau, int* kept, int* settled, void* factor, void* inv_h,
-                    void* stream) {
-  g_err.clear();
-  if (!G || !kept || !settled) return fail(QTT_ERR_ARG, "NULL argument");
-  if (n < 1 || n > 128) return fail(QTT_ERR_SHAPE, "n %d outside [1, 128]", n);
-  if (batch < 1) return fail(QTT_ERR_ARG, "bad batch");
-  CholSpec h;
-  h.G = (const double*)G; h.ld = n; h.gstride = (ll)n * n;
-  h.n = dx(n); h.n_bound = n; h.tau = tau;
-  h.kcap_dev = nullptr;
-  h.kout = kept; h.kstride = 1;
-  h.neff = settled; h.nstride = 1;      // neff written in place, turned into flags below
-  h.batch = batch;
-  h.nemit = 0;
-  if (factor) {
-    h.emit[h.nemit] = emit(factor, 1, n, 0, 1, 0, 0, 1, (ll)n * n);
-    h.src[h.nemit++] = CH_L;
-  }
-  if (inv_h) {
-    h.emit[h.nemit] = emit(inv_h, 1, n, 0, 1, 0, 0, 1, (ll)n * n);
-    h.src[h.nemit++] = CH_XH;
-  }
-  hipStream_t s = (hipStream_t)stream;
-  HIPCHK(chol_certify(h, s));
-  hipLaunchKernelGGL(settled_flags_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, settled, settled, batch);
-  HIPCHK(hipGetLastError());
   return QTT_OK;
 }
 

@@ -836,7 +836,6 @@ __global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, dou
   const int b = blockIdx.x;
   if (b >= batch) return;
   const int n = min(dim_eval(nexp, b), nb);
-  if (n == 0) return;      // settled by the caller (chol_certify): its count is already written
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double red[KP_NT / 64];
   __shared__ double slam[EIG_NMAX];
@@ -926,7 +925,7 @@ __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, lon
   const int k = kin[b * kstride];
   const int t = threadIdx.x;
   const int vi = blockIdx.x * vpw + t;
-  if (n == 0 || blockIdx.x * vpw >= k) return;          // settled by the caller, or whole workgroup idle
+  if (blockIdx.x * vpw >= k) return;          // whole workgroup idle
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   for (int i = t; i < n; i += 64) {
     sd[i] = W.d[i];
@@ -1121,7 +1120,6 @@ __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, 
                                                         int nb, int kc, double reltol) {
   const int b = blockIdx.x;
   const int n = min(dim_eval(nexp, b), nb);
-  if (n == 0) return;                         // settled by the caller
   const int k = kin[b * kstride];
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double red[CL_NT / 64];
@@ -1203,7 +1201,6 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
   constexpr int DEPTH = NM <= 256 ? 6 : 3;    // reflector rows in flight
   const int b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
-  if (n == 0) return;                         // settled by the caller
   const int k = kin[b * kstride];
   const int t = blockIdx.x * (BT_NT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1314,6 +1311,7 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
   }
 }
 
+// Kept eigenvalues to a caller array (zero beyond the kept count).
 // The tridiagonal form of one matrix between its workspace and a compact
 // buffer [d | e | e^2 | Householder scalars (re, im)] of 5 nb doubles at
 // batch stride tld.  load 0: workspace -> buffer; 1: buffer -> workspace.
@@ -1331,7 +1329,6 @@ __global__ void tri_copy_kernel(void* wsbase, int nb, int kc, double* buf, long 
   }
 }
 
-// Kept eigenvalues to a caller array (zero beyond the kept count).
 __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long kstride, void* wsbase, int nb, int kc,
                                   double* out, int ldo) {
   (void)nexp;
@@ -1525,155 +1522,6 @@ hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s
   const int kc = sp.kcap < nb ? sp.kcap : nb;
   hipLaunchKernelGGL(copy_evals_kernel, dim3(sp.batch), dim3(64), 0, s, sp.n, kc, sp.kout, sp.kstride, sp.ws, nb, kc,
                      out, ldo);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------ 7. full-rank certificate
-// A truncation whose cap and cutoff cannot cut (checked by the caller on the
-// host) keeps every direction unless the Gram matrix has eigenvalues at or
-// below tau * lambda_1.  When it is safely nonsingular, any orthonormal basis
-// of the range carries the same state with the same bond, and a Cholesky
-// factorisation supplies one: G = L L^H, X = L^{-1}, so that the columns of
-// M X^H (column side, G = M^H M) or the rows of X M (row side, G = M M^H) are
-// orthonormal.  The certificate
-//     ||X||_F^2 * trace(G) * tau * 4 < 1
-// gives lambda_min(G) = 1/||X||_2^2 >= 1/||X||_F^2 > 4 tau trace(G) >= 4 tau
-// lambda_1, so the keep rule would keep all n pairs (the factor 4 covers the
-// rounding of both computations).  One workgroup per matrix (n <= 128), the
-// packed lower triangle in LDS, 8 threads per row: right-looking Cholesky,
-// then the inverse in place, column by column from the last, one barrier per
-// column.  A certified matrix gets kout = n, its emits written and neff = 0,
-// which the eigensolver's kernels read as "nothing to do"; any other matrix
-// (not positive definite, not finite, capped per field below n, or too close
-// to singular) gets neff = n and goes through the eigensolver as before.
-struct CholPack {
-  EigEmit e[2];
-  int src[2];
-  int ne;
-};
-
-template <int NT>
-__global__ __launch_bounds__(NT) void chol_kernel(const double2* Gall, int ld, long long gstride, DimExpr nexp, int nb,
-                                                  double tau, const int* kcap_dev, int* kout, long long kstride,
-                                                  int* neff, long long nstride, CholPack ep) {
-  constexpr int NW = NT / 64;
-  const int b = blockIdx.x;
-  const int n = min(dim_eval(nexp, b), nb);
-  const double2* A = Gall + (long long)b * gstride;
-  __shared__ double2 L[TL_TRI];
-  __shared__ double2 col[2][TL_NMAX];
-  __shared__ double red[NW];
-  const int tid = threadIdx.x, r = tid >> 3, sl = tid & 7;
-  const int T = n * (n + 1) / 2;
-  for (int e = tid; e < T; e += NT) {
-    int rr = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-    while (tri(rr + 1, 0) <= e) ++rr;
-    while (tri(rr, 0) > e) --rr;
-    L[e] = A[(long long)rr * ld + (e - tri(rr, 0))];
-  }
-  const double trace = block_sum<NT>(sl == 0 && r < n ? A[(long long)r * ld + r].x : 0.0, red);
-  bool ok = n >= 1 && isfinite(trace) && trace > 0.0 && (!kcap_dev || kcap_dev[b] >= n);
-  // ---- Cholesky: column k scaled by 1/sqrt(pivot), then the trailing update
-  for (int k = 0; ok && k < n; ++k) {
-    const double d = L[tri(k, k)].x;        // the same value in every thread
-    if (!(d > 0.0 && d <= 1e300)) { ok = false; break; }
-    const double sq = sqrt(d), inv = 1.0 / sq;
-    if (sl == 0 && r > k && r < n) {
-      const double2 v = L[tri(r, k)];
-      const double2 w = make_double2(v.x * inv, v.y * inv);
-      L[tri(r, k)] = w;
-      col[0][r] = w;
-    }
-    __syncthreads();
-    if (r > k && r < n) {
-      const double2 vr = col[0][r];
-      for (int c = k + 1 + sl; c <= r; c += 8) {
-        const double2 vc = col[0][c];
-        L[tri(r, c)] = csub(L[tri(r, c)], cmul(vr, make_double2(vc.x, -vc.y)));
-      }
-    }
-    if (tid == 0) L[tri(k, k)] = make_double2(sq, 0.0);
-    __syncthreads();
-  }
-  auto emit_all = [&](int which) {
-    for (int q = 0; q < ep.ne; ++q) {
-      if (ep.src[q] != which) continue;
-      const EigEmit& em = ep.e[q];
-      char* base = (char*)em.ptr;
-      for (int e = tid; e < n * n; e += NT) {
-        const int p = e / n, i = e - p * n;
-        double2 x;
-        if (which == CH_L) x = i <= p ? L[tri(p, i)] : make_double2(0.0, 0.0);
-        else if (which == CH_XH) x = p <= i ? make_double2(L[tri(i, p)].x, -L[tri(i, p)].y) : make_double2(0.0, 0.0);
-        else x = make_double2(p == i ? 1.0 : 0.0, 0.0);
-        if (em.conj) x.y = -x.y;
-        const int h = p / em.lo, l = p - h * em.lo;
-        const long long off = (long long)b * em.s_batch + (long long)h * em.s_hi + (long long)l * em.s_lo +
-                              (long long)i * em.s_col;
-        if (em.dtype == 0) ((float2*)base)[off] = make_float2((float)x.x, (float)x.y);
-        else ((double2*)base)[off] = x;
-      }
-    }
-  };
-  // the factor itself is wanted before it is overwritten (an uncertified
-  // matrix's emits are overwritten by the eigensolver's)
-  if (ok) emit_all(CH_L);
-  // ---- X = L^{-1} in place.  Step j: col[j & 1] holds column j of L (rows
-  // >= j); X[r][j] = -(sum_{l = j+1..r} X[r][l] L[l][j]) / L[j][j] for r > j
-  // and X[j][j] = 1 / L[j][j]; column j - 1 of L is copied for the next step.
-  double fro = 0.0;
-  if (ok) {
-    if (sl == 0 && r == n - 1) col[(n - 1) & 1][r] = L[tri(r, n - 1)];
-    __syncthreads();
-    for (int j = n - 1; j >= 0; --j) {
-      const int cb = j & 1;
-      const double xjj = 1.0 / col[cb][j].x;
-      if (j > 0 && sl == 0 && r >= j - 1 && r < n) col[cb ^ 1][r] = L[tri(r, j - 1)];
-      double2 acc = make_double2(0.0, 0.0);
-      if (r > j && r < n)
-        for (int l = j + 1 + sl; l <= r; l += 8) acc = cadd(acc, cmul(L[tri(r, l)], col[cb][l]));
-#pragma unroll
-      for (int o = 1; o < 8; o <<= 1) {
-        acc.x += __shfl_xor(acc.x, o);
-        acc.y += __shfl_xor(acc.y, o);
-      }
-      if (sl == 0 && r > j && r < n) L[tri(r, j)] = make_double2(-acc.x * xjj, -acc.y * xjj);
-      if (tid == 0) L[tri(j, j)] = make_double2(xjj, 0.0);
-      __syncthreads();
-    }
-    for (int e = tid; e < T; e += NT) fro += L[e].x * L[e].x + L[e].y * L[e].y;
-  }
-  const double fro2 = block_sum<NT>(fro, red);
-  ok = ok && isfinite(fro2) && fro2 * trace * tau * 4.0 < 1.0;
-  if (ok) {
-    emit_all(CH_XH);
-    emit_all(CH_EYE);
-  }
-  if (tid == 0) {
-    neff[b * nstride] = ok ? 0 : n;
-    if (ok) kout[b * kstride] = n;
-  }
-}
-
-hipError_t chol_certify(const CholSpec& sp, hipStream_t s) {
-  const int nb = sp.n_bound;
-  if (nb < 1 || nb > TL_NMAX || sp.batch < 1) return hipErrorInvalidValue;
-  CholPack ep;
-  ep.ne = sp.nemit;
-  for (int i = 0; i < sp.nemit && i < 2; ++i) { ep.e[i] = sp.emit[i]; ep.src[i] = sp.src[i]; }
-  const double tau = sp.tau > 0.0 ? sp.tau : 1e-13;
-  if (nb <= 16)
-    hipLaunchKernelGGL(chol_kernel<128>, dim3(sp.batch), dim3(128), 0, s, (const double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, nb, tau, sp.kcap_dev, sp.kout, sp.kstride, sp.neff, sp.nstride, ep);
-  else if (nb <= 32)
-    hipLaunchKernelGGL(chol_kernel<256>, dim3(sp.batch), dim3(256), 0, s, (const double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, nb, tau, sp.kcap_dev, sp.kout, sp.kstride, sp.neff, sp.nstride, ep);
-  else if (nb <= 64)
-    hipLaunchKernelGGL(chol_kernel<512>, dim3(sp.batch), dim3(512), 0, s, (const double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, nb, tau, sp.kcap_dev, sp.kout, sp.kstride, sp.neff, sp.nstride, ep);
-  else
-    hipLaunchKernelGGL(chol_kernel<1024>, dim3(sp.batch), dim3(1024), 0, s, (const double2*)sp.G, sp.ld, sp.gstride,
-                       sp.n, nb, tau, sp.kcap_dev, sp.kout, sp.kstride, sp.neff, sp.nstride, ep);
   return hipGetLastError();
 }
 

@@ -119,32 +119,6 @@ struct ProfHook {
 };
 extern ProfHook g_prof;
 hipError_t eig_launch(const EigSpec& sp, hipStream_t s);
-
-// Full-rank certificate of a batch of Hermitian matrices (n <= 128) whose
-// truncation cannot cut by its cap or cutoff: a Cholesky factorisation
-// G = L L^H and X = L^{-1}; when lambda_min(G) is provably above 4 tau
-// lambda_1 the matrix is settled here (kout = n, emits of L, X^H or the
-// identity, neff = 0), otherwise neff = n.  The eigen-decomposition called
-// afterwards with n read from neff skips the settled matrices.
-enum { CH_L = 0, CH_XH = 1, CH_EYE = 2 };
-struct CholSpec {
-  const double* G;
-  int ld;
-  long long gstride;
-  DimExpr n;
-  int n_bound;
-  double tau;
-  const int* kcap_dev = nullptr;
-  int* kout;
-  long long kstride;
-  int* neff;
-  long long nstride;
-  int batch;
-  EigEmit emit[2];
-  int src[2];
-  int nemit;
-};
-hipError_t chol_certify(const CholSpec& sp, hipStream_t s);
 hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s);
 // Eigenvector-adjoint scaling after a full decomposition (sp.kcap = n, every
 // pair kept): Y[j][i] (row j = eigenvector index, column i < kk[f]) becomes

@@ -106,50 +106,6 @@ def test_heev_random(n):
         assert np.max(np.abs(res)) < 1e-10 * abs(w[0])
 
 
-def test_chol_certificate_vs_numpy():
-    """The full-rank certificate: factor and inverse against numpy on
-    certified matrices; matrices with an eigenvalue at or below a few tau
-    lambda_1 (or singular, or indefinite) are not certified."""
-    torch = need_gpu()
-    L, lib = _lib()
-    rng = np.random.default_rng(11)
-    tau = 1e-13
-    for n in (1, 2, 8, 16, 17, 33, 64, 100, 128):
-        say("chol certificate", n)
-        specs = [np.sort(rng.uniform(0.5, 2.0, n))[::-1],                    # well conditioned
-                 np.sort(10.0 ** rng.uniform(-8, 0, n))[::-1],               # lambda_min >= 1e-8 lambda_1
-                 np.r_[np.ones(max(n - 1, 0)), [1e-14]][:n],                 # one eigenvalue below tau
-                 np.r_[np.ones(max(n - 1, 0)), [0.0]][:n],                   # singular
-                 np.r_[np.ones(max(n - 1, 0)), [-1e-3]][:n]]                 # indefinite
-        mats = np.stack([_rand_herm(rng, n, sp) for sp in specs])
-        g = torch.from_numpy(mats).to(torch.complex128).cuda()
-        kept = torch.full((len(specs),), -1, dtype=torch.int32, device="cuda")
-        settled = torch.zeros(len(specs), dtype=torch.int32, device="cuda")
-        fac = torch.zeros((len(specs), n, n), dtype=torch.complex128, device="cuda")
-        invh = torch.zeros_like(fac)
-        rc = lib.tt_chol_certify(g.data_ptr(), n, len(specs), tau, kept.data_ptr(), settled.data_ptr(),
-                                 fac.data_ptr(), invh.data_ptr(), _stream(torch))
-        L.check(rc, "tt_chol_certify")
-        torch.cuda.synchronize()
-        st, kp = settled.cpu().numpy(), kept.cpu().numpy()
-        assert np.allclose(g.cpu().numpy(), mats)            # input untouched
-        want = [1, 1, 0, 0, 0] if n > 1 else [1, 1, 1, 0, 0]  # n = 1: the single eigenvalue is lambda_1
-        assert list(st) == want, (n, list(st))
-        for b in range(len(specs)):
-            if not st[b]:
-                assert kp[b] == -1
-                continue
-            assert kp[b] == n
-            lf = fac[b].cpu().numpy()
-            assert np.max(np.abs(np.triu(lf, 1))) == 0.0
-            assert np.max(np.abs(lf @ lf.conj().T - mats[b])) < 1e-13 * specs[b][0] * n
-            if b == 0:
-                assert np.max(np.abs(lf - np.linalg.cholesky(mats[b]))) < 1e-12 * np.sqrt(specs[b][0]) * n
-            xh = invh[b].cpu().numpy()
-            assert np.max(np.abs(np.tril(xh, -1))) == 0.0
-            assert np.max(np.abs(xh.conj().T @ lf - np.eye(n))) < 1e-12 * np.sqrt(specs[b][0] / specs[b][-1]) * n
-
-
 def _check_heev(mats, kept, ev, vec, kcap):
     for b in range(mats.shape[0]):
         w, v = np.linalg.eigh(mats[b])
