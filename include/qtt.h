@@ -183,7 +183,8 @@ int tt_encode(const void* img, int img_dtype, int log2_side, const qtt_opts* opt
  * tt_encode, tt_truncate and mpo_apply).  out is left-canonical, *out->norm =
  * ||out||.  in and out must not alias.  saved: if non-NULL, a device buffer of
  * at least tt_saved_size(...) bytes that receives what mpo_apply_backward needs
- * (per-site carries and centres, the Gram reductions); NULL skips it. */
+ * (per-site carries and centres, every truncation's full eigen-decomposition);
+ * NULL skips it. */
 int mpo_apply(const qtt_mps* in, const qtt_mpo* W, const qtt_opts* opts,
               qtt_mps* out, void* saved, size_t saved_bytes,
               void* ws, size_t ws_bytes, void* stream);
@@ -236,11 +237,13 @@ int tt_to_dense(const qtt_mps* in, void* out, int out_dtype, void* ws, size_t ws
  * backward call (capacity bound for chi_zip <= chi_cap; the call itself
  * checks the exact requirement).  The buffer receives the bonds chosen by the
  * forward call, the zip-up cores, the carry entering each zip-up site, the
- * centre entering each sweep step, and the Householder reduction of every
- * truncation's Gram matrix (an L x L complex FP64 matrix plus 5 L doubles per
- * truncation and field, L = twice the largest bond a truncation splits; two
- * truncations per site), so that the backward call completes the very
- * factorisations the forward truncated with instead of recomputing them. */
+ * centre entering each sweep step, and the full eigen-decomposition of every
+ * truncation's Gram matrix, computed by the forward beside its keep rule (all
+ * n eigenvectors as an L x L matrix in the working precision plus L FP64
+ * eigenvalues per truncation and field, L = twice the largest bond a
+ * truncation splits; two truncations per site), so that the backward call
+ * differentiates the very factorisations the forward truncated with and runs
+ * no eigensolver of its own. */
 size_t tt_saved_size(int n_sites, int chi_cap, int d_cap, int prec);
 size_t tt_saved_size_batched(int count, int n_sites, int chi_cap, int d_cap, int prec);
 
@@ -252,8 +255,8 @@ size_t tt_saved_size_batched(int count, int n_sites, int chi_cap, int d_cap, int
  * dL/dRe + i dL/dIm), writes grad_in (same shape as in; padding zeroed,
  * bonds = the forward input bonds).  Each truncation is differentiated at the
  * forward's kept ranks through the full FP64 eigen-decomposition of its Gram
- * matrix, completed from the Householder reduction the forward kept in
- * `saved` (the buffer is read, not modified); the contribution of
+ * matrix that the forward computed and kept in `saved` (the buffer is read,
+ * not modified); the contribution of
  * rotations inside a kept block is omitted (it vanishes for every function of
  * the decompressed field).  Valid for cotangents of such functions (e.g. the
  * output of tt_to_dense_backward).  Workspace: tt_workspace_size(

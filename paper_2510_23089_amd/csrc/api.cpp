@@ -185,24 +185,24 @@ int gemm(Ctx& c, DimExpr M, int mlo, int mb, DimExpr N, int nlo, int nb, DimExpr
   return QTT_OK;
 }
 
-EigEmit emit(void* p, int lo, ll s_hi, ll s_lo, ll s_col, int conj, int pow, int dtype, ll s_batch = 0) {
+EigEmit emit(void* p, int lo, ll s_hi, ll s_lo, ll s_col, int conj, int pow, int dtype, ll s_batch = 0, int all = 0) {
   EigEmit e;
   e.ptr = p; e.lo = lo; e.s_hi = s_hi; e.s_lo = s_lo; e.s_col = s_col;
-  e.conj = conj; e.pow = pow; e.dtype = dtype; e.s_batch = s_batch;
+  e.conj = conj; e.pow = pow; e.dtype = dtype; e.s_batch = s_batch; e.all = all;
   return e;
 }
 
-// Kept reduction of an eig call: save receives the tridiagonal forms, load
-// starts from forms saved by an earlier call on the same Gram buffer (whose
-// reflectors must still be in place); ld: per-matrix stride in doubles.
-struct TriIO {
-  double* save = nullptr;
-  const double* load = nullptr;
-  ll ld = 0;
+// A full decomposition beside a truncation (EigSpec::lam_out): every pair is
+// computed, the eigenvalues go to lam (stride lam_ld per matrix), emits marked
+// `all` receive every vector, and the keep rule uses keep_cap.
+struct FullOut {
+  double* lam = nullptr;
+  ll lam_ld = 0;
+  int keep_cap = 0;
 };
 
 int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kout, std::initializer_list<EigEmit> em,
-        EigSpec* spec_out = nullptr, TriIO tio = TriIO()) {
+        EigSpec* spec_out = nullptr, FullOut full = FullOut()) {
   EigSpec e;
   e.G = c.G; e.ld = c.gld; e.gstride = (ll)c.gld * c.gld;
   e.n = n; e.n_bound = nb;
@@ -216,9 +216,9 @@ int eig(Ctx& c, DimExpr n, int nb, int kcap, double cutoff, double tau, int* kou
   e.nemit = 0;
   for (const EigEmit& x : em) e.emit[e.nemit++] = x;
   e.sigma_out = nullptr;
-  e.tri_save = tio.save;
-  e.tri_load = tio.load;
-  e.tri_ld = tio.ld;
+  e.lam_out = full.lam;
+  e.lam_ld = full.lam_ld;
+  e.keep_cap = full.keep_cap;
   if (nb > c.eig_nb) return fail(QTT_ERR_WORKSPACE, "eig size %d exceeds workspace bound %d", nb, c.eig_nb);
   HIPCHK(eig_launch(e, c.s));
   if (spec_out) *spec_out = e;
@@ -237,6 +237,7 @@ struct ApplyPlan {
   int m, chi_in, chi_out, chi_zip, chi_max, dcap, zc;   // zc: zip capacity stride
   int refine = 0;                                        // fitting sweep instead of the plain sweep
   int free_in = 0;                                       // inner input bonds bounded by the capacity only
+  int diff = 0;                                          // keeps state (full decompositions) for an adjoint
   std::vector<int> rin, beta, rout, D;
   std::vector<int> kind;
   int gram_nb;     // largest Gram size
@@ -253,6 +254,7 @@ ApplyPlan make_apply_plan(int m, int chi_in, int chi_out, int chi_max, int chi_z
                           const int* kind, int dcap, int refine = 0, int diff = 0, int free_in = 0) {
   ApplyPlan p;
   p.refine = refine;
+  p.diff = diff;
   p.m = m; p.chi_in = chi_in; p.chi_out = chi_out; p.chi_max = chi_max;
   p.chi_zip = chi_zip; p.dcap = dcap;
   p.rin = mps_bounds(m, chi_in);
@@ -349,7 +351,8 @@ ApplyBufs carve_apply(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   b.R = cv.take(nf * b.sR * csz);
   b.G = (double*)cv.take((size_t)nf * nmax * nmax * 16);
   b.part = (double*)cv.take(std::min<size_t>(PART_BYTES, 256 * nmax * nmax * 16 * (size_t)nf));
-  b.eigws = cv.take(eig_ws_bytes((int)nmax, std::max(p.chi_zip, p.chi_max), nf));
+  // an application that keeps state computes every eigenpair of each Gram matrix
+  b.eigws = cv.take(eig_ws_bytes((int)nmax, p.diff ? (int)nmax : std::max(p.chi_zip, p.chi_max), nf));
   b.sY = (ll)zc * p.dmax * p.rmax * 2;
   b.sTh = (ll)2 * zc * 2 * zc;
   b.sL = (ll)zc * p.dmax * p.rmax;
@@ -375,24 +378,27 @@ int bwd_nmax(const ApplyPlan& p) {
 
 // What a forward application keeps for its adjoint (caller-owned `saved`
 // buffer): the bonds it chose, the zip-up cores, the carry entering every
-// zip-up site, the centre entering every sweep step, and every truncation's
-// Householder reduction (reflectors in an L x L FP64 complex matrix plus the
-// tridiagonal form), so that the adjoint's full decompositions start from the
-// very reduction the forward truncated with.  Slot k of the carries and
-// centres holds all fields (field stride as in the workspace); reduction slot
-// k is zip-up site k, slot m + k sweep step k.
+// zip-up site, the centre entering every sweep step, and the full
+// eigen-decomposition of every truncation's Gram matrix (all n eigenvectors,
+// [p][i] with leading dimension L, in the working precision, and the n
+// eigenvalues in FP64), computed once by the forward beside its keep rule, so
+// that the adjoint differentiates the very factorisation the forward
+// truncated with and runs no eigensolver of its own.  Slot k of the carries
+// and centres holds all fields (field stride as in the workspace);
+// decomposition slot k is zip-up site k, slot m + k sweep step k.
 struct SavedBufs {
   int* inb;
   int* zbonds;
   void* Z;
   void* C;
   void* N;
-  double* G;
-  double* T;
+  void* V;
+  double* lam;
   ll sZ, sC, sCtr;
   int L, nf;
-  double* gslot(int j) const { return G + (size_t)j * nf * L * L * 2; }
-  double* tslot(int j) const { return T + (size_t)j * nf * 5 * L; }
+  size_t csz;
+  void* vslot(int j) const { return (char*)V + (size_t)j * nf * L * L * csz; }
+  double* lslot(int j) const { return lam + (size_t)j * nf * L; }
 };
 
 SavedBufs carve_saved(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
@@ -402,13 +408,14 @@ SavedBufs carve_saved(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   v.sZ = t.sZ; v.sC = t.sC; v.sCtr = t.sCtr;
   v.L = bwd_nmax(p);
   v.nf = nf;
+  v.csz = csz;
   v.inb = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
   v.zbonds = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
   v.Z = cv.take(nf * v.sZ * csz);
   v.C = cv.take((size_t)p.m * nf * v.sC * csz);
   v.N = cv.take((size_t)p.m * nf * v.sCtr * csz);
-  v.G = (double*)cv.take((size_t)2 * p.m * nf * v.L * v.L * 16);
-  v.T = (double*)cv.take((size_t)2 * p.m * nf * 5 * v.L * sizeof(double));
+  v.V = cv.take((size_t)2 * p.m * nf * v.L * v.L * csz);
+  v.lam = (double*)cv.take((size_t)2 * p.m * nf * v.L * sizeof(double));
   return v;
 }
 
@@ -498,7 +505,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
   if (o.prec == QTT_PREC_BF16) c.gemm_t = GEMM_BF16;
   if (o.prec == QTT_PREC_BF16X3) c.gemm_t = GEMM_BF16X3;
   c.G = b.G; c.gld = std::max(p.gram_nb, 1); c.part = b.part; c.eigws = b.eigws;
-  c.eig_nb = c.gld; c.eig_kc = std::max(p.chi_zip, p.chi_max);
+  c.eig_nb = c.gld; c.eig_kc = p.diff ? c.gld : std::max(p.chi_zip, p.chi_max);
   const ll ci = in.cap, co = out.cap, zc = p.zc;
   const size_t csz = c.csz;
   const ll sIn = in.fstride(), sOut = out.fstride(), sW = W.fstride();
@@ -575,22 +582,23 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     // rebuild V_k as U^H M / sigma, whose small-sigma directions carry the
     // FP32 error of M divided by sigma
     if (qb <= pb || sv) {
-      // column side: G = M^H M (q x q); with saved state reduced in the
-      // saved slot of this site and its tridiagonal form kept beside it
-      Ctx cg = c;
-      TriIO tio;
-      if (sv) {
-        cg.G = sv->gslot(k); cg.gld = sv->L;
-        tio.save = sv->tslot(k); tio.ld = 5ll * sv->L;
-      }
+      // column side: G = M^H M (q x q); with saved state the full
+      // decomposition goes to the saved slot of this site beside the kept part
       Operand A = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
       Operand B = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
-      int r = gram(cg, A, B, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da, pb);
+      int r = gram(c, A, B, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da, pb);
       if (r) return r;
-      r = eig(cg, dv(c, 2, bet), (int)qb, p.beta[k], o.cutoff, o.tau, kout,
-              {emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV),                      // V [q][i]
-               emit(core_z(k), 2, 1, zc, 2 * zc, 1, 0, real, b.sZ)},           // B_k[i][t][b] = conj V[(b,t)][i]
-              nullptr, tio);
+      const EigEmit eV = emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV);              // V [q][i]
+      const EigEmit eB = emit(core_z(k), 2, 1, zc, 2 * zc, 1, 0, real, b.sZ);   // B_k[i][t][b] = conj V[(b,t)][i]
+      if (sv) {
+        const ll L = sv->L;
+        FullOut fo;
+        fo.lam = sv->lslot(k); fo.lam_ld = L; fo.keep_cap = p.beta[k];
+        r = eig(c, dv(c, 2, bet), (int)qb, (int)qb, o.cutoff, o.tau, kout,
+                {eV, eB, emit(sv->vslot(k), 1, L, 0, 1, 0, 0, real, L * L, 1)}, nullptr, fo);
+      } else {
+        r = eig(c, dv(c, 2, bet), (int)qb, p.beta[k], o.cutoff, o.tau, kout, {eV, eB});
+      }
       if (r) return r;
       // carry_next[a][i][w'] = sum_q M[(a,w')][q] V[q][i]
       Operand A2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
@@ -761,20 +769,21 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
                opd(next, 2 * zc, 0, 1, zc, 0, b.sCtr));
       if (r) return r;
     } else {
-      Ctx cg = c;
-      TriIO tio;
-      if (sv) {
-        cg.G = sv->gslot(m + k); cg.gld = sv->L;
-        tio.save = sv->tslot(m + k); tio.ld = 5ll * sv->L;
-      }
       Operand A = opd(center, 2 * zc, zc, 1, 0, 0, sCenter);
       Operand B = opd(center, 1, 0, 2 * zc, zc, 1, sCenter);
-      int r = gram(cg, A, B, dv(c, 2, rk), 2, (int)pb, dv(c, 1, bk), 1, qb);
+      int r = gram(c, A, B, dv(c, 2, rk), 2, (int)pb, dv(c, 1, bk), 1, qb);
       if (r) return r;
-      r = eig(cg, dv(c, 2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout,
-              {emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut),   // out core k = U
-               emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV)},             // U [p][i]
-              nullptr, tio);
+      const EigEmit eU = emit(core_out(k), 2, 2 * co, co, 1, 0, 0, real, sOut);   // out core k = U
+      const EigEmit eV1 = emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV);             // U [p][i]
+      if (sv) {
+        const ll L = sv->L;
+        FullOut fo;
+        fo.lam = sv->lslot(m + k); fo.lam_ld = L; fo.keep_cap = p.rout[k + 1];
+        r = eig(c, dv(c, 2, rk), (int)pb, (int)pb, o.cutoff, o.tau, kout,
+                {eU, eV1, emit(sv->vslot(m + k), 1, L, 0, 1, 0, 0, real, L * L, 1)}, nullptr, fo);
+      } else {
+        r = eig(c, dv(c, 2, rk), (int)pb, p.rout[k + 1], o.cutoff, o.tau, kout, {eU, eV1});
+      }
       if (r) return r;
       // R[i][b] = sum_p conj(U[p][i]) M[p][b]
       r = gemm(c, dv(c, 1, kout), 1, p.rout[k + 1], dv(c, 1, bk), 1, (int)qb, dv(c, 2, rk), 2,
@@ -899,9 +908,9 @@ int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_op
 // Reverse of the sweep (right to left), then of the zip-up (left to right).
 // Every truncation M -> (V_k, M V_k) (zip-up: B = V_k^H, carry = M V_k; sweep
 // on N^H: U = V_k, R = U^H N) is differentiated with the full FP64 eigen-
-// decomposition G = M^H M = V diag(lam) V^H, completed from the Householder
-// reduction the forward kept (the Gram product and the reduction are not
-// redone, and the adjoint sees the factorisation the forward truncated with):
+// decomposition G = M^H M = V diag(lam) V^H that the forward computed beside
+// its keep rule and saved (no eigensolver runs here, and the adjoint sees the
+// very factorisation the forward truncated with):
 //   Vbar = gV + M^H gC,  Z = F o (V^H Vbar) with F_ji = 1/(lam_i - lam_j) for
 //   discarded j and kept i (0 elsewhere),  P = V Z,
 //   Mbar = (gC + M P) V_k^H + (M V_k) P^H.
@@ -910,14 +919,12 @@ int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_op
 // nothing to the gradient of any function of the final field.
 struct BwdBufs {
   int* status;
-  int* kfull;
   void *X, *Mb, *Mbar, *Xbar;
   void* gC[2];
   void* Zbar;
   void* Nbar[2];
   void *R, *Rbar;
-  void *Vall, *Vbar, *Y, *P;
-  void* eigws;
+  void *Vbar, *Y, *P;
   ll sX, sC, sZ, sCtr, sR, sE;
   int nmax;
 };
@@ -930,7 +937,6 @@ BwdBufs carve_bwd(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   b.sX = t.sX; b.sC = t.sC; b.sZ = t.sZ; b.sCtr = t.sCtr; b.sR = t.sR;
   b.sE = (ll)b.nmax * b.nmax;
   b.status = (int*)cv.take(256);
-  b.kfull = (int*)cv.take((size_t)nf * (p.m + 1) * sizeof(int));
   b.X = cv.take(nf * b.sX * csz);
   b.Mb = cv.take(nf * b.sX * csz);
   b.Mbar = cv.take(nf * b.sX * csz);
@@ -942,11 +948,9 @@ BwdBufs carve_bwd(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   b.Nbar[1] = cv.take(nf * b.sCtr * csz);
   b.R = cv.take(nf * b.sR * csz);
   b.Rbar = cv.take(nf * b.sR * csz);
-  b.Vall = cv.take(nf * b.sE * csz);
   b.Vbar = cv.take(nf * b.sE * csz);
   b.Y = cv.take(nf * b.sE * csz);
   b.P = cv.take(nf * b.sE * csz);
-  b.eigws = cv.take(eig_ws_bytes(b.nmax, b.nmax, nf));
   return b;
 }
 
@@ -961,8 +965,8 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
   const int m = p.m, nf = in.nf;
   const int real = in.dtype == QTT_C128 ? 1 : 0;
   Ctx c = make_ctx(s, real, nf, m, b.status);
-  c.G = nullptr; c.gld = 0; c.part = nullptr; c.eigws = b.eigws;
-  c.eig_nb = b.nmax; c.eig_kc = b.nmax;
+  c.G = nullptr; c.gld = 0; c.part = nullptr; c.eigws = nullptr;
+  c.eig_nb = 0; c.eig_kc = 0;
   c.kcap_dev = nullptr;
   const ll ci = in.cap, co = out.cap, zc = p.zc, L = b.nmax;
   const size_t csz = c.csz;
@@ -978,19 +982,6 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
   auto center_at = [&](int k) { return k == 0 ? core_z(0) : (char*)sv.N + (size_t)k * nf * b.sCtr * csz; };
   const char* Wc = (const char*)W.cores;
   const ll dcap = p.dcap;
-  // the forward's Gram reduction of truncation slot j (reflectors and form)
-  auto reduced = [&](int j) {
-    Ctx cg = c;
-    cg.G = sv.gslot(j);
-    cg.gld = sv.L;
-    return cg;
-  };
-  auto kept = [&](int j) {
-    TriIO t;
-    t.load = sv.tslot(j);
-    t.ld = 5ll * sv.L;
-    return t;
-  };
   int r;
 
   HIPCHK(zero_fill(gin.cores, (size_t)nf * sIn * csz, s));
@@ -1027,18 +1018,14 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
     r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 1, bk), 1, opd(N, zc, 0, 1, 0, 0, sN),
              opd(b.Rbar, 1, 0, zc, 0, 1, b.sR), opd(b.Vbar, L, 0, 1, 0, 0, b.sE), dx(1), 1, 1);
     if (r) return r;
-    // full decomposition of N N^H, from the forward's reduction
-    EigSpec es;
-    Ctx cr = reduced(m + k);
-    r = eig(cr, dv(c, 2, rk), nr, nr, 0.0, -1.0, b.kfull, {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)},
-            &es, kept(m + k));
-    if (r) return r;
-    // Y = Vall^H Vbar, scaled in place to Z; P = Vall Z
-    r = gemm(c, dv(c, 1, b.kfull), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 2, rk), 1, opd(b.Vall, 1, 0, L, 0, 1, b.sE),
+    // the full decomposition of N N^H the forward computed: Y = Vall^H Vbar,
+    // scaled in place to Z; P = Vall Z
+    const void* Vall = sv.vslot(m + k);
+    r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 2, rk), 1, opd(Vall, 1, 0, L, 0, 1, b.sE),
              opd(b.Vbar, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE));
     if (r) return r;
-    HIPCHK(eig_adjoint_scale(es, b.Y, L, b.sE, rk1, bs, nr1, real, s));
-    r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 1, b.kfull), 1, opd(b.Vall, L, 0, 1, 0, 0, b.sE),
+    HIPCHK(eig_adjoint_scale(dv(c, 2, rk), nr, sv.lslot(m + k), L, nf, b.Y, L, b.sE, rk1, bs, nr1, real, s));
+    r = gemm(c, dv(c, 2, rk), 1, nr, dv(c, 1, rk1), 1, nr1, dv(c, 2, rk), 1, opd(Vall, L, 0, 1, 0, 0, b.sE),
              opd(b.Y, L, 0, 1, 0, 0, b.sE), opd(b.P, L, 0, 1, 0, 0, b.sE));
     if (r) return r;
     // Rbar += P^H N;  Nbar = U Rbar + P R
@@ -1102,18 +1089,15 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
                opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX), opd(gcur, zc * Da, 1, Da, 0, 0, b.sC),
                opd(b.Vbar, L, 0, 1, 0, 0, b.sE), dx(1), 1, 1);
       if (r) return r;
-      // full decomposition of M^H M, from the forward's reduction
-      EigSpec es;
-      Ctx cr = reduced(k);
-      r = eig(cr, dv(c, 2, bet), (int)qb, (int)qb, 0.0, -1.0, b.kfull,
-              {emit(b.Vall, 1, L, 0, 1, 0, 0, real, b.sE)}, &es, kept(k));
+      // the full decomposition of M^H M the forward computed
+      const void* Vall = sv.vslot(k);
+      r = gemm(c, dv(c, 2, bet), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 2, bet), 1,
+               opd(Vall, 1, 0, L, 0, 1, b.sE), opd(b.Vbar, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE));
       if (r) return r;
-      r = gemm(c, dv(c, 1, b.kfull), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 2, bet), 1,
-               opd(b.Vall, 1, 0, L, 0, 1, b.sE), opd(b.Vbar, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE));
-      if (r) return r;
-      HIPCHK(eig_adjoint_scale(es, b.Y, L, b.sE, kkp, bs, p.beta[k], real, s));
-      r = gemm(c, dv(c, 2, bet), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 1, b.kfull), 1,
-               opd(b.Vall, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE), opd(b.P, L, 0, 1, 0, 0, b.sE));
+      HIPCHK(eig_adjoint_scale(dv(c, 2, bet), (int)qb, sv.lslot(k), L, nf, b.Y, L, b.sE, kkp, bs, p.beta[k], real,
+                               s));
+      r = gemm(c, dv(c, 2, bet), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 2, bet), 1,
+               opd(Vall, L, 0, 1, 0, 0, b.sE), opd(b.Y, L, 0, 1, 0, 0, b.sE), opd(b.P, L, 0, 1, 0, 0, b.sE));
       if (r) return r;
       // gC += M P;  Mbar = gC V^H (V^H is B_k itself) + (M V) P^H
       r = gemm(c, dv(c, Da, ra), Da, (int)pb, dv(c, 1, kkp), 1, p.beta[k], dv(c, 2, bet), 1, Mrows,

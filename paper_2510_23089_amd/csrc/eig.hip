@@ -917,12 +917,12 @@ __device__ __forceinline__ double xs_next(unsigned long long& st) {
 }
 
 __global__ __launch_bounds__(64) void inviter_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase,
-                                                     int nb, int kc, int vpw) {
+                                                     int nb, int kc, int vpw, int vec_all) {
   extern __shared__ double ivs[];
   __shared__ double sd[EIG_NMAX], se[EIG_NMAX];
   const int b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
-  const int k = kin[b * kstride];
+  const int k = vec_all ? min(n, kc) : kin[b * kstride];
   const int t = threadIdx.x;
   const int vi = blockIdx.x * vpw + t;
   if (blockIdx.x * vpw >= k) return;          // whole workgroup idle
@@ -1117,10 +1117,10 @@ __device__ void cluster_gs(double* Z, int ldz, int m, int n, double* coef, doubl
 }
 
 __global__ __launch_bounds__(CL_NT) void cluster_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase,
-                                                        int nb, int kc, double reltol) {
+                                                        int nb, int kc, double reltol, int vec_all) {
   const int b = blockIdx.x;
   const int n = min(dim_eval(nexp, b), nb);
-  const int k = kin[b * kstride];
+  const int k = vec_all ? min(n, kc) : kin[b * kstride];
   EigWs W = eig_ws_carve(wsbase, b, nb, kc);
   __shared__ double red[CL_NT / 64];
   __shared__ double coef[EIG_NMAX];
@@ -1196,12 +1196,13 @@ constexpr int BT_NT = 256;
 template <int NM>
 __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int ld, long long gstride,
                                                        DimExpr nexp, int* kin, long long kstride, void* wsbase,
-                                                       int nb, int kc, EmitPack ep) {
+                                                       int nb, int kc, EmitPack ep, int vec_all) {
   constexpr int PL = NM / 64;                 // entries per lane
   constexpr int DEPTH = NM <= 256 ? 6 : 3;    // reflector rows in flight
   const int b = blockIdx.y;
   const int n = min(dim_eval(nexp, b), nb);
-  const int k = kin[b * kstride];
+  const int kept = kin[b * kstride];
+  const int k = vec_all ? min(n, kc) : kept;
   const int t = blockIdx.x * (BT_NT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const double2* A = Gall + (long long)b * gstride;
@@ -1290,9 +1291,10 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
       }
     }
   }
-  const double sg = W.sig[t];
+  const double sg = t < kept ? W.sig[t] : 0.0;
   for (int e = 0; e < ep.ne; ++e) {
     const EigEmit& em = ep.e[e];
+    if (t >= kept && !em.all) continue;
     double sc = 1.0;
     if (em.pow == 1) sc = sg;
     else if (em.pow == -1) sc = sg > 0.0 ? 1.0 / sg : 0.0;
@@ -1311,24 +1313,15 @@ __global__ __launch_bounds__(BT_NT) void backtr_kernel(const double2* Gall, int 
   }
 }
 
-// Kept eigenvalues to a caller array (zero beyond the kept count).
-// The tridiagonal form of one matrix between its workspace and a compact
-// buffer [d | e | e^2 | Householder scalars (re, im)] of 5 nb doubles at
-// batch stride tld.  load 0: workspace -> buffer; 1: buffer -> workspace.
-__global__ void tri_copy_kernel(void* wsbase, int nb, int kc, double* buf, long long tld, int load) {
-  EigWs W = eig_ws_carve(wsbase, blockIdx.x, nb, kc);
-  double* t = buf + (long long)blockIdx.x * tld;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    double* w[5] = {W.d + i, W.e + i, W.e2 + i, &W.tau[i].x, &W.tau[i].y};
-#pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      double* c = t + (long long)j * nb + i;
-      if (load) *w[j] = *c;
-      else *c = *w[j];
-    }
-  }
+// Every computed eigenvalue to a caller array (t < n).
+__global__ void lam_out_kernel(DimExpr nexp, void* wsbase, int nb, int kc, double* out, long long ldo) {
+  const int b = blockIdx.x;
+  const int n = min(min(dim_eval(nexp, b), nb), kc);
+  EigWs W = eig_ws_carve(wsbase, b, nb, kc);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) out[(long long)b * ldo + t] = W.lam[t];
 }
 
+// Kept eigenvalues to a caller array (zero beyond the kept count).
 __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long kstride, void* wsbase, int nb, int kc,
                                   double* out, int ldo) {
   (void)nexp;
@@ -1350,23 +1343,22 @@ __global__ void copy_evals_kernel(DimExpr nexp, int kcap, int* kin, long long ks
 // the float64 reference, and the exact derivative differs from the cut one
 // by about 5e-4 relative there.
 constexpr double ADJ_GAP = 1e-10;
-__global__ void adj_scale_kernel(DimExpr nexp, int* kin, long long kstride, void* wsbase, int nb, int kc, void* Y,
+__global__ void adj_scale_kernel(DimExpr nexp, int nb, const double* lamall, long long lam_ld, void* Y,
                                  long long ldy, long long s_batch, const int* kk, long long kk_stride, int kk_bound,
                                  int dtype, double gap_rel) {
   const int b = blockIdx.y;
   const int j = blockIdx.x;
   const int n = min(dim_eval(nexp, b), nb);
-  const int kfull = min(kin[b * kstride], n);
   const int kkb = min(kk[b * kk_stride], kk_bound);
-  EigWs W = eig_ws_carve(wsbase, b, nb, kc);
+  const double* lam = lamall + (long long)b * lam_ld;
   if (j >= n) return;
-  const double lj = W.lam[j < kc ? j : 0];
+  const double lj = lam[j];
   // pairs closer than ADJ_GAP lam_1 have no resolvable derivative: their term is 0
-  const double gmin = gap_rel * fabs(W.lam[0]);
+  const double gmin = gap_rel * fabs(lam[0]);
   for (int i = threadIdx.x; i < kkb; i += blockDim.x) {
     double f = 0.0;
-    if (j >= kkb && j < kfull) {
-      const double d = W.lam[i] - lj;
+    if (j >= kkb) {
+      const double d = lam[i] - lj;
       f = d > gmin ? 1.0 / d : 0.0;
     }
     long long o = (long long)b * s_batch + (long long)j * ldy + i;
@@ -1428,92 +1420,89 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
     g_prof.launches++;
     g_prof.slot += sp.batch;
   };
-  if (sp.tri_load) {
-    // a reduction kept from an earlier call on the same matrices
-    hipLaunchKernelGGL(tri_copy_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc,
-                       const_cast<double*>(sp.tri_load), sp.tri_ld, 1);
-  } else {
-    const int cb = nb <= 256 ? 32 : 16;
-    const int groups = (nb + cb - 1) / cb;
-    const bool mwg = nb > TL_NMAX && (long long)groups * sp.batch <= compute_units();
-    if (mwg) hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc);
-    if (nb > TL_NMAX && !mwg) {
-      // the streaming reduction updates the full matrix in place: complete it
-      // from the lower triangle first
-      hipError_t fe = hermitian_fill(sp.G, sp.ld, sp.gstride, sp.n, nb, sp.batch, s);
-      if (fe != hipSuccess) return fe;
-    }
-    const bool prof = prof_on(nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG);
-    int* nl = prof ? prof_begin() : (int*)nullptr;
-    if (nb <= TL_NMAX) {
-      if (nb <= 16)
-        hipLaunchKernelGGL(tridiag_lds_kernel<128>, dim3(sp.batch), dim3(128), 0, s, (double2*)sp.G, sp.ld,
-                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
-      else if (nb <= 32)
-        hipLaunchKernelGGL(tridiag_lds_kernel<256>, dim3(sp.batch), dim3(256), 0, s, (double2*)sp.G, sp.ld,
-                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
-      else if (nb <= 64)
-        hipLaunchKernelGGL(tridiag_lds_kernel<512>, dim3(sp.batch), dim3(512), 0, s, (double2*)sp.G, sp.ld,
-                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
-      else
-        hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
-                           sp.gstride, sp.n, sp.ws, nb, kc, nl);
-    } else if (mwg) {
-      if (cb == 32)
-        hipLaunchKernelGGL(tridiag_mwg_kernel<32>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
-                           sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
-      else
-        hipLaunchKernelGGL(tridiag_mwg_kernel<16>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
-                           sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
-    } else {
-      hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TS_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
-                         sp.n, sp.ws, nb, kc, nl);
-    }
-    if (prof) prof_end();
-    // the last 128 steps of the reductions (c) and (b), on one workgroup
-    if (nb > TL_NMAX) {
-      const bool pt = prof_on(PROF_TRIDIAG_LDS);
-      int* nt = pt ? prof_begin() : (int*)nullptr;
-      hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
-                         sp.gstride, sp.n, sp.ws, nb, kc, nt);
-      if (pt) prof_end();
-    }
-    if (sp.tri_save)
-      hipLaunchKernelGGL(tri_copy_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc, sp.tri_save, sp.tri_ld, 0);
+  const int cb = nb <= 256 ? 32 : 16;
+  const int groups = (nb + cb - 1) / cb;
+  const bool mwg = nb > TL_NMAX && (long long)groups * sp.batch <= compute_units();
+  if (mwg) hipLaunchKernelGGL(mw_reset_kernel, dim3(sp.batch), dim3(256), 0, s, sp.ws, nb, kc);
+  if (nb > TL_NMAX && !mwg) {
+    // the streaming reduction updates the full matrix in place: complete it
+    // from the lower triangle first
+    hipError_t fe = hermitian_fill(sp.G, sp.ld, sp.gstride, sp.n, nb, sp.batch, s);
+    if (fe != hipSuccess) return fe;
   }
+  const bool prof = prof_on(nb <= TL_NMAX ? PROF_TRIDIAG_LDS : PROF_TRIDIAG);
+  int* nl = prof ? prof_begin() : (int*)nullptr;
+  if (nb <= TL_NMAX) {
+    if (nb <= 16)
+      hipLaunchKernelGGL(tridiag_lds_kernel<128>, dim3(sp.batch), dim3(128), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
+    else if (nb <= 32)
+      hipLaunchKernelGGL(tridiag_lds_kernel<256>, dim3(sp.batch), dim3(256), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
+    else if (nb <= 64)
+      hipLaunchKernelGGL(tridiag_lds_kernel<512>, dim3(sp.batch), dim3(512), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
+    else
+      hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, nl);
+  } else if (mwg) {
+    if (cb == 32)
+      hipLaunchKernelGGL(tridiag_mwg_kernel<32>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
+    else
+      hipLaunchKernelGGL(tridiag_mwg_kernel<16>, dim3(groups, sp.batch), dim3(MW_NT), 0, s, (double2*)sp.G, sp.ld,
+                         sp.gstride, sp.n, sp.ws, nb, kc, sp.status, nl);
+  } else {
+    hipLaunchKernelGGL(tridiag_kernel, dim3(sp.batch), dim3(TS_NT), 0, s, (double2*)sp.G, sp.ld, sp.gstride,
+                       sp.n, sp.ws, nb, kc, nl);
+  }
+  if (prof) prof_end();
+  // the last 128 steps of the reductions (c) and (b), on one workgroup
+  if (nb > TL_NMAX) {
+    const bool pt = prof_on(PROF_TRIDIAG_LDS);
+    int* nt = pt ? prof_begin() : (int*)nullptr;
+    hipLaunchKernelGGL(tridiag_lds_kernel<TL_NT>, dim3(sp.batch), dim3(TL_NT), 0, s, (double2*)sp.G, sp.ld,
+                       sp.gstride, sp.n, sp.ws, nb, kc, nt);
+    if (pt) prof_end();
+  }
+  // a full decomposition beside the truncation computes every pair (no
+  // per-field cap on the eigenvalues) and keeps by keep_cap
+  const int vec_all = sp.lam_out ? 1 : 0;
+  const int kkeep = vec_all && sp.keep_cap > 0 && sp.keep_cap < kc ? sp.keep_cap : kc;
   hipLaunchKernelGGL(eigvals_kernel, dim3((kc + 3) / 4, sp.batch), dim3(EV_NT), 0, s, sp.n, kc, sp.ws, nb, kc,
-                     sp.kcap_dev);
-  hipLaunchKernelGGL(keep_kernel, dim3(sp.batch), dim3(KP_NT), 0, s, sp.n, kc, sp.cutoff, tau, sp.kout,
+                     vec_all ? (const int*)nullptr : sp.kcap_dev);
+  hipLaunchKernelGGL(keep_kernel, dim3(sp.batch), dim3(KP_NT), 0, s, sp.n, kkeep, sp.cutoff, tau, sp.kout,
                      sp.kstride, sp.ws, nb, kc, sp.batch, sp.status, sp.sigma_out, sp.kcap_dev);
+  if (vec_all)
+    hipLaunchKernelGGL(lam_out_kernel, dim3(sp.batch), dim3(256), 0, s, sp.n, sp.ws, nb, kc, sp.lam_out, sp.lam_ld);
   const int vpw = iv_vpw(nb);
   const size_t ivlds = (size_t)vpw * nb * 41;
   hipLaunchKernelGGL(inviter_kernel, dim3((kc + vpw - 1) / vpw, sp.batch), dim3(64), ivlds, s, sp.n, sp.kout,
-                     sp.kstride, sp.ws, nb, kc, vpw);
+                     sp.kstride, sp.ws, nb, kc, vpw, vec_all);
   // inverse-iteration vectors are orthogonal to ~eps*||T||/gap: re-orthogonalise
   // runs of eigenvalues closer than 1e-10 ||T|| (outside them the loss of
   // orthogonality is <= ~1e-6 and confined to directions whose singular
   // values are tiny relative to the largest)
   hipLaunchKernelGGL(cluster_kernel, dim3(sp.batch), dim3(CL_NT), 0, s, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc,
-                     1e-10);
+                     1e-10, vec_all);
   EmitPack ep;
   ep.ne = sp.nemit;
   for (int i = 0; i < sp.nemit && i < 3; ++i) ep.e[i] = sp.emit[i];
   if (nb <= 256)
     hipLaunchKernelGGL(backtr_kernel<256>, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s, (const double2*)sp.G,
-                       sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep);
+                       sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep, vec_all);
   else
     hipLaunchKernelGGL(backtr_kernel<EIG_NMAX>, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s,
-                       (const double2*)sp.G, sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep);
+                       (const double2*)sp.G, sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep, vec_all);
   return hipGetLastError();
 }
 
-hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long long s_batch, const int* kk,
-                             long long kk_stride, int kk_bound, int dtype, hipStream_t s) {
-  const int nb = sp.n_bound;
-  const int kc = sp.kcap < nb ? sp.kcap : nb;
-  if (kc < nb) return hipErrorInvalidValue;      // needs the full decomposition
-  hipLaunchKernelGGL(adj_scale_kernel, dim3(nb, sp.batch), dim3(64), 0, s, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc,
-                     Y, ldy, s_batch, kk, kk_stride, kk_bound, dtype, ADJ_GAP);
+hipError_t eig_adjoint_scale(DimExpr n, int n_bound, const double* lam, long long lam_ld, int batch, void* Y,
+                             long long ldy, long long s_batch, const int* kk, long long kk_stride, int kk_bound,
+                             int dtype, hipStream_t s) {
+  if (n_bound < 1 || batch < 1 || !lam) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(adj_scale_kernel, dim3(n_bound, batch), dim3(64), 0, s, n, n_bound, lam, lam_ld, Y, ldy, s_batch,
+                     kk, kk_stride, kk_bound, dtype, ADJ_GAP);
   return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ struct EigEmit {
   int conj = 0;
   int pow = 0;
   int dtype = 0;
+  int all = 0;                // with EigSpec::lam_out: every computed vector, not only the kept ones (pow 0)
 };
 
 struct EigSpec {
@@ -90,14 +91,14 @@ struct EigSpec {
   EigEmit emit[3];
   int nemit;
   double* sigma_out;          // optional: device FP64 singular values [batch][kcap]
-  // Optional kept reduction.  tri_save: once the matrices are reduced, their
-  // tridiagonal forms (d, e, e^2 and the complex Householder scalars, 5
-  // n_bound doubles per matrix, batch stride tri_ld) are copied there; the
-  // reflectors stay in G.  tri_load: no reduction at all; the forms are read
-  // back from there and G must hold the reflectors the same reduction left.
-  double* tri_save = nullptr;
-  const double* tri_load = nullptr;
-  long long tri_ld = 0;
+  // Optional full decomposition beside the truncation: with lam_out set,
+  // every eigenpair up to kcap (normally n_bound) is computed, all of them
+  // reach the emits marked `all` and the eigenvalues reach lam_out[b * lam_ld
+  // + t] (t < n, descending), while the keep rule and the other emits use the
+  // cap keep_cap.
+  double* lam_out = nullptr;
+  long long lam_ld = 0;
+  int keep_cap = 0;
 };
 
 size_t eig_ws_bytes(int n_bound, int kcap, int batch);
@@ -120,14 +121,15 @@ struct ProfHook {
 extern ProfHook g_prof;
 hipError_t eig_launch(const EigSpec& sp, hipStream_t s);
 hipError_t eig_copy_evals(const EigSpec& sp, double* out, int ldo, hipStream_t s);
-// Eigenvector-adjoint scaling after a full decomposition (sp.kcap = n, every
-// pair kept): Y[j][i] (row j = eigenvector index, column i < kk[f]) becomes
-//   Y[j][i] / (lam_i - lam_j)  for kk[f] <= j < kept where lam_i - lam_j >
+// Eigenvector-adjoint scaling after a full decomposition: Y[j][i] (row j =
+// eigenvector index < n, column i < kk[f]) becomes
+//   Y[j][i] / (lam_i - lam_j)  for kk[f] <= j < n where lam_i - lam_j >
 //   1e-10 lam_1, and 0 otherwise (pairs whose Gram eigenvectors are not
 //   resolved well enough for a term divided by their gap),
-// with lam from the decomposition just run.
-hipError_t eig_adjoint_scale(const EigSpec& sp, void* Y, long long ldy, long long s_batch, const int* kk,
-                             long long kk_stride, int kk_bound, int dtype, hipStream_t s);
+// with lam[f * lam_ld + t] the n eigenvalues (descending) of matrix f.
+hipError_t eig_adjoint_scale(DimExpr n, int n_bound, const double* lam, long long lam_ld, int batch, void* Y,
+                             long long ldy, long long s_batch, const int* kk, long long kk_stride, int kk_bound,
+                             int dtype, hipStream_t s);
 
 // ---------------------------------------------------------------- misc
 // Quantics permutation of a row-major N x N image into the flat quantics
