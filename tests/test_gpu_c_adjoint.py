@@ -125,6 +125,7 @@ def test_apply_backward_linear_functional_vs_oracle(prec, n, chi, z):
     s2 = api.saved_buffer(mid, Wy, chi)
     out = api.mpo_apply(mid, Wy, chi, saved=s2)
     g_out = api.tt_to_dense_backward(out, torch.from_numpy(probe).to(dt).cuda())
+    s1c, s2c = s1.clone(), s2.clone()
     g_mid = api.mpo_apply_backward(mid, Wy, chi, s2, out, g_out)
     g_in = api.mpo_apply_backward(psi, Wx, chi, s1, mid, g_mid)
     api.check_status()
@@ -133,6 +134,11 @@ def test_apply_backward_linear_functional_vs_oracle(prec, n, chi, z):
     err = _rel_list(got, ref)
     say("  rel err", err)
     assert err < (1e-4 if prec == "fp32" else 1e-10)
+    # the saved buffers are only read: a second adjoint from them repeats the first bit for bit
+    assert torch.equal(s1, s1c) and torch.equal(s2, s2c)
+    g_in2 = api.mpo_apply_backward(psi, Wx, chi, s1, mid, api.mpo_apply_backward(mid, Wy, chi, s2, out, g_out))
+    api.check_status()
+    assert torch.equal(g_in2.cores, g_in.cores)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
