@@ -26,7 +26,7 @@ Parity status: every function above is pinned by at least one test in
 ``tests/test_oracle_*.py``; see the docstrings for which.  The truncating
 zip-up is pinned in closed form for operators of bond 1 (single-site
 unitaries on a left-canonical input: the right-to-left sequential truncated
-SVD of the exact result, i.e. the TT-SVD of the site-reversed vector); with
-operator bonds above 1 the truncating regime is pinned only as "the identical
-algorithm" plus bounds (parity unpinned beyond that).
+SVD of the exact result, i.e. the TT-SVD of the site-reversed vector), and
+with operator bonds above 1 by brute force on 8-site chains (the definition
+evaluated densely, without the carry recursion).
 """

@@ -177,3 +177,84 @@ def test_truncating_zipup_of_site_unitaries_is_right_to_left_ttsvd(chi_zip, seed
     assert Z.bonds(out) == T.bonds(cr)[::-1]
     # and the cut really truncates
     assert max(Z.bonds(out)) == chi_zip
+
+
+def _zipup_dense_brute_force(psi, mpo, chi_zip, tau=1e-13):
+    """The zip-up's definition evaluated without carries, for tiny chains.
+    Before the cut at bond k-1 the exact right part of W psi,
+        R[(a_(k-1), w_(k-1)), (t_k .. t_m)] = sum_s prod_(j >= k) A_j W_j,
+    is formed densely from all cores at once; the output's right basis P
+    (rows beta_k, columns t_(k+1) .. t_m) is formed densely from the cores
+    already fixed; then M = R (I_2 (x) P)^H as [(a, w), (t_k, beta_k)], its
+    singular vectors give B_k (top r rows of V^H, r = min(chi_zip,
+    #{s^2 > tau s_1^2})) and P is extended by B_k.  The carry recursion of
+    the oracle never appears."""
+    m = len(psi)
+    out = [None] * m
+    P = np.ones((1, 1), dtype=np.complex128)           # [beta, T] with T = () at the right end
+    for k in range(m - 1, -1, -1):
+        # exact right part from site k: contract A_j W_j for j = k..m-1 densely
+        R = np.ones((1, 1, 1), dtype=np.complex128)     # [a_j, w_j, T]
+        for j in range(m - 1, k - 1, -1):
+            a, w = psi[j], mpo[j]                       # [ra, s, rb], [da, t, s, db]
+            x = np.einsum("asb,dtsc,bcT->adtT", a, w, R)
+            R = x.reshape(a.shape[0], w.shape[0], -1)
+        ra, da, nt = R.shape
+        Rm = R.reshape(ra * da, 2, nt // 2)             # [(a, w), t_k, T']
+        M = np.einsum("xtT,bT->xtb", Rm, P.conj()).reshape(ra * da, -1)
+        if k == 0:
+            out[0] = M.reshape(1, 2, -1)
+            break
+        u, s, vh = np.linalg.svd(M, full_matrices=False)
+        lam = s * s
+        r = max(1, min(chi_zip, int(np.sum(lam > tau * lam[0]))))
+        bk = vh[:r].reshape(r, 2, -1)
+        out[k] = bk
+        P = np.einsum("itb,bT->itT", bk, P).reshape(r, -1)
+    return out
+
+
+def _random_mpo(rng, m, d):
+    bonds = [1] + [d] * (m - 1) + [1]
+    return [(rng.standard_normal((bonds[k], 2, 2, bonds[k + 1])) +
+             1j * rng.standard_normal((bonds[k], 2, 2, bonds[k + 1]))) / 2.0 for k in range(m)]
+
+
+@pytest.mark.parametrize("case", ["fresnel", "random"])
+@pytest.mark.parametrize("chi_zip", [2, 3, 5])
+def test_truncating_zipup_with_operator_bonds_vs_dense_brute_force(case, chi_zip):
+    """Truncating regime with operator bonds above 1: the oracle's zip-up
+    (carry recursion) equals the zip-up definition evaluated densely without
+    carries (brute force on an 8-site chain) -- same bonds, same state; and
+    a carry without its singular values (a plausible slip) is caught."""
+    rng = np.random.default_rng(700 + chi_zip)
+    n, m = 4, 8
+    v = rng.standard_normal(1 << m) + 1j * rng.standard_normal(1 << m)
+    psi = T.tt_svd(v, m, chi=BIG)
+    if case == "fresnel":
+        wx, _ = _axis_mpos(n, 3e-6)
+        mpo = wx
+    else:
+        mpo = _random_mpo(rng, m, 3)
+    assert max(w.shape[0] for w in mpo) > 1
+    got = Z.zip_up(psi, mpo, chi_zip)
+    want = _zipup_dense_brute_force(psi, mpo, chi_zip)
+    assert Z.bonds(got) == Z.bonds(want)
+    assert max(Z.bonds(got)) == chi_zip                  # the cut really truncates
+    assert _rel(T.tt_dense(got), T.tt_dense(want)) < 1e-10
+    # planted slip: carry U instead of U S
+    slip = [None] * m
+    carry = np.ones((1, 1, 1), dtype=np.complex128)
+    for k in range(m - 1, -1, -1):
+        x = np.tensordot(psi[k], carry, axes=(2, 0))
+        t = np.tensordot(x, mpo[k], axes=([1, 2], [2, 3])).transpose(0, 2, 3, 1)
+        ra, da, _, beta = t.shape
+        mat = t.reshape(ra * da, 2 * beta)
+        if k == 0:
+            slip[0] = mat.reshape(1, 2, beta)
+            break
+        u, s, vh = np.linalg.svd(mat, full_matrices=False)
+        r = max(1, min(chi_zip, int(np.sum(s * s > 1e-13 * s[0] ** 2))))
+        slip[k] = vh[:r].reshape(r, 2, beta)
+        carry = u[:, :r].reshape(ra, da, r)
+    assert _rel(T.tt_dense(slip), T.tt_dense(want)) > 1e-3
