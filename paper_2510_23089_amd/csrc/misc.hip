@@ -67,8 +67,55 @@ __global__ void quantics_kernel(const void* src, int sdt, void* dst, int ddt, in
   }
 }
 
+// Tiled form (log2_side >= 5): one 32 x 32 pixel block per step of the
+// grid-stride loop.  Its pixels are 1024 consecutive quantics indices (the
+// low 10 bits of q interleave the low 5 bits of a and b, the high bits those
+// of the block's position), so the quantics side moves as one contiguous run
+// and the row-major side as 32 runs of 32 pixels; the block passes through
+// LDS.  The per-element form above reads (dir 1) or writes (dir 0) the
+// row-major side in runs of one or two pixels.
+constexpr int QT_J = 5, QT_T = 1 << QT_J, QT_E = QT_T * QT_T;
+__global__ __launch_bounds__(256) void quantics_tiled_kernel(const void* src, int sdt, void* dst, int ddt, int n,
+                                                             long long tiles, int dir, long long s_src,
+                                                             long long s_dst) {
+  __shared__ double2 tile[QT_T][QT_T + 1];
+  const long long fs = blockIdx.y * s_src, fd = blockIdx.y * s_dst;
+  for (long long tq = blockIdx.x; tq < tiles; tq += gridDim.x) {
+    const uint32_t ah = compact_even((uint32_t)tq >> 1), bh = compact_even((uint32_t)tq);
+    const long long qbase = tq << (2 * QT_J);
+    const long long rbase = ((long long)ah << (QT_J + n)) + ((long long)bh << QT_J);   // pixel (ah T, bh T)
+    for (int e = threadIdx.x; e < QT_E; e += 256) {
+      int al, bl;
+      long long in;
+      if (dir == 0) { al = e >> QT_J; bl = e & (QT_T - 1); in = rbase + ((long long)al << n) + bl; }
+      else { al = (int)compact_even((uint32_t)e >> 1); bl = (int)compact_even((uint32_t)e); in = qbase + e; }
+      double re, im;
+      load_elem(src, sdt, fs + in, re, im);
+      tile[al][bl] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < QT_E; e += 256) {
+      int al, bl;
+      long long o;
+      if (dir == 0) { al = (int)compact_even((uint32_t)e >> 1); bl = (int)compact_even((uint32_t)e); o = qbase + e; }
+      else { al = e >> QT_J; bl = e & (QT_T - 1); o = rbase + ((long long)al << n) + bl; }
+      const double2 v = tile[al][bl];
+      store_elem(dst, ddt, fd + o, v.x, v.y);
+    }
+    __syncthreads();
+  }
+}
+
 hipError_t quantics_permute(const void* src, int src_dtype, void* dst, int dst_dtype, int log2_side, int dir,
                             hipStream_t s, int nf, long long s_src, long long s_dst) {
+  if (nf < 1) return hipSuccess;
+  if (dir != 2 && log2_side >= QT_J) {
+    const long long tiles = 1ll << (2 * (log2_side - QT_J));
+    const long long cap = std::max<long long>(1, 65536 / nf);
+    hipLaunchKernelGGL(quantics_tiled_kernel, dim3((unsigned)std::min(tiles, cap), nf), dim3(256), 0, s, src,
+                       src_dtype, dst, dst_dtype, log2_side, tiles, dir, s_src, s_dst);
+    return hipGetLastError();
+  }
   long long total = 1ll << (2 * log2_side);
   long long blocks = (total + 255) / 256;
   long long cap = std::max<long long>(1, 65536 / std::max(nf, 1));
