@@ -236,14 +236,14 @@ int tt_to_dense(const qtt_mps* in, void* out, int out_dtype, void* ws, size_t ws
 /* Bytes of the `saved` buffer mpo_apply / mpo_apply_batched need for a later
  * backward call (capacity bound for chi_zip <= chi_cap; the call itself
  * checks the exact requirement).  The buffer receives the bonds chosen by the
- * forward call, the zip-up cores, the carry entering each zip-up site, the
- * centre entering each sweep step, and the full eigen-decomposition of every
- * truncation's Gram matrix, computed by the forward beside its keep rule (all
- * n eigenvectors as an L x L matrix in the working precision plus L FP64
- * eigenvalues per truncation and field, L = twice the largest bond a
- * truncation splits; two truncations per site), so that the backward call
- * differentiates the very factorisations the forward truncated with and runs
- * no eigensolver of its own. */
+ * forward call, the zip-up cores, the carry entering each zip-up site and the
+ * site matrix M formed there, the centre entering each sweep step, and the
+ * full eigen-decomposition of every truncation's Gram matrix, computed by the
+ * forward beside its keep rule (all n eigenvectors as an L x L matrix in the
+ * working precision plus L FP64 eigenvalues per truncation and field, L =
+ * twice the largest bond a truncation splits; two truncations per site), so
+ * that the backward call differentiates the very factorisations the forward
+ * truncated with and runs no eigensolver and no site product of its own. */
 size_t tt_saved_size(int n_sites, int chi_cap, int d_cap, int prec);
 size_t tt_saved_size_batched(int count, int n_sites, int chi_cap, int d_cap, int prec);
 

@@ -378,8 +378,8 @@ int bwd_nmax(const ApplyPlan& p) {
 
 // What a forward application keeps for its adjoint (caller-owned `saved`
 // buffer): the bonds it chose, the zip-up cores, the carry entering every
-// zip-up site, the centre entering every sweep step, and the full
-// eigen-decomposition of every truncation's Gram matrix (all n eigenvectors,
+// zip-up site and its site matrix M, the centre entering every sweep step,
+// and the full eigen-decomposition of every truncation's Gram matrix (all n eigenvectors,
 // [p][i] with leading dimension L, in the working precision, and the n
 // eigenvalues in FP64), computed once by the forward beside its keep rule, so
 // that the adjoint differentiates the very factorisation the forward
@@ -394,10 +394,12 @@ struct SavedBufs {
   void* N;
   void* V;
   double* lam;
-  ll sZ, sC, sCtr;
+  void* M;
+  ll sZ, sC, sCtr, sX;
   int L, nf;
   size_t csz;
   void* vslot(int j) const { return (char*)V + (size_t)j * nf * L * L * csz; }
+  void* mslot(int k) const { return (char*)M + (size_t)k * nf * sX * csz; }
   double* lslot(int j) const { return lam + (size_t)j * nf * L; }
 };
 
@@ -405,7 +407,7 @@ SavedBufs carve_saved(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   Carver dry(nullptr);
   ApplyBufs t = carve_apply(dry, p, csz, nf);
   SavedBufs v;
-  v.sZ = t.sZ; v.sC = t.sC; v.sCtr = t.sCtr;
+  v.sZ = t.sZ; v.sC = t.sC; v.sCtr = t.sCtr; v.sX = t.sX;
   v.L = bwd_nmax(p);
   v.nf = nf;
   v.csz = csz;
@@ -416,6 +418,7 @@ SavedBufs carve_saved(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   v.N = cv.take((size_t)p.m * nf * v.sCtr * csz);
   v.V = cv.take((size_t)2 * p.m * nf * v.L * v.L * csz);
   v.lam = (double*)cv.take((size_t)2 * p.m * nf * v.L * sizeof(double));
+  v.M = cv.take((size_t)p.m * nf * v.sX * csz);
   return v;
 }
 
@@ -539,11 +542,13 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     const bool ident = p.kind[k] == 1;
     void* carry = carry_at(k);
     void* carry_next = k > 0 ? carry_at(k - 1) : nullptr;
+    // the site matrix M: in the saved buffer when the adjoint will need it
+    void* Mb = sv ? sv->mslot(k) : b.Mb;
     // GEMM1: X[(a,s),(b,w)] = A_k[(a,s), a'] C[a', (b,w)]
     {
       Operand A = opd(core_in(k), 2 * ci, ci, 1, 0, 0, sIn);
       Operand B = opd(carry, zc * Db, 0, Db, 1, 0, b.sC);
-      Operand C = ident ? opd(b.Mb, 2 * zc * Db, 1, 2, 2 * zc, 0, b.sX) : opd(b.X, zc * 2 * Db, Db, 2 * Db, 1, 0, b.sX);
+      Operand C = ident ? opd(Mb, 2 * zc * Db, 1, 2, 2 * zc, 0, b.sX) : opd(b.X, zc * 2 * Db, Db, 2 * Db, 1, 0, b.sX);
       int r = gemm(c, dv(c, 2, ra), 2, 2 * p.rin[k], dv(c, Db, bet), Db, Db * p.beta[k + 1], dv(c, 1, rb), 1, A, B, C);
       if (r) return r;
     }
@@ -555,7 +560,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       for (int t = 0; t < 2; ++t) {
         Operand A = opd((const char*)b.X + (size_t)t * Db * csz, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db);
         Operand B = opd(Wk + (size_t)3 * t * Db * csz, 1, 0, 4 * Db, 0, 0, sW);
-        Operand C = opd((char*)b.Mb + (size_t)t * csz, 2, 0, 2 * zc, 0, 0, b.sX, (ll)Da * zc * 2);
+        Operand C = opd((char*)Mb + (size_t)t * csz, 2, 0, 2 * zc, 0, 0, b.sX, (ll)Da * zc * 2);
         int r = gemm(c, dv(c, 1, bet), 1, p.beta[k + 1], dx(Da), 1, Da, dx(Db), 1, A, B, C, dv(c, 1, ra), p.rin[k]);
         if (r) return r;
       }
@@ -563,7 +568,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       // GEMM2 (inner batch over a): M[a][w'][b][t] = sum_{s,w} X[a][b][s][w] W[w'][t][s][w]
       Operand A = opd(b.X, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db);
       Operand B = opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 1, 0, 4 * Db, 2 * Db, 0, sW);
-      Operand C = opd(b.Mb, 2, 0, 2 * zc, 1, 0, b.sX, (ll)Da * zc * 2);
+      Operand C = opd(Mb, 2, 0, 2 * zc, 1, 0, b.sX, (ll)Da * zc * 2);
       int r = gemm(c, dv(c, 1, bet), 1, p.beta[k + 1], dx(2 * Da), 2, 2 * Da, dx(2 * Db), 1, A, B, C, dv(c, 1, ra),
                    p.rin[k]);
       if (r) return r;
@@ -571,7 +576,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     // M_k = [(a, w'), (b, t)]: rows p = a*Da + w' (strides 2 zc Da, 2 zc), cols q = 2b + t (stride 1)
     if (k == 0) {
       // one row: B_0[0][t][b] = M[0][0][b][t]
-      HIPCHK(block_copy_b(b.Mb, 2, 1, b.sX, core_z(0), 1, zc, b.sZ, dv(c, 1, bet), dx(2), p.beta[1], 2, real, nf, s));
+      HIPCHK(block_copy_b(Mb, 2, 1, b.sX, core_z(0), 1, zc, b.sZ, dv(c, 1, bet), dx(2), p.beta[1], 2, real, nf, s));
       break;
     }
     const ll pb = (ll)p.rin[k] * Da, qb = 2ll * p.beta[k + 1];
@@ -584,8 +589,8 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
     if (qb <= pb || sv) {
       // column side: G = M^H M (q x q); with saved state the full
       // decomposition goes to the saved slot of this site beside the kept part
-      Operand A = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
-      Operand B = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
+      Operand A = opd(Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
+      Operand B = opd(Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
       int r = gram(c, A, B, dv(c, 2, bet), 1, (int)qb, dv(c, Da, ra), Da, pb);
       if (r) return r;
       const EigEmit eV = emit(b.V1, 1, zc, 0, 1, 0, 0, real, b.sV);              // V [q][i]
@@ -601,15 +606,15 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       }
       if (r) return r;
       // carry_next[a][i][w'] = sum_q M[(a,w')][q] V[q][i]
-      Operand A2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
+      Operand A2 = opd(Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
       Operand B2 = opd(b.V1, zc, 0, 1, 0, 0, b.sV);
       Operand C2 = opd(carry_next, zc * Da, 1, Da, 0, 0, b.sC);
       r = gemm(c, dv(c, Da, ra), Da, (int)pb, dv(c, 1, kout), 1, p.beta[k], dv(c, 2, bet), 1, A2, B2, C2);
       if (r) return r;
     } else {
       // row side: G = M M^H (p x p)
-      Operand A = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
-      Operand B = opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
+      Operand A = opd(Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);
+      Operand B = opd(Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX);
       int r = gram(c, A, B, dv(c, Da, ra), Da, (int)pb, dv(c, 2, bet), 1, qb);
       if (r) return r;
       r = eig(c, dv(c, Da, ra), (int)pb, p.beta[k], o.cutoff, o.tau, kout,
@@ -618,7 +623,7 @@ int run_apply(const MpsB& in, const MpoB& W, const qtt_opts& o, const MpsB& out,
       if (r) return r;
       // B_k[i][t][b] = sum_p conj(U/sigma)[p][i] M[p][(b,t)]
       Operand A2 = opd(b.V1, 1, 0, (ll)Da * zc, zc, 1, b.sV);     // K index p = (a, w') of a plain [p][i] matrix
-      Operand B2 = opd(b.Mb, 2 * zc * Da, 2 * zc, 2, 1, 0, b.sX);
+      Operand B2 = opd(Mb, 2 * zc * Da, 2 * zc, 2, 1, 0, b.sX);
       Operand C2 = opd(core_z(k), 2 * zc, 0, 1, zc, 0, b.sZ);
       r = gemm(c, dv(c, 1, kout), 1, p.beta[k], dv(c, 2, bet), 2, (int)qb, dv(c, Da, ra), Da, A2, B2, C2);
       if (r) return r;
@@ -919,7 +924,7 @@ int apply_common(const MpsB& in, const qtt_mpo* W1, const MpoB* Wb, const qtt_op
 // nothing to the gradient of any function of the final field.
 struct BwdBufs {
   int* status;
-  void *X, *Mb, *Mbar, *Xbar;
+  void *Mbar, *Xbar;
   void* gC[2];
   void* Zbar;
   void* Nbar[2];
@@ -937,8 +942,6 @@ BwdBufs carve_bwd(Carver& cv, const ApplyPlan& p, size_t csz, int nf) {
   b.sX = t.sX; b.sC = t.sC; b.sZ = t.sZ; b.sCtr = t.sCtr; b.sR = t.sR;
   b.sE = (ll)b.nmax * b.nmax;
   b.status = (int*)cv.take(256);
-  b.X = cv.take(nf * b.sX * csz);
-  b.Mb = cv.take(nf * b.sX * csz);
   b.Mbar = cv.take(nf * b.sX * csz);
   b.Xbar = cv.take(nf * b.sX * csz);
   b.gC[0] = cv.take(nf * b.sC * csz);
@@ -1058,23 +1061,9 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
     const bool ident = p.kind[k] == 1;
     void* Cin = carry_at(k);
     const ll pb = (ll)p.rin[k] * Da, qb = 2ll * p.beta[k + 1];
-    // recompute X and M exactly as the forward did
-    {
-      Operand A = opd(core_in(k), 2 * ci, ci, 1, 0, 0, sIn);
-      Operand B = opd(Cin, zc * Db, 0, Db, 1, 0, b.sC);
-      Operand C = ident ? opd(b.Mb, 2 * zc * Db, 1, 2, 2 * zc, 0, b.sX) : opd(b.X, zc * 2 * Db, Db, 2 * Db, 1, 0, b.sX);
-      r = gemm(c, dv(c, 2, ra), 2, 2 * p.rin[k], dv(c, Db, bet), Db, Db * p.beta[k + 1], dv(c, 1, rb), 1, A, B, C);
-      if (r) return r;
-    }
-    if (!ident) {
-      Operand A = opd(b.X, 2 * Db, 0, 1, 0, 0, b.sX, zc * 2 * Db);
-      Operand B = opd(Wc + (size_t)k * dcap * 4 * dcap * csz, 1, 0, 4 * Db, 2 * Db, 0, sW);
-      Operand C = opd(b.Mb, 2, 0, 2 * zc, 1, 0, b.sX, (ll)Da * zc * 2);
-      r = gemm(c, dv(c, 1, bet), 1, p.beta[k + 1], dx(2 * Da), 2, 2 * Da, dx(2 * Db), 1, A, B, C, dv(c, 1, ra),
-               p.rin[k]);
-      if (r) return r;
-    }
-    const Operand Mrows = opd(b.Mb, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);      // [p = (a, w')][q]
+    // the site matrix M the forward formed (and truncated), from the saved buffer
+    const void* Mk = sv.mslot(k);
+    const Operand Mrows = opd(Mk, 2 * zc * Da, 2 * zc, 1, 0, 0, b.sX);        // [p = (a, w')][q]
     const Operand Mbar_v = opd(b.Mbar, 2 * zc * Da, 2 * zc, 2, 1, 0, b.sX);   // [p][q = (b, t)], N split lo 2
     if (k == 0) {
       // M[0][0][b][t] = B_0[0][t][b]
@@ -1086,7 +1075,7 @@ int run_apply_backward(const MpsB& in, const MpoB& W, const MpsB& out, const Mps
         HIPCHK(block_copy_b(core_zbar(k) + (size_t)t * zc * csz, 1, 2 * zc, b.sZ, (char*)b.Vbar + (size_t)t * L * csz,
                             2 * L, 1, b.sE, dv(c, 1, bet), dv(c, 1, kkp), p.beta[k + 1], p.beta[k], real, nf, s, 1));
       r = gemm(c, dv(c, 2, bet), 1, (int)qb, dv(c, 1, kkp), 1, p.beta[k], dv(c, Da, ra), Da,
-               opd(b.Mb, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX), opd(gcur, zc * Da, 1, Da, 0, 0, b.sC),
+               opd(Mk, 1, 0, 2 * zc * Da, 2 * zc, 1, b.sX), opd(gcur, zc * Da, 1, Da, 0, 0, b.sC),
                opd(b.Vbar, L, 0, 1, 0, 0, b.sE), dx(1), 1, 1);
       if (r) return r;
       // the full decomposition of M^H M the forward computed
