@@ -422,13 +422,16 @@ int tt_prof_times(float* ms, int max);
 
 /* ---- tile autotuner of the contraction kernel ----
  * The contraction kernel has several output-tile variants (64x64, 32x64,
- * 32x32 complex per workgroup).  tt_autotune_record(1) starts collecting the
- * call shapes (element types, host bounds of the output, grid depth, operand
- * access pattern) of every contraction enqueued afterwards; (0) stops.
- * tt_autotune_run times every variant on synthetic operands of each recorded
- * shape on `stream` (synchronises; needs tt_autotune_workspace_size() bytes
- * of device memory) and from then on every contraction of that shape uses
- * the fastest (outputs larger than 512 x 512 keep the 64x64 tile).
+ * 32x32 complex per workgroup; for FP32 operands with FP32 accumulation also
+ * 128x64 and 128x128, variants 3 and 4).  tt_autotune_record(1) starts
+ * collecting the call shapes (element types, host bounds of the output, grid
+ * depth, operand access pattern) of every contraction enqueued afterwards,
+ * each with the largest contraction depth one workgroup reduces over; (0)
+ * stops.  tt_autotune_run times every variant on synthetic operands of each
+ * recorded shape at that depth (clamped to 16..1024) on `stream`
+ * (synchronises; needs tt_autotune_workspace_size() bytes of device memory)
+ * and from then on every contraction of that shape uses the fastest (outputs
+ * larger than 4096 x 4096 keep the 64x64 tile).
  * Variants differ only in how the output is partitioned, so results are
  * bit-identical whatever is chosen.  tt_autotune_export writes
  * up to max_entries 6-int entries (types, m, n, depth, pattern, variant) and

@@ -6,13 +6,15 @@
 // strides).  A complex product is run as ONE real product on the embedding
 //   [Re C | Im C] = [Re A | Im A] . [[Re B, Im B], [-Im B, Re B]],
 // i.e. the interleaved complex rows of A are already the real operand and the
-// 2x2 real block of each B element is generated while reading B's LDS tile.
-// This keeps complex64/complex128 interleaved in HBM and in the output with no
-// separate real/imaginary planes and no extra passes.
+// 2x2 real block of each B element is written out when B's tile is stored to
+// LDS.  This keeps complex64/complex128 interleaved in HBM and in the output
+// with no separate real/imaginary planes and no extra passes.
 //
-// Tiles: 64x64 complex outputs per 256-thread workgroup, 16 complex of depth
-// per LDS stage, 4 waves in a 2x2 arrangement, each wave a 32x64 real block
-// made of 16x16 MFMA tiles (v_mfma_f32_16x16x4f32 for FP32,
+// Tiles: 64x64 complex outputs per 256-thread workgroup by default (32x64,
+// 32x32 and, for FP32, 128x64 and 128x128 picked per call shape by the
+// autotuner), 16 complex of depth per LDS stage, 4 waves in a 2x2
+// arrangement, each wave a (BM/2)x(BN) real block made of 16x16 MFMA tiles
+// (v_mfma_f32_16x16x4f32 for FP32,
 // v_mfma_f64_16x16x4f64 for FP64 Gram matrices and the FP64 path).  The
 // BF16 precision forms (operands rounded to bfloat16, or split into two
 // bfloat16 terms with three products, FP32 accumulation) run a separate
@@ -63,10 +65,15 @@ constexpr int BKC = 16;                     // complex depth per LDS stage
 constexpr int PADA = 4, PADB = 4;
 constexpr int NT = 256;
 // Output tile variants (complex rows x complex columns per workgroup); the
-// autotuner picks one per call shape, 64 x 64 by default.
-constexpr int N_TILES = 3;
-constexpr int TILE_M[N_TILES] = {64, 32, 32};
-constexpr int TILE_N[N_TILES] = {64, 64, 32};
+// autotuner picks one per call shape, 64 x 64 by default.  The two wide
+// variants (FP32 operands and accumulation only) halve the operand bytes per
+// flop of the 64 x 64 tile: at 16 complex of depth per stage a 64 x 64 tile
+// reads 32 flops' worth of operands per byte, which at the FP32 matrix peak
+// is more L2 traffic than the chip serves.
+constexpr int N_TILES = 5;
+constexpr int N_TILES_NARROW = 3;            // variants of the FP64-accumulating and bfloat16 forms
+constexpr int TILE_M[N_TILES] = {64, 32, 32, 128, 128};
+constexpr int TILE_N[N_TILES] = {64, 64, 32, 64, 128};
 
 __device__ __forceinline__ long long split_off(const FastDiv& f, uint32_t x, long long sh, long long sl) {
   uint32_t h = fdiv(f, x);
@@ -103,14 +110,18 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
   // FP32 A tile without padding, its columns XOR-swizzled per row: the MFMA
   // reads (4 k-rows x 16 columns) and the k-major stores (16 even or odd
   // k-rows x 4 columns) then touch every bank exactly twice, the minimum for
-  // 64 four-byte accesses (a 4-float pad gave 4-way conflicts on both).  The
-  // FP32 B tile, when not stored k-major, pads its rows by 16 floats so the
-  // two k-rows of a read fall on opposite bank halves.
+  // 64 four-byte accesses (a 4-float pad gave 4-way conflicts on both).
+  // B is stored as the real right operand of the embedding: complex row k
+  // becomes real rows 2k = [re, im] and 2k + 1 = [-im, re] per column, so an
+  // MFMA operand is one plain LDS read with no sign select after it (a select
+  // per value made every read wait for its own data).  FP32 rows are padded
+  // by 16 floats (8 when stored k-major) so the four k-rows of a read cover
+  // the banks twice.
   constexpr bool SWZ = sizeof(TC) == 4;
   constexpr int SA = SWZ ? BM : BM + PADA;
-  constexpr int SB = 2 * BN + (SWZ && !BKM ? 16 : PADB);
+  constexpr int SB = 2 * BN + (SWZ ? (BKM ? 8 : 16) : PADB);
   __shared__ TC Asb[NBUF][2 * BKC][SA];
-  __shared__ TC Bsb[NBUF][BKC][SB];
+  __shared__ __align__(16) TC Bsb[NBUF][2 * BKC][SB];
   auto acol = [](int row, int col) -> int {
     if constexpr (SWZ) return col ^ ((((row >> 1) & 3) << 2) | ((((row >> 3) ^ row) & 1) << 4));
     else return col;
@@ -170,6 +181,7 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
     }
   };
   auto store_stage = [&](int bi) {
+    typedef typename Vec2<TC>::t tc2;
     TC (*As)[SA] = Asb[bi];
     TC (*Bs)[SB] = Bsb[bi];
 #pragma unroll
@@ -181,8 +193,12 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < B_PER_T; ++r) {
       TC re = (TC)rb[r].x, im = (TC)rb[r].y;
-      Bs[b_k[r]][2 * b_j[r]] = re;
-      Bs[b_k[r]][2 * b_j[r] + 1] = g.B.conj ? -im : im;
+      if (g.B.conj) im = -im;
+      tc2 top, bot;
+      top.x = re; top.y = im;
+      bot.x = -im; bot.y = re;
+      *(tc2*)&Bs[2 * b_k[r]][2 * b_j[r]] = top;
+      *(tc2*)&Bs[2 * b_k[r] + 1][2 * b_j[r]] = bot;
     }
   };
 
@@ -197,8 +213,6 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
       for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
 
   const int l16 = lane & 15, lq = lane >> 4;
-  const int cpart = lq & 1;
-  const TC bsign = cpart ? (TC)-1 : (TC)1;
 
   if (kbeg < kend) {
     load_stage(kbeg);
@@ -221,13 +235,8 @@ __global__ __launch_bounds__(NT) void cgemm_kernel(GemmArgs g) {
         TC af[MI], bf[NJ];
 #pragma unroll
         for (int i = 0; i < MI; ++i) af[i] = As[ks * 4 + lq][acol(ks * 4 + lq, wm * (BM / 2) + i * 16 + l16)];
-        const int kc = ks * 2 + (lane >> 5);
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          int jr = wn * BN + j * 16 + l16;
-          TC v = Bs[kc][jr ^ cpart];
-          bf[j] = (jr & 1) ? v : v * bsign;
-        }
+        for (int j = 0; j < NJ; ++j) bf[j] = Bs[ks * 4 + lq][wn * BN + j * 16 + l16];
 #pragma unroll
         for (int i = 0; i < MI; ++i)
 #pragma unroll
@@ -683,18 +692,29 @@ static hipError_t launch_tile(const GemmArgs& g, dim3 grid, bool akm, bool bkm, 
 
 template <typename TIn, typename TC, typename TOut, int BF = 0>
 static hipError_t launch_typed(const GemmArgs& g, dim3 grid, bool akm, bool bkm, int tile, hipStream_t s) {
+  constexpr bool wide = sizeof(TIn) == 4 && sizeof(TC) == 4 && BF == 0;
   switch (tile) {
     case 1: return launch_tile<TIn, TC, TOut, BF, 32, 64>(g, grid, akm, bkm, s);
     case 2: return launch_tile<TIn, TC, TOut, BF, 32, 32>(g, grid, akm, bkm, s);
+    case 3:
+      if constexpr (wide) return launch_tile<TIn, TC, TOut, BF, 128, 64>(g, grid, akm, bkm, s);
+      return hipErrorInvalidValue;
+    case 4:
+      if constexpr (wide) return launch_tile<TIn, TC, TOut, BF, 128, 128>(g, grid, akm, bkm, s);
+      return hipErrorInvalidValue;
     default: return launch_tile<TIn, TC, TOut, BF, 64, 64>(g, grid, akm, bkm, s);
   }
 }
 
+// Tile variants available to one element-type combination.
+static int tile_count(int types) { return types == GEMM_F32 ? N_TILES : N_TILES_NARROW; }
+
 // ---------------------------------------------------------------- autotuner
 // Per call shape (element types, host bounds of M and N, grid depth = inner
 // batch x fields, operand access pattern) the tile variant measured fastest
-// on this device.  Shapes are collected while recording is on; tuning times
-// every variant on synthetic operands of that shape (K = TUNE_K).
+// on this device.  Shapes are collected while recording is on, each with the
+// largest depth one workgroup reduces over (K, or its K-split chunk); tuning
+// times every variant on synthetic operands of that shape and depth.
 namespace {
 struct TileKey {
   int types, mb, nb, zb, pat;
@@ -707,19 +727,25 @@ struct TileKey {
   }
 };
 std::map<TileKey, int> g_tiles;
-std::set<TileKey> g_seen;
+std::map<TileKey, int> g_seen;       // recorded shapes -> largest depth per workgroup
 bool g_record = false;
-constexpr int TUNE_K = 64;
+constexpr int TUNE_KMIN = 16, TUNE_KMAX = 1024;  // synthetic depth range
 constexpr int TUNE_ZMAX = 2048;      // grid depth used for timing (larger grids all saturate)
-constexpr int TUNE_MN_MAX = 512 * 512;          // larger outputs keep the 64 x 64 tile
+constexpr long long TUNE_MN_MAX = 4096ll * 4096;  // larger outputs keep the 64 x 64 tile
 constexpr size_t TUNE_BYTES = 256ull << 20;     // synthetic operands per shape
 
-// Grid depth used to time shape k (0: not tuned).
-int tune_depth(const TileKey& k) {
+// Synthetic depth for a recorded depth: rounded up to a whole stage, clamped.
+int tune_k(int kd) {
+  const int k = (kd + BKC - 1) / BKC * BKC;
+  return std::min(std::max(k, TUNE_KMIN), TUNE_KMAX);
+}
+
+// Grid depth used to time shape k at depth kk (0: not tuned).
+int tune_depth(const TileKey& k, int kk) {
   if ((long long)k.mb * k.nb > TUNE_MN_MAX) return 0;
   const size_t esz = k.types == GEMM_F64 ? 16 : 8;
   const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
-  const size_t per = (size_t)k.mb * TUNE_K * esz + (size_t)TUNE_K * k.nb * esz + (size_t)k.mb * k.nb * csz + 768;
+  const size_t per = (size_t)k.mb * kk * esz + (size_t)kk * k.nb * esz + (size_t)k.mb * k.nb * csz + 768;
   size_t z = std::min<size_t>({(size_t)k.zb, (size_t)TUNE_ZMAX, TUNE_BYTES / per});
   return (int)z;
 }
@@ -799,7 +825,11 @@ hipError_t gemm_launch(const GemmSpec& sp, hipStream_t s) {
   TileKey key = make_key(sp, akm, bkm);
   // every product is recorded, the FP64-accumulating Gram matrices included:
   // their K-split chunks are short enough for the tuner's synthetic K
-  if (g_record) g_seen.insert(key);
+  if (g_record) {
+    const int kd = (sp.k_bound + g.ksplit - 1) / g.ksplit;
+    int& rec = g_seen[key];
+    rec = std::max(rec, kd);
+  }
   auto it = g_tiles.find(key);
   // untuned default: 32-row tiles when the rows (or both sides) are that small
   const int tile = it != g_tiles.end() ? it->second
@@ -831,12 +861,14 @@ void autotune_record(bool on) {
 
 size_t autotune_ws_bytes() {
   size_t need = 0;
-  for (const TileKey& k : g_seen) {
+  for (const auto& kv : g_seen) {
+    const TileKey& k = kv.first;
+    const int kk = tune_k(kv.second);
     const size_t esz = k.types == GEMM_F64 ? 16 : 8;
     const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
-    const size_t z = (size_t)tune_depth(k);
+    const size_t z = (size_t)tune_depth(k, kk);
     if (z == 0) continue;
-    size_t a = z * k.mb * TUNE_K * esz, b = z * TUNE_K * k.nb * esz;
+    size_t a = z * k.mb * kk * esz, b = z * kk * k.nb * esz;
     size_t c = z * k.mb * k.nb * csz;
     need = std::max(need, ((a + 255) / 256 + (b + 255) / 256 + (c + 255) / 256) * 256);
   }
@@ -851,36 +883,36 @@ hipError_t autotune_run(void* ws, size_t ws_bytes, hipStream_t s, int* n_tuned) 
   if (err != hipSuccess) return err;
   err = hipEventCreate(&e1);
   if (err != hipSuccess) { hipEventDestroy(e0); return err; }
-  for (const TileKey& k : g_seen) {
+  for (const auto& kv : g_seen) {
+    const TileKey& k = kv.first;
+    const int kk = tune_k(kv.second);
     const size_t esz = k.types == GEMM_F64 ? 16 : 8;
-    const size_t csz = (k.types == GEMM_F64 || k.types == GEMM_F32_GRAM64) ? 16 : 8;
     char* base = (char*)ws;
-    const int zt = tune_depth(k);
-    (void)csz;
+    const int zt = tune_depth(k, kk);
     if (zt == 0) continue;
-    const size_t a = ((size_t)zt * k.mb * TUNE_K * esz + 255) / 256 * 256;
-    const size_t b = ((size_t)zt * TUNE_K * k.nb * esz + 255) / 256 * 256;
+    const size_t a = ((size_t)zt * k.mb * kk * esz + 255) / 256 * 256;
+    const size_t b = ((size_t)zt * kk * k.nb * esz + 255) / 256 * 256;
     // plain row-major operands with the recorded access pattern: A [z][M][K]
     // (K unit stride if pat bit 0) or [z][K][M]; B likewise
     GemmArgs g;
     g.M = DimExpr{k.mb, nullptr, nullptr, 0};
     g.N = DimExpr{k.nb, nullptr, nullptr, 0};
-    g.K = DimExpr{TUNE_K, nullptr, nullptr, 0};
+    g.K = DimExpr{kk, nullptr, nullptr, 0};
     g.batch = DimExpr{1, nullptr, nullptr, 0};
     g.b2cap = 1;
     g.fm = make_fastdiv(1); g.fn = make_fastdiv(1); g.fk = make_fastdiv(1);
     const bool akm = k.pat & 1, bkm = (k.pat >> 1) & 1;
-    g.A = Operand{base, akm ? TUNE_K : 1, 0, akm ? 1 : k.mb, 0, (long long)k.mb * TUNE_K, 0, 0};
-    g.B = Operand{base + a, bkm ? 1 : k.nb, 0, bkm ? TUNE_K : 1, 0, (long long)TUNE_K * k.nb, 0, 0};
+    g.A = Operand{base, akm ? kk : 1, 0, akm ? 1 : k.mb, 0, (long long)k.mb * kk, 0, 0};
+    g.B = Operand{base + a, bkm ? 1 : k.nb, 0, bkm ? kk : 1, 0, (long long)kk * k.nb, 0, 0};
     g.C = Operand{base + a + b, k.nb, 0, 1, 0, (long long)k.mb * k.nb, 0, 0};
     g.accumulate = 0;
     g.lower = 0;
     g.ksplit = 1;
     g.csplit = 0;
-    g.Mmax = k.mb; g.Nmax = k.nb; g.Kmax = TUNE_K; g.Bmax = 1;
+    g.Mmax = k.mb; g.Nmax = k.nb; g.Kmax = kk; g.Bmax = 1;
     float best = 1e30f;
     int best_t = 0;
-    for (int t = 0; t < N_TILES; ++t) {
+    for (int t = 0; t < tile_count(k.types); ++t) {
       // warm-up, then the mean of three launches
       err = launch_variant(g, k.types, akm, bkm, t, k.mb, k.nb, zt, 1, s);
       if (err != hipSuccess) break;
@@ -920,7 +952,7 @@ int autotune_import(const int* entries, int n) {
   int bad = 0;
   for (int i = 0; i < n; ++i) {
     const int* e = entries + 6 * i;
-    if (e[5] < 0 || e[5] >= N_TILES || e[1] < 1 || e[2] < 1 || e[3] < 1) { ++bad; continue; }
+    if (e[5] < 0 || e[5] >= tile_count(e[0]) || e[1] < 1 || e[2] < 1 || e[3] < 1) { ++bad; continue; }
     TileKey k;
     k.types = e[0]; k.mb = e[1]; k.nb = e[2]; k.zb = e[3]; k.pat = e[4];
     g_tiles[k] = e[5];

@@ -152,6 +152,9 @@ def test_autotune_table_host_side(lib):
     assert sorted([tuple(out[0:6]), tuple(out[6:12])]) == sorted([tuple(good[0:6]), tuple(good[6:12])])
     bad = (C.c_int32 * 6)(0, 64, 32, 8, 1, 7)          # variant out of range
     assert lib.tt_autotune_import(C.cast(bad, C.c_void_p), 1) == -1
+    wide = (C.c_int32 * 12)(0, 300, 260, 1, 1, 4, 1, 300, 260, 1, 1, 4)   # wide tile: FP32 only
+    assert lib.tt_autotune_import(C.cast(wide, C.c_void_p), 2) == -1
+    assert lib.tt_autotune_export(None, 0) == 3
     assert lib.tt_autotune_clear() == 0
     assert lib.tt_autotune_export(None, 0) == 0
     assert lib.tt_autotune_record(0) == 0

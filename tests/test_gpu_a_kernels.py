@@ -51,6 +51,45 @@ def test_cgemm(prec, shape, conj):
     assert rel(got, ref) < tol
 
 
+@pytest.mark.parametrize("shape", [(300, 260, 70), (129, 129, 33), (1000, 100, 300), (64, 513, 17)])
+def test_cgemm_every_tile_variant_bit_identical(shape):
+    """Every output-tile variant of the FP32 contraction (the two wide ones
+    included), forced through the tuning table, gives the default variant's
+    bits: the variants differ only in how the output is partitioned."""
+    torch = need_gpu()
+    L, lib = _lib()
+    M, N, K = shape
+    say("cgemm variants", shape)
+    rng = np.random.default_rng(M + 7 * N + 13 * K)
+    a = rng.standard_normal((M, K)) + 1j * rng.standard_normal((M, K))
+    b = rng.standard_normal((K, N)) + 1j * rng.standard_normal((K, N))
+    da = torch.from_numpy(a).to(torch.complex64).cuda()
+    db = torch.from_numpy(b).to(torch.complex64).cuda()
+
+    def run():
+        dc = torch.zeros((M, N), dtype=torch.complex64, device="cuda")
+        L.check(lib.tt_cgemm(M, N, K, da.data_ptr(), K, 0, db.data_ptr(), N, 0, dc.data_ptr(), N, L.PREC_FP32,
+                             _stream(torch)), "tt_cgemm")
+        torch.cuda.synchronize()
+        return dc.cpu()
+
+    from paper_2510_23089_amd import api
+    L.check(lib.tt_autotune_clear(), "clear")
+    base = run()
+    ref = a.astype(np.complex64).astype(np.complex128) @ b.astype(np.complex64).astype(np.complex128)
+    assert rel(base.numpy(), ref) < 2e-6
+    assert api.autotune(run) >= 1
+    table = api.autotune_table()
+    assert all(e[0] == 0 and 0 <= e[5] < 5 for e in table)
+    try:
+        for v in range(5):
+            L.check(lib.tt_autotune_clear(), "clear")
+            api.autotune_load([list(e[:5]) + [v] for e in table])
+            assert torch.equal(run(), base), v
+    finally:
+        L.check(lib.tt_autotune_clear(), "clear")
+
+
 def _heev(torch, L, lib, mats, kcap, cutoff=0.0, tau=0.0):
     batch, n, _ = mats.shape
     g = torch.from_numpy(np.ascontiguousarray(mats)).to(torch.complex128).cuda()

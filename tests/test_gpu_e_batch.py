@@ -148,7 +148,8 @@ def test_autotune_keeps_results_bit_identical():
     n = b.tune()
     assert n > 0
     table = api.autotune_table()
-    assert len(table) == n and all(0 <= e[5] < 3 for e in table)
+    # FP32 products have five tile variants, the other forms three
+    assert len(table) == n and all(0 <= e[5] < (5 if e[0] == 0 else 3) for e in table)
     after = b.run().clone()
     torch.cuda.synchronize()
     assert torch.equal(before, after)
