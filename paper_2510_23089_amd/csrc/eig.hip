@@ -1488,7 +1488,14 @@ hipError_t eig_launch(const EigSpec& sp, hipStream_t s) {
   EmitPack ep;
   ep.ne = sp.nemit;
   for (int i = 0; i < sp.nemit && i < 3; ++i) ep.e[i] = sp.emit[i];
-  if (nb <= 256)
+  // entries per lane from the size bound (lanes beyond n carry zeros, which
+  // add nothing to the sums but cost their arithmetic; with one entry per
+  // lane the compiler contracts the sums differently, so the smallest form
+  // keeps two)
+  if (nb <= 128)
+    hipLaunchKernelGGL(backtr_kernel<128>, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s, (const double2*)sp.G,
+                       sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep, vec_all);
+  else if (nb <= 256)
     hipLaunchKernelGGL(backtr_kernel<256>, dim3((kc + 3) / 4, sp.batch), dim3(BT_NT), 0, s, (const double2*)sp.G,
                        sp.ld, sp.gstride, sp.n, sp.kout, sp.kstride, sp.ws, nb, kc, ep, vec_all);
   else
