@@ -595,9 +595,12 @@ def main():
     wall = time.perf_counter() - t0
     for ln in lanes:
         ln.check()
-    # ---- latency of one field's step (one field, its nz distances, one stream)
-    run(2, 1, [single])
-    serial_ms = timed(lambda: run(a.serial_steps, 1, [single])) / a.serial_steps
+    # ---- latency of one field's step (one field, its nz distances, one stream);
+    # --serial-steps 0 skips it (reported as null)
+    serial_ms = None
+    if a.serial_steps > 0:
+        run(2, 1, [single])
+        serial_ms = timed(lambda: run(a.serial_steps, 1, [single])) / a.serial_steps
     # ---- dominant kernel, its launches bracketed by HIP events on their
     # streams, in a pass of its own: the same steps on the same lanes
     lib = L.load()
