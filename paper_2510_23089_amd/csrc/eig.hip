@@ -892,7 +892,9 @@ __global__ __launch_bounds__(KP_NT) void keep_kernel(DimExpr nexp, int kcap, dou
 // v_rcp_f64 and two Newton steps), carry their running values in registers
 // and read their LDS inputs in blocks of eight issued ahead of the
 // arithmetic.  The start vector comes from a per-vector xorshift stream,
-// generated inside the first forward pass.
+// drawn in a pass of its own before the first solve (drawn inside the first
+// forward pass, its 64-bit shift chain slowed that pass by more than the
+// separate pass costs).
 constexpr int IV_LDS = 55 * 1024;     // dynamic LDS per workgroup (with the static part under 64 KB)
 constexpr int IV_B = 8;               // recurrence steps per prefetched block
 constexpr int IV_ITERS = 3;           // inverse-iteration solves
