@@ -163,6 +163,52 @@ def test_autotune_keeps_results_bit_identical():
     api.check_status()
 
 
+def test_every_contraction_variant_gives_the_same_propagation():
+    """An FP32 encode, batched propagation (both axes) and decompression with
+    every recorded contraction shape forced to each tile variant in turn (the
+    wide FP32 tiles and the k-major operand forms included; the FP64-
+    accumulated Gram shapes cycle through their three) reproduces the default
+    run's bits: the variants only partition the outputs differently."""
+    torch = need_gpu()
+    from paper_2510_23089_amd import api
+    from paper_2510_23089_amd import _lib as L
+    lib = L.load()
+    n, chi = 9, 48
+    zs = (0.5e-3, 2e-3)
+    m = 2 * n
+    d = torch.from_numpy(synth.aperture_field(71, n=1 << n)).to(torch.complex64).cuda()
+    prop = api.FresnelBatch(n, LAM, DX, zs, device="cuda")
+    bi = api.MPSBatch(len(zs), m, chi)
+    mid = api.MPSBatch(len(zs), m, chi)
+    out = api.MPSBatch(len(zs), m, chi)
+
+    def run():
+        psi = api.tt_encode(d, chi)
+        bi.fill_from(psi)
+        prop(bi, chi, tmp=mid, out=out)
+        dens = api.tt_to_dense_batched(out)
+        torch.cuda.synchronize()
+        return dens.clone(), out.bonds.clone()
+
+    L.check(lib.tt_autotune_clear(), "clear")
+    try:
+        base, bonds = run()
+        api.check_status()
+        assert api.autotune(run) > 0
+        table = api.autotune_table()
+        assert any(e[0] == 0 for e in table) and any(e[0] != 0 for e in table)
+        for v in range(5):
+            say("forced variant", v)
+            L.check(lib.tt_autotune_clear(), "clear")
+            api.autotune_load([list(e[:5]) + [v if e[0] == 0 else v % 3] for e in table])
+            got, gb = run()
+            assert torch.equal(gb, bonds), v
+            assert torch.equal(got, base), v
+        api.check_status()
+    finally:
+        L.check(lib.tt_autotune_clear(), "clear")
+
+
 def test_native_group_encode_matches_padded_encode():
     """UnevenBatch encodes each side on its own grid and puts 2(K - k) leading
     |0> sites in front; the result must be the encode of the zero-padded
